@@ -1,0 +1,188 @@
+"""Throughput of the Gaussian-RBF hot path on one MI355X.
+
+One step = one pass of the whole path over the torus workload (200,000
+surface points, 600,000 centres, sigma 0.02, cutoff 4 sigma):
+  setup      extended centres, Morton sort, cells, source lists;
+  solve      one refinement step of the chosen pipeline: a GMRES(30) cycle on
+             the float32 operator (30 applications) and the float64 true
+             residual of its result (1 application);
+  grid       the interpolant on the 256^3 grid around the cloud.
+value = useful kernel evaluations (pairs with r <= cutoff) of every operator
+application and of the grid, divided by the step time.  Inputs (points,
+normals) are resident in device memory before timing starts.
+
+Prints one JSON line.  --gpus above 1 is refused: this path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RBF kernel evals/s (% FP32 roofline); solve+grid time to resid 1e-8 vs plain"
+
+# Pair roofline of the float32 kernel (alu bound; derivation in the design doc):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-slots/s.  One useful
+# pair is 7 float32 add/mul/FMA operations and one v_exp_f32.  At the
+# published vector FP32 peak (packed FMA, two operations per lane-slot) the
+# seven take 3.5 slots and the exponential one issue slot: 4.5 slots/pair.
+LANE_SLOTS = 256 * 4 * 16 * 2.4e9
+PEAK_PAIRS = LANE_SLOTS / 4.5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=1200, help="operator rows the CPU oracle evaluates")
+    ap.add_argument("--solve", action="store_true",
+                    help="also time full solves (float32+refinement vs plain float64) to a common residual")
+    ap.add_argument("--solve-iters", type=int, default=3000)
+    return ap.parse_args()
+
+
+def cpu_baseline(X, sigma, cutoff, rows_n):
+    """The oracle's float64 operator rows on the host, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rbf_oracle as o
+    from paper_1305_5179_amd import workloads as w
+
+    x = w.random_vector(X.shape[0], seed=4)
+    rows = np.random.default_rng(7).choice(X.shape[0], rows_n, replace=False)
+    with threadpool_limits(limits=1):
+        o.matvec_rows(X, x, rows[:8], sigma, cutoff)
+        t0 = time.perf_counter()
+        o.matvec_rows(X, x, rows, sigma, cutoff)
+        dt = time.perf_counter() - t0
+        r2_in = 0
+        for i in rows:
+            r2 = o.sqdist(X[i:i + 1], X)[0]
+            r2_in += int(np.count_nonzero(r2 <= cutoff * cutoff))
+    return {"value": r2_in / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows_n} random rows of the float64 operator (brute force over all {X.shape[0]} "
+                      f"centres, {r2_in} useful pairs, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no multi-GPU "
+              f"implementation in this build", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1305_5179_amd import rbf
+    from paper_1305_5179_amd import workloads as w
+
+    cfg = w.TORUS_200K
+    cloud = w.torus(cfg["n"], cfg["seed"])
+    eps, sigma, cutoff, restart = cfg["eps"], cfg["sigma"], cfg["cutoff"], cfg["restart"]
+    g = w.Grid.around(cloud.points, cfg["grid_n"])
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pts = torch.as_tensor(cloud.points, device=dev).contiguous()
+    nrm = torch.as_tensor(cloud.normals, device=dev).contiguous()
+    grid_out = torch.empty(g.size, dtype=torch.float32, device=dev)
+    lib = rbf.load_library()
+
+    def step():
+        ctx = rbf.Rbf(pts, nrm, eps, sigma, cutoff)
+        coef, info = ctx.solve(tol=1e-8, restart=restart, max_iters=restart, max_outer=1,
+                               mode=rbf.RBF_SOLVE_IR_FP32)
+        ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32, out=grid_out)
+        st = ctx.stats()
+        ctx.close()
+        return info, st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # pair counts of one step (fixed by the geometry)
+    ctx = rbf.Rbf(pts, nrm, eps, sigma, cutoff)
+    st = ctx.stats()
+    grid_useful, grid_examined = ctx.count_grid_pairs(g.origin, g.h, g.dims)
+    ctx.close()
+
+    rbf.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step()[0] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = rbf.profile_end()
+
+    applications = infos[0].iters + 1   # cycle + true residual of its result
+    useful_step = applications * st.useful_pairs + grid_useful
+    value = useful_step * args.steps / dt
+    ms_step = 1e3 * dt / args.steps
+
+    # dominant kernel: the float32 pair sum (operator and grid launches)
+    f32_ms = prof.kernel_ms[0]
+    f32_launch = prof.launches[0]
+    achieved = prof.useful_pairs[0] / (f32_ms * 1e-3)
+    roofline = {
+        "bound": "alu", "kernel": "k_pairsum_f32",
+        "achieved": achieved / 1e9, "peak": PEAK_PAIRS / 1e9, "unit": "Gpair/s",
+        "frac": achieved / PEAK_PAIRS, "traffic": None,
+        "launches": f32_launch, "avg_launch_ms": f32_ms / max(f32_launch, 1),
+        "examined_per_useful": prof.examined_pairs[0] / max(prof.useful_pairs[0], 1),
+        "examined_rate": prof.examined_pairs[0] / (f32_ms * 1e-3) / 1e9,
+    }
+    out = {
+        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "torus R=1 r=0.35, 200000 points, 600000 centres, sigma 0.02, cutoff 0.08; "
+                               "setup + IR-GMRES(30) cycle (float32 operator) + float64 residual + 256^3 grid",
+                   "n_points": cfg["n"], "n_centres": 3 * cfg["n"], "sigma": sigma, "cutoff": cutoff,
+                   "restart": restart, "grid": list(g.dims)},
+        "roofline": roofline,
+        "pairs": {"operator_useful": st.useful_pairs, "operator_examined": st.examined_pairs,
+                  "grid_useful": grid_useful, "grid_examined": grid_examined,
+                  "applications_per_step": applications},
+        "fp64_kernel": {"launches": prof.launches[1], "avg_launch_ms": prof.kernel_ms[1] / max(prof.launches[1], 1),
+                        "useful_rate": prof.useful_pairs[1] / max(prof.kernel_ms[1] * 1e-3, 1e-30) / 1e9},
+    }
+    if args.solve:
+        out["solve"] = solve_comparison(rbf, pts, nrm, cfg, g, args.solve_iters)
+    if not args.no_cpu:
+        from oracle import rbf_oracle as o
+        X, _ = o.extended_centres(cloud.points, cloud.normals, eps)
+        out["cpu_baseline"] = cpu_baseline(X, sigma, cutoff, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+def solve_comparison(rbf, pts, nrm, cfg, g, iters):
+    """Chosen pipeline (float32 operator + float64 refinement) and the plain
+    float64 method, each timed from setup to grid; compared at the lowest
+    residual both reach."""
+    import torch
+    res = {}
+    for name, mode in (("ir_fp32", rbf.RBF_SOLVE_IR_FP32), ("plain_fp64", rbf.RBF_SOLVE_PLAIN_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = rbf.Rbf(pts, nrm, cfg["eps"], cfg["sigma"], cfg["cutoff"])
+        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode)
+        ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32 if mode else rbf.RBF_FP64,
+                      out=torch.empty(g.size, dtype=torch.float32 if mode else torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        res[name] = {"seconds": time.perf_counter() - t0, "status": info.status, "iters": info.iters,
+                     "rel_resid": info.rel_resid, "history": info.history}
+        ctx.close()
+    return res
+
+
+if __name__ == "__main__":
+    main()

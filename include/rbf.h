@@ -1,0 +1,183 @@
+/*
+ * rbf.h -- C ABI of librbf, a GPU library for implicit surface
+ * reconstruction with Gaussian radial basis functions on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: Cuomo, Galletti, Giunta, Starace, "Surface Reconstruction from
+ * Scattered Point via RBF Interpolation on GPU" (arXiv 1305.5179):
+ *   1. extend the cloud by off-surface points along the normals (Sec. II.A.1);
+ *   2. solve the Gaussian interpolation system A c = b with GMRES
+ *      (Sec. II.B eq. RBFsys, Sec. III.A eqs. matrixEntries);
+ *   3. evaluate the interpolant on a grid (Sec. II.B eq. matxvet, Sec. II.A.3).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers (hipMalloc'ed or torch tensors on
+ *     the GPU) owned by the caller; they must stay valid until the work
+ *     enqueued on `stream` has finished.  Host pointers are rejected with
+ *     RBF_EINVAL.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; calls that must read a result back (rbf_setup,
+ *     rbf_solve, rbf_count_pairs) synchronise with it before returning.
+ *   - Centre order is the paper's: centre i is point i, centre N+i the
+ *     outside point x_i + eps*n_i, centre 2N+i the inside point
+ *     x_i - eps*n_i (Sec. II.A.1).  Vectors of length 3N (x, y, b, c) are in
+ *     that order; any internal reordering is invisible to the caller.
+ *   - The kernel is phi(r) = exp(-r^2 / (2 sigma^2)); A_ij = phi(|x_i - x_j|)
+ *     when |x_i - x_j|^2 <= cutoff^2 (decided in float64, with
+ *     r^2 = (dx*dx + dy*dy) + dz*dz), else 0.  cutoff = +INFINITY keeps every
+ *     pair.  The paper's 1/(sqrt(2 pi) sigma) factor is left out: a constant
+ *     factor scales the weights and leaves the interpolant unchanged.
+ *   - Every function returns an rbf_status; nothing aborts.  After an error
+ *     rbf_last_error() describes it.  One context must not be used from two
+ *     host threads at once.
+ */
+#ifndef RBF_H
+#define RBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbf_ctx rbf_ctx;
+
+typedef enum {
+    RBF_OK = 0,
+    RBF_EINVAL = -1,      /* bad argument (NaN/Inf input, sigma/eps/cutoff <= 0, zero normal, n <= 0, host pointer, ...) */
+    RBF_ENOMEM = -2,      /* device allocation failed */
+    RBF_EDEVICE = -3,     /* no usable gfx950 device, or a HIP runtime error */
+    RBF_ENOCONV = -4,     /* rbf_solve stopped at its iteration limit; c and info hold the best iterate */
+    RBF_EBREAKDOWN = -5   /* a non-finite value appeared in the solve */
+} rbf_status;
+
+typedef enum { RBF_FP32 = 0, RBF_FP64 = 1 } rbf_prec;
+
+typedef enum {
+    RBF_SOLVE_PLAIN_FP64 = 0,  /* restarted GMRES, float64 operator throughout */
+    RBF_SOLVE_IR_FP32 = 1      /* float64 outer refinement, GMRES cycles on the float32 operator */
+} rbf_mode;
+
+typedef struct {
+    double tol;        /* stop when |b - A c|_2 / |b|_2 <= tol, float64 operator (default 1e-8) */
+    int restart;       /* GMRES restart length m, 1..64 (default 30) */
+    int max_outer;     /* maximum restarts / refinement steps (default 1000) */
+    int max_iters;     /* maximum operator applications inside GMRES cycles (default 30000) */
+    int mode;          /* rbf_mode (default RBF_SOLVE_IR_FP32) */
+    int reserved;      /* must be 0 */
+} rbf_solve_opts;
+
+typedef struct {
+    int iters;               /* operator applications inside GMRES cycles */
+    int outer;               /* restarts (plain) or refinement steps (IR) performed */
+    double rel_resid;        /* final |b - A c|_2 / |b|_2 with the float64 operator */
+    int status;              /* same value rbf_solve returned */
+    int n_history;
+    const double* history;   /* host array: true relative residual at the start of each outer
+                                step and at the end; owned by the context, valid until the next
+                                call on it */
+} rbf_solve_info;
+
+typedef struct {
+    double origin[3];   /* node (i,j,k) = origin + (i*h[0], j*h[1], k*h[2]) */
+    double h[3];
+    int64_t dims[3];    /* nodes per axis; output index i + dims[0]*(j + dims[1]*k) (x fastest) */
+} rbf_grid;
+
+typedef struct {
+    int64_t n_points;        /* N */
+    int64_t n_centres;       /* 3N */
+    int64_t n_groups;        /* target groups of 16 centres */
+    int64_t list_entries;    /* source-list entries over all groups (padded) */
+    int64_t useful_pairs;    /* nonzeros of A: pairs with r^2 <= cutoff^2 (3N^2 without cutoff) */
+    int64_t examined_pairs;  /* pairs one matvec evaluates (list entries x 16) */
+    int64_t n_cells;         /* occupied cells of the neighbour lattice */
+    double cell_size;        /* side of a lattice cell */
+    double sigma, cutoff, eps;
+} rbf_stats;
+
+/* Fill `opts` with the defaults listed in rbf_solve_opts. */
+int rbf_default_solve_opts(rbf_solve_opts* opts);
+
+/* Step 1 of the paper's Alg. 1 plus the neighbour structure for truncation
+ * (Sec. II.A.1; Sec. III.A, the finite-bandwidth remark).
+ *   points, normals: device, n x 3 float64, row-major (x, y, z per row).
+ *     Normals need not be unit length; a normal shorter than 1e-12 is
+ *     RBF_EINVAL.  Coordinates must be finite.
+ *   off_surface_eps > 0: the offset delta along the unit normals.
+ *   sigma > 0, cutoff > 0 (or +INFINITY).
+ * Copies everything it needs; keeps no caller pointer.  *out receives a new
+ * context (NULL on failure). */
+int rbf_setup(const double* points, const double* normals, int64_t n,
+              double off_surface_eps, double sigma, double cutoff,
+              void* stream, rbf_ctx** out);
+
+/* The extended centre set and default data values (Sec. II.A.1-2).
+ * centres: device, 3n x 3 float64 (paper order); values: device, 3n float64,
+ * 0 / +eps / -eps.  Either pointer may be NULL. */
+int rbf_centres(rbf_ctx* ctx, double* centres, double* values, void* stream);
+
+/* y = A x (Sec. II.B eq. RBFsys), matrix-free.  x, y: device, 3n float64.
+ * RBF_FP32 evaluates the pair sums in float32 (cutoff still decided as in
+ * float64); RBF_FP64 entirely in float64.  x and y may not overlap. */
+int rbf_matvec(rbf_ctx* ctx, const double* x, double* y, int prec, void* stream);
+
+/* Weights c with A c = b (Sec. III.A: GMRES on the interpolation system).
+ *   b: device 3n float64, or NULL for the default values (0, +eps, -eps).
+ *   x0: device 3n initial guess, or NULL for zero.  c: device 3n output
+ *   (may alias x0).  opts: NULL for defaults.  info: may be NULL.
+ * Blocks the host until done.  Returns RBF_OK when the float64 relative
+ * residual reached opts->tol, RBF_ENOCONV when a limit stopped it (c and
+ * info still hold the last iterate), RBF_EBREAKDOWN on non-finite values. */
+int rbf_solve(rbf_ctx* ctx, const double* b, const double* x0, double* c,
+              const rbf_solve_opts* opts, rbf_solve_info* info, void* stream);
+
+/* f on a regular grid (Sec. II.A.3; Sec. II.B eq. matxvet).
+ *   c: device 3n float64 weights.  out: device, dims[0]*dims[1]*dims[2]
+ *   values, float32 when prec == RBF_FP32, float64 when RBF_FP64.
+ * Nodes farther than cutoff from every centre get exactly 0. */
+int rbf_eval_grid(rbf_ctx* ctx, const double* c, const rbf_grid* grid, void* out,
+                  int prec, void* stream);
+
+/* f at m arbitrary points.  pts: device m x 3 float64; out: device m float64. */
+int rbf_eval_points(rbf_ctx* ctx, const double* c, const double* pts, int64_t m,
+                    double* out, int prec, void* stream);
+
+/* Sizes and pair counts of the context (host call, no device work). */
+int rbf_get_stats(const rbf_ctx* ctx, rbf_stats* stats);
+
+/* Pairs one rbf_eval_grid over `grid` evaluates: useful = node-centre pairs
+ * with r^2 <= cutoff^2 (decided in float64), examined = pairs the kernel
+ * computes.  Synchronises with `stream`. */
+int rbf_count_grid_pairs(rbf_ctx* ctx, const rbf_grid* grid, int64_t* useful,
+                         int64_t* examined, void* stream);
+
+/* Kernel timing for measurement tools (process-wide, off by default).
+ * Between rbf_profile_begin() and rbf_profile_end() every pair-sum kernel
+ * launch (operator, grid or point evaluation) is bracketed by HIP events on
+ * the stream it runs on; rbf_profile_end() waits for them and reports, per
+ * precision, the launches, their summed device time and the pairs they
+ * evaluated.  Not thread-safe; adds two event records per launch. */
+typedef struct {
+    int64_t launches[2];        /* [RBF_FP32], [RBF_FP64] */
+    double kernel_ms[2];        /* summed event-to-event time of those launches */
+    int64_t useful_pairs[2];    /* pairs with r^2 <= cutoff^2 they evaluated */
+    int64_t examined_pairs[2];  /* pairs they computed (list entries x 16) */
+} rbf_profile;
+
+int rbf_profile_begin(void);
+int rbf_profile_end(rbf_profile* out);
+
+/* Release every resource of the context (NULL is ignored).  Waits for work
+ * enqueued by the context. */
+void rbf_destroy(rbf_ctx* ctx);
+
+/* Message describing the last error on `ctx`, or on the calling thread when
+ * ctx is NULL (e.g. after a failed rbf_setup).  Never NULL. */
+const char* rbf_last_error(const rbf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBF_H */

@@ -1,0 +1,547 @@
+// C ABI of librbf (declared in include/rbf.h): argument checks, the setup
+// pipeline, the operator, the GMRES driver and the evaluation entry points.
+#include <algorithm>
+#include <cstring>
+#include <limits>
+
+#include "common.h"
+
+namespace rbf {
+
+// krylov.hip
+int gm_max_restart();
+size_t gm_state_bytes();
+int64_t gm_partial_count(int64_t n);
+void gm_start(const double* b, const double* y, double* r, int64_t n, double* V, double* partial, int m,
+              double tol_abs, void* state, hipStream_t s);
+void gm_step(double* V, int64_t ldv, double* w, int64_t n, int j, double* partial, void* state, hipStream_t s);
+void gm_finish(double* V, int64_t ldv, double* x, int64_t n, void* state, hipStream_t s);
+void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s);
+const int* gm_done_flag(const void* state);
+
+namespace {
+
+thread_local std::string t_err = "no error";
+
+int fail(Ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  t_err = msg;
+  return code;
+}
+
+template <class F>
+int guarded(Ctx* c, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return fail(c, e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(c, RBF_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, RBF_EDEVICE, e.what());
+  }
+}
+
+// The library is built for gfx950 only.
+int check_device(Ctx* c, int* dev_out) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0)
+    return fail(c, RBF_EDEVICE, std::string("no HIP device available (") + hipGetErrorString(e) + ")");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(c, RBF_EDEVICE, "hipGetDevice failed");
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return fail(c, RBF_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
+    return fail(c, RBF_EDEVICE, std::string("device ") + p.gcnArchName + " is not gfx950");
+  *dev_out = dev;
+  return RBF_OK;
+}
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+void free_targets(TargetSet& ts) {
+  for (void* p : ts.owned) dfree(p);
+  ts.owned.clear();
+  dfree(ts.pts);
+  ts.pts = nullptr;
+  ts.groups = nullptr;
+  ts.list = nullptr;
+}
+
+void free_ctx(Ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_targets(c->centres);
+  for (void* p : {(void*)c->perm, (void*)c->keys, (void*)c->xs, (void*)c->xk, (void*)c->xpaper, (void*)c->cell_start,
+                  (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->vin, (void*)c->vout,
+                  (void*)c->V, (void*)c->w, (void*)c->r, (void*)c->csol, (void*)c->bsort, (void*)c->partial,
+                  (void*)c->state})
+    dfree(p);
+}
+
+// Neighbour lattice for the centre bounding box (see the Lattice comment).
+Lattice make_lattice(const double box[6], double cutoff) {
+  Lattice L{};
+  double ext[3], maxext = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = box[3 + d] - box[d];
+    maxext = std::max(maxext, ext[d]);
+  }
+  if (!(maxext > 0.0)) maxext = 1.0;
+  const double fine0 = maxext / 1000.0;
+  if (std::isfinite(cutoff)) {
+    const double target = 0.5 * cutoff;
+    int shift = 0;
+    double fine = fine0;
+    if (target >= fine0) {
+      shift = (int)std::floor(std::log2(target / fine0));
+      shift = std::min(std::max(shift, 0), 7);
+      fine = target / std::ldexp(1.0, shift);
+    }
+    L.fine = fine;
+    L.shift = shift;
+  } else {
+    L.fine = fine0;
+    L.shift = 0;
+  }
+  L.coarse = L.fine * std::ldexp(1.0, L.shift);
+  for (int d = 0; d < 3; ++d) {
+    L.origin[d] = box[d] - 0.5 * L.fine;
+    int64_t fd = (int64_t)std::floor(ext[d] / L.fine) + 2;
+    L.fdims[d] = (int)std::min<int64_t>(fd, kFineMax);
+    L.cdims[d] = (int)ceil_div(L.fdims[d], (int64_t)1 << L.shift);
+  }
+  return L;
+}
+
+void ensure_solver(Ctx* c, int m) {
+  if (c->V && c->krylov_m >= m) return;
+  dfree(c->V);
+  c->V = dalloc<double>((int64_t)(m + 1) * c->mpad);
+  RBF_HIP(hipMemset(c->V, 0, sizeof(double) * (size_t)(m + 1) * c->mpad));
+  c->krylov_m = m;
+  if (!c->w) {
+    c->w = dalloc<double>(c->mpad);
+    c->r = dalloc<double>(c->mpad);
+    c->csol = dalloc<double>(c->mpad);
+    c->bsort = dalloc<double>(c->mpad);
+    RBF_HIP(hipMemset(c->w, 0, sizeof(double) * c->mpad));
+    RBF_HIP(hipMemset(c->r, 0, sizeof(double) * c->mpad));
+    RBF_HIP(hipMemset(c->csol, 0, sizeof(double) * c->mpad));
+    RBF_HIP(hipMemset(c->bsort, 0, sizeof(double) * c->mpad));
+    c->state = dalloc<char>((int64_t)gm_state_bytes());
+    RBF_HIP(hipMemset(c->state, 0, gm_state_bytes()));
+  }
+  const int64_t pc = gm_partial_count(c->m);
+  if (c->partial_cap < pc) {
+    dfree(c->partial);
+    c->partial = dalloc<double>(pc);
+    c->partial_cap = pc;
+  }
+}
+
+// y_sorted = A x_sorted (x_sorted has a zero at index m).
+void apply_sorted(Ctx* c, const double* x, double* y, int prec, hipStream_t s, const int* skip = nullptr) {
+  if (prec == RBF_FP32)
+    pairsum_f32(*c, c->centres, x, OUT_SORTED64, y, nullptr, s, skip);
+  else
+    pairsum_f64(*c, c->centres, x, OUT_SORTED64, y, nullptr, s, skip);
+}
+
+}  // namespace
+
+void set_thread_error(const std::string& msg) { t_err = msg; }
+const char* thread_error() { return t_err.c_str(); }
+
+}  // namespace rbf
+
+using namespace rbf;
+
+struct rbf_ctx : rbf::Ctx {};
+
+extern "C" {
+
+int rbf_default_solve_opts(rbf_solve_opts* o) {
+  if (!o) return fail(nullptr, RBF_EINVAL, "opts is NULL");
+  o->tol = 1e-8;
+  o->restart = 30;
+  o->max_outer = 1000;
+  o->max_iters = 30000;
+  o->mode = RBF_SOLVE_IR_FP32;
+  o->reserved = 0;
+  return RBF_OK;
+}
+
+int rbf_setup(const double* points, const double* normals, int64_t n, double off_surface_eps, double sigma,
+              double cutoff, void* stream, rbf_ctx** out) {
+  if (!out) return fail(nullptr, RBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n <= 0) return fail(nullptr, RBF_EINVAL, "n must be positive");
+  if (n > ((int64_t)1 << 29)) return fail(nullptr, RBF_EINVAL, "n too large (3n must fit 31-bit indices)");
+  if (!(off_surface_eps > 0.0) || !std::isfinite(off_surface_eps))
+    return fail(nullptr, RBF_EINVAL, "off_surface_eps must be finite and > 0");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(nullptr, RBF_EINVAL, "sigma must be finite and > 0");
+  if (!(cutoff > 0.0)) return fail(nullptr, RBF_EINVAL, "cutoff must be > 0 (or +INFINITY)");
+  int dev = 0;
+  int st = check_device(nullptr, &dev);
+  if (st != RBF_OK) return st;
+  if (!is_device_ptr(points) || !is_device_ptr(normals))
+    return fail(nullptr, RBF_EINVAL, "points and normals must be device pointers");
+  rbf_ctx* c = new (std::nothrow) rbf_ctx();
+  if (!c) return fail(nullptr, RBF_ENOMEM, "host allocation failed");
+  hipStream_t s = (hipStream_t)stream;
+  st = guarded(c, [&]() -> int {
+    c->device = dev;
+    c->n = n;
+    c->m = 3 * n;
+    c->mpad = round_up(c->m + 1, 256);
+    c->eps = off_surface_eps;
+    c->sigma = sigma;
+    c->cutoff = cutoff;
+    c->rc2 = std::isfinite(cutoff) ? cutoff * cutoff : INFINITY;
+    c->sqrt_k = std::sqrt(1.4426950408889634 / (2.0 * sigma * sigma));
+    c->inv_two_s2 = 1.0 / (2.0 * sigma * sigma);
+    // 1. inputs
+    int* flags = dalloc<int>(2);
+    RBF_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+    check_inputs(points, normals, n, flags, s);
+    int hf[2] = {0, 0};
+    RBF_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    dfree(flags);
+    if (hf[0]) return fail(c, RBF_EINVAL, "points or normals contain NaN or Inf");
+    if (hf[1]) return fail(c, RBF_EINVAL, "a normal is shorter than 1e-12");
+    // 2. extended set (paper order)
+    c->xpaper = dalloc<double>(3 * c->m);
+    build_centres(points, normals, n, off_surface_eps, c->xpaper, s);
+    // 3. lattice from the bounding box
+    double* box = dalloc<double>(6 + 6 * 1024);
+    bounding_box(c->xpaper, c->m, box, box + 6, s);
+    double hb[6];
+    RBF_HIP(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    dfree(box);
+    c->lat = make_lattice(hb, cutoff);
+    if (std::isfinite(cutoff)) {
+      const double cells = (double)c->lat.cdims[0] * c->lat.cdims[1] * c->lat.cdims[2];
+      if (cells > (double)((int64_t)1 << 28))
+        return fail(c, RBF_EINVAL, "cutoff too small for the extent of the cloud (neighbour lattice too large)");
+    }
+    // 4. Morton order
+    c->perm = dalloc<uint32_t>(c->m);
+    c->keys = dalloc<uint32_t>(c->m);
+    sort_points(c->xpaper, c->m, c->lat, c->perm, c->keys, s);
+    c->xs = dalloc<double4>(c->m + 1);
+    c->xk = dalloc<double4>(c->m + 1);
+    gather_sorted(c->xpaper, c->perm, c->m, c->sqrt_k, c->xs, c->xk, s);
+    // 5. coarse cells
+    if (std::isfinite(cutoff))
+      c->n_cells = build_cells(c->keys, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
+    // 6. the centres as targets, with their source lists
+    TargetSet& ts = c->centres;
+    ts.n_targets = c->m;
+    ts.n_groups = ceil_div(c->m, kGroup);
+    ts.dense = !std::isfinite(cutoff);
+    ts.pts = dalloc<double4>(ts.n_groups * kGroup);
+    centre_targets(c->xs, c->m, ts.pts, ts.n_groups, s);
+    build_lists(*c, ts, s);
+    // 7. work vectors
+    c->vin = dalloc<double>(c->mpad);
+    c->vout = dalloc<double>(c->mpad);
+    RBF_HIP(hipMemsetAsync(c->vin, 0, sizeof(double) * c->mpad, s));
+    RBF_HIP(hipMemsetAsync(c->vout, 0, sizeof(double) * c->mpad, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    return RBF_OK;
+  });
+  if (st != RBF_OK) {
+    t_err = c->err;
+    free_ctx(c);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return RBF_OK;
+}
+
+int rbf_centres(rbf_ctx* c, double* centres, double* values, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if ((centres && !is_device_ptr(centres)) || (values && !is_device_ptr(values)))
+    return fail(c, RBF_EINVAL, "outputs must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    if (centres)
+      RBF_HIP(hipMemcpyAsync(centres, c->xpaper, sizeof(double) * 3 * c->m, hipMemcpyDeviceToDevice, s));
+    if (values) {
+      fill_f64(values, 0.0, c->n, s);
+      fill_f64(values + c->n, c->eps, c->n, s);
+      fill_f64(values + 2 * c->n, -c->eps, c->n, s);
+    }
+    return RBF_OK;
+  });
+}
+
+int rbf_matvec(rbf_ctx* c, const double* x, double* y, int prec, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (prec != RBF_FP32 && prec != RBF_FP64) return fail(c, RBF_EINVAL, "prec must be RBF_FP32 or RBF_FP64");
+  if (!is_device_ptr(x) || !is_device_ptr(y)) return fail(c, RBF_EINVAL, "x and y must be device pointers");
+  if (x == y) return fail(c, RBF_EINVAL, "x and y must not overlap");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    gather_to_sorted(x, c->perm, c->m, c->vin, s);
+    apply_sorted(c, c->vin, c->vout, prec, s);
+    scatter_from_sorted(c->vout, c->perm, c->m, y, s);
+    return RBF_OK;
+  });
+}
+
+int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const rbf_solve_opts* opts_in,
+              rbf_solve_info* info, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  rbf_solve_opts o;
+  rbf_default_solve_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) return fail(c, RBF_EINVAL, "tol must be finite and >= 0");
+  if (o.restart < 1 || o.restart > gm_max_restart()) return fail(c, RBF_EINVAL, "restart must be in 1..64");
+  if (o.max_outer < 1 || o.max_iters < 0) return fail(c, RBF_EINVAL, "max_outer >= 1 and max_iters >= 0 required");
+  if (o.mode != RBF_SOLVE_PLAIN_FP64 && o.mode != RBF_SOLVE_IR_FP32) return fail(c, RBF_EINVAL, "unknown mode");
+  if ((b && !is_device_ptr(b)) || (x0 && !is_device_ptr(x0)) || !is_device_ptr(cout))
+    return fail(c, RBF_EINVAL, "b, x0 and c must be device pointers");
+  const int prec = o.mode == RBF_SOLVE_IR_FP32 ? RBF_FP32 : RBF_FP64;
+  int result = guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    ensure_solver(c, o.restart);
+    const int64_t m = c->m;
+    const int64_t ldv = c->mpad;
+    // b and x0 in sorted order
+    if (b) {
+      gather_to_sorted(b, c->perm, m, c->bsort, s);
+    } else {
+      // values 0 / +eps / -eps in paper order, then sorted
+      fill_f64(c->w, 0.0, c->n, s);
+      fill_f64(c->w + c->n, c->eps, c->n, s);
+      fill_f64(c->w + 2 * c->n, -c->eps, c->n, s);
+      gather_to_sorted(c->w, c->perm, m, c->bsort, s);
+      fill_f64(c->w, 0.0, c->mpad, s);
+    }
+    bool have_x = x0 != nullptr;
+    if (x0)
+      gather_to_sorted(x0, c->perm, m, c->csol, s);
+    else
+      fill_f64(c->csol, 0.0, c->mpad, s);
+    // |b|
+    gm_start(c->bsort, nullptr, c->r, m, c->V, c->partial, o.restart, 0.0, c->state, s);
+    int k, done, bd;
+    double bnorm, gk;
+    gm_read(c->state, &k, &done, &bd, &bnorm, &gk, s);
+    c->history.clear();
+    int iters = 0, outer = 0, status = RBF_ENOCONV;
+    double rel = 0.0;
+    if (!std::isfinite(bnorm)) {
+      status = RBF_EBREAKDOWN;
+    } else if (bnorm == 0.0) {
+      fill_f64(c->csol, 0.0, c->mpad, s);
+      rel = 0.0;
+      c->history.push_back(0.0);
+      status = RBF_OK;
+    } else {
+      for (;;) {
+        // true residual with the float64 operator
+        const double* y = nullptr;
+        if (have_x) {
+          apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
+          y = c->vout;
+        }
+        gm_start(c->bsort, y, c->r, m, c->V, c->partial, o.restart, o.tol * bnorm, c->state, s);
+        double beta;
+        gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
+        rel = beta / bnorm;
+        c->history.push_back(rel);
+        if (!std::isfinite(rel)) {
+          status = RBF_EBREAKDOWN;
+          break;
+        }
+        if (rel <= o.tol) {
+          status = RBF_OK;
+          break;
+        }
+        if (outer >= o.max_outer || iters >= o.max_iters) {
+          status = RBF_ENOCONV;
+          break;
+        }
+        const int steps = std::min<int64_t>(o.restart, (int64_t)o.max_iters - iters);
+        const int* skip = gm_done_flag(c->state);
+        for (int j = 0; j < steps; ++j) {
+          apply_sorted(c, c->V + (int64_t)j * ldv, c->w, prec, s, skip);
+          gm_step(c->V, ldv, c->w, m, j, c->partial, c->state, s);
+        }
+        gm_finish(c->V, ldv, c->csol, m, c->state, s);
+        gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
+        iters += k;
+        ++outer;
+        have_x = true;
+        if (bd) {
+          status = RBF_EBREAKDOWN;
+          // the true residual of the current iterate is still reported
+          apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
+          gm_start(c->bsort, c->vout, c->r, m, c->V, c->partial, o.restart, 0.0, c->state, s);
+          gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
+          rel = beta / bnorm;
+          c->history.push_back(rel);
+          break;
+        }
+        if (k == 0 && steps > 0) {
+          // no progress possible (degenerate Krylov space)
+          status = RBF_ENOCONV;
+          break;
+        }
+      }
+    }
+    scatter_from_sorted(c->csol, c->perm, m, cout, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    if (info) {
+      info->iters = iters;
+      info->outer = outer;
+      info->rel_resid = rel;
+      info->status = status;
+      info->n_history = (int)c->history.size();
+      info->history = c->history.data();
+    }
+    if (status == RBF_ENOCONV) c->err = "solve stopped at its iteration limit";
+    if (status == RBF_EBREAKDOWN) c->err = "non-finite value in the solve";
+    return status;
+  });
+  if (result == RBF_ENOCONV || result == RBF_EBREAKDOWN) t_err = c->err;
+  return result;
+}
+
+static int check_grid(rbf_ctx* c, const rbf_grid* g) {
+  if (!g) return fail(c, RBF_EINVAL, "grid is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (g->dims[d] <= 0) return fail(c, RBF_EINVAL, "grid dims must be positive");
+    if (!std::isfinite(g->origin[d]) || !std::isfinite(g->h[d]) || g->h[d] < 0.0)
+      return fail(c, RBF_EINVAL, "grid origin/h must be finite, h >= 0");
+  }
+  const double total = (double)g->dims[0] * (double)g->dims[1] * (double)g->dims[2];
+  if (total > 4.0e9) return fail(c, RBF_EINVAL, "grid too large");
+  return RBF_OK;
+}
+
+int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out, int prec, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  int st = check_grid(c, grid);
+  if (st != RBF_OK) return st;
+  if (prec != RBF_FP32 && prec != RBF_FP64) return fail(c, RBF_EINVAL, "prec must be RBF_FP32 or RBF_FP64");
+  if (!is_device_ptr(cw) || !is_device_ptr(out)) return fail(c, RBF_EINVAL, "c and out must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t total = grid->dims[0] * grid->dims[1] * grid->dims[2];
+    gather_to_sorted(cw, c->perm, c->m, c->vin, s);
+    if (prec == RBF_FP32)
+      fill_f32(static_cast<float*>(out), 0.0f, total, s);
+    else
+      fill_f64(static_cast<double*>(out), 0.0, total, s);
+    TargetSet ts;
+    int64_t* oidx = nullptr;
+    grid_targets(*c, *grid, ts, &oidx, s);
+    if (ts.n_groups > 0) {
+      if (prec == RBF_FP32)
+        pairsum_f32(*c, ts, c->vin, OUT_INDEXED32, out, oidx, s);
+      else
+        pairsum_f64(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+    }
+    RBF_HIP(hipStreamSynchronize(s));
+    free_targets(ts);
+    dfree(oidx);
+    return RBF_OK;
+  });
+}
+
+int rbf_count_grid_pairs(rbf_ctx* c, const rbf_grid* grid, int64_t* useful, int64_t* examined, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  int st = check_grid(c, grid);
+  if (st != RBF_OK) return st;
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    TargetSet ts;
+    int64_t* oidx = nullptr;
+    grid_targets(*c, *grid, ts, &oidx, s);
+    if (useful) *useful = ts.useful;
+    if (examined) *examined = ts.list_entries * kGroup;
+    free_targets(ts);
+    dfree(oidx);
+    return RBF_OK;
+  });
+}
+
+int rbf_eval_points(rbf_ctx* c, const double* cw, const double* pts, int64_t npts, double* out, int prec,
+                    void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (npts < 0) return fail(c, RBF_EINVAL, "m must be >= 0");
+  if (prec != RBF_FP32 && prec != RBF_FP64) return fail(c, RBF_EINVAL, "prec must be RBF_FP32 or RBF_FP64");
+  if (npts == 0) return RBF_OK;
+  if (npts > ((int64_t)1 << 31) - 2) return fail(c, RBF_EINVAL, "too many points");
+  if (!is_device_ptr(cw) || !is_device_ptr(pts) || !is_device_ptr(out))
+    return fail(c, RBF_EINVAL, "c, pts and out must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    gather_to_sorted(cw, c->perm, c->m, c->vin, s);
+    TargetSet ts;
+    int64_t* oidx = nullptr;
+    point_targets(*c, pts, npts, ts, &oidx, s);
+    if (prec == RBF_FP32)
+      pairsum_f32(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+    else
+      pairsum_f64(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    free_targets(ts);
+    dfree(oidx);
+    return RBF_OK;
+  });
+}
+
+int rbf_get_stats(const rbf_ctx* c, rbf_stats* st) {
+  if (!c || !st) return fail(nullptr, RBF_EINVAL, "ctx and stats must not be NULL");
+  st->n_points = c->n;
+  st->n_centres = c->m;
+  st->n_groups = c->centres.n_groups;
+  st->list_entries = c->centres.list_entries;
+  st->useful_pairs = c->centres.useful;
+  st->examined_pairs = c->centres.list_entries * kGroup;
+  st->n_cells = c->n_cells;
+  st->cell_size = c->lat.coarse;
+  st->sigma = c->sigma;
+  st->cutoff = c->cutoff;
+  st->eps = c->eps;
+  return RBF_OK;
+}
+
+int rbf_profile_begin(void) {
+  return guarded(nullptr, []() -> int { return profile_begin(); });
+}
+
+int rbf_profile_end(rbf_profile* out) {
+  return guarded(nullptr, [&]() -> int { return profile_end(out); });
+}
+
+void rbf_destroy(rbf_ctx* c) {
+  if (!c) return;
+  free_ctx(c);
+  delete c;
+}
+
+const char* rbf_last_error(const rbf_ctx* c) {
+  if (c) return c->err.empty() ? "no error" : c->err.c_str();
+  return thread_error();
+}
+
+}  // extern "C"

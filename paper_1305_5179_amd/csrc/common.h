@@ -1,0 +1,190 @@
+// Internal declarations shared by the librbf sources (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rbf.h"
+
+namespace rbf {
+
+// ---------------------------------------------------------------------------
+// Work decomposition of the pair sums.
+//   A wave (64 lanes) owns one group of kGroup = 16 targets.  Its four DPP
+//   rows (lanes 16r .. 16r+15) all hold the same 16 targets and walk four
+//   interleaved streams of the group's source list; a chunk is 64 list
+//   entries, one per lane, and inside a chunk every row broadcasts its 16
+//   sources to its lanes one by one (DPP row_newbcast), so each lane
+//   evaluates 16 pairs per chunk with its own target.
+// ---------------------------------------------------------------------------
+constexpr int kGroup = 16;
+constexpr int kWave = 64;
+constexpr int kChunk = 64;
+constexpr int kBlock = 256;          // threads per block of the pair kernels (4 independent waves)
+
+// Morton keys: 10 bits per axis on the fine lattice.
+constexpr int kMortonBits = 10;
+constexpr int kFineMax = 1 << kMortonBits;
+
+// Far-away coordinate of the padding source/target (index M of the sorted
+// arrays): every pair with it underflows to exactly 0 and its weight is 0.
+constexpr double kFar = 1.0e6;
+
+// Per-group metadata of a target set.
+struct GroupInfo {
+  int64_t off;          // first list entry of the group
+  int32_t n_chunks;     // list length / 64
+  int32_t n_inner;      // leading chunks in which every pair lies inside the cutoff
+  double ax, ay, az;    // anchor (unscaled float64); float32 coordinates are taken relative to it
+  double radius;        // max distance of a valid target from the anchor
+};
+
+// A set of targets grouped by 16 (centres, grid nodes or evaluation points)
+// together with the source list of every group.
+struct TargetSet {
+  int64_t n_targets = 0;    // valid targets
+  int64_t n_groups = 0;
+  double4* pts = nullptr;   // n_groups*16 targets, unscaled; .w = 1 valid, 0 padding
+  GroupInfo* groups = nullptr;
+  uint32_t* list = nullptr; // sorted-source indices (M = padding source)
+  int64_t list_entries = 0;
+  int64_t useful = 0;       // pairs with r^2 <= cutoff^2 (float64 decision)
+  double max_radius = 0.0;
+  bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
+  std::vector<void*> owned; // device allocations to free with the set
+};
+
+// Neighbour lattice.  Fine cells (side f) order the centres along a Morton
+// curve; a coarse cell is an aligned block of 2^shift fine cells per axis
+// and therefore a contiguous run of the sorted centres.
+struct Lattice {
+  double origin[3];
+  double fine;              // side of a fine cell
+  int shift;                // coarse = fine << shift
+  double coarse;            // side of a coarse cell
+  int fdims[3];             // fine cells per axis (<= 1024)
+  int cdims[3];             // coarse cells per axis
+};
+
+struct Ctx {
+  int device = 0;
+  int64_t n = 0;            // points
+  int64_t m = 0;            // centres = 3n
+  int64_t mpad = 0;         // padded vector length (>= m + 1, multiple of 256)
+  double eps = 0, sigma = 0, cutoff = 0;
+  double rc2 = 0;           // cutoff^2 (float64), +inf without cutoff
+  double sqrt_k = 0;        // coordinates scaled by sqrt(log2(e) / (2 sigma^2)): phi = exp2(-|x'|^2)
+  double inv_two_s2 = 0;    // 1 / (2 sigma^2)
+  Lattice lat{};
+  // Sorted centres (Morton order); index m is the far padding source.
+  uint32_t* perm = nullptr;     // sorted position -> paper index
+  uint32_t* keys = nullptr;     // Morton keys of the sorted centres
+  double4* xs = nullptr;        // unscaled coordinates, m+1
+  double4* xk = nullptr;        // scaled coordinates, m+1
+  double* xpaper = nullptr;     // paper-order centres, m x 3 (for rbf_centres)
+  // Coarse cells: start/count in the sorted order; dense map coarse cell -> id.
+  int32_t* cell_start = nullptr;
+  int32_t* cell_count = nullptr;
+  int32_t* cell_map = nullptr;  // product of cdims entries, -1 = empty
+  int32_t* cell_xyz = nullptr;  // coarse coordinates of every cell, x | y << 10 | z << 20
+  int64_t n_cells = 0;
+  TargetSet centres;            // the centres as targets of the operator
+  // Work vectors (sorted order, length mpad, entry m kept 0).
+  double* vin = nullptr;
+  double* vout = nullptr;
+  // Solver storage, allocated on first use.
+  int krylov_m = 0;
+  double* V = nullptr;          // (m+1) basis vectors of length mpad
+  double* w = nullptr;
+  double* r = nullptr;
+  double* csol = nullptr;
+  double* bsort = nullptr;
+  double* partial = nullptr;    // block partial sums
+  int64_t partial_cap = 0;
+  void* state = nullptr;        // device GMRES state
+  std::vector<double> history;
+  std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// Error plumbing.
+// ---------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_thread_error(const std::string& msg);
+const char* thread_error();
+
+#define RBF_HIP(call)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      throw ::rbf::Error{e_ == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE,    \
+                         std::string(#call) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+template <class T>
+T* dalloc(int64_t count) {
+  void* p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
+  if (e != hipSuccess)
+    throw Error{e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE,
+                std::string("hipMalloc(") + std::to_string(sizeof(T) * (size_t)count) + " bytes): " +
+                    hipGetErrorString(e)};
+  return static_cast<T*>(p);
+}
+inline void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+// setup.hip
+void check_inputs(const double* points, const double* normals, int64_t n, int* flags, hipStream_t s);
+void build_centres(const double* points, const double* normals, int64_t n, double eps, double* xpaper,
+                   hipStream_t s);
+void bounding_box(const double* xpaper, int64_t m, double* box6, double* scratch, hipStream_t s);
+void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* perm, uint32_t* keys_out,
+                 hipStream_t s);
+void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double sqrt_k, double4* xs,
+                   double4* xk, hipStream_t s);
+int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t** cell_start,
+                    int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
+void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
+void centre_targets(const double4* xs, int64_t m, double4* pts, int64_t n_groups, hipStream_t s);
+void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+void fill_f64(double* p, double v, int64_t n, hipStream_t s);
+void fill_f32(float* p, float v, int64_t n, hipStream_t s);
+
+// pairsum.hip
+enum OutKind { OUT_SORTED64 = 0, OUT_INDEXED64 = 1, OUT_INDEXED32 = 2 };
+// `skip`: optional device flag; when it is nonzero the kernel returns at once.
+void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
+                 const int64_t* out_index, hipStream_t s, const int* skip = nullptr);
+void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
+                 const int64_t* out_index, hipStream_t s, const int* skip = nullptr);
+
+int profile_begin();
+int profile_end(rbf_profile* out);
+
+// krylov.hip
+void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s);
+void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s);
+
+// setup.hip: targets of the evaluation entry points
+void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_index, hipStream_t s);
+void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, int64_t** out_index,
+                   hipStream_t s);
+
+}  // namespace rbf

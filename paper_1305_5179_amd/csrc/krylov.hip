@@ -1,0 +1,345 @@
+// Restarted GMRES on the device, float64 throughout (Sec. III.A: the
+// interpolation system is solved by GMRES; the paper relies on PETSc's
+// KSPSolve).  One Arnoldi step after the operator has produced w = A v_j:
+//   pass 1  h1 = V^T w                       (block partial dot products)
+//   pass 2  w <- w - V h1,  h2 = V^T w       (one sweep: update, then dots)
+//   pass 3  w <- w - V h2,  |w|^2            (classical Gram-Schmidt applied
+//                                             twice, "twice is enough")
+//   finish  H(:,j) = h1 + h2, H(j+1,j) = |w|, Givens rotations, |g_{j+1}|
+//   scale   v_{j+1} = w / |w|
+// Every kernel of a step first reads the device flag `done`, set when the
+// residual estimate |g_{j+1}| reaches the tolerance (or on breakdown), so the
+// host can enqueue a whole cycle without waiting on it.
+#include "common.h"
+
+namespace rbf {
+
+constexpr int kMaxRestart = 64;
+constexpr int kVecThreads = 256;
+constexpr int kRowsPerThread = 4;
+constexpr int kRowsPerBlock = kVecThreads * kRowsPerThread;
+
+struct GmState {
+  int m;
+  int k;
+  int done;
+  int breakdown;
+  double tol_abs;
+  double beta0;
+  double inv_beta;
+  double h1[kMaxRestart + 1];
+  double h2[kMaxRestart + 1];
+  double H[(kMaxRestart + 1) * kMaxRestart];  // column j at H[j*(kMaxRestart+1) + i]
+  double cs[kMaxRestart], sn[kMaxRestart];
+  double g[kMaxRestart + 1];
+  double y[kMaxRestart];
+};
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Block sums: every wave folds its lanes (fixed butterfly order) into
+// s[wave][i]; thread i then adds the four waves in order.
+__device__ __forceinline__ void wave_partial(double v, int i, double (*s)[kMaxRestart + 1]) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][i] = v;
+}
+__device__ __forceinline__ void block_store(double (*s)[kMaxRestart + 1], int ncols, double* partial) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncols; i += kVecThreads)
+    partial[(int64_t)blockIdx.x * (kMaxRestart + 1) + i] = ((s[0][i] + s[1][i]) + s[2][i]) + s[3][i];
+}
+
+// pass 1: partial[b][i] = sum_{r in block b} V_i[r] w[r]
+__global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                      const double* __restrict__ w, int64_t n,
+                                                      const GmState* __restrict__ st, double* __restrict__ partial) {
+  if (st->done) return;
+  __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+  double wr[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t r = base + (int64_t)q * kVecThreads;
+    wr[q] = r < n ? w[r] : 0.0;
+  }
+  for (int i = 0; i < ncols; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      const int64_t r = base + (int64_t)q * kVecThreads;
+      if (r < n) a = fma(V[(int64_t)i * ldv + r], wr[q], a);
+    }
+    wave_partial(a, i, s);
+  }
+  block_store(s, ncols, partial);
+}
+
+// pass 2: w <- w - V h1 ; partial = V^T w
+__global__ __launch_bounds__(kVecThreads) void k_update_dots(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                             double* __restrict__ w, int64_t n,
+                                                             const GmState* __restrict__ st,
+                                                             double* __restrict__ partial) {
+  if (st->done) return;
+  __shared__ double h[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < ncols; i += kVecThreads) h[i] = st->h1[i];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+  double wr[kRowsPerThread];
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t r = base + (int64_t)q * kVecThreads;
+    if (r < n) {
+      double v = w[r];
+      for (int i = 0; i < ncols; ++i) v = fma(-h[i], V[(int64_t)i * ldv + r], v);
+      w[r] = v;
+      wr[q] = v;
+    } else {
+      wr[q] = 0.0;
+    }
+  }
+  __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
+  for (int i = 0; i < ncols; ++i) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      const int64_t r = base + (int64_t)q * kVecThreads;
+      if (r < n) a = fma(V[(int64_t)i * ldv + r], wr[q], a);
+    }
+    wave_partial(a, i, s);
+  }
+  block_store(s, ncols, partial);
+}
+
+// pass 3: w <- w - V h2 ; partial = |w|^2
+__global__ __launch_bounds__(kVecThreads) void k_update_norm(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                             double* __restrict__ w, int64_t n,
+                                                             const GmState* __restrict__ st,
+                                                             double* __restrict__ partial) {
+  if (st->done) return;
+  __shared__ double h[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < ncols; i += kVecThreads) h[i] = st->h2[i];
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+  double a = 0.0;
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t r = base + (int64_t)q * kVecThreads;
+    if (r < n) {
+      double v = w[r];
+      for (int i = 0; i < ncols; ++i) v = fma(-h[i], V[(int64_t)i * ldv + r], v);
+      w[r] = v;
+      a = fma(v, v, a);
+    }
+  }
+  __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
+  wave_partial(a, 0, s);
+  block_store(s, 1, partial);
+}
+
+// Sum the block partials of columns 0..ncols-1 in block order.
+__device__ __forceinline__ double fold_partials(const double* partial, int nb, int i) {
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * (kMaxRestart + 1) + i];
+  return s;
+}
+
+__global__ void k_reduce_h1(const double* __restrict__ partial, int nb, int ncols, GmState* __restrict__ st) {
+  if (st->done) return;
+  for (int i = threadIdx.x; i < ncols; i += blockDim.x) st->h1[i] = fold_partials(partial, nb, i);
+}
+__global__ void k_reduce_h2(const double* __restrict__ partial, int nb, int ncols, GmState* __restrict__ st) {
+  if (st->done) return;
+  for (int i = threadIdx.x; i < ncols; i += blockDim.x) st->h2[i] = fold_partials(partial, nb, i);
+}
+
+// Column j of the Hessenberg matrix, its Givens rotations and the residual
+// estimate |g_{j+1}|.
+__global__ void k_finish_step(const double* __restrict__ partial, int nb, int j, GmState* __restrict__ st) {
+  if (threadIdx.x != 0 || st->done) return;
+  const int ld = kMaxRestart + 1;
+  double* Hc = st->H + (int64_t)j * ld;
+  const double beta = sqrt(fold_partials(partial, nb, 0));
+  for (int i = 0; i <= j; ++i) Hc[i] = st->h1[i] + st->h2[i];
+  Hc[j + 1] = beta;
+  for (int i = 0; i < j; ++i) {
+    const double a = Hc[i], b = Hc[i + 1];
+    Hc[i] = st->cs[i] * a + st->sn[i] * b;
+    Hc[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+  }
+  const double a = Hc[j], b = Hc[j + 1];
+  const double rho = hypot(a, b);
+  double c = 1.0, s = 0.0;
+  if (rho != 0.0) {
+    c = a / rho;
+    s = b / rho;
+  }
+  st->cs[j] = c;
+  st->sn[j] = s;
+  Hc[j] = rho;
+  Hc[j + 1] = 0.0;
+  const double gj = st->g[j];
+  st->g[j + 1] = -s * gj;
+  st->g[j] = c * gj;
+  st->k = j + 1;
+  st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+  const bool finite = isfinite(beta) && isfinite(rho) && isfinite(st->g[j + 1]);
+  if (!finite) {
+    st->breakdown = 1;
+    st->done = 1;
+    st->k = j;  // drop the column that went bad
+  } else if (fabs(st->g[j + 1]) <= st->tol_abs || beta == 0.0 || rho == 0.0) {
+    st->done = 1;
+  }
+}
+
+// v_{j+1} = w / |w|
+__global__ __launch_bounds__(kVecThreads) void k_scale(const double* __restrict__ w, int64_t n,
+                                                       const GmState* __restrict__ st, double* __restrict__ out) {
+  if (st->done) return;
+  const double s = st->inv_beta;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = w[i] * s;
+}
+
+// r = b - y and |r|^2 partials (y may be null: r = b)
+__global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restrict__ b, const double* __restrict__ y,
+                                                          double* __restrict__ r, int64_t n,
+                                                          double* __restrict__ partial) {
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+  double a = 0.0;
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t i = base + (int64_t)q * kVecThreads;
+    if (i < n) {
+      const double v = y ? b[i] - y[i] : b[i];
+      r[i] = v;
+      a = fma(v, v, a);
+    }
+  }
+  __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
+  wave_partial(a, 0, s);
+  block_store(s, 1, partial);
+}
+
+__global__ void k_start_cycle(const double* __restrict__ partial, int nb, int m, double tol_abs,
+                              GmState* __restrict__ st) {
+  if (threadIdx.x != 0) return;
+  const double beta = sqrt(fold_partials(partial, nb, 0));
+  st->m = m;
+  st->k = 0;
+  st->tol_abs = tol_abs;
+  st->beta0 = beta;
+  st->g[0] = beta;
+  for (int i = 1; i <= kMaxRestart; ++i) st->g[i] = 0.0;
+  st->breakdown = isfinite(beta) ? 0 : 1;
+  st->done = (beta == 0.0 || !isfinite(beta)) ? 1 : 0;
+  st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+}
+
+// Least squares: back substitution with the rotated Hessenberg matrix.
+__global__ void k_solve_y(GmState* __restrict__ st) {
+  if (threadIdx.x != 0) return;
+  const int ld = kMaxRestart + 1;
+  const int k = st->k;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = st->g[i];
+    for (int l = i + 1; l < k; ++l) s -= st->H[(int64_t)l * ld + i] * st->y[l];
+    st->y[i] = s / st->H[(int64_t)i * ld + i];
+  }
+}
+
+// x <- x + V y  (k columns, k read from the state)
+__global__ __launch_bounds__(kVecThreads) void k_update_x(const double* __restrict__ V, int64_t ldv,
+                                                          const GmState* __restrict__ st, double* __restrict__ x,
+                                                          int64_t n) {
+  const int k = st->k;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || k == 0) return;
+  double v = x[i];
+  for (int l = 0; l < k; ++l) v = fma(st->y[l], V[(int64_t)l * ldv + i], v);
+  x[i] = v;
+}
+
+__global__ void k_gather(const double* __restrict__ src, const uint32_t* __restrict__ perm, int64_t m,
+                         double* __restrict__ dst) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) dst[k] = src[perm[k]];
+}
+__global__ void k_scatter(const double* __restrict__ src, const uint32_t* __restrict__ perm, int64_t m,
+                          double* __restrict__ dst) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) dst[perm[k]] = src[k];
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+static unsigned vec_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kRowsPerBlock)); }
+static unsigned elt_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kVecThreads)); }
+
+void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather, dim3(elt_blocks(m)), dim3(kVecThreads), 0, s, src, perm, m, dst_sorted);
+  RBF_HIP(hipGetLastError());
+}
+void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(elt_blocks(m)), dim3(kVecThreads), 0, s, src_sorted, perm, m, dst);
+  RBF_HIP(hipGetLastError());
+}
+
+int gm_max_restart() { return kMaxRestart; }
+size_t gm_state_bytes() { return sizeof(GmState); }
+int64_t gm_partial_count(int64_t n) { return (int64_t)vec_blocks(n) * (kMaxRestart + 1); }
+
+// r = b - y (y may be null); starts a cycle: beta0 = |r|, v_0 = r / beta0.
+void gm_start(const double* b, const double* y, double* r, int64_t n, double* V, double* partial, int m,
+              double tol_abs, void* state, hipStream_t s) {
+  GmState* st = static_cast<GmState*>(state);
+  const unsigned nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kVecThreads), 0, s, b, y, r, n, partial);
+  hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(64), 0, s, partial, (int)nb, m, tol_abs, st);
+  hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, r, n, st, V);
+  RBF_HIP(hipGetLastError());
+}
+
+// Orthogonalisation and bookkeeping of step j after w = A v_j.
+void gm_step(double* V, int64_t ldv, double* w, int64_t n, int j, double* partial, void* state, hipStream_t s) {
+  GmState* st = static_cast<GmState*>(state);
+  const unsigned nb = vec_blocks(n);
+  const int ncols = j + 1;
+  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_reduce_h1, dim3(1), dim3(64), 0, s, partial, (int)nb, ncols, st);
+  hipLaunchKernelGGL(k_update_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_reduce_h2, dim3(1), dim3(64), 0, s, partial, (int)nb, ncols, st);
+  hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(64), 0, s, partial, (int)nb, j, st);
+  hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, w, n, st, V + (int64_t)(j + 1) * ldv);
+  RBF_HIP(hipGetLastError());
+}
+
+// x += V y after the cycle.
+void gm_finish(double* V, int64_t ldv, double* x, int64_t n, void* state, hipStream_t s) {
+  GmState* st = static_cast<GmState*>(state);
+  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_update_x, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, V, ldv, st, x, n);
+  RBF_HIP(hipGetLastError());
+}
+
+// Host copy of the fields the driver loop needs.
+void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s) {
+  GmState h;
+  RBF_HIP(hipMemcpyAsync(&h, state, sizeof(GmState), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  *k = h.k;
+  *done = h.done;
+  *breakdown = h.breakdown;
+  *beta0 = h.beta0;
+  *gk = h.g[h.k];
+}
+
+const int* gm_done_flag(const void* state) { return &static_cast<const GmState*>(state)->done; }
+
+}  // namespace rbf

@@ -1,0 +1,902 @@
+// Setup kernels: input checks, the extended centre set, Morton ordering
+// (wave-ballot LSD radix sort), coarse cells and per-group source lists.
+#include "common.h"
+
+namespace rbf {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+int grid_for(int64_t n, int threads = kThreads) {
+  int64_t b = ceil_div(n, threads);
+  if (b < 1) b = 1;
+  if (b > (int64_t)1 << 30) b = (int64_t)1 << 30;
+  return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// Input checks: flags[0] = a non-finite coordinate, flags[1] = a normal
+// shorter than 1e-12.
+// ---------------------------------------------------------------------------
+__global__ void k_check_inputs(const double* __restrict__ p, const double* __restrict__ nrm, int64_t n,
+                               int* __restrict__ flags) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+  double a = nrm[3 * i], b = nrm[3 * i + 1], c = nrm[3 * i + 2];
+  bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(a) && isfinite(b) && isfinite(c);
+  if (!fin) {
+    flags[0] = 1;
+    return;
+  }
+  double s = (a * a + b * b) + c * c;
+  if (!(sqrt(s) >= 1e-12)) flags[1] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Extended set (Sec. II.A.1): centre i = x_i, N+i = x_i + eps n_i,
+// 2N+i = x_i - eps n_i with n_i normalised.  Paper order, m x 3 rows.
+// ---------------------------------------------------------------------------
+__global__ void k_build_centres(const double* __restrict__ p, const double* __restrict__ nrm, int64_t n,
+                                double eps, double* __restrict__ X) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+  double a = nrm[3 * i], b = nrm[3 * i + 1], c = nrm[3 * i + 2];
+  double len = sqrt((a * a + b * b) + c * c);
+  double nx = a / len, ny = b / len, nz = c / len;
+  double ox = eps * nx, oy = eps * ny, oz = eps * nz;
+  X[3 * i] = x;
+  X[3 * i + 1] = y;
+  X[3 * i + 2] = z;
+  X[3 * (n + i)] = x + ox;
+  X[3 * (n + i) + 1] = y + oy;
+  X[3 * (n + i) + 2] = z + oz;
+  X[3 * (2 * n + i)] = x - ox;
+  X[3 * (2 * n + i) + 1] = y - oy;
+  X[3 * (2 * n + i) + 2] = z - oz;
+}
+
+// ---------------------------------------------------------------------------
+// Bounding box: per-block min/max, then one block folds the partials.
+// ---------------------------------------------------------------------------
+__global__ void k_bbox_partial(const double* __restrict__ X, int64_t m, double* __restrict__ part) {
+  __shared__ double s[6][kThreads];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int d = 0; d < 3; ++d) {
+      double v = X[3 * i + d];
+      lo[d] = fmin(lo[d], v);
+      hi[d] = fmax(hi[d], v);
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    s[d][threadIdx.x] = lo[d];
+    s[3 + d][threadIdx.x] = hi[d];
+  }
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + w]);
+        s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ box) {
+  if (threadIdx.x != 0) return;
+  double r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nb; ++b)
+    for (int d = 0; d < 3; ++d) {
+      r[d] = fmin(r[d], part[b * 6 + d]);
+      r[3 + d] = fmax(r[3 + d], part[b * 6 + 3 + d]);
+    }
+  for (int d = 0; d < 6; ++d) box[d] = r[d];
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys on the fine lattice (10 bits per axis, x in bit 0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x3ffu;
+  return v;
+}
+__device__ __forceinline__ uint32_t fine_coord(double x, double o, double f, int dim) {
+  double q = floor((x - o) / f);
+  if (!(q >= 0.0)) q = 0.0;
+  if (q > (double)(dim - 1)) q = (double)(dim - 1);
+  return (uint32_t)q;
+}
+
+__global__ void k_morton(const double* __restrict__ X, int64_t m, Lattice lat, uint32_t* __restrict__ keys,
+                         uint32_t* __restrict__ idx) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  uint32_t cx = fine_coord(X[3 * i], lat.origin[0], lat.fine, lat.fdims[0]);
+  uint32_t cy = fine_coord(X[3 * i + 1], lat.origin[1], lat.fine, lat.fdims[1]);
+  uint32_t cz = fine_coord(X[3 * i + 2], lat.origin[2], lat.fine, lat.fdims[2]);
+  keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+  idx[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+//   hist:    per-block digit counts, stored digit-major [256][nb].
+//   scan:    exclusive prefix over that array = global start of every
+//            (digit, block) bucket.
+//   scatter: every wave ranks its lanes among equal digits with eight
+//            ballots (the peers of a lane share all eight digit bits) and
+//            mbcnt; waves of a block are offset by a per-digit prefix in LDS,
+//            blocks by the scanned histogram, so the order of equal keys is
+//            the input order.
+// ---------------------------------------------------------------------------
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;
+
+__global__ void k_rs_hist(const uint32_t* __restrict__ keys, int64_t m, int shift, int64_t* __restrict__ hist,
+                          int nb) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; ++r) {
+    int64_t i = base + r * kThreads + threadIdx.x;
+    if (i < m) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t m, int shift,
+                             const int64_t* __restrict__ offs, int nb) {
+  __shared__ int64_t base[256];
+  __shared__ uint32_t tot[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  base[t] = offs[(int64_t)t * nb + blockIdx.x];
+  const int64_t tile = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsItems; ++r) {
+    for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+    __syncthreads();
+    int64_t i = tile + r * kThreads + t;
+    bool valid = i < m;
+    uint32_t key = valid ? kin[i] : 0u, val = valid ? vin[i] : 0u;
+    uint32_t dig = (key >> shift) & 255u;
+    uint64_t peers = ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (dig >> b) & 1u;
+      uint64_t s = ballot(bit);
+      peers &= bit ? s : ~s;
+    }
+    uint32_t rank = lanes_below(peers);
+    if (valid && rank == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    {
+      uint32_t c0 = wcnt[0][t], c1 = wcnt[1][t], c2 = wcnt[2][t], c3 = wcnt[3][t];
+      wcnt[0][t] = 0;
+      wcnt[1][t] = c0;
+      wcnt[2][t] = c0 + c1;
+      wcnt[3][t] = c0 + c1 + c2;
+      tot[t] = c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    if (valid) {
+      int64_t pos = base[dig] + wcnt[wave][dig] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    base[t] += tot[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of int64 values (three phases, recursive on the
+// block sums).
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;
+
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* total) {
+  __shared__ int64_t s[kThreads];
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int64_t add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int64_t incl = s[t];
+  *total = s[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_tiles(const int64_t* __restrict__ in, int64_t* __restrict__ out, int64_t n,
+                             int64_t* __restrict__ sums) {
+  int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t loc[kScanItems];
+  int64_t run = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    int64_t v = i < n ? in[i] : 0;
+    loc[k] = run;
+    run += v;
+  }
+  int64_t total;
+  int64_t pre = block_exclusive_scan(run, &total);
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = pre + loc[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ sums_scanned) {
+  int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t add = sums_scanned[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanTile; k += kThreads) {
+    int64_t i = base + k;
+    if (i < n) out[i] += add;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sorted copies of the centres, with the far padding source at index m.
+// ---------------------------------------------------------------------------
+__global__ void k_gather_sorted(const double* __restrict__ X, const uint32_t* __restrict__ perm, int64_t m,
+                                double sk, double4* __restrict__ xs, double4* __restrict__ xk) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k > m) return;
+  double x, y, z;
+  if (k < m) {
+    int64_t i = perm[k];
+    x = X[3 * i];
+    y = X[3 * i + 1];
+    z = X[3 * i + 2];
+  } else {
+    x = y = z = kFar;
+  }
+  xs[k] = make_double4(x, y, z, 0.0);
+  xk[k] = make_double4(x * sk, y * sk, z * sk, 0.0);
+}
+
+// Coarse cells of the sorted centres.
+__global__ void k_cell_flags(const uint32_t* __restrict__ keys, int64_t m, int cshift, int64_t* __restrict__ flag) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  flag[k] = (k == 0 || (keys[k] >> cshift) != (keys[k - 1] >> cshift)) ? 1 : 0;
+}
+
+__global__ void k_cell_fill(const uint32_t* __restrict__ keys, int64_t m, int cshift, const int64_t* __restrict__ flag,
+                            const int64_t* __restrict__ cid, Lattice lat, int32_t* __restrict__ start,
+                            int32_t* __restrict__ count, int32_t* __restrict__ map, int32_t* __restrict__ xyz) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  if (!flag[k]) return;
+  int64_t c = cid[k];
+  // the run ends where the next run starts (or at m)
+  int64_t e = k + 1;
+  while (e < m && !flag[e]) ++e;
+  start[c] = (int32_t)k;
+  count[c] = (int32_t)(e - k);
+  uint32_t ck = keys[k] >> cshift;
+  uint32_t cx = compact3(ck), cy = compact3(ck >> 1), cz = compact3(ck >> 2);
+  int64_t lin = (int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz);
+  map[lin] = (int32_t)c;
+  xyz[c] = (int32_t)(cx | (cy << 10) | (cz << 20));
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* p, float v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Centres as targets: group g holds sorted centres 16g .. 16g+15.
+__global__ void k_centre_targets(const double4* __restrict__ xs, int64_t m, double4* __restrict__ pts, int64_t total) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  if (k < m) {
+    double4 v = xs[k];
+    pts[k] = make_double4(v.x, v.y, v.z, 1.0);
+  } else {
+    pts[k] = make_double4(kFar, kFar, kFar, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Source lists.  One wave per group of 16 targets.  Candidate sources are
+// the centres of the coarse cells that the group's box, grown by the cutoff,
+// touches; each candidate is classified in float64 against every valid
+// target of the group with the exact truncation test r^2 <= r_c^2:
+//   inside for all targets  -> "inner" part of the list (no test needed later)
+//   inside for some targets -> "outer" part (the pair kernels test it)
+//   inside for none         -> dropped.
+// Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
+// list order is deterministic.  Lists are padded to whole chunks with the
+// padding source m.
+// ---------------------------------------------------------------------------
+template <bool WRITE>
+__global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
+                                                    const double4* __restrict__ xs, int64_t m,
+                                                    const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
+                                                    const int32_t* __restrict__ cmap, Lattice lat, double rc, double rc2,
+                                                    int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out,
+                                                    int64_t* __restrict__ useful, uint32_t* __restrict__ list) {
+  __shared__ double4 tg[4][kGroup];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  if (g >= G) return;
+  if (lane < kGroup) tg[wave][lane] = tpts[g * kGroup + lane];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int nvalid = 0;
+  for (int l = 0; l < kGroup; ++l) {
+    double4 t = tg[wave][l];
+    if (t.w != 0.0) {
+      ++nvalid;
+      lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
+      lo[1] = fmin(lo[1], t.y); hi[1] = fmax(hi[1], t.y);
+      lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
+    }
+  }
+  int64_t wbase_in = 0, wbase_out = 0;
+  if (WRITE) {
+    wbase_in = groups[g].off;
+    wbase_out = wbase_in + cnt_in[g];
+  }
+  if (nvalid == 0) {
+    if (!WRITE) {
+      if (lane == 0) {
+        cnt_in[g] = 0;
+        cnt_out[g] = 0;
+        useful[g] = 0;
+        GroupInfo gi;
+        gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0;
+        gi.ax = gi.ay = gi.az = 0.0;
+        gi.radius = 0.0;
+        groups[g] = gi;
+      }
+    }
+    return;
+  }
+  const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]), az = 0.5 * (lo[2] + hi[2]);
+
+  int cl[3], ch[3];
+  const bool finite_rc = isfinite(rc);
+  for (int d = 0; d < 3; ++d) {
+    if (finite_rc) {
+      double a = floor((lo[d] - rc - lat.origin[d]) / lat.coarse) - 1.0;
+      double b = floor((hi[d] + rc - lat.origin[d]) / lat.coarse) + 1.0;
+      cl[d] = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
+      ch[d] = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
+    } else {
+      cl[d] = 0;
+      ch[d] = lat.cdims[d] - 1;
+    }
+  }
+  const double box_slack = rc2 * (1.0 + 1e-9) + 1e-300;
+  int64_t n_in = 0, n_out = 0, use = 0;
+  for (int cz = cl[2]; cz <= ch[2]; ++cz)
+    for (int cy = cl[1]; cy <= ch[1]; ++cy)
+      for (int cx = cl[0]; cx <= ch[0]; ++cx) {
+        int32_t cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
+        if (cid < 0) continue;
+        if (finite_rc) {
+          double bl[3] = {lat.origin[0] + cx * lat.coarse, lat.origin[1] + cy * lat.coarse, lat.origin[2] + cz * lat.coarse};
+          double gsum = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            double gap = fmax(0.0, fmax(bl[d] - hi[d], lo[d] - (bl[d] + lat.coarse)));
+            gsum += gap * gap;
+          }
+          if (gsum > box_slack) continue;
+        }
+        const int32_t st = cstart[cid], ct = ccount[cid];
+        for (int b0 = 0; b0 < ct; b0 += kWave) {
+          const bool valid = b0 + lane < ct;
+          const int64_t k = (int64_t)st + b0 + lane;
+          int inside = 0;
+          if (valid) {
+            double4 s = xs[k];
+            for (int l = 0; l < kGroup; ++l) {
+              double4 t = tg[wave][l];
+              double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+              double r2 = (dx * dx + dy * dy) + dz * dz;
+              inside += (t.w != 0.0 && r2 <= rc2) ? 1 : 0;
+            }
+          }
+          const bool is_in = valid && inside == nvalid;
+          const bool is_out = valid && inside > 0 && inside < nvalid;
+          const uint64_t mi = ballot(is_in), mo = ballot(is_out);
+          if (WRITE) {
+            if (is_in) list[wbase_in + n_in + lanes_below(mi)] = (uint32_t)k;
+            if (is_out) list[wbase_out + n_out + lanes_below(mo)] = (uint32_t)k;
+          }
+          n_in += __popcll(mi);
+          n_out += __popcll(mo);
+          use += inside;
+        }
+      }
+  if (!WRITE) {
+    // wave sum of the useful-pair counts
+    for (int off = 32; off > 0; off >>= 1) use += __shfl_xor(use, off);
+    double rad = 0.0;
+    for (int l = 0; l < kGroup; ++l) {
+      double4 t = tg[wave][l];
+      if (t.w != 0.0) {
+        double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
+        rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
+      }
+    }
+    if (lane == 0) {
+      cnt_in[g] = (int32_t)n_in;
+      cnt_out[g] = (int32_t)n_out;
+      useful[g] = use;
+      GroupInfo gi;
+      gi.off = 0;
+      gi.n_chunks = (int32_t)ceil_div(n_in + n_out, kChunk);
+      gi.n_inner = (int32_t)(n_in / kChunk);
+      gi.ax = ax; gi.ay = ay; gi.az = az;
+      gi.radius = rad;
+      groups[g] = gi;
+    }
+  } else {
+    const int64_t total = n_in + n_out;
+    const int64_t padded = round_up(total, kChunk);
+    for (int64_t e = total + lane; e < padded; e += kWave) list[wbase_in + e] = (uint32_t)m;
+  }
+}
+
+__global__ void k_list_lengths(const GroupInfo* __restrict__ groups, int64_t G, int64_t* __restrict__ len) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < G) len[g] = (int64_t)groups[g].n_chunks * kChunk;
+}
+__global__ void k_list_offsets(GroupInfo* __restrict__ groups, int64_t G, const int64_t* __restrict__ off) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < G) groups[g].off = off[g];
+}
+// Dense sets: every group sees all m centres (padded to whole chunks).
+__global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int64_t m, GroupInfo* __restrict__ groups) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int nv = 0;
+  for (int l = 0; l < kGroup; ++l) {
+    double4 t = tpts[g * kGroup + l];
+    if (t.w != 0.0) {
+      ++nv;
+      lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
+      lo[1] = fmin(lo[1], t.y); hi[1] = fmax(hi[1], t.y);
+      lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
+    }
+  }
+  GroupInfo gi;
+  gi.off = 0;
+  gi.n_chunks = nv ? (int32_t)ceil_div(m, kChunk) : 0;
+  gi.n_inner = gi.n_chunks;
+  if (nv) {
+    gi.ax = 0.5 * (lo[0] + hi[0]); gi.ay = 0.5 * (lo[1] + hi[1]); gi.az = 0.5 * (lo[2] + hi[2]);
+    double rad = 0.0;
+    for (int l = 0; l < kGroup; ++l) {
+      double4 t = tpts[g * kGroup + l];
+      if (t.w != 0.0) {
+        double dx = t.x - gi.ax, dy = t.y - gi.ay, dz = t.z - gi.az;
+        rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
+      }
+    }
+    gi.radius = rad;
+  } else {
+    gi.ax = gi.ay = gi.az = 0.0;
+    gi.radius = 0.0;
+  }
+  groups[g] = gi;
+}
+
+__global__ void k_sum_i64(const int64_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
+  __shared__ int64_t s[kThreads];
+  int64_t acc = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) acc += in[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void k_max_radius(const GroupInfo* __restrict__ groups, int64_t G, double* __restrict__ out) {
+  __shared__ double s[kThreads];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < G; i += kThreads) acc = fmax(acc, groups[i].radius);
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+
+// ---------------------------------------------------------------------------
+// Grid targets.  The grid is cut into bricks of 4 x 2 x 2 nodes (16 nodes, one
+// group); a brick is active when some occupied coarse cell, grown by the
+// cutoff, reaches one of its nodes.  Nodes of inactive bricks have no centre
+// within the cutoff and keep the zero written beforehand.
+// ---------------------------------------------------------------------------
+struct GridDesc {
+  double o[3], h[3];
+  int64_t n[3];
+  int64_t nb[3];
+};
+__device__ __forceinline__ bool node_range(double lo, double hi, double o, double h, int64_t n, int64_t* a, int64_t* b) {
+  if (h == 0.0) {
+    if (o < lo || o > hi) return false;
+    *a = 0;
+    *b = n - 1;
+    return true;
+  }
+  double fa = ceil((lo - o) / h), fb = floor((hi - o) / h);
+  fa = fmax(fa, 0.0);
+  fb = fmin(fb, (double)(n - 1));
+  if (fa > fb) return false;
+  *a = (int64_t)fa;
+  *b = (int64_t)fb;
+  return true;
+}
+
+__global__ void k_mark_bricks(const int32_t* __restrict__ xyz, int64_t ncell, Lattice lat, double rc, GridDesc gd,
+                              int64_t* __restrict__ mark) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int32_t v = xyz[c];
+  const int cc[3] = {v & 1023, (v >> 10) & 1023, (v >> 20) & 1023};
+  const int bs[3] = {4, 2, 2};
+  int64_t blo[3], bhi[3];
+  for (int d = 0; d < 3; ++d) {
+    const double lo = lat.origin[d] + cc[d] * lat.coarse - rc;
+    const double hi = lat.origin[d] + (cc[d] + 1) * lat.coarse + rc;
+    int64_t a, b;
+    // one node of slack on each side keeps rounding from dropping a node
+    if (!node_range(lo - gd.h[d], hi + gd.h[d], gd.o[d], gd.h[d], gd.n[d], &a, &b)) return;
+    blo[d] = a / bs[d];
+    bhi[d] = b / bs[d];
+  }
+  for (int64_t bz = blo[2]; bz <= bhi[2]; ++bz)
+    for (int64_t by = blo[1]; by <= bhi[1]; ++by)
+      for (int64_t bx = blo[0]; bx <= bhi[0]; ++bx) mark[bx + gd.nb[0] * (by + gd.nb[1] * bz)] = 1;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_compact(const int64_t* __restrict__ mark, const int64_t* __restrict__ pos, int64_t n,
+                          int64_t* __restrict__ ids) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && mark[i]) ids[pos[i]] = i;
+}
+
+__global__ void k_brick_targets(const int64_t* __restrict__ ids, int64_t nact, GridDesc gd, double4* __restrict__ pts,
+                                int64_t* __restrict__ oidx) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nact * kGroup) return;
+  const int64_t g = t / kGroup;
+  const int l = (int)(t % kGroup);
+  const int64_t b = ids ? ids[g] : g;
+  const int64_t bx = b % gd.nb[0], by = (b / gd.nb[0]) % gd.nb[1], bz = b / (gd.nb[0] * gd.nb[1]);
+  const int64_t i = bx * 4 + (l & 3), j = by * 2 + ((l >> 2) & 1), k = bz * 2 + (l >> 3);
+  if (i < gd.n[0] && j < gd.n[1] && k < gd.n[2]) {
+    pts[t] = make_double4(gd.o[0] + (double)i * gd.h[0], gd.o[1] + (double)j * gd.h[1], gd.o[2] + (double)k * gd.h[2], 1.0);
+    oidx[t] = i + gd.n[0] * (j + gd.n[1] * k);
+  } else {
+    pts[t] = make_double4(kFar, kFar, kFar, 0.0);
+    oidx[t] = 0;
+  }
+}
+
+__global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_t* __restrict__ out) {
+  __shared__ int64_t s[kThreads];
+  int64_t acc = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += pts[i].w != 0.0 ? 1 : 0;
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)out, (unsigned long long)s[0]);
+}
+
+// Evaluation points in Morton order, grouped by 16.
+__global__ void k_point_targets(const double* __restrict__ P, const uint32_t* __restrict__ perm, int64_t np,
+                                double4* __restrict__ pts, int64_t* __restrict__ oidx, int64_t total) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  if (t < np) {
+    const int64_t i = perm[t];
+    pts[t] = make_double4(P[3 * i], P[3 * i + 1], P[3 * i + 2], 1.0);
+    oidx[t] = i;
+  } else {
+    pts[t] = make_double4(kFar, kFar, kFar, 0.0);
+    oidx[t] = 0;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+void check_inputs(const double* points, const double* normals, int64_t n, int* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_inputs, dim3(grid_for(n)), dim3(kThreads), 0, s, points, normals, n, flags);
+  RBF_HIP(hipGetLastError());
+}
+
+void build_centres(const double* points, const double* normals, int64_t n, double eps, double* xpaper,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_build_centres, dim3(grid_for(n)), dim3(kThreads), 0, s, points, normals, n, eps, xpaper);
+  RBF_HIP(hipGetLastError());
+}
+
+void bounding_box(const double* X, int64_t m, double* box6, double* scratch, hipStream_t s) {
+  int nb = (int)std::min<int64_t>(1024, ceil_div(m, kThreads));
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kThreads), 0, s, X, m, scratch);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, scratch, nb, box6);
+  RBF_HIP(hipGetLastError());
+}
+
+void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t nb = ceil_div(n, kScanTile);
+  int64_t* sums = dalloc<int64_t>(nb);
+  int64_t* sums_scanned = dalloc<int64_t>(nb);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n, sums);
+  RBF_HIP(hipGetLastError());
+  if (nb > 1) {
+    scan_exclusive_i64(sums, sums_scanned, nb, s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kThreads), 0, s, out, n, sums_scanned);
+    RBF_HIP(hipGetLastError());
+  }
+  RBF_HIP(hipStreamSynchronize(s));
+  dfree(sums);
+  dfree(sums_scanned);
+}
+
+void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* perm, uint32_t* keys_out,
+                 hipStream_t s) {
+  const int nb = (int)ceil_div(m, kRsTile);
+  uint32_t* k0 = dalloc<uint32_t>(m);
+  uint32_t* v0 = dalloc<uint32_t>(m);
+  uint32_t* k1 = dalloc<uint32_t>(m);
+  uint32_t* v1 = dalloc<uint32_t>(m);
+  int64_t* hist = dalloc<int64_t>((int64_t)256 * nb);
+  int64_t* offs = dalloc<int64_t>((int64_t)256 * nb);
+  hipLaunchKernelGGL(k_morton, dim3(grid_for(m)), dim3(kThreads), 0, s, pts3, m, lat, k0, v0);
+  RBF_HIP(hipGetLastError());
+  uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+  for (int shift = 0; shift < 3 * kMortonBits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, ki, m, shift, hist, nb);
+    RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(hist, offs, (int64_t)256 * nb, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, ko, vo, m, shift, offs, nb);
+    RBF_HIP(hipGetLastError());
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  RBF_HIP(hipMemcpyAsync(perm, vi, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+  if (keys_out) RBF_HIP(hipMemcpyAsync(keys_out, ki, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  dfree(k0); dfree(v0); dfree(k1); dfree(v1); dfree(hist); dfree(offs);
+}
+
+void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double sqrt_k, double4* xs, double4* xk,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_sorted, dim3(grid_for(m + 1)), dim3(kThreads), 0, s, pts3, perm, m, sqrt_k, xs, xk);
+  RBF_HIP(hipGetLastError());
+}
+
+int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t** cell_start, int32_t** cell_count,
+                    int32_t** cell_map, int32_t** cell_xyz, hipStream_t s) {
+  const int cshift = 3 * lat.shift;
+  int64_t* flag = dalloc<int64_t>(m);
+  int64_t* cid = dalloc<int64_t>(m);
+  hipLaunchKernelGGL(k_cell_flags, dim3(grid_for(m)), dim3(kThreads), 0, s, keys, m, cshift, flag);
+  RBF_HIP(hipGetLastError());
+  scan_exclusive_i64(flag, cid, m, s);
+  int64_t last_cid = 0, last_flag = 0;
+  RBF_HIP(hipMemcpy(&last_cid, cid + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+  RBF_HIP(hipMemcpy(&last_flag, flag + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+  const int64_t ncell = last_cid + last_flag;
+  const int64_t nmap = (int64_t)lat.cdims[0] * lat.cdims[1] * lat.cdims[2];
+  *cell_start = dalloc<int32_t>(ncell);
+  *cell_count = dalloc<int32_t>(ncell);
+  *cell_map = dalloc<int32_t>(nmap);
+  *cell_xyz = dalloc<int32_t>(ncell);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nmap)), dim3(kThreads), 0, s, *cell_map, -1, nmap);
+  hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, keys, m, cshift, flag, cid, lat,
+                     *cell_start, *cell_count, *cell_map, *cell_xyz);
+  RBF_HIP(hipGetLastError());
+  RBF_HIP(hipStreamSynchronize(s));
+  dfree(flag);
+  dfree(cid);
+  return ncell;
+}
+
+void centre_targets(const double4* xs, int64_t m, double4* pts, int64_t n_groups, hipStream_t s) {
+  const int64_t total = n_groups * kGroup;
+  hipLaunchKernelGGL(k_centre_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, xs, m, pts, total);
+  RBF_HIP(hipGetLastError());
+}
+
+void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
+  RBF_HIP(hipGetLastError());
+}
+void fill_f32(float* p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
+  RBF_HIP(hipGetLastError());
+}
+
+// Builds ts.groups / ts.list for the targets in ts.pts (n_groups*16 points).
+void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
+  const int64_t G = ts.n_groups;
+  ts.groups = dalloc<GroupInfo>(G);
+  ts.owned.push_back(ts.groups);
+  int64_t* tmp = dalloc<int64_t>(1);
+  double* tmpd = dalloc<double>(1);
+  if (ts.dense) {
+    hipLaunchKernelGGL(k_dense_groups, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.pts, G, c.m, ts.groups);
+    RBF_HIP(hipGetLastError());
+    ts.list = nullptr;
+    ts.list_entries = G * round_up(c.m, kChunk);
+    ts.useful = ts.n_targets * c.m;
+  } else {
+    int32_t* cin = dalloc<int32_t>(G);
+    int32_t* cout = dalloc<int32_t>(G);
+    int64_t* use = dalloc<int64_t>(G);
+    int64_t* len = dalloc<int64_t>(G);
+    int64_t* off = dalloc<int64_t>(G);
+    const unsigned nblk = (unsigned)ceil_div(G, 4);
+    hipLaunchKernelGGL(k_lists<false>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use,
+                       (uint32_t*)nullptr);
+    RBF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
+    RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(len, off, G, s);
+    hipLaunchKernelGGL(k_list_offsets, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, off);
+    hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(kThreads), 0, s, use, G, tmp);
+    RBF_HIP(hipGetLastError());
+    int64_t last_off = 0, last_len = 0;
+    RBF_HIP(hipMemcpyAsync(&last_off, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(&last_len, len + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(&ts.useful, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    ts.list_entries = last_off + last_len;
+    ts.list = dalloc<uint32_t>(ts.list_entries);
+    ts.owned.push_back(ts.list);
+    hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use, ts.list);
+    RBF_HIP(hipGetLastError());
+    RBF_HIP(hipStreamSynchronize(s));
+    dfree(cin); dfree(cout); dfree(use); dfree(len); dfree(off);
+  }
+  hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(kThreads), 0, s, ts.groups, G, tmpd);
+  RBF_HIP(hipGetLastError());
+  RBF_HIP(hipMemcpyAsync(&ts.max_radius, tmpd, sizeof(double), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  dfree(tmp);
+  dfree(tmpd);
+}
+
+void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_index, hipStream_t s) {
+  GridDesc gd;
+  const int bs[3] = {4, 2, 2};
+  for (int d = 0; d < 3; ++d) {
+    gd.o[d] = g.origin[d];
+    gd.h[d] = g.h[d];
+    gd.n[d] = g.dims[d];
+    gd.nb[d] = ceil_div(g.dims[d], bs[d]);
+  }
+  const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
+  int64_t* ids = nullptr;
+  int64_t nact = nbricks;
+  ts.dense = !std::isfinite(c.cutoff);
+  if (!ts.dense) {
+    int64_t* mark = dalloc<int64_t>(nbricks);
+    int64_t* pos = dalloc<int64_t>(nbricks);
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
+    hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
+                       c.cutoff, gd, mark);
+    RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(mark, pos, nbricks, s);
+    int64_t last_pos = 0, last_mark = 0;
+    RBF_HIP(hipMemcpy(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+    RBF_HIP(hipMemcpy(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+    nact = last_pos + last_mark;
+    ids = dalloc<int64_t>(nact);
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, pos, nbricks, ids);
+    RBF_HIP(hipGetLastError());
+    RBF_HIP(hipStreamSynchronize(s));
+    dfree(mark);
+    dfree(pos);
+  }
+  ts.n_groups = nact;
+  ts.pts = dalloc<double4>(nact * kGroup);
+  *out_index = dalloc<int64_t>(nact * kGroup);
+  if (nact > 0) {
+    hipLaunchKernelGGL(k_brick_targets, dim3(grid_for(nact * kGroup)), dim3(kThreads), 0, s, ids, nact, gd, ts.pts,
+                       *out_index);
+    RBF_HIP(hipGetLastError());
+    int64_t* cnt = dalloc<int64_t>(1);
+    RBF_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t), s));
+    const int nbk = (int)std::min<int64_t>(1024, ceil_div(nact * kGroup, kThreads));
+    hipLaunchKernelGGL(k_count_valid, dim3(nbk), dim3(kThreads), 0, s, ts.pts, nact * kGroup, cnt);
+    RBF_HIP(hipGetLastError());
+    RBF_HIP(hipMemcpyAsync(&ts.n_targets, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    dfree(cnt);
+    build_lists(c, ts, s);
+  }
+  dfree(ids);
+}
+
+void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, int64_t** out_index, hipStream_t s) {
+  uint32_t* perm = dalloc<uint32_t>(npts);
+  sort_points(pts, npts, c.lat, perm, nullptr, s);
+  ts.dense = !std::isfinite(c.cutoff);
+  ts.n_targets = npts;
+  ts.n_groups = ceil_div(npts, kGroup);
+  const int64_t total = ts.n_groups * kGroup;
+  ts.pts = dalloc<double4>(total);
+  *out_index = dalloc<int64_t>(total);
+  hipLaunchKernelGGL(k_point_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, pts, perm, npts, ts.pts,
+                     *out_index, total);
+  RBF_HIP(hipGetLastError());
+  build_lists(c, ts, s);
+  dfree(perm);
+}
+
+}  // namespace rbf

@@ -1,0 +1,239 @@
+"""ctypes binding of librbf (include/rbf.h).
+
+Argument marshalling only: every step runs in the HIP library.  Arrays are
+torch tensors on the GPU (float64, contiguous); calls are enqueued on the
+current torch stream.  The library must have been built
+(``python -m paper_1305_5179_amd.build``); loading raises when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbf.so")
+
+RBF_OK, RBF_EINVAL, RBF_ENOMEM, RBF_EDEVICE, RBF_ENOCONV, RBF_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+RBF_FP32, RBF_FP64 = 0, 1
+RBF_SOLVE_PLAIN_FP64, RBF_SOLVE_IR_FP32 = 0, 1
+STATUS_NAMES = {0: "RBF_OK", -1: "RBF_EINVAL", -2: "RBF_ENOMEM", -3: "RBF_EDEVICE",
+                -4: "RBF_ENOCONV", -5: "RBF_EBREAKDOWN"}
+
+# Every symbol include/rbf.h declares.
+EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "rbf_solve",
+           "rbf_eval_grid", "rbf_eval_points", "rbf_get_stats", "rbf_count_grid_pairs",
+           "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error"]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_outer", C.c_int),
+                ("max_iters", C.c_int), ("mode", C.c_int), ("reserved", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("rel_resid", C.c_double), ("status", C.c_int),
+                ("n_history", C.c_int), ("history", C.POINTER(C.c_double))]
+
+
+class Grid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("h", C.c_double * 3), ("dims", C.c_int64 * 3)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("n_centres", C.c_int64), ("n_groups", C.c_int64),
+                ("list_entries", C.c_int64), ("useful_pairs", C.c_int64), ("examined_pairs", C.c_int64),
+                ("n_cells", C.c_int64), ("cell_size", C.c_double), ("sigma", C.c_double),
+                ("cutoff", C.c_double), ("eps", C.c_double)]
+
+
+class Profile(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 2), ("kernel_ms", C.c_double * 2),
+                ("useful_pairs", C.c_int64 * 2), ("examined_pairs", C.c_int64 * 2)]
+
+
+class RbfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Load librbf.so and declare its prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1305_5179_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    lib.rbf_default_solve_opts.argtypes = [C.POINTER(SolveOpts)]
+    lib.rbf_setup.argtypes = [vp, vp, i64, dbl, dbl, dbl, vp, C.POINTER(vp)]
+    lib.rbf_centres.argtypes = [vp, vp, vp, vp]
+    lib.rbf_matvec.argtypes = [vp, vp, vp, i32, vp]
+    lib.rbf_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+    lib.rbf_eval_grid.argtypes = [vp, vp, C.POINTER(Grid), vp, i32, vp]
+    lib.rbf_eval_points.argtypes = [vp, vp, vp, i64, vp, i32, vp]
+    lib.rbf_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
+    lib.rbf_profile_begin.argtypes = []
+    lib.rbf_profile_end.argtypes = [C.POINTER(Profile)]
+    lib.rbf_destroy.argtypes = [vp]
+    lib.rbf_destroy.restype = None
+    lib.rbf_last_error.argtypes = [vp]
+    lib.rbf_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("rbf_destroy", "rbf_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def profile_begin() -> None:
+    st = load_library().rbf_profile_begin()
+    if st != RBF_OK:
+        raise RbfError(st, load_library().rbf_last_error(None).decode())
+
+
+def profile_end() -> Profile:
+    p = Profile()
+    st = load_library().rbf_profile_end(C.byref(p))
+    if st != RBF_OK:
+        raise RbfError(st, load_library().rbf_last_error(None).decode())
+    return p
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    load_library().rbf_default_solve_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_grid(origin, h, dims) -> Grid:
+    g = Grid()
+    for d in range(3):
+        g.origin[d] = float(origin[d])
+        g.h[d] = float(h[d])
+        g.dims[d] = int(dims[d])
+    return g
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iters: int
+    outer: int
+    rel_resid: float
+    history: list
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype_name: str = "float64"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"expected dtype {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Rbf:
+    """A context: extended centre set, neighbour structure and solver storage."""
+
+    def __init__(self, points, normals, eps: float, sigma: float, cutoff: float = math.inf):
+        lib = load_library()
+        self._lib = lib
+        self.ctx = C.c_void_p()
+        n = int(points.shape[0])
+        st = lib.rbf_setup(_ptr(points), _ptr(normals), n, float(eps), float(sigma), float(cutoff), _stream(),
+                           C.byref(self.ctx))
+        if st != RBF_OK:
+            raise RbfError(st, lib.rbf_last_error(None).decode())
+        self.n = n
+        self.m = 3 * n
+
+    def _check(self, st):
+        if st != RBF_OK:
+            raise RbfError(st, self._lib.rbf_last_error(self.ctx).decode())
+
+    def close(self):
+        if self.ctx:
+            self._lib.rbf_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def centres(self):
+        import torch
+        X = torch.empty((self.m, 3), dtype=torch.float64, device="cuda")
+        b = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        self._check(self._lib.rbf_centres(self.ctx, _ptr(X), _ptr(b), _stream()))
+        return X, b
+
+    def matvec(self, x, y=None, prec: int = RBF_FP32):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(self._lib.rbf_matvec(self.ctx, _ptr(x), _ptr(y), int(prec), _stream()))
+        return y
+
+    def solve(self, b=None, x0=None, c=None, **opts) -> tuple:
+        import torch
+        if c is None:
+            c = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        o = default_opts(**opts)
+        info = SolveInfo()
+        st = self._lib.rbf_solve(self.ctx, _ptr(b) if b is not None else None,
+                                 _ptr(x0) if x0 is not None else None, _ptr(c), C.byref(o), C.byref(info),
+                                 _stream())
+        if st not in (RBF_OK, RBF_ENOCONV):
+            raise RbfError(st, self._lib.rbf_last_error(self.ctx).decode())
+        hist = [info.history[i] for i in range(info.n_history)]
+        return c, SolveResult(st, info.iters, info.outer, info.rel_resid, hist)
+
+    def eval_grid(self, c, origin, h, dims, prec: int = RBF_FP32, out=None):
+        import torch
+        g = make_grid(origin, h, dims)
+        total = int(dims[0]) * int(dims[1]) * int(dims[2])
+        dt = torch.float32 if prec == RBF_FP32 else torch.float64
+        if out is None:
+            out = torch.empty(total, dtype=dt, device="cuda")
+        self._check(self._lib.rbf_eval_grid(self.ctx, _ptr(c), C.byref(g),
+                                            _ptr(out, "float32" if prec == RBF_FP32 else "float64"),
+                                            int(prec), _stream()))
+        return out
+
+    def eval_points(self, c, pts, prec: int = RBF_FP32, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(int(pts.shape[0]), dtype=torch.float64, device="cuda")
+        self._check(self._lib.rbf_eval_points(self.ctx, _ptr(c), _ptr(pts), int(pts.shape[0]), _ptr(out),
+                                              int(prec), _stream()))
+        return out
+
+    def stats(self) -> Stats:
+        s = Stats()
+        self._check(self._lib.rbf_get_stats(self.ctx, C.byref(s)))
+        return s
+
+    def count_grid_pairs(self, origin, h, dims):
+        g = make_grid(origin, h, dims)
+        u, e = C.c_int64(), C.c_int64()
+        self._check(self._lib.rbf_count_grid_pairs(self.ctx, C.byref(g), C.byref(u), C.byref(e), _stream()))
+        return u.value, e.value
