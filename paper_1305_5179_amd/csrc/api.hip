@@ -153,9 +153,9 @@ void ensure_solver(Ctx* c, int m) {
 // y_sorted = A x_sorted (x_sorted has a zero at index m).
 void apply_sorted(Ctx* c, const double* x, double* y, int prec, hipStream_t s, const int* skip = nullptr) {
   if (prec == RBF_FP32)
-    pairsum_f32(*c, c->centres, x, OUT_SORTED64, y, nullptr, s, skip);
+    pairsum_f32(*c, c->centres, x, false, y, s, skip);
   else
-    pairsum_f64(*c, c->centres, x, OUT_SORTED64, y, nullptr, s, skip);
+    pairsum_f64(*c, c->centres, x, false, y, s, skip);
 }
 
 }  // namespace
@@ -249,11 +249,8 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
       c->n_cells = build_cells(c->keys, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
     // 6. the centres as targets, with their source lists
     TargetSet& ts = c->centres;
-    ts.n_targets = c->m;
-    ts.n_groups = ceil_div(c->m, kGroup);
     ts.dense = !std::isfinite(cutoff);
-    ts.pts = dalloc<double4>(ts.n_groups * kGroup);
-    centre_targets(c->xs, c->m, ts.pts, ts.n_groups, s);
+    group_targets(*c, c->xs, nullptr, c->m, ts, s);
     build_lists(*c, ts, s);
     // 7. work vectors
     c->vin = dalloc<double>(c->mpad);
@@ -451,17 +448,15 @@ int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out,
     else
       fill_f64(static_cast<double*>(out), 0.0, total, s);
     TargetSet ts;
-    int64_t* oidx = nullptr;
-    grid_targets(*c, *grid, ts, &oidx, s);
+    grid_targets(*c, *grid, ts, s);
     if (ts.n_groups > 0) {
       if (prec == RBF_FP32)
-        pairsum_f32(*c, ts, c->vin, OUT_INDEXED32, out, oidx, s);
+        pairsum_f32(*c, ts, c->vin, true, out, s);
       else
-        pairsum_f64(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+        pairsum_f64(*c, ts, c->vin, false, out, s);
     }
     RBF_HIP(hipStreamSynchronize(s));
     free_targets(ts);
-    dfree(oidx);
     return RBF_OK;
   });
 }
@@ -473,12 +468,10 @@ int rbf_count_grid_pairs(rbf_ctx* c, const rbf_grid* grid, int64_t* useful, int6
   return guarded(c, [&]() -> int {
     hipStream_t s = (hipStream_t)stream;
     TargetSet ts;
-    int64_t* oidx = nullptr;
-    grid_targets(*c, *grid, ts, &oidx, s);
+    grid_targets(*c, *grid, ts, s);
     if (useful) *useful = ts.useful;
     if (examined) *examined = ts.list_entries * kGroup;
     free_targets(ts);
-    dfree(oidx);
     return RBF_OK;
   });
 }
@@ -496,15 +489,13 @@ int rbf_eval_points(rbf_ctx* c, const double* cw, const double* pts, int64_t npt
     hipStream_t s = (hipStream_t)stream;
     gather_to_sorted(cw, c->perm, c->m, c->vin, s);
     TargetSet ts;
-    int64_t* oidx = nullptr;
-    point_targets(*c, pts, npts, ts, &oidx, s);
+    point_targets(*c, pts, npts, ts, s);
     if (prec == RBF_FP32)
-      pairsum_f32(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+      pairsum_f32(*c, ts, c->vin, false, out, s);
     else
-      pairsum_f64(*c, ts, c->vin, OUT_INDEXED64, out, oidx, s);
+      pairsum_f64(*c, ts, c->vin, false, out, s);
     RBF_HIP(hipStreamSynchronize(s));
     free_targets(ts);
-    dfree(oidx);
     return RBF_OK;
   });
 }

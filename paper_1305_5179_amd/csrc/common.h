@@ -49,6 +49,7 @@ struct TargetSet {
   int64_t n_targets = 0;    // valid targets
   int64_t n_groups = 0;
   double4* pts = nullptr;   // n_groups*16 targets, unscaled; .w = 1 valid, 0 padding
+  int64_t* index = nullptr; // output position of every target slot
   GroupInfo* groups = nullptr;
   uint32_t* list = nullptr; // sorted-source indices (M = padding source)
   int64_t list_entries = 0;
@@ -162,18 +163,19 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
 int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t** cell_start,
                     int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
-void centre_targets(const double4* xs, int64_t m, double4* pts, int64_t n_groups, hipStream_t s);
+void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void fill_f32(float* p, float v, int64_t n, hipStream_t s);
 
 // pairsum.hip
-enum OutKind { OUT_SORTED64 = 0, OUT_INDEXED64 = 1, OUT_INDEXED32 = 2 };
-// `skip`: optional device flag; when it is nonzero the kernel returns at once.
-void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
-                 const int64_t* out_index, hipStream_t s, const int* skip = nullptr);
-void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
-                 const int64_t* out_index, hipStream_t s, const int* skip = nullptr);
+// out[ts.index[t]] = sum over the source list of target t (float output when
+// out_f32, else double).  `skip`: optional device flag; when it is nonzero the
+// kernel returns at once.
+void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
+                 const int* skip = nullptr);
+void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
+                 const int* skip = nullptr);
 
 int profile_begin();
 int profile_end(rbf_profile* out);
@@ -183,8 +185,7 @@ void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double
 void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s);
 
 // setup.hip: targets of the evaluation entry points
-void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_index, hipStream_t s);
-void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, int64_t** out_index,
-                   hipStream_t s);
+void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s);
+void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, hipStream_t s);
 
 }  // namespace rbf

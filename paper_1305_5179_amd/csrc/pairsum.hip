@@ -41,7 +41,7 @@ struct PairArgs {
   float TH;            // T * H, T = scaled cutoff^2 in float32
   float GH;            // ambiguity half-width times H
   int dense;
-  int kind;
+  int out_f32;
   void* out;
   const int64_t* out_index;
   const int* skip;
@@ -135,13 +135,10 @@ __device__ __forceinline__ void step_outer(float& acc, float tx, float ty, float
   F<12>(__VA_ARGS__); F<13>(__VA_ARGS__); F<14>(__VA_ARGS__); F<15>(__VA_ARGS__)
 
 __device__ __forceinline__ void store_result(const PairArgs& a, int64_t tid, double v) {
-  if (a.kind == OUT_SORTED64) {
-    static_cast<double*>(a.out)[tid] = v;
-  } else if (a.kind == OUT_INDEXED64) {
-    static_cast<double*>(a.out)[a.out_index[tid]] = v;
-  } else {
+  if (a.out_f32)
     static_cast<float*>(a.out)[a.out_index[tid]] = (float)v;
-  }
+  else
+    static_cast<double*>(a.out)[a.out_index[tid]] = v;
 }
 
 __device__ __forceinline__ uint32_t list_entry(const PairArgs& a, const GroupInfo& gi, int c, int lane) {
@@ -237,8 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
   if (row == 0 && tp.w != 0.0) store_result(a, tid, acc);
 }
 
-PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
-                   const int64_t* out_index, const int* skip) {
+PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out,
+                   const int* skip) {
   PairArgs a;
   a.tpts = ts.pts;
   a.groups = ts.groups;
@@ -252,9 +249,9 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, OutKind k
   a.inv_two_s2 = c.inv_two_s2;
   a.rc2 = c.rc2;
   a.dense = ts.dense ? 1 : 0;
-  a.kind = (int)kind;
+  a.out_f32 = out_f32 ? 1 : 0;
   a.out = out;
-  a.out_index = out_index;
+  a.out_index = ts.index;
   a.skip = skip;
   // Scaled cutoff T = k r_c^2 and the float32 error bound of d near it:
   // |d32 - d| <= u (10 T + 6 sqrt(T) R) with u = 2^-24 and R the largest
@@ -343,10 +340,10 @@ int profile_end(rbf_profile* out) {
   return RBF_OK;
 }
 
-void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
-                 const int64_t* out_index, hipStream_t s, const int* skip) {
+void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
+                 const int* skip) {
   if (ts.n_groups == 0) return;
-  PairArgs a = make_args(c, ts, w, kind, out, out_index, skip);
+  PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
   ProfScope prof(RBF_FP32, ts, s);
   hipLaunchKernelGGL(k_pairsum_f32, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
@@ -354,10 +351,10 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, OutKind kin
   prof.done();
 }
 
-void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, OutKind kind, void* out,
-                 const int64_t* out_index, hipStream_t s, const int* skip) {
+void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
+                 const int* skip) {
   if (ts.n_groups == 0) return;
-  PairArgs a = make_args(c, ts, w, kind, out, out_index, skip);
+  PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
   ProfScope prof(RBF_FP64, ts, s);
   hipLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, a);

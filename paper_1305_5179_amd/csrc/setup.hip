@@ -324,18 +324,6 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-// Centres as targets: group g holds sorted centres 16g .. 16g+15.
-__global__ void k_centre_targets(const double4* __restrict__ xs, int64_t m, double4* __restrict__ pts, int64_t total) {
-  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= total) return;
-  if (k < m) {
-    double4 v = xs[k];
-    pts[k] = make_double4(v.x, v.y, v.z, 1.0);
-  } else {
-    pts[k] = make_double4(kFar, kFar, kFar, 0.0);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Source lists.  One wave per group of 16 targets.  Candidate sources are
 // the centres of the coarse cells that the group's box, grown by the cutoff,
@@ -646,19 +634,72 @@ __global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_
   if (threadIdx.x == 0) atomicAdd((unsigned long long*)out, (unsigned long long)s[0]);
 }
 
-// Evaluation points in Morton order, grouped by 16.
-__global__ void k_point_targets(const double* __restrict__ P, const uint32_t* __restrict__ perm, int64_t np,
-                                double4* __restrict__ pts, int64_t* __restrict__ oidx, int64_t total) {
+
+// ---------------------------------------------------------------------------
+// Target groups.  Consecutive targets of the Morton order are packed into
+// groups of at most 16 whose bounding box has a diagonal of at most E (the
+// float32 coordinates of a group are taken relative to its centre, so their
+// rounding error scales with E).  The packing is greedy inside segments of
+// kGroupSeg targets, one thread per segment: pass 1 counts the groups of
+// every segment, pass 2 (after a scan) assigns each target its slot.
+// ---------------------------------------------------------------------------
+constexpr int kGroupSeg = 512;
+
+template <bool ASSIGN>
+__global__ void k_group_greedy(const double4* __restrict__ sp, int64_t M, double E2, int64_t* __restrict__ gcount,
+                               const int64_t* __restrict__ goff, int64_t* __restrict__ slot_of) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nseg = ceil_div(M, kGroupSeg);
+  if (s >= nseg) return;
+  const int64_t k0 = s * kGroupSeg, k1 = min(M, k0 + kGroupSeg);
+  int64_t g = ASSIGN ? goff[s] : 0, ng = 0;
+  int64_t k = k0;
+  while (k < k1) {
+    const double4 p = sp[k];
+    double lx = p.x, ly = p.y, lz = p.z, hx = p.x, hy = p.y, hz = p.z;
+    if (ASSIGN) slot_of[k] = g * kGroup;
+    int64_t j = k + 1;
+    for (; j < k1 && j - k < kGroup; ++j) {
+      const double4 q = sp[j];
+      const double nlx = fmin(lx, q.x), nly = fmin(ly, q.y), nlz = fmin(lz, q.z);
+      const double nhx = fmax(hx, q.x), nhy = fmax(hy, q.y), nhz = fmax(hz, q.z);
+      const double dx = nhx - nlx, dy = nhy - nly, dz = nhz - nlz;
+      if ((dx * dx + dy * dy) + dz * dz > E2) break;
+      lx = nlx; ly = nly; lz = nlz; hx = nhx; hy = nhy; hz = nhz;
+      if (ASSIGN) slot_of[j] = g * kGroup + (j - k);
+    }
+    k = j;
+    ++g;
+    ++ng;
+  }
+  if (!ASSIGN) gcount[s] = ng;
+}
+
+__global__ void k_pad_targets(double4* __restrict__ pts, int64_t* __restrict__ oidx, int64_t total) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= total) return;
-  if (t < np) {
-    const int64_t i = perm[t];
-    pts[t] = make_double4(P[3 * i], P[3 * i + 1], P[3 * i + 2], 1.0);
-    oidx[t] = i;
-  } else {
-    pts[t] = make_double4(kFar, kFar, kFar, 0.0);
-    oidx[t] = 0;
-  }
+  pts[t] = make_double4(kFar, kFar, kFar, 0.0);
+  oidx[t] = 0;
+}
+
+__global__ void k_place_targets(const double4* __restrict__ sp, const uint32_t* __restrict__ orig, int64_t M,
+                                const int64_t* __restrict__ slot_of, double4* __restrict__ pts,
+                                int64_t* __restrict__ oidx) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const double4 p = sp[k];
+  const int64_t t = slot_of[k];
+  pts[t] = make_double4(p.x, p.y, p.z, 1.0);
+  oidx[t] = orig ? (int64_t)orig[k] : k;
+}
+
+// Points of an evaluation set in a given order, as double4.
+__global__ void k_gather_points(const double* __restrict__ P, const uint32_t* __restrict__ perm, int64_t n,
+                                double4* __restrict__ sp) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t i = perm[k];
+  sp[k] = make_double4(P[3 * i], P[3 * i + 1], P[3 * i + 2], 0.0);
 }
 
 }  // namespace
@@ -762,10 +803,37 @@ int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t
   return ncell;
 }
 
-void centre_targets(const double4* xs, int64_t m, double4* pts, int64_t n_groups, hipStream_t s) {
-  const int64_t total = n_groups * kGroup;
-  hipLaunchKernelGGL(k_centre_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, xs, m, pts, total);
+void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts,
+                   hipStream_t s) {
+  const double E = 8.0 * c.sigma;
+  const int64_t nseg = ceil_div(M, kGroupSeg);
+  int64_t* gcount = dalloc<int64_t>(nseg);
+  int64_t* goff = dalloc<int64_t>(nseg);
+  int64_t* slot_of = dalloc<int64_t>(M);
+  hipLaunchKernelGGL(k_group_greedy<false>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount,
+                     (const int64_t*)nullptr, (int64_t*)nullptr);
   RBF_HIP(hipGetLastError());
+  scan_exclusive_i64(gcount, goff, nseg, s);
+  int64_t last_off = 0, last_cnt = 0;
+  RBF_HIP(hipMemcpyAsync(&last_off, goff + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_cnt, gcount + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  ts.n_targets = M;
+  ts.n_groups = last_off + last_cnt;
+  const int64_t total = ts.n_groups * kGroup;
+  ts.pts = dalloc<double4>(total);
+  ts.index = dalloc<int64_t>(total);
+  ts.owned.push_back(ts.index);
+  hipLaunchKernelGGL(k_group_greedy<true>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount, goff,
+                     slot_of);
+  hipLaunchKernelGGL(k_pad_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, ts.pts, ts.index, total);
+  hipLaunchKernelGGL(k_place_targets, dim3(grid_for(M)), dim3(kThreads), 0, s, sp, orig, M, slot_of, ts.pts,
+                     ts.index);
+  RBF_HIP(hipGetLastError());
+  RBF_HIP(hipStreamSynchronize(s));
+  dfree(gcount);
+  dfree(goff);
+  dfree(slot_of);
 }
 
 void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
@@ -831,7 +899,7 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
   dfree(tmpd);
 }
 
-void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_index, hipStream_t s) {
+void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s) {
   GridDesc gd;
   const int bs[3] = {4, 2, 2};
   for (int d = 0; d < 3; ++d) {
@@ -865,10 +933,11 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_
   }
   ts.n_groups = nact;
   ts.pts = dalloc<double4>(nact * kGroup);
-  *out_index = dalloc<int64_t>(nact * kGroup);
+  ts.index = dalloc<int64_t>(nact * kGroup);
+  ts.owned.push_back(ts.index);
   if (nact > 0) {
     hipLaunchKernelGGL(k_brick_targets, dim3(grid_for(nact * kGroup)), dim3(kThreads), 0, s, ids, nact, gd, ts.pts,
-                       *out_index);
+                       ts.index);
     RBF_HIP(hipGetLastError());
     int64_t* cnt = dalloc<int64_t>(1);
     RBF_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t), s));
@@ -883,20 +952,17 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, int64_t** out_
   dfree(ids);
 }
 
-void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, int64_t** out_index, hipStream_t s) {
+void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, hipStream_t s) {
   uint32_t* perm = dalloc<uint32_t>(npts);
+  double4* sp = dalloc<double4>(npts);
   sort_points(pts, npts, c.lat, perm, nullptr, s);
-  ts.dense = !std::isfinite(c.cutoff);
-  ts.n_targets = npts;
-  ts.n_groups = ceil_div(npts, kGroup);
-  const int64_t total = ts.n_groups * kGroup;
-  ts.pts = dalloc<double4>(total);
-  *out_index = dalloc<int64_t>(total);
-  hipLaunchKernelGGL(k_point_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, pts, perm, npts, ts.pts,
-                     *out_index, total);
+  hipLaunchKernelGGL(k_gather_points, dim3(grid_for(npts)), dim3(kThreads), 0, s, pts, perm, npts, sp);
   RBF_HIP(hipGetLastError());
+  ts.dense = !std::isfinite(c.cutoff);
+  group_targets(c, sp, perm, npts, ts, s);
   build_lists(c, ts, s);
   dfree(perm);
+  dfree(sp);
 }
 
 }  // namespace rbf
