@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--solve", action="store_true",
                     help="also time full solves (float32+refinement vs plain float64) to a common residual")
     ap.add_argument("--solve-iters", type=int, default=3000)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="after the timed steps, run one plain 256 MiB device copy (the reference a "
+                         "hardware-counter run scales FETCH_SIZE / WRITE_SIZE by)")
     return ap.parse_args()
 
 
@@ -115,6 +118,33 @@ def main():
     grid_useful, grid_examined = ctx.count_grid_pairs(g.origin, g.h, g.dims)
     ctx.close()
 
+    # phase breakdown of one (untimed) step
+    phases = {}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx = rbf.Rbf(pts, nrm, eps, sigma, cutoff)
+    torch.cuda.synchronize()
+    phases["setup_ms"] = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    coef, _ = ctx.solve(tol=1e-8, restart=restart, max_iters=restart, max_outer=1, mode=rbf.RBF_SOLVE_IR_FP32)
+    torch.cuda.synchronize()
+    phases["solve_cycle_ms"] = 1e3 * (time.perf_counter() - t)
+    t = time.perf_counter()
+    ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32, out=grid_out)
+    torch.cuda.synchronize()
+    phases["grid_ms"] = 1e3 * (time.perf_counter() - t)
+    x = torch.as_tensor(w.random_vector(3 * cfg["n"], seed=4), device=dev)
+    y = torch.empty_like(x)
+    for prec, key in ((rbf.RBF_FP32, "matvec_f32_ms"), (rbf.RBF_FP64, "matvec_f64_ms")):
+        ctx.matvec(x, y, prec=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            ctx.matvec(x, y, prec=prec)
+        torch.cuda.synchronize()
+        phases[key] = 1e3 * (time.perf_counter() - t) / 5
+    ctx.close()
+
     rbf.profile_begin()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -149,12 +179,19 @@ def main():
                    "n_points": cfg["n"], "n_centres": 3 * cfg["n"], "sigma": sigma, "cutoff": cutoff,
                    "restart": restart, "grid": list(g.dims)},
         "roofline": roofline,
+        "phases": phases,
         "pairs": {"operator_useful": st.useful_pairs, "operator_examined": st.examined_pairs,
                   "grid_useful": grid_useful, "grid_examined": grid_examined,
                   "applications_per_step": applications},
         "fp64_kernel": {"launches": prof.launches[1], "avg_launch_ms": prof.kernel_ms[1] / max(prof.launches[1], 1),
                         "useful_rate": prof.useful_pairs[1] / max(prof.kernel_ms[1] * 1e-3, 1e-30) / 1e9},
     }
+    if args.calibrate:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = int(src.numel() * 8)
     if args.solve:
         out["solve"] = solve_comparison(rbf, pts, nrm, cfg, g, args.solve_iters)
     if not args.no_cpu:

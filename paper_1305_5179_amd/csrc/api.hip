@@ -69,9 +69,15 @@ bool is_device_ptr(const void* p) {
 }
 
 void free_targets(TargetSet& ts) {
-  for (void* p : ts.owned) dfree(p);
+  auto release = [&](void* p) {
+    if (ts.temp)
+      temp_free(p);
+    else
+      dfree(p);
+  };
+  for (void* p : ts.owned) release(p);
   ts.owned.clear();
-  dfree(ts.pts);
+  release(ts.pts);
   ts.pts = nullptr;
   ts.groups = nullptr;
   ts.list = nullptr;
@@ -184,6 +190,7 @@ int rbf_default_solve_opts(rbf_solve_opts* o) {
 
 int rbf_setup(const double* points, const double* normals, int64_t n, double off_surface_eps, double sigma,
               double cutoff, void* stream, rbf_ctx** out) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!out) return fail(nullptr, RBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (n <= 0) return fail(nullptr, RBF_EINVAL, "n must be positive");
@@ -212,32 +219,32 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     c->sqrt_k = std::sqrt(1.4426950408889634 / (2.0 * sigma * sigma));
     c->inv_two_s2 = 1.0 / (2.0 * sigma * sigma);
     // 1. inputs
-    int* flags = dalloc<int>(2);
+    int* flags = talloc<int>(2);
     RBF_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
     check_inputs(points, normals, n, flags, s);
     int hf[2] = {0, 0};
     RBF_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    dfree(flags);
+    temp_free(flags);
     if (hf[0]) return fail(c, RBF_EINVAL, "points or normals contain NaN or Inf");
     if (hf[1]) return fail(c, RBF_EINVAL, "a normal is shorter than 1e-12");
     // 2. extended set (paper order)
     c->xpaper = dalloc<double>(3 * c->m);
     build_centres(points, normals, n, off_surface_eps, c->xpaper, s);
     // 3. lattice from the bounding box
-    double* box = dalloc<double>(6 + 6 * 1024);
+    double* box = talloc<double>(6 + 6 * 1024);
     bounding_box(c->xpaper, c->m, box, box + 6, s);
     double hb[6];
     RBF_HIP(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    dfree(box);
+    temp_free(box);
     c->lat = make_lattice(hb, cutoff);
     if (std::isfinite(cutoff)) {
       const double cells = (double)c->lat.cdims[0] * c->lat.cdims[1] * c->lat.cdims[2];
       if (cells > (double)((int64_t)1 << 28))
         return fail(c, RBF_EINVAL, "cutoff too small for the extent of the cloud (neighbour lattice too large)");
     }
-    // 4. Morton order
+    // 4. Hilbert order
     c->perm = dalloc<uint32_t>(c->m);
     c->keys = dalloc<uint32_t>(c->m);
     sort_points(c->xpaper, c->m, c->lat, c->perm, c->keys, s);
@@ -246,7 +253,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     gather_sorted(c->xpaper, c->perm, c->m, c->sqrt_k, c->xs, c->xk, s);
     // 5. coarse cells
     if (std::isfinite(cutoff))
-      c->n_cells = build_cells(c->keys, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
+      c->n_cells = build_cells(c->keys, c->xs, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
     // 6. the centres as targets, with their source lists
     TargetSet& ts = c->centres;
     ts.dense = !std::isfinite(cutoff);
@@ -271,6 +278,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
 }
 
 int rbf_centres(rbf_ctx* c, double* centres, double* values, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   if ((centres && !is_device_ptr(centres)) || (values && !is_device_ptr(values)))
     return fail(c, RBF_EINVAL, "outputs must be device pointers");
@@ -288,6 +296,7 @@ int rbf_centres(rbf_ctx* c, double* centres, double* values, void* stream) {
 }
 
 int rbf_matvec(rbf_ctx* c, const double* x, double* y, int prec, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   if (prec != RBF_FP32 && prec != RBF_FP64) return fail(c, RBF_EINVAL, "prec must be RBF_FP32 or RBF_FP64");
   if (!is_device_ptr(x) || !is_device_ptr(y)) return fail(c, RBF_EINVAL, "x and y must be device pointers");
@@ -303,6 +312,7 @@ int rbf_matvec(rbf_ctx* c, const double* x, double* y, int prec, void* stream) {
 
 int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const rbf_solve_opts* opts_in,
               rbf_solve_info* info, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   rbf_solve_opts o;
   rbf_default_solve_opts(&o);
@@ -434,6 +444,7 @@ static int check_grid(rbf_ctx* c, const rbf_grid* g) {
 }
 
 int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out, int prec, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   int st = check_grid(c, grid);
   if (st != RBF_OK) return st;
@@ -462,6 +473,7 @@ int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out,
 }
 
 int rbf_count_grid_pairs(rbf_ctx* c, const rbf_grid* grid, int64_t* useful, int64_t* examined, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   int st = check_grid(c, grid);
   if (st != RBF_OK) return st;
@@ -478,6 +490,7 @@ int rbf_count_grid_pairs(rbf_ctx* c, const rbf_grid* grid, int64_t* useful, int6
 
 int rbf_eval_points(rbf_ctx* c, const double* cw, const double* pts, int64_t npts, double* out, int prec,
                     void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
   if (npts < 0) return fail(c, RBF_EINVAL, "m must be >= 0");
   if (prec != RBF_FP32 && prec != RBF_FP64) return fail(c, RBF_EINVAL, "prec must be RBF_FP32 or RBF_FP64");

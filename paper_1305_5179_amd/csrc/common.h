@@ -26,22 +26,38 @@ constexpr int kWave = 64;
 constexpr int kChunk = 64;
 constexpr int kBlock = 256;          // threads per block of the pair kernels (4 independent waves)
 
-// Morton keys: 10 bits per axis on the fine lattice.
-constexpr int kMortonBits = 10;
-constexpr int kFineMax = 1 << kMortonBits;
+// Curve keys (Hilbert order): 10 bits per axis on the fine lattice.
+constexpr int kCurveBits = 10;
+constexpr int kFineMax = 1 << kCurveBits;
 
 // Far-away coordinate of the padding source/target (index M of the sorted
 // arrays): every pair with it underflows to exactly 0 and its weight is 0.
 constexpr double kFar = 1.0e6;
 
 // Per-group metadata of a target set.
+// The list of a group is [inner | outer-safe | outer-risky], padded to whole
+// chunks: inner sources are inside the cutoff for every target of the
+// group; outer ones for some; a risky source has a pair whose scaled squared
+// distance lies within twice the float32 error band of the cutoff, so the
+// float32 kernel must check those pairs against the float64 decision.
 struct GroupInfo {
   int64_t off;          // first list entry of the group
   int32_t n_chunks;     // list length / 64
-  int32_t n_inner;      // leading chunks in which every pair lies inside the cutoff
+  int32_t n_inner;      // chunks [0, n_inner) hold inner sources only
+  int32_t first_risky;  // chunks [first_risky, n_chunks) may hold risky sources
+  int32_t pad_;
   double ax, ay, az;    // anchor (unscaled float64); float32 coordinates are taken relative to it
   double radius;        // max distance of a valid target from the anchor
 };
+
+// Half-width of the band around the scaled cutoff T inside which the float32
+// scaled squared distance may decide differently from float64, for a group
+// of scaled radius R: four times the bound u (10 T + 7 sqrt(T) R), u = 2^-24
+// (rounding of the anchor-relative coordinates, of the differences, of the
+// three products and of T itself).
+__host__ __device__ inline double f32_cutoff_band(double T, double R) {
+  return 4.0 * 5.9604644775390625e-08 * (10.0 * T + 7.0 * sqrt(T) * R);
+}
 
 // A set of targets grouped by 16 (centres, grid nodes or evaluation points)
 // together with the source list of every group.
@@ -56,10 +72,11 @@ struct TargetSet {
   int64_t useful = 0;       // pairs with r^2 <= cutoff^2 (float64 decision)
   double max_radius = 0.0;
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
+  bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
   std::vector<void*> owned; // device allocations to free with the set
 };
 
-// Neighbour lattice.  Fine cells (side f) order the centres along a Morton
+// Neighbour lattice.  Fine cells (side f) order the centres along a Hilbert
 // curve; a coarse cell is an aligned block of 2^shift fine cells per axis
 // and therefore a contiguous run of the sorted centres.
 struct Lattice {
@@ -81,9 +98,9 @@ struct Ctx {
   double sqrt_k = 0;        // coordinates scaled by sqrt(log2(e) / (2 sigma^2)): phi = exp2(-|x'|^2)
   double inv_two_s2 = 0;    // 1 / (2 sigma^2)
   Lattice lat{};
-  // Sorted centres (Morton order); index m is the far padding source.
+  // Sorted centres (Hilbert order); index m is the far padding source.
   uint32_t* perm = nullptr;     // sorted position -> paper index
-  uint32_t* keys = nullptr;     // Morton keys of the sorted centres
+  uint32_t* keys = nullptr;     // curve keys of the sorted centres
   double4* xs = nullptr;        // unscaled coordinates, m+1
   double4* xk = nullptr;        // scaled coordinates, m+1
   double* xpaper = nullptr;     // paper-order centres, m x 3 (for rbf_centres)
@@ -148,6 +165,28 @@ inline void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// Temporaries: stream-ordered allocations on the stream of the current API
+// call (set by TempStream), served from the device's memory pool without a
+// device-wide synchronisation.
+hipStream_t& temp_stream();
+struct TempStream {
+  hipStream_t prev;
+  explicit TempStream(hipStream_t s) : prev(temp_stream()) { temp_stream() = s; }
+  ~TempStream() { temp_stream() = prev; }
+};
+void* temp_alloc_bytes(size_t bytes);
+void temp_free(void* p);
+template <class T>
+T* talloc(int64_t count) {
+  if (count <= 0) count = 1;
+  return static_cast<T*>(temp_alloc_bytes(sizeof(T) * (size_t)count));
+}
+// Arrays of a target set: persistent or stream-ordered as the set asks.
+template <class T>
+T* set_alloc(const TargetSet& ts, int64_t count) {
+  return ts.temp ? talloc<T>(count) : dalloc<T>(count);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).
 // ---------------------------------------------------------------------------
@@ -160,7 +199,7 @@ void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* pe
                  hipStream_t s);
 void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double sqrt_k, double4* xs,
                    double4* xk, hipStream_t s);
-int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t** cell_start,
+int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
                     int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);

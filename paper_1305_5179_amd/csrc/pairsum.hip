@@ -38,8 +38,8 @@ struct PairArgs {
   double sqrt_k;
   double inv_two_s2;
   double rc2;
+  double Tk;           // scaled cutoff^2, k r_c^2 (float64)
   float TH;            // T * H, T = scaled cutoff^2 in float32
-  float GH;            // ambiguity half-width times H
   int dense;
   int out_f32;
   void* out;
@@ -114,13 +114,25 @@ __device__ __forceinline__ float resolve_f64(const PairArgs& a, int64_t tid, uin
   return r2 <= a.rc2 ? -d : -INFINITY;
 }
 
+// Outer chunk without risky sources: every pair is farther than the band
+// from the cutoff, so the float32 test decides as float64 does.
 template <int K>
 __device__ __forceinline__ void step_outer(float& acc, float tx, float ty, float tz, float sx, float sy, float sz,
-                                           float sw, float th, const PairArgs& a, int64_t tid, uint32_t idx, int row) {
+                                           float sw, float th) {
+  const float d = sqdist_bcast<K>(tx, ty, tz, sx, sy, sz);
+  const float v = __builtin_fmaf(d, -kH, th);
+  const float e = __builtin_amdgcn_exp2f(__builtin_fminf(-d, v));
+  fmac_bcast<K>(acc, sw, e);
+}
+
+template <int K>
+__device__ __forceinline__ void step_risky(float& acc, float tx, float ty, float tz, float sx, float sy, float sz,
+                                           float sw, float th, float gh, const PairArgs& a, int64_t tid, uint32_t idx,
+                                           int row) {
   const float d = sqdist_bcast<K>(tx, ty, tz, sx, sy, sz);
   const float v = __builtin_fmaf(d, -kH, th);
   float arg = __builtin_fminf(-d, v);
-  const bool amb = __builtin_fabsf(v) <= a.GH;
+  const bool amb = __builtin_fabsf(v) <= gh;
   if (__builtin_expect(__builtin_amdgcn_ballot_w64(amb) != 0, 0)) {
     if (amb) arg = resolve_f64(a, tid, idx, row, K, d);
   }
@@ -166,8 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
   // the truncation threshold T*H held in a VGPR (v_fma_f32 takes it as its addend)
   float th;
   asm volatile("v_mov_b32 %0, %1" : "=v"(th) : "s"(a.TH));
+  // ambiguity half-width of this group, times H
+  const float gh = (float)(f32_cutoff_band(a.Tk, gi.radius * a.sqrt_k) * (double)kH);
   float acc = 0.0f;
-  const int nch = gi.n_chunks, nin = gi.n_inner;
+  const int nch = gi.n_chunks, nin = gi.n_inner, nrisk = gi.first_risky;
   for (int c = 0; c < nch; ++c) {
     const uint32_t idx = list_entry(a, gi, c, lane);
     const double4 s = a.xk[idx];
@@ -176,8 +190,10 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
     const float sw = (float)wv;
     if (c < nin) {
       RBF_STEPS(step_inner, acc, tx, ty, tz, sx, sy, sz, sw);
+    } else if (c < nrisk) {
+      RBF_STEPS(step_outer, acc, tx, ty, tz, sx, sy, sz, sw, th);
     } else {
-      RBF_STEPS(step_outer, acc, tx, ty, tz, sx, sy, sz, sw, th, a, tid, idx, row);
+      RBF_STEPS(step_risky, acc, tx, ty, tz, sx, sy, sz, sw, th, gh, a, tid, idx, row);
     }
   }
   acc += __shfl_xor(acc, 16);
@@ -253,21 +269,14 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.out = out;
   a.out_index = ts.index;
   a.skip = skip;
-  // Scaled cutoff T = k r_c^2 and the float32 error bound of d near it:
-  // |d32 - d| <= u (10 T + 6 sqrt(T) R) with u = 2^-24 and R the largest
-  // scaled distance of a target from its group's anchor (rounding of the
-  // relative coordinates, of the differences, of the three products and of
-  // T itself); the band is four times wider than that bound.
+  // Scaled cutoff T = k r_c^2 (the per-group ambiguity band is
+  // f32_cutoff_band(T, scaled group radius)).
   if (std::isfinite(c.rc2)) {
-    const double T = c.rc2 * c.sqrt_k * c.sqrt_k;
-    const double R = ts.max_radius * c.sqrt_k;
-    const double u = std::ldexp(1.0, -24);
-    const double band = 4.0 * u * (10.0 * T + 6.0 * std::sqrt(T) * R) + 1e-30;
-    a.TH = (float)(T) * kH;
-    a.GH = (float)(band * (double)kH);
+    a.Tk = c.rc2 * c.sqrt_k * c.sqrt_k;
+    a.TH = (float)(a.Tk) * kH;
   } else {
+    a.Tk = INFINITY;
     a.TH = INFINITY;
-    a.GH = -1.0f;
   }
   return a;
 }

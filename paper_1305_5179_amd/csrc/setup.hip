@@ -1,4 +1,4 @@
-// Setup kernels: input checks, the extended centre set, Morton ordering
+// Setup kernels: input checks, the extended centre set, Hilbert ordering
 // (wave-ballot LSD radix sort), coarse cells and per-group source lists.
 #include "common.h"
 
@@ -104,24 +104,8 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __
 }
 
 // ---------------------------------------------------------------------------
-// Morton keys on the fine lattice (10 bits per axis, x in bit 0).
+// Space-filling-curve keys on the fine lattice (10 bits per axis).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0x030000FFu;
-  v = (v | (v << 8)) & 0x0300F00Fu;
-  v = (v | (v << 4)) & 0x030C30C3u;
-  v = (v | (v << 2)) & 0x09249249u;
-  return v;
-}
-__device__ __forceinline__ uint32_t compact3(uint32_t v) {
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030C30C3u;
-  v = (v | (v >> 4)) & 0x0300F00Fu;
-  v = (v | (v >> 8)) & 0x030000FFu;
-  v = (v | (v >> 16)) & 0x3ffu;
-  return v;
-}
 __device__ __forceinline__ uint32_t fine_coord(double x, double o, double f, int dim) {
   double q = floor((x - o) / f);
   if (!(q >= 0.0)) q = 0.0;
@@ -129,14 +113,47 @@ __device__ __forceinline__ uint32_t fine_coord(double x, double o, double f, int
   return (uint32_t)q;
 }
 
-__global__ void k_morton(const double* __restrict__ X, int64_t m, Lattice lat, uint32_t* __restrict__ keys,
-                         uint32_t* __restrict__ idx) {
+// Hilbert index of a fine cell (Skilling's transpose algorithm: undo the
+// per-level rotations and reflections, Gray-decode, then interleave the bits
+// with the most significant level first).  Like Morton order it keeps every
+// aligned block of 2^s fine cells contiguous, with fewer long jumps.
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t X[3] = {x, y, z};
+  const uint32_t M = 1u << (kCurveBits - 1);
+  for (uint32_t Q = M; Q > 1; Q >>= 1) {
+    const uint32_t P = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= P;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & P;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Q = M; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  uint32_t key = 0;
+  for (int b = kCurveBits - 1; b >= 0; --b)
+    for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> b) & 1u);
+  return key;
+}
+
+__global__ void k_curve_keys(const double* __restrict__ X, int64_t m, Lattice lat, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ idx) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= m) return;
   uint32_t cx = fine_coord(X[3 * i], lat.origin[0], lat.fine, lat.fdims[0]);
   uint32_t cy = fine_coord(X[3 * i + 1], lat.origin[1], lat.fine, lat.fdims[1]);
   uint32_t cz = fine_coord(X[3 * i + 2], lat.origin[2], lat.fine, lat.fdims[2]);
-  keys[i] = spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+  keys[i] = hilbert3(cx, cy, cz);
   idx[i] = (uint32_t)i;
 }
 
@@ -292,7 +309,7 @@ __global__ void k_cell_flags(const uint32_t* __restrict__ keys, int64_t m, int c
   flag[k] = (k == 0 || (keys[k] >> cshift) != (keys[k - 1] >> cshift)) ? 1 : 0;
 }
 
-__global__ void k_cell_fill(const uint32_t* __restrict__ keys, int64_t m, int cshift, const int64_t* __restrict__ flag,
+__global__ void k_cell_fill(const double4* __restrict__ xs, int64_t m, const int64_t* __restrict__ flag,
                             const int64_t* __restrict__ cid, Lattice lat, int32_t* __restrict__ start,
                             int32_t* __restrict__ count, int32_t* __restrict__ map, int32_t* __restrict__ xyz) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -304,8 +321,10 @@ __global__ void k_cell_fill(const uint32_t* __restrict__ keys, int64_t m, int cs
   while (e < m && !flag[e]) ++e;
   start[c] = (int32_t)k;
   count[c] = (int32_t)(e - k);
-  uint32_t ck = keys[k] >> cshift;
-  uint32_t cx = compact3(ck), cy = compact3(ck >> 1), cz = compact3(ck >> 2);
+  const double4 p = xs[k];
+  const uint32_t cx = fine_coord(p.x, lat.origin[0], lat.fine, lat.fdims[0]) >> lat.shift;
+  const uint32_t cy = fine_coord(p.y, lat.origin[1], lat.fine, lat.fdims[1]) >> lat.shift;
+  const uint32_t cz = fine_coord(p.z, lat.origin[2], lat.fine, lat.fdims[2]) >> lat.shift;
   int64_t lin = (int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz);
   map[lin] = (int32_t)c;
   xyz[c] = (int32_t)(cx | (cy << 10) | (cz << 20));
@@ -341,7 +360,8 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
                                                     const double4* __restrict__ xs, int64_t m,
                                                     const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
                                                     const int32_t* __restrict__ cmap, Lattice lat, double rc, double rc2,
-                                                    int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out,
+                                                    double kscale, int32_t* __restrict__ cnt_in,
+                                                    int32_t* __restrict__ cnt_out, int32_t* __restrict__ cnt_risk,
                                                     int64_t* __restrict__ useful, uint32_t* __restrict__ list) {
   __shared__ double4 tg[4][kGroup];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -363,19 +383,21 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
     }
   }
-  int64_t wbase_in = 0, wbase_out = 0;
+  int64_t wbase_in = 0, wbase_out = 0, wbase_risk = 0;
   if (WRITE) {
     wbase_in = groups[g].off;
     wbase_out = wbase_in + cnt_in[g];
+    wbase_risk = wbase_out + cnt_out[g];
   }
   if (nvalid == 0) {
     if (!WRITE) {
       if (lane == 0) {
         cnt_in[g] = 0;
         cnt_out[g] = 0;
+        cnt_risk[g] = 0;
         useful[g] = 0;
         GroupInfo gi;
-        gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0;
+        gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0; gi.first_risky = 0; gi.pad_ = 0;
         gi.ax = gi.ay = gi.az = 0.0;
         gi.radius = 0.0;
         groups[g] = gi;
@@ -384,6 +406,17 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     return;
   }
   const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]), az = 0.5 * (lo[2] + hi[2]);
+  double rad = 0.0;
+  for (int l = 0; l < kGroup; ++l) {
+    double4 t = tg[wave][l];
+    if (t.w != 0.0) {
+      double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
+      rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
+    }
+  }
+  // scaled cutoff and twice the float32 band of this group (risky sources)
+  const double Tk = rc2 * kscale;
+  const double risk = isfinite(Tk) ? 2.0 * f32_cutoff_band(Tk, rad * sqrt(kscale)) : -1.0;
 
   int cl[3], ch[3];
   const bool finite_rc = isfinite(rc);
@@ -399,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     }
   }
   const double box_slack = rc2 * (1.0 + 1e-9) + 1e-300;
-  int64_t n_in = 0, n_out = 0, use = 0;
+  int64_t n_in = 0, n_out = 0, n_risk = 0, use = 0;
   for (int cz = cl[2]; cz <= ch[2]; ++cz)
     for (int cy = cl[1]; cy <= ch[1]; ++cy)
       for (int cx = cl[0]; cx <= ch[0]; ++cx) {
@@ -419,6 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
           const bool valid = b0 + lane < ct;
           const int64_t k = (int64_t)st + b0 + lane;
           int inside = 0;
+          bool near_cut = false;
           if (valid) {
             double4 s = xs[k];
             for (int l = 0; l < kGroup; ++l) {
@@ -426,45 +460,45 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
               double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
               double r2 = (dx * dx + dy * dy) + dz * dz;
               inside += (t.w != 0.0 && r2 <= rc2) ? 1 : 0;
+              near_cut = near_cut || (t.w != 0.0 && fabs(r2 * kscale - Tk) <= risk);
             }
           }
           const bool is_in = valid && inside == nvalid;
           const bool is_out = valid && inside > 0 && inside < nvalid;
-          const uint64_t mi = ballot(is_in), mo = ballot(is_out);
+          const bool is_risk = is_out && near_cut;
+          const bool is_safe = is_out && !near_cut;
+          const uint64_t mi = ballot(is_in), mo = ballot(is_safe), mr = ballot(is_risk);
           if (WRITE) {
             if (is_in) list[wbase_in + n_in + lanes_below(mi)] = (uint32_t)k;
-            if (is_out) list[wbase_out + n_out + lanes_below(mo)] = (uint32_t)k;
+            if (is_safe) list[wbase_out + n_out + lanes_below(mo)] = (uint32_t)k;
+            if (is_risk) list[wbase_risk + n_risk + lanes_below(mr)] = (uint32_t)k;
           }
           n_in += __popcll(mi);
           n_out += __popcll(mo);
+          n_risk += __popcll(mr);
           use += inside;
         }
       }
   if (!WRITE) {
     // wave sum of the useful-pair counts
     for (int off = 32; off > 0; off >>= 1) use += __shfl_xor(use, off);
-    double rad = 0.0;
-    for (int l = 0; l < kGroup; ++l) {
-      double4 t = tg[wave][l];
-      if (t.w != 0.0) {
-        double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
-        rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
-      }
-    }
     if (lane == 0) {
       cnt_in[g] = (int32_t)n_in;
       cnt_out[g] = (int32_t)n_out;
+      cnt_risk[g] = (int32_t)n_risk;
       useful[g] = use;
       GroupInfo gi;
       gi.off = 0;
-      gi.n_chunks = (int32_t)ceil_div(n_in + n_out, kChunk);
+      gi.n_chunks = (int32_t)ceil_div(n_in + n_out + n_risk, kChunk);
       gi.n_inner = (int32_t)(n_in / kChunk);
+      gi.first_risky = n_risk > 0 ? (int32_t)((n_in + n_out) / kChunk) : gi.n_chunks;
+      gi.pad_ = 0;
       gi.ax = ax; gi.ay = ay; gi.az = az;
       gi.radius = rad;
       groups[g] = gi;
     }
   } else {
-    const int64_t total = n_in + n_out;
+    const int64_t total = n_in + n_out + n_risk;
     const int64_t padded = round_up(total, kChunk);
     for (int64_t e = total + lane; e < padded; e += kWave) list[wbase_in + e] = (uint32_t)m;
   }
@@ -497,6 +531,8 @@ __global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int6
   gi.off = 0;
   gi.n_chunks = nv ? (int32_t)ceil_div(m, kChunk) : 0;
   gi.n_inner = gi.n_chunks;
+  gi.first_risky = gi.n_chunks;
+  gi.pad_ = 0;
   if (nv) {
     gi.ax = 0.5 * (lo[0] + hi[0]); gi.ay = 0.5 * (lo[1] + hi[1]); gi.az = 0.5 * (lo[2] + hi[2]);
     double rad = 0.0;
@@ -636,7 +672,7 @@ __global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_
 
 
 // ---------------------------------------------------------------------------
-// Target groups.  Consecutive targets of the Morton order are packed into
+// Target groups.  Consecutive targets of the curve order are packed into
 // groups of at most 16 whose bounding box has a diagonal of at most E (the
 // float32 coordinates of a group are taken relative to its centre, so their
 // rounding error scales with E).  The packing is greedy inside segments of
@@ -729,8 +765,8 @@ void bounding_box(const double* X, int64_t m, double* box6, double* scratch, hip
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   int64_t nb = ceil_div(n, kScanTile);
-  int64_t* sums = dalloc<int64_t>(nb);
-  int64_t* sums_scanned = dalloc<int64_t>(nb);
+  int64_t* sums = talloc<int64_t>(nb);
+  int64_t* sums_scanned = talloc<int64_t>(nb);
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n, sums);
   RBF_HIP(hipGetLastError());
   if (nb > 1) {
@@ -738,24 +774,23 @@ void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t 
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kThreads), 0, s, out, n, sums_scanned);
     RBF_HIP(hipGetLastError());
   }
-  RBF_HIP(hipStreamSynchronize(s));
-  dfree(sums);
-  dfree(sums_scanned);
+  temp_free(sums);
+  temp_free(sums_scanned);
 }
 
 void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* perm, uint32_t* keys_out,
                  hipStream_t s) {
   const int nb = (int)ceil_div(m, kRsTile);
-  uint32_t* k0 = dalloc<uint32_t>(m);
-  uint32_t* v0 = dalloc<uint32_t>(m);
-  uint32_t* k1 = dalloc<uint32_t>(m);
-  uint32_t* v1 = dalloc<uint32_t>(m);
-  int64_t* hist = dalloc<int64_t>((int64_t)256 * nb);
-  int64_t* offs = dalloc<int64_t>((int64_t)256 * nb);
-  hipLaunchKernelGGL(k_morton, dim3(grid_for(m)), dim3(kThreads), 0, s, pts3, m, lat, k0, v0);
+  uint32_t* k0 = talloc<uint32_t>(m);
+  uint32_t* v0 = talloc<uint32_t>(m);
+  uint32_t* k1 = talloc<uint32_t>(m);
+  uint32_t* v1 = talloc<uint32_t>(m);
+  int64_t* hist = talloc<int64_t>((int64_t)256 * nb);
+  int64_t* offs = talloc<int64_t>((int64_t)256 * nb);
+  hipLaunchKernelGGL(k_curve_keys, dim3(grid_for(m)), dim3(kThreads), 0, s, pts3, m, lat, k0, v0);
   RBF_HIP(hipGetLastError());
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-  for (int shift = 0; shift < 3 * kMortonBits; shift += 8) {
+  for (int shift = 0; shift < 3 * kCurveBits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, ki, m, shift, hist, nb);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(hist, offs, (int64_t)256 * nb, s);
@@ -766,8 +801,7 @@ void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* pe
   }
   RBF_HIP(hipMemcpyAsync(perm, vi, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
   if (keys_out) RBF_HIP(hipMemcpyAsync(keys_out, ki, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
-  RBF_HIP(hipStreamSynchronize(s));
-  dfree(k0); dfree(v0); dfree(k1); dfree(v1); dfree(hist); dfree(offs);
+  temp_free(k0); temp_free(v0); temp_free(k1); temp_free(v1); temp_free(hist); temp_free(offs);
 }
 
 void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double sqrt_k, double4* xs, double4* xk,
@@ -776,17 +810,18 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
   RBF_HIP(hipGetLastError());
 }
 
-int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t** cell_start, int32_t** cell_count,
-                    int32_t** cell_map, int32_t** cell_xyz, hipStream_t s) {
+int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
+                    int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s) {
   const int cshift = 3 * lat.shift;
-  int64_t* flag = dalloc<int64_t>(m);
-  int64_t* cid = dalloc<int64_t>(m);
+  int64_t* flag = talloc<int64_t>(m);
+  int64_t* cid = talloc<int64_t>(m);
   hipLaunchKernelGGL(k_cell_flags, dim3(grid_for(m)), dim3(kThreads), 0, s, keys, m, cshift, flag);
   RBF_HIP(hipGetLastError());
   scan_exclusive_i64(flag, cid, m, s);
   int64_t last_cid = 0, last_flag = 0;
-  RBF_HIP(hipMemcpy(&last_cid, cid + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
-  RBF_HIP(hipMemcpy(&last_flag, flag + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+  RBF_HIP(hipMemcpyAsync(&last_cid, cid + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
   const int64_t ncell = last_cid + last_flag;
   const int64_t nmap = (int64_t)lat.cdims[0] * lat.cdims[1] * lat.cdims[2];
   *cell_start = dalloc<int32_t>(ncell);
@@ -794,12 +829,11 @@ int64_t build_cells(const uint32_t* keys, int64_t m, const Lattice& lat, int32_t
   *cell_map = dalloc<int32_t>(nmap);
   *cell_xyz = dalloc<int32_t>(ncell);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nmap)), dim3(kThreads), 0, s, *cell_map, -1, nmap);
-  hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, keys, m, cshift, flag, cid, lat,
+  hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, xs, m, flag, cid, lat,
                      *cell_start, *cell_count, *cell_map, *cell_xyz);
   RBF_HIP(hipGetLastError());
-  RBF_HIP(hipStreamSynchronize(s));
-  dfree(flag);
-  dfree(cid);
+  temp_free(flag);
+  temp_free(cid);
   return ncell;
 }
 
@@ -807,9 +841,9 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
                    hipStream_t s) {
   const double E = 8.0 * c.sigma;
   const int64_t nseg = ceil_div(M, kGroupSeg);
-  int64_t* gcount = dalloc<int64_t>(nseg);
-  int64_t* goff = dalloc<int64_t>(nseg);
-  int64_t* slot_of = dalloc<int64_t>(M);
+  int64_t* gcount = talloc<int64_t>(nseg);
+  int64_t* goff = talloc<int64_t>(nseg);
+  int64_t* slot_of = talloc<int64_t>(M);
   hipLaunchKernelGGL(k_group_greedy<false>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount,
                      (const int64_t*)nullptr, (int64_t*)nullptr);
   RBF_HIP(hipGetLastError());
@@ -821,8 +855,8 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   ts.n_targets = M;
   ts.n_groups = last_off + last_cnt;
   const int64_t total = ts.n_groups * kGroup;
-  ts.pts = dalloc<double4>(total);
-  ts.index = dalloc<int64_t>(total);
+  ts.pts = set_alloc<double4>(ts, total);
+  ts.index = set_alloc<int64_t>(ts, total);
   ts.owned.push_back(ts.index);
   hipLaunchKernelGGL(k_group_greedy<true>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount, goff,
                      slot_of);
@@ -830,10 +864,38 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   hipLaunchKernelGGL(k_place_targets, dim3(grid_for(M)), dim3(kThreads), 0, s, sp, orig, M, slot_of, ts.pts,
                      ts.index);
   RBF_HIP(hipGetLastError());
-  RBF_HIP(hipStreamSynchronize(s));
-  dfree(gcount);
-  dfree(goff);
-  dfree(slot_of);
+  temp_free(gcount);
+  temp_free(goff);
+  temp_free(slot_of);
+}
+
+hipStream_t& temp_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+
+void* temp_alloc_bytes(size_t bytes) {
+  static bool pool_ready = false;
+  if (!pool_ready) {
+    // keep freed blocks in the pool instead of returning them at every sync
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t keep = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    pool_ready = true;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, bytes, temp_stream());
+  if (e != hipSuccess)
+    throw Error{e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE,
+                std::string("hipMallocAsync(") + std::to_string(bytes) + " bytes): " + hipGetErrorString(e)};
+  return p;
+}
+
+void temp_free(void* p) {
+  if (p) (void)hipFreeAsync(p, temp_stream());
 }
 
 void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
@@ -850,10 +912,10 @@ void fill_f32(float* p, float v, int64_t n, hipStream_t s) {
 // Builds ts.groups / ts.list for the targets in ts.pts (n_groups*16 points).
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
   const int64_t G = ts.n_groups;
-  ts.groups = dalloc<GroupInfo>(G);
+  ts.groups = set_alloc<GroupInfo>(ts, G);
   ts.owned.push_back(ts.groups);
-  int64_t* tmp = dalloc<int64_t>(1);
-  double* tmpd = dalloc<double>(1);
+  int64_t* tmp = talloc<int64_t>(1);
+  double* tmpd = talloc<double>(1);
   if (ts.dense) {
     hipLaunchKernelGGL(k_dense_groups, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.pts, G, c.m, ts.groups);
     RBF_HIP(hipGetLastError());
@@ -861,15 +923,17 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     ts.list_entries = G * round_up(c.m, kChunk);
     ts.useful = ts.n_targets * c.m;
   } else {
-    int32_t* cin = dalloc<int32_t>(G);
-    int32_t* cout = dalloc<int32_t>(G);
-    int64_t* use = dalloc<int64_t>(G);
-    int64_t* len = dalloc<int64_t>(G);
-    int64_t* off = dalloc<int64_t>(G);
+    int32_t* cin = talloc<int32_t>(G);
+    int32_t* cout = talloc<int32_t>(G);
+    int32_t* crisk = talloc<int32_t>(G);
+    const double kscale = c.sqrt_k * c.sqrt_k;
+    int64_t* use = talloc<int64_t>(G);
+    int64_t* len = talloc<int64_t>(G);
+    int64_t* off = talloc<int64_t>(G);
     const unsigned nblk = (unsigned)ceil_div(G, 4);
     hipLaunchKernelGGL(k_lists<false>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use,
-                       (uint32_t*)nullptr);
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, kscale, cin, cout, crisk,
+                       use, (uint32_t*)nullptr);
     RBF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
     RBF_HIP(hipGetLastError());
@@ -883,20 +947,20 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     RBF_HIP(hipMemcpyAsync(&ts.useful, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
     ts.list_entries = last_off + last_len;
-    ts.list = dalloc<uint32_t>(ts.list_entries);
+    ts.list = set_alloc<uint32_t>(ts, ts.list_entries);
     ts.owned.push_back(ts.list);
     hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use, ts.list);
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, kscale, cin, cout, crisk,
+                       use, ts.list);
     RBF_HIP(hipGetLastError());
-    RBF_HIP(hipStreamSynchronize(s));
-    dfree(cin); dfree(cout); dfree(use); dfree(len); dfree(off);
+    temp_free(cin); temp_free(cout); temp_free(crisk); temp_free(use); temp_free(len); temp_free(off);
   }
   hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(kThreads), 0, s, ts.groups, G, tmpd);
   RBF_HIP(hipGetLastError());
   RBF_HIP(hipMemcpyAsync(&ts.max_radius, tmpd, sizeof(double), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
-  dfree(tmp);
-  dfree(tmpd);
+  temp_free(tmp);
+  temp_free(tmpd);
 }
 
 void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s) {
@@ -909,60 +973,62 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s)
     gd.nb[d] = ceil_div(g.dims[d], bs[d]);
   }
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
+  ts.temp = true;
   int64_t* ids = nullptr;
   int64_t nact = nbricks;
   ts.dense = !std::isfinite(c.cutoff);
   if (!ts.dense) {
-    int64_t* mark = dalloc<int64_t>(nbricks);
-    int64_t* pos = dalloc<int64_t>(nbricks);
+    int64_t* mark = talloc<int64_t>(nbricks);
+    int64_t* pos = talloc<int64_t>(nbricks);
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
     hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
                        c.cutoff, gd, mark);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(mark, pos, nbricks, s);
     int64_t last_pos = 0, last_mark = 0;
-    RBF_HIP(hipMemcpy(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
-    RBF_HIP(hipMemcpy(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost));
+    RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
     nact = last_pos + last_mark;
-    ids = dalloc<int64_t>(nact);
+    ids = talloc<int64_t>(nact);
     hipLaunchKernelGGL(k_compact, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, pos, nbricks, ids);
     RBF_HIP(hipGetLastError());
-    RBF_HIP(hipStreamSynchronize(s));
-    dfree(mark);
-    dfree(pos);
+    temp_free(mark);
+    temp_free(pos);
   }
   ts.n_groups = nact;
-  ts.pts = dalloc<double4>(nact * kGroup);
-  ts.index = dalloc<int64_t>(nact * kGroup);
+  ts.pts = set_alloc<double4>(ts, nact * kGroup);
+  ts.index = set_alloc<int64_t>(ts, nact * kGroup);
   ts.owned.push_back(ts.index);
   if (nact > 0) {
     hipLaunchKernelGGL(k_brick_targets, dim3(grid_for(nact * kGroup)), dim3(kThreads), 0, s, ids, nact, gd, ts.pts,
                        ts.index);
     RBF_HIP(hipGetLastError());
-    int64_t* cnt = dalloc<int64_t>(1);
+    int64_t* cnt = talloc<int64_t>(1);
     RBF_HIP(hipMemsetAsync(cnt, 0, sizeof(int64_t), s));
     const int nbk = (int)std::min<int64_t>(1024, ceil_div(nact * kGroup, kThreads));
     hipLaunchKernelGGL(k_count_valid, dim3(nbk), dim3(kThreads), 0, s, ts.pts, nact * kGroup, cnt);
     RBF_HIP(hipGetLastError());
     RBF_HIP(hipMemcpyAsync(&ts.n_targets, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    dfree(cnt);
+    temp_free(cnt);
     build_lists(c, ts, s);
   }
-  dfree(ids);
+  temp_free(ids);
 }
 
 void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, hipStream_t s) {
-  uint32_t* perm = dalloc<uint32_t>(npts);
-  double4* sp = dalloc<double4>(npts);
+  ts.temp = true;
+  uint32_t* perm = talloc<uint32_t>(npts);
+  double4* sp = talloc<double4>(npts);
   sort_points(pts, npts, c.lat, perm, nullptr, s);
   hipLaunchKernelGGL(k_gather_points, dim3(grid_for(npts)), dim3(kThreads), 0, s, pts, perm, npts, sp);
   RBF_HIP(hipGetLastError());
   ts.dense = !std::isfinite(c.cutoff);
   group_targets(c, sp, perm, npts, ts, s);
   build_lists(c, ts, s);
-  dfree(perm);
-  dfree(sp);
+  temp_free(perm);
+  temp_free(sp);
 }
 
 }  // namespace rbf
