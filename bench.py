@@ -36,6 +36,28 @@ METRIC = "RBF kernel evals/s (% FP32 roofline); solve+grid time to resid 1e-8 vs
 LANE_SLOTS = 256 * 4 * 16 * 2.4e9
 PEAK_PAIRS = LANE_SLOTS / 4.5
 
+# HBM bytes per operator launch of the float32 kernel, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a copy of
+# known size; valid only for the kernel source they were taken on.
+COUNTERS = os.path.join(ROOT, "profiles", "k_pairsum_f32_torus200k_hbm_counters.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1305_5179_amd", "csrc", "pairsum.hip")
+
+
+def measured_traffic():
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None, "no counter summary"
+    text = open(COUNTERS).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_b = re.search(r"operator_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_sha and m_b):
+        return None, "counter summary unreadable"
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if sha != m_sha.group(1):
+        return None, "kernel changed since the counters were taken"
+    return float(m_b.group(1)), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -158,18 +180,25 @@ def main():
     value = useful_step * args.steps / dt
     ms_step = 1e3 * dt / args.steps
 
-    # dominant kernel: the float32 pair sum (operator and grid launches)
-    f32_ms = prof.kernel_ms[0]
-    f32_launch = prof.launches[0]
-    achieved = prof.useful_pairs[0] / (f32_ms * 1e-3)
+    # dominant kernel: the float32 pair sum, operator launches (the GMRES cycle)
+    OP, EV, F32, F64 = 0, 1, 0, 1
+    f32_ms = prof.kernel_ms[OP][F32]
+    f32_launch = prof.launches[OP][F32]
+    achieved = prof.useful_pairs[OP][F32] / (f32_ms * 1e-3)
+    traffic, traffic_src = measured_traffic()
     roofline = {
-        "bound": "alu", "kernel": "k_pairsum_f32",
+        "bound": "alu", "kernel": "k_pairsum_f32 (operator launches)",
         "achieved": achieved / 1e9, "peak": PEAK_PAIRS / 1e9, "unit": "Gpair/s",
-        "frac": achieved / PEAK_PAIRS, "traffic": None,
+        "frac": achieved / PEAK_PAIRS, "traffic": traffic, "traffic_unit": "bytes/launch",
+        "traffic_source": traffic_src,
         "launches": f32_launch, "avg_launch_ms": f32_ms / max(f32_launch, 1),
-        "examined_per_useful": prof.examined_pairs[0] / max(prof.useful_pairs[0], 1),
-        "examined_rate": prof.examined_pairs[0] / (f32_ms * 1e-3) / 1e9,
+        "useful_pairs_per_launch": prof.useful_pairs[OP][F32] / max(f32_launch, 1),
+        "examined_per_useful": prof.examined_pairs[OP][F32] / max(prof.useful_pairs[OP][F32], 1),
+        "examined_rate": prof.examined_pairs[OP][F32] / (f32_ms * 1e-3) / 1e9,
     }
+    ev_ms = prof.kernel_ms[EV][F32]
+    evaluation = {"launches": prof.launches[EV][F32], "avg_launch_ms": ev_ms / max(prof.launches[EV][F32], 1),
+                  "useful_rate": prof.useful_pairs[EV][F32] / max(ev_ms * 1e-3, 1e-30) / 1e9}
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -183,8 +212,10 @@ def main():
         "pairs": {"operator_useful": st.useful_pairs, "operator_examined": st.examined_pairs,
                   "grid_useful": grid_useful, "grid_examined": grid_examined,
                   "applications_per_step": applications},
-        "fp64_kernel": {"launches": prof.launches[1], "avg_launch_ms": prof.kernel_ms[1] / max(prof.launches[1], 1),
-                        "useful_rate": prof.useful_pairs[1] / max(prof.kernel_ms[1] * 1e-3, 1e-30) / 1e9},
+        "grid_kernel_f32": evaluation,
+        "fp64_kernel": {"launches": prof.launches[OP][F64],
+                        "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
+                        "useful_rate": prof.useful_pairs[OP][F64] / max(prof.kernel_ms[OP][F64] * 1e-3, 1e-30) / 1e9},
     }
     if args.calibrate:
         src = torch.ones(1 << 25, dtype=torch.float64, device=dev)   # 256 MiB
@@ -202,23 +233,34 @@ def main():
 
 
 def solve_comparison(rbf, pts, nrm, cfg, g, iters):
-    """Chosen pipeline (float32 operator + float64 refinement) and the plain
-    float64 method, each timed from setup to grid; compared at the lowest
-    residual both reach."""
+    """Chosen pipeline (float32 operator + float64 refinement) against the plain
+    float64 method, each from setup to grid.  When either stops above 1e-8,
+    both are compared at the lowest residual both reach (the common
+    residual): time to it = setup + solve up to that residual + grid."""
     import torch
     res = {}
     for name, mode in (("ir_fp32", rbf.RBF_SOLVE_IR_FP32), ("plain_fp64", rbf.RBF_SOLVE_PLAIN_FP64)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rbf.Rbf(pts, nrm, cfg["eps"], cfg["sigma"], cfg["cutoff"])
-        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode)
-        ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32 if mode else rbf.RBF_FP64,
-                      out=torch.empty(g.size, dtype=torch.float32 if mode else torch.float64, device="cuda"))
         torch.cuda.synchronize()
-        res[name] = {"seconds": time.perf_counter() - t0, "status": info.status, "iters": info.iters,
-                     "rel_resid": info.rel_resid, "history": info.history}
+        setup_ms = 1e3 * (time.perf_counter() - t0)
+        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode)
+        t1 = time.perf_counter()
+        prec = rbf.RBF_FP32 if mode == rbf.RBF_SOLVE_IR_FP32 else rbf.RBF_FP64
+        out = torch.empty(g.size, dtype=torch.float32 if prec == rbf.RBF_FP32 else torch.float64, device="cuda")
+        ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=prec, out=out)
+        torch.cuda.synchronize()
+        grid_ms = 1e3 * (time.perf_counter() - t1)
+        res[name] = {"setup_ms": setup_ms, "grid_ms": grid_ms, "status": info.status, "iters": info.iters,
+                     "rel_resid": info.rel_resid, "history": info.history, "history_ms": info.history_ms}
         ctx.close()
-    return res
+    common = max(min(res["ir_fp32"]["history"]), min(res["plain_fp64"]["history"]), 1e-8)
+    for r in res.values():
+        t = next(ms for h, ms in zip(r["history"], r["history_ms"]) if h <= common)
+        r["ms_to_common"] = r["setup_ms"] + t + r["grid_ms"]
+    return {"target": 1e-8, "common_resid": common,
+            "speedup_at_common": res["plain_fp64"]["ms_to_common"] / res["ir_fp32"]["ms_to_common"], **res}
 
 
 if __name__ == "__main__":

@@ -76,6 +76,8 @@ typedef struct {
     const double* history;   /* host array: true relative residual at the start of each outer
                                 step and at the end; owned by the context, valid until the next
                                 call on it */
+    const double* history_ms;  /* host array, same length: milliseconds since the call began
+                                  when each history entry was known */
 } rbf_solve_info;
 
 typedef struct {
@@ -154,15 +156,16 @@ int rbf_count_grid_pairs(rbf_ctx* ctx, const rbf_grid* grid, int64_t* useful,
 
 /* Kernel timing for measurement tools (process-wide, off by default).
  * Between rbf_profile_begin() and rbf_profile_end() every pair-sum kernel
- * launch (operator, grid or point evaluation) is bracketed by HIP events on
- * the stream it runs on; rbf_profile_end() waits for them and reports, per
+ * launch is bracketed by HIP events on the stream it runs on;
+ * rbf_profile_end() waits for them and reports, per launch kind (operator
+ * = rbf_matvec and the solves, evaluation = grid and point evaluation) and
  * precision, the launches, their summed device time and the pairs they
  * evaluated.  Not thread-safe; adds two event records per launch. */
 typedef struct {
-    int64_t launches[2];        /* [RBF_FP32], [RBF_FP64] */
-    double kernel_ms[2];        /* summed event-to-event time of those launches */
-    int64_t useful_pairs[2];    /* pairs with r^2 <= cutoff^2 they evaluated */
-    int64_t examined_pairs[2];  /* pairs they computed (list entries x 16) */
+    int64_t launches[2][2];        /* [kind: 0 operator, 1 evaluation][RBF_FP32 / RBF_FP64] */
+    double kernel_ms[2][2];        /* summed event-to-event time of those launches */
+    int64_t useful_pairs[2][2];    /* pairs with r^2 <= cutoff^2 they evaluated */
+    int64_t examined_pairs[2][2];  /* pairs they computed (list entries x 16) */
 } rbf_profile;
 
 int rbf_profile_begin(void);

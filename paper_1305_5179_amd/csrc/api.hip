@@ -1,6 +1,7 @@
 // C ABI of librbf (declared in include/rbf.h): argument checks, the setup
 // pipeline, the operator, the GMRES driver and the evaluation entry points.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <limits>
 
@@ -351,6 +352,13 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
     double bnorm, gk;
     gm_read(c->state, &k, &done, &bd, &bnorm, &gk, s);
     c->history.clear();
+    c->history_ms.clear();
+    const auto t_start = std::chrono::steady_clock::now();
+    auto stamp = [&](double rel) {
+      c->history.push_back(rel);
+      c->history_ms.push_back(
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count());
+    };
     int iters = 0, outer = 0, status = RBF_ENOCONV;
     double rel = 0.0;
     if (!std::isfinite(bnorm)) {
@@ -358,7 +366,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
     } else if (bnorm == 0.0) {
       fill_f64(c->csol, 0.0, c->mpad, s);
       rel = 0.0;
-      c->history.push_back(0.0);
+      stamp(0.0);
       status = RBF_OK;
     } else {
       for (;;) {
@@ -372,7 +380,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         double beta;
         gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
         rel = beta / bnorm;
-        c->history.push_back(rel);
+        stamp(rel);
         if (!std::isfinite(rel)) {
           status = RBF_EBREAKDOWN;
           break;
@@ -403,7 +411,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
           gm_start(c->bsort, c->vout, c->r, m, c->V, c->partial, o.restart, 0.0, c->state, s);
           gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
           rel = beta / bnorm;
-          c->history.push_back(rel);
+          stamp(rel);
           break;
         }
         if (k == 0 && steps > 0) {
@@ -422,6 +430,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
       info->status = status;
       info->n_history = (int)c->history.size();
       info->history = c->history.data();
+      info->history_ms = c->history_ms.data();
     }
     if (status == RBF_ENOCONV) c->err = "solve stopped at its iteration limit";
     if (status == RBF_EBREAKDOWN) c->err = "non-finite value in the solve";

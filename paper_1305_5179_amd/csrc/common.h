@@ -73,6 +73,7 @@ struct TargetSet {
   double max_radius = 0.0;
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
   bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
+  int kind = 0;             // 0: the centres (operator), 1: evaluation targets
   std::vector<void*> owned; // device allocations to free with the set
 };
 
@@ -125,6 +126,7 @@ struct Ctx {
   int64_t partial_cap = 0;
   void* state = nullptr;        // device GMRES state
   std::vector<double> history;
+  std::vector<double> history_ms;
   std::string err;
 };
 

@@ -139,29 +139,48 @@ __global__ __launch_bounds__(kVecThreads) void k_update_norm(const double* __res
   block_store(s, 1, partial);
 }
 
-// Sum the block partials of columns 0..ncols-1 in block order.
-__device__ __forceinline__ double fold_partials(const double* partial, int nb, int i) {
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * (kMaxRestart + 1) + i];
-  return s;
+// Sum of the block partials of one column by a whole block: thread t adds
+// partials t, t+256, ... in order, then a fixed tree adds the 256 sums, so
+// the result does not depend on scheduling.  Every thread gets the sum.
+__device__ double block_fold(const double* __restrict__ partial, int nb, int col) {
+  __shared__ double s[kVecThreads];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int b = t; b < nb; b += kVecThreads) acc += partial[(int64_t)b * (kMaxRestart + 1) + col];
+  s[t] = acc;
+  __syncthreads();
+  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
+    if (t < w) s[t] += s[t + w];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
 }
 
-__global__ void k_reduce_h1(const double* __restrict__ partial, int nb, int ncols, GmState* __restrict__ st) {
+// one block per column
+__global__ __launch_bounds__(kVecThreads) void k_reduce_h1(const double* __restrict__ partial, int nb,
+                                                           GmState* __restrict__ st) {
   if (st->done) return;
-  for (int i = threadIdx.x; i < ncols; i += blockDim.x) st->h1[i] = fold_partials(partial, nb, i);
+  const double v = block_fold(partial, nb, blockIdx.x);
+  if (threadIdx.x == 0) st->h1[blockIdx.x] = v;
 }
-__global__ void k_reduce_h2(const double* __restrict__ partial, int nb, int ncols, GmState* __restrict__ st) {
+__global__ __launch_bounds__(kVecThreads) void k_reduce_h2(const double* __restrict__ partial, int nb,
+                                                           GmState* __restrict__ st) {
   if (st->done) return;
-  for (int i = threadIdx.x; i < ncols; i += blockDim.x) st->h2[i] = fold_partials(partial, nb, i);
+  const double v = block_fold(partial, nb, blockIdx.x);
+  if (threadIdx.x == 0) st->h2[blockIdx.x] = v;
 }
 
 // Column j of the Hessenberg matrix, its Givens rotations and the residual
 // estimate |g_{j+1}|.
-__global__ void k_finish_step(const double* __restrict__ partial, int nb, int j, GmState* __restrict__ st) {
-  if (threadIdx.x != 0 || st->done) return;
+__global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __restrict__ partial, int nb, int j,
+                                                             GmState* __restrict__ st) {
+  if (st->done) return;
+  const double beta = sqrt(block_fold(partial, nb, 0));
+  if (threadIdx.x != 0) return;
   const int ld = kMaxRestart + 1;
   double* Hc = st->H + (int64_t)j * ld;
-  const double beta = sqrt(fold_partials(partial, nb, 0));
   for (int i = 0; i <= j; ++i) Hc[i] = st->h1[i] + st->h2[i];
   Hc[j + 1] = beta;
   for (int i = 0; i < j; ++i) {
@@ -223,10 +242,10 @@ __global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restri
   block_store(s, 1, partial);
 }
 
-__global__ void k_start_cycle(const double* __restrict__ partial, int nb, int m, double tol_abs,
-                              GmState* __restrict__ st) {
+__global__ __launch_bounds__(kVecThreads) void k_start_cycle(const double* __restrict__ partial, int nb, int m,
+                                                             double tol_abs, GmState* __restrict__ st) {
+  const double beta = sqrt(block_fold(partial, nb, 0));
   if (threadIdx.x != 0) return;
-  const double beta = sqrt(fold_partials(partial, nb, 0));
   st->m = m;
   st->k = 0;
   st->tol_abs = tol_abs;
@@ -300,7 +319,7 @@ void gm_start(const double* b, const double* y, double* r, int64_t n, double* V,
   GmState* st = static_cast<GmState*>(state);
   const unsigned nb = vec_blocks(n);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kVecThreads), 0, s, b, y, r, n, partial);
-  hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(64), 0, s, partial, (int)nb, m, tol_abs, st);
+  hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, m, tol_abs, st);
   hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, r, n, st, V);
   RBF_HIP(hipGetLastError());
 }
@@ -311,11 +330,11 @@ void gm_step(double* V, int64_t ldv, double* w, int64_t n, int j, double* partia
   const unsigned nb = vec_blocks(n);
   const int ncols = j + 1;
   hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
-  hipLaunchKernelGGL(k_reduce_h1, dim3(1), dim3(64), 0, s, partial, (int)nb, ncols, st);
+  hipLaunchKernelGGL(k_reduce_h1, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
   hipLaunchKernelGGL(k_update_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
-  hipLaunchKernelGGL(k_reduce_h2, dim3(1), dim3(64), 0, s, partial, (int)nb, ncols, st);
+  hipLaunchKernelGGL(k_reduce_h2, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
   hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
-  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(64), 0, s, partial, (int)nb, j, st);
+  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, j, st);
   hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, w, n, st, V + (int64_t)(j + 1) * ldv);
   RBF_HIP(hipGetLastError());
 }

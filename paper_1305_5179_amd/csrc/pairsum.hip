@@ -284,7 +284,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
 // Launch timing (rbf_profile_begin / rbf_profile_end).
 struct ProfRec {
   hipEvent_t a, b;
-  int prec;
+  int kind, prec;
   int64_t useful, examined;
 };
 struct Profiler {
@@ -303,6 +303,7 @@ struct ProfScope {
   ProfScope(int prec, const TargetSet& ts, hipStream_t st) : on(profiler().on), s(st) {
     if (!on) return;
     rec.prec = prec;
+    rec.kind = ts.kind;
     rec.useful = ts.useful;
     rec.examined = ts.list_entries * kGroup;
     RBF_HIP(hipEventCreate(&rec.a));
@@ -337,10 +338,10 @@ int profile_end(rbf_profile* out) {
     RBF_HIP(hipEventSynchronize(q.b));
     float ms = 0.f;
     RBF_HIP(hipEventElapsedTime(&ms, q.a, q.b));
-    r.launches[q.prec] += 1;
-    r.kernel_ms[q.prec] += ms;
-    r.useful_pairs[q.prec] += q.useful;
-    r.examined_pairs[q.prec] += q.examined;
+    r.launches[q.kind][q.prec] += 1;
+    r.kernel_ms[q.kind][q.prec] += ms;
+    r.useful_pairs[q.kind][q.prec] += q.useful;
+    r.examined_pairs[q.kind][q.prec] += q.examined;
     (void)hipEventDestroy(q.a);
     (void)hipEventDestroy(q.b);
   }

@@ -974,6 +974,7 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s)
   }
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
   ts.temp = true;
+  ts.kind = 1;
   int64_t* ids = nullptr;
   int64_t nact = nbricks;
   ts.dense = !std::isfinite(c.cutoff);
@@ -1019,6 +1020,7 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s)
 
 void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, hipStream_t s) {
   ts.temp = true;
+  ts.kind = 1;
   uint32_t* perm = talloc<uint32_t>(npts);
   double4* sp = talloc<double4>(npts);
   sort_points(pts, npts, c.lat, perm, nullptr, s);

@@ -34,7 +34,8 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("rel_resid", C.c_double), ("status", C.c_int),
-                ("n_history", C.c_int), ("history", C.POINTER(C.c_double))]
+                ("n_history", C.c_int), ("history", C.POINTER(C.c_double)),
+                ("history_ms", C.POINTER(C.c_double))]
 
 
 class Grid(C.Structure):
@@ -49,8 +50,9 @@ class Stats(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 2), ("kernel_ms", C.c_double * 2),
-                ("useful_pairs", C.c_int64 * 2), ("examined_pairs", C.c_int64 * 2)]
+    """Arrays indexed [kind][prec]: kind 0 = operator, 1 = evaluation."""
+    _fields_ = [("launches", (C.c_int64 * 2) * 2), ("kernel_ms", (C.c_double * 2) * 2),
+                ("useful_pairs", (C.c_int64 * 2) * 2), ("examined_pairs", (C.c_int64 * 2) * 2)]
 
 
 class RbfError(RuntimeError):
@@ -131,6 +133,7 @@ class SolveResult:
     outer: int
     rel_resid: float
     history: list
+    history_ms: list
 
 
 def _stream():
@@ -205,7 +208,8 @@ class Rbf:
         if st not in (RBF_OK, RBF_ENOCONV):
             raise RbfError(st, self._lib.rbf_last_error(self.ctx).decode())
         hist = [info.history[i] for i in range(info.n_history)]
-        return c, SolveResult(st, info.iters, info.outer, info.rel_resid, hist)
+        hms = [info.history_ms[i] for i in range(info.n_history)]
+        return c, SolveResult(st, info.iters, info.outer, info.rel_resid, hist, hms)
 
     def eval_grid(self, c, origin, h, dims, prec: int = RBF_FP32, out=None):
         import torch
