@@ -344,17 +344,76 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Source lists.  One wave per group of 16 targets.  Candidate sources are
-// the centres of the coarse cells that the group's box, grown by the cutoff,
-// touches; each candidate is classified in float64 against every valid
-// target of the group with the exact truncation test r^2 <= r_c^2:
-//   inside for all targets  -> "inner" part of the list (no test needed later)
-//   inside for some targets -> "outer" part (the pair kernels test it)
+// Source lists.  One wave per group of 16 targets, anchor a (centre of their
+// bounding box) and radius R (largest distance of a target from a).  Every
+// source s of a coarse cell near the group is classified against the exact
+// float64 truncation test r^2 <= r_c^2 of every valid target:
+//   inside for all targets  -> "inner" (the pair kernels skip the test)
+//   inside for some targets -> "outer", split into "safe" and "risky" (a pair
+//                              within twice the float32 error band of the
+//                              cutoff: the float32 kernel checks those pairs)
 //   inside for none         -> dropped.
+// By the triangle inequality |s - a| + R <= r_c (1 - 1e-12) makes s inner
+// and |s - a| - R > r_c (1 + 1e-12) drops it, without looking at the
+// targets (the relative margin covers the float64 rounding of the distances
+// and of the exact test), whole cells at a time when the cell box allows.
+// The remaining "shell" sources are queued in LDS and tested exactly, four
+// per step: lane l holds target l mod 16, row r of the wave takes the r-th
+// source, and the row's ballot gives the source's inside count.
 // Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
 // list order is deterministic.  Lists are padded to whole chunks with the
 // padding source m.
 // ---------------------------------------------------------------------------
+struct ListCounts {
+  int64_t n_in, n_out, n_risk, use;
+};
+
+template <bool WRITE>
+__device__ __forceinline__ void emit(uint32_t* list, int64_t base, int64_t n, uint64_t mask, bool mine, uint32_t k) {
+  if (WRITE && mine) list[base + n + lanes_below(mask)] = k;
+}
+
+// Exact test of the first `cnt` queued shell sources.
+template <bool WRITE>
+__device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const double4* __restrict__ xs,
+                                              const double4& tme, bool tvalid, int nvalid, double rc2, double kscale,
+                                              double Tk, double risk, int64_t wb_in, int64_t wb_out,
+                                              int64_t wb_risk, uint32_t* __restrict__ list, ListCounts& n) {
+  const int lane = threadIdx.x & 63, row = lane >> 4;
+  for (int i0 = 0; i0 < cnt; i0 += 4) {
+    const bool svalid = i0 + row < cnt;
+    const uint32_t k = svalid ? q[i0 + row] : 0u;
+    bool inside = false, near = false;
+    if (svalid) {
+      const double4 s = xs[k];
+      const double dx = tme.x - s.x, dy = tme.y - s.y, dz = tme.z - s.z;
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      inside = tvalid && r2 <= rc2;
+      near = tvalid && fabs(r2 * kscale - Tk) <= risk;
+    }
+    const uint64_t mi = ballot(inside), mn = ballot(near);
+    // classify the four rows (wave-uniform), in row order
+    int64_t pos_row = -1;
+    for (int rr = 0; rr < 4; ++rr) {
+      if (i0 + rr >= cnt) break;
+      const int c = __popcll((mi >> (16 * rr)) & 0xffffull);
+      const bool nr = ((mn >> (16 * rr)) & 0xffffull) != 0;
+      int64_t p = -1;
+      if (c == nvalid) {
+        p = wb_in + n.n_in++;
+      } else if (c > 0) {
+        if (nr)
+          p = wb_risk + n.n_risk++;
+        else
+          p = wb_out + n.n_out++;
+      }
+      n.use += c;
+      if (row == rr) pos_row = p;
+    }
+    if (WRITE && (lane & 15) == 0 && svalid && pos_row >= 0) list[pos_row] = k;
+  }
+}
+
 template <bool WRITE>
 __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
                                                     const double4* __restrict__ xs, int64_t m,
@@ -363,19 +422,19 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
                                                     double kscale, int32_t* __restrict__ cnt_in,
                                                     int32_t* __restrict__ cnt_out, int32_t* __restrict__ cnt_risk,
                                                     int64_t* __restrict__ useful, uint32_t* __restrict__ list) {
-  __shared__ double4 tg[4][kGroup];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ uint32_t qbuf[kThreads / kWave][2 * kWave];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= G) return;
-  if (lane < kGroup) tg[wave][lane] = tpts[g * kGroup + lane];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
+  uint32_t* q = qbuf[wave];
+  // this lane's target (lane mod 16) and the group's box, anchor and radius
+  const double4 tme = tpts[g * kGroup + (lane & 15)];
+  const bool tvalid = tme.w != 0.0;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int nvalid = 0;
   for (int l = 0; l < kGroup; ++l) {
-    double4 t = tg[wave][l];
+    const double4 t = tpts[g * kGroup + l];
     if (t.w != 0.0) {
       ++nvalid;
       lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
@@ -383,124 +442,131 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
     }
   }
-  int64_t wbase_in = 0, wbase_out = 0, wbase_risk = 0;
+  int64_t wb_in = 0, wb_out = 0, wb_risk = 0;
   if (WRITE) {
-    wbase_in = groups[g].off;
-    wbase_out = wbase_in + cnt_in[g];
-    wbase_risk = wbase_out + cnt_out[g];
+    wb_in = groups[g].off;
+    wb_out = wb_in + cnt_in[g];
+    wb_risk = wb_out + cnt_out[g];
   }
   if (nvalid == 0) {
-    if (!WRITE) {
-      if (lane == 0) {
-        cnt_in[g] = 0;
-        cnt_out[g] = 0;
-        cnt_risk[g] = 0;
-        useful[g] = 0;
-        GroupInfo gi;
-        gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0; gi.first_risky = 0; gi.pad_ = 0;
-        gi.ax = gi.ay = gi.az = 0.0;
-        gi.radius = 0.0;
-        groups[g] = gi;
-      }
+    if (!WRITE && lane == 0) {
+      cnt_in[g] = 0;
+      cnt_out[g] = 0;
+      cnt_risk[g] = 0;
+      useful[g] = 0;
+      GroupInfo gi;
+      gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0; gi.first_risky = 0; gi.pad_ = 0;
+      gi.ax = gi.ay = gi.az = 0.0;
+      gi.radius = 0.0;
+      groups[g] = gi;
     }
     return;
   }
   const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]), az = 0.5 * (lo[2] + hi[2]);
   double rad = 0.0;
   for (int l = 0; l < kGroup; ++l) {
-    double4 t = tg[wave][l];
+    const double4 t = tpts[g * kGroup + l];
     if (t.w != 0.0) {
-      double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
+      const double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
       rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
     }
   }
-  // scaled cutoff and twice the float32 band of this group (risky sources)
   const double Tk = rc2 * kscale;
   const double risk = isfinite(Tk) ? 2.0 * f32_cutoff_band(Tk, rad * sqrt(kscale)) : -1.0;
+  const double r_in = rc * (1.0 - 1e-12) - rad;   // |s - a| <= r_in: inside for every target
+  const double r_out = rc * (1.0 + 1e-12) + rad;  // |s - a| >  r_out: inside for none
+  const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
+  const double r_out2 = r_out * r_out;
 
   int cl[3], ch[3];
-  const bool finite_rc = isfinite(rc);
+  const double ac[3] = {ax, ay, az};
   for (int d = 0; d < 3; ++d) {
-    if (finite_rc) {
-      double a = floor((lo[d] - rc - lat.origin[d]) / lat.coarse) - 1.0;
-      double b = floor((hi[d] + rc - lat.origin[d]) / lat.coarse) + 1.0;
-      cl[d] = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
-      ch[d] = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
-    } else {
-      cl[d] = 0;
-      ch[d] = lat.cdims[d] - 1;
-    }
+    const double a = floor((ac[d] - r_out - lat.origin[d]) / lat.coarse) - 1.0;
+    const double b = floor((ac[d] + r_out - lat.origin[d]) / lat.coarse) + 1.0;
+    cl[d] = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
+    ch[d] = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
   }
-  const double box_slack = rc2 * (1.0 + 1e-9) + 1e-300;
-  int64_t n_in = 0, n_out = 0, n_risk = 0, use = 0;
+  ListCounts n{0, 0, 0, 0};
+  int qn = 0;
   for (int cz = cl[2]; cz <= ch[2]; ++cz)
     for (int cy = cl[1]; cy <= ch[1]; ++cy)
       for (int cx = cl[0]; cx <= ch[0]; ++cx) {
-        int32_t cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
+        const int32_t cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
         if (cid < 0) continue;
-        if (finite_rc) {
-          double bl[3] = {lat.origin[0] + cx * lat.coarse, lat.origin[1] + cy * lat.coarse, lat.origin[2] + cz * lat.coarse};
-          double gsum = 0.0;
-          for (int d = 0; d < 3; ++d) {
-            double gap = fmax(0.0, fmax(bl[d] - hi[d], lo[d] - (bl[d] + lat.coarse)));
-            gsum += gap * gap;
-          }
-          if (gsum > box_slack) continue;
+        // nearest and farthest points of the cell box from the anchor
+        const int cc[3] = {cx, cy, cz};
+        double dmin2 = 0.0, dmax2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double b0 = lat.origin[d] + cc[d] * lat.coarse, b1 = b0 + lat.coarse;
+          const double gap = fmax(0.0, fmax(b0 - ac[d], ac[d] - b1));
+          const double far = fmax(fabs(ac[d] - b0), fabs(ac[d] - b1));
+          dmin2 += gap * gap;
+          dmax2 += far * far;
         }
+        if (dmin2 > r_out2 * (1.0 + 1e-9)) continue;
+        const bool cell_inner = dmax2 * (1.0 + 1e-9) <= r_in2;
         const int32_t st = cstart[cid], ct = ccount[cid];
         for (int b0 = 0; b0 < ct; b0 += kWave) {
           const bool valid = b0 + lane < ct;
-          const int64_t k = (int64_t)st + b0 + lane;
-          int inside = 0;
-          bool near_cut = false;
+          const uint32_t k = (uint32_t)(st + b0 + lane);
+          bool is_in = false, is_shell = false;
           if (valid) {
-            double4 s = xs[k];
-            for (int l = 0; l < kGroup; ++l) {
-              double4 t = tg[wave][l];
-              double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
-              double r2 = (dx * dx + dy * dy) + dz * dz;
-              inside += (t.w != 0.0 && r2 <= rc2) ? 1 : 0;
-              near_cut = near_cut || (t.w != 0.0 && fabs(r2 * kscale - Tk) <= risk);
+            if (cell_inner) {
+              is_in = true;
+            } else {
+              const double4 s = xs[k];
+              const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
+              const double d2 = (dx * dx + dy * dy) + dz * dz;
+              is_in = d2 <= r_in2;
+              is_shell = !is_in && d2 <= r_out2;
             }
           }
-          const bool is_in = valid && inside == nvalid;
-          const bool is_out = valid && inside > 0 && inside < nvalid;
-          const bool is_risk = is_out && near_cut;
-          const bool is_safe = is_out && !near_cut;
-          const uint64_t mi = ballot(is_in), mo = ballot(is_safe), mr = ballot(is_risk);
-          if (WRITE) {
-            if (is_in) list[wbase_in + n_in + lanes_below(mi)] = (uint32_t)k;
-            if (is_safe) list[wbase_out + n_out + lanes_below(mo)] = (uint32_t)k;
-            if (is_risk) list[wbase_risk + n_risk + lanes_below(mr)] = (uint32_t)k;
+          const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
+          emit<WRITE>(list, wb_in, n.n_in, mi, is_in, k);
+          n.n_in += __popcll(mi);
+          n.use += (int64_t)__popcll(mi) * nvalid;
+          if (is_shell) q[qn + lanes_below(ms)] = k;
+          qn += __popcll(ms);
+          if (qn >= kWave) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            process_shell<WRITE>(q, kWave, xs, tme, tvalid, nvalid, rc2, kscale, Tk, risk, wb_in, wb_out, wb_risk,
+                                 list, n);
+            const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane + kWave < qn) q[lane] = rest;
+            qn -= kWave;
           }
-          n_in += __popcll(mi);
-          n_out += __popcll(mo);
-          n_risk += __popcll(mr);
-          use += inside;
         }
       }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (qn > 0)
+    process_shell<WRITE>(q, qn, xs, tme, tvalid, nvalid, rc2, kscale, Tk, risk, wb_in, wb_out, wb_risk, list, n);
   if (!WRITE) {
-    // wave sum of the useful-pair counts
-    for (int off = 32; off > 0; off >>= 1) use += __shfl_xor(use, off);
     if (lane == 0) {
-      cnt_in[g] = (int32_t)n_in;
-      cnt_out[g] = (int32_t)n_out;
-      cnt_risk[g] = (int32_t)n_risk;
-      useful[g] = use;
+      cnt_in[g] = (int32_t)n.n_in;
+      cnt_out[g] = (int32_t)n.n_out;
+      cnt_risk[g] = (int32_t)n.n_risk;
+      useful[g] = n.use;
       GroupInfo gi;
       gi.off = 0;
-      gi.n_chunks = (int32_t)ceil_div(n_in + n_out + n_risk, kChunk);
-      gi.n_inner = (int32_t)(n_in / kChunk);
-      gi.first_risky = n_risk > 0 ? (int32_t)((n_in + n_out) / kChunk) : gi.n_chunks;
+      gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out + n.n_risk, kChunk);
+      gi.n_inner = (int32_t)(n.n_in / kChunk);
+      gi.first_risky = n.n_risk > 0 ? (int32_t)((n.n_in + n.n_out) / kChunk) : gi.n_chunks;
       gi.pad_ = 0;
       gi.ax = ax; gi.ay = ay; gi.az = az;
       gi.radius = rad;
       groups[g] = gi;
     }
   } else {
-    const int64_t total = n_in + n_out + n_risk;
+    const int64_t total = n.n_in + n.n_out + n.n_risk;
     const int64_t padded = round_up(total, kChunk);
-    for (int64_t e = total + lane; e < padded; e += kWave) list[wbase_in + e] = (uint32_t)m;
+    for (int64_t e = total + lane; e < padded; e += kWave) list[wb_in + e] = (uint32_t)m;
   }
 }
 

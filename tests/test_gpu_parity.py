@@ -95,6 +95,14 @@ def test_centres_equal_oracle(case, torch):
     np.testing.assert_array_equal(host(bg), case["b"])
 
 
+def test_pair_count_equals_oracle_nonzeros(case):
+    """The lists hold every pair inside the cutoff exactly once."""
+    st = case["ctx"].stats()
+    A = o.interpolation_matrix(case["X"], case["sigma"], case["cutoff"])
+    assert st.useful_pairs == np.count_nonzero(A)
+    assert st.examined_pairs >= st.useful_pairs
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_operator_matches_oracle(case, torch, R, prec):
     X, sigma, cutoff = case["X"], case["sigma"], case["cutoff"]
