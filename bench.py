@@ -62,6 +62,9 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["torus", "metaballs"], default="torus",
+                    help="torus: 200k points / 600k centres (default); metaballs: 2M points / 6M centres, "
+                         "hole and noise, 512^3 grid")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -111,8 +114,17 @@ def main():
     from paper_1305_5179_amd import rbf
     from paper_1305_5179_amd import workloads as w
 
-    cfg = w.TORUS_200K
-    cloud = w.torus(cfg["n"], cfg["seed"])
+    if args.workload == "torus":
+        cfg = w.TORUS_200K
+        cloud = w.torus(cfg["n"], cfg["seed"])
+        wl_name = ("torus R=1 r=0.35, 200000 points, 600000 centres, sigma 0.02, cutoff 0.08; "
+                   "setup + IR-GMRES(30) cycle (float32 operator) + float64 residual + 256^3 grid")
+    else:
+        cfg = w.METABALLS_2M
+        cloud = w.metaballs(cfg["n"], cfg["seed"])
+        wl_name = ("12 Gaussian metaballs with a hole and N(0,1e-3) noise, 2000000 points, 6000000 centres, "
+                   "sigma 0.01, cutoff 0.04; setup + IR-GMRES(30) cycle (float32 operator) + float64 residual "
+                   "+ 512^3 grid")
     eps, sigma, cutoff, restart = cfg["eps"], cfg["sigma"], cfg["cutoff"], cfg["restart"]
     g = w.Grid.around(cloud.points, cfg["grid_n"])
     dev = torch.device("cuda", 0)
@@ -185,7 +197,7 @@ def main():
     f32_ms = prof.kernel_ms[OP][F32]
     f32_launch = prof.launches[OP][F32]
     achieved = prof.useful_pairs[OP][F32] / (f32_ms * 1e-3)
-    traffic, traffic_src = measured_traffic()
+    traffic, traffic_src = measured_traffic() if args.workload == "torus" else (None, "not measured")
     roofline = {
         "bound": "alu", "kernel": "k_pairsum_f32 (operator launches)",
         "achieved": achieved / 1e9, "peak": PEAK_PAIRS / 1e9, "unit": "Gpair/s",
@@ -203,8 +215,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "torus R=1 r=0.35, 200000 points, 600000 centres, sigma 0.02, cutoff 0.08; "
-                               "setup + IR-GMRES(30) cycle (float32 operator) + float64 residual + 256^3 grid",
+        "config": {"workload": wl_name,
                    "n_points": cfg["n"], "n_centres": 3 * cfg["n"], "sigma": sigma, "cutoff": cutoff,
                    "restart": restart, "grid": list(g.dims)},
         "roofline": roofline,

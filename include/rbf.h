@@ -145,6 +145,19 @@ int rbf_eval_grid(rbf_ctx* ctx, const double* c, const rbf_grid* grid, void* out
 int rbf_eval_points(rbf_ctx* ctx, const double* c, const double* pts, int64_t m,
                     double* out, int prec, void* stream);
 
+/* Density measures of the point cloud the context was built from (Sec. IV,
+ * eqs. sepDist, fillDist, hmax), used by the paper to choose sigma
+ * (sigma ~ 2q, eq. h1; sigma ~ sqrt(2) h, eq. h2; h ~ sqrt(2) h_max):
+ *   q      = 1/2 min_{i != j} |x_i - x_j| over the n cloud points;
+ *   h_max  = max_j min_{i != j} |x_i - x_j|;
+ *   h_fill = max over the `samples` (device, n_samples x 3 float64, points of
+ *            the domain chosen by the caller) of min_j |s - x_j|, the
+ *            sampled fill distance; NaN when samples is NULL.
+ * Exact float64 minima (all pairs).  Any output pointer may be NULL (host
+ * pointers).  Synchronises with `stream`. */
+int rbf_density(rbf_ctx* ctx, const double* samples, int64_t n_samples, double* q, double* h_max,
+                double* h_fill, void* stream);
+
 /* Sizes and pair counts of the context (host call, no device work). */
 int rbf_get_stats(const rbf_ctx* ctx, rbf_stats* stats);
 

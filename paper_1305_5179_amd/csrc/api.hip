@@ -135,19 +135,19 @@ void ensure_solver(Ctx* c, int m) {
   if (c->V && c->krylov_m >= m) return;
   dfree(c->V);
   c->V = dalloc<double>((int64_t)(m + 1) * c->mpad);
-  RBF_HIP(hipMemset(c->V, 0, sizeof(double) * (size_t)(m + 1) * c->mpad));
+  RBF_HIP(hipMemsetAsync(c->V, 0, sizeof(double) * (size_t)(m + 1) * c->mpad, temp_stream()));
   c->krylov_m = m;
   if (!c->w) {
     c->w = dalloc<double>(c->mpad);
     c->r = dalloc<double>(c->mpad);
     c->csol = dalloc<double>(c->mpad);
     c->bsort = dalloc<double>(c->mpad);
-    RBF_HIP(hipMemset(c->w, 0, sizeof(double) * c->mpad));
-    RBF_HIP(hipMemset(c->r, 0, sizeof(double) * c->mpad));
-    RBF_HIP(hipMemset(c->csol, 0, sizeof(double) * c->mpad));
-    RBF_HIP(hipMemset(c->bsort, 0, sizeof(double) * c->mpad));
+    RBF_HIP(hipMemsetAsync(c->w, 0, sizeof(double) * c->mpad, temp_stream()));
+    RBF_HIP(hipMemsetAsync(c->r, 0, sizeof(double) * c->mpad, temp_stream()));
+    RBF_HIP(hipMemsetAsync(c->csol, 0, sizeof(double) * c->mpad, temp_stream()));
+    RBF_HIP(hipMemsetAsync(c->bsort, 0, sizeof(double) * c->mpad, temp_stream()));
     c->state = dalloc<char>((int64_t)gm_state_bytes());
-    RBF_HIP(hipMemset(c->state, 0, gm_state_bytes()));
+    RBF_HIP(hipMemsetAsync(c->state, 0, gm_state_bytes(), temp_stream()));
   }
   const int64_t pc = gm_partial_count(c->m);
   if (c->partial_cap < pc) {
@@ -518,6 +518,18 @@ int rbf_eval_points(rbf_ctx* c, const double* cw, const double* pts, int64_t npt
       pairsum_f64(*c, ts, c->vin, false, out, s);
     RBF_HIP(hipStreamSynchronize(s));
     free_targets(ts);
+    return RBF_OK;
+  });
+}
+
+int rbf_density(rbf_ctx* c, const double* samples, int64_t ns, double* q, double* hmax, double* hfill,
+                void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (ns < 0) return fail(c, RBF_EINVAL, "n_samples must be >= 0");
+  if (samples && ns > 0 && !is_device_ptr(samples)) return fail(c, RBF_EINVAL, "samples must be a device pointer");
+  return guarded(c, [&]() -> int {
+    density_measures(c->xpaper, c->n, samples, samples ? ns : 0, q, hmax, hfill, (hipStream_t)stream);
     return RBF_OK;
   });
 }

@@ -70,7 +70,6 @@ struct TargetSet {
   uint32_t* list = nullptr; // sorted-source indices (M = padding source)
   int64_t list_entries = 0;
   int64_t useful = 0;       // pairs with r^2 <= cutoff^2 (float64 decision)
-  double max_radius = 0.0;
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
   bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
   int kind = 0;             // 0: the centres (operator), 1: evaluation targets
@@ -152,20 +151,6 @@ const char* thread_error();
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
-template <class T>
-T* dalloc(int64_t count) {
-  void* p = nullptr;
-  if (count <= 0) count = 1;
-  hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)count);
-  if (e != hipSuccess)
-    throw Error{e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE,
-                std::string("hipMalloc(") + std::to_string(sizeof(T) * (size_t)count) + " bytes): " +
-                    hipGetErrorString(e)};
-  return static_cast<T*>(p);
-}
-inline void dfree(void* p) {
-  if (p) (void)hipFree(p);
-}
 
 // Temporaries: stream-ordered allocations on the stream of the current API
 // call (set by TempStream), served from the device's memory pool without a
@@ -183,6 +168,14 @@ T* talloc(int64_t count) {
   if (count <= 0) count = 1;
   return static_cast<T*>(temp_alloc_bytes(sizeof(T) * (size_t)count));
 }
+// Context arrays come from the same pool (allocated on the stream of the
+// call that creates them; rbf_setup returns only after that stream is idle,
+// and rbf_destroy waits for the device before returning them).
+template <class T>
+T* dalloc(int64_t count) {
+  return talloc<T>(count);
+}
+inline void dfree(void* p) { temp_free(p); }
 // Arrays of a target set: persistent or stream-ordered as the set asks.
 template <class T>
 T* set_alloc(const TargetSet& ts, int64_t count) {
@@ -217,6 +210,10 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
                  const int* skip = nullptr);
 void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
                  const int* skip = nullptr);
+
+// density.hip
+void density_measures(const double* P, int64_t n, const double* samples, int64_t ns, double* q, double* hmax,
+                      double* hfill, hipStream_t s);
 
 int profile_begin();
 int profile_end(rbf_profile* out);

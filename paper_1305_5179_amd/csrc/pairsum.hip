@@ -182,12 +182,22 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
   const float gh = (float)(f32_cutoff_band(a.Tk, gi.radius * a.sqrt_k) * (double)kH);
   float acc = 0.0f;
   const int nch = gi.n_chunks, nin = gi.n_inner, nrisk = gi.first_risky;
+  // Software pipeline over the chunks: the list index two chunks ahead and
+  // the source gather one chunk ahead are in flight while a chunk computes.
+  uint32_t idx_next = nch > 0 ? list_entry(a, gi, 0, lane) : (uint32_t)a.m;
+  double4 s_next = a.xk[idx_next];
+  double w_next = a.w[idx_next];
+  uint32_t idx_after = nch > 1 ? list_entry(a, gi, 1, lane) : (uint32_t)a.m;
   for (int c = 0; c < nch; ++c) {
-    const uint32_t idx = list_entry(a, gi, c, lane);
-    const double4 s = a.xk[idx];
-    const double wv = a.w[idx];
-    const float sx = (float)(s.x - akx), sy = (float)(s.y - aky), sz = (float)(s.z - akz);
-    const float sw = (float)wv;
+    const uint32_t idx = idx_next;
+    const float sx = (float)(s_next.x - akx), sy = (float)(s_next.y - aky), sz = (float)(s_next.z - akz);
+    const float sw = (float)w_next;
+    if (c + 1 < nch) {
+      idx_next = idx_after;
+      s_next = a.xk[idx_next];
+      w_next = a.w[idx_next];
+    }
+    if (c + 2 < nch) idx_after = list_entry(a, gi, c + 2, lane);
     if (c < nin) {
       RBF_STEPS(step_inner, acc, tx, ty, tz, sx, sy, sz, sw);
     } else if (c < nrisk) {

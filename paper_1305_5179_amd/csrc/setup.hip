@@ -92,15 +92,26 @@ __global__ void k_bbox_partial(const double* __restrict__ X, int64_t m, double* 
   if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nb, double* __restrict__ box) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(kThreads) void k_bbox_final(const double* __restrict__ part, int nb,
+                                                          double* __restrict__ box) {
+  __shared__ double s[6][kThreads];
   double r[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nb; ++b)
+  for (int b = threadIdx.x; b < nb; b += kThreads)
     for (int d = 0; d < 3; ++d) {
       r[d] = fmin(r[d], part[b * 6 + d]);
       r[3 + d] = fmax(r[3 + d], part[b * 6 + 3 + d]);
     }
-  for (int d = 0; d < 6; ++d) box[d] = r[d];
+  for (int d = 0; d < 6; ++d) s[d][threadIdx.x] = r[d];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int d = 0; d < 3; ++d) {
+        s[d][threadIdx.x] = fmin(s[d][threadIdx.x], s[d][threadIdx.x + w]);
+        s[3 + d][threadIdx.x] = fmax(s[3 + d][threadIdx.x], s[3 + d][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) box[threadIdx.x] = s[threadIdx.x][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -357,9 +368,10 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 // and |s - a| - R > r_c (1 + 1e-12) drops it, without looking at the
 // targets (the relative margin covers the float64 rounding of the distances
 // and of the exact test), whole cells at a time when the cell box allows.
-// The remaining "shell" sources are queued in LDS and tested exactly, four
-// per step: lane l holds target l mod 16, row r of the wave takes the r-th
-// source, and the row's ballot gives the source's inside count.
+// The cells near the anchor are examined one per lane; the sources of the
+// cells that remain are classified one per lane; the remaining "shell"
+// sources are queued in LDS and tested exactly against the 16 targets, 64
+// at a time (targets in scalar registers).
 // Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
 // list order is deterministic.  Lists are padded to whole chunks with the
 // padding source m.
@@ -368,50 +380,51 @@ struct ListCounts {
   int64_t n_in, n_out, n_risk, use;
 };
 
+// Exact test of `cnt` (<= 64) queued shell sources, one per lane, against
+// the group's 16 targets (uniform loads: scalar registers).
 template <bool WRITE>
-__device__ __forceinline__ void emit(uint32_t* list, int64_t base, int64_t n, uint64_t mask, bool mine, uint32_t k) {
-  if (WRITE && mine) list[base + n + lanes_below(mask)] = k;
+__device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const double4* __restrict__ tg,
+                                              const double4* __restrict__ xs, int nvalid, double rc2, double near_lo,
+                                              double near_hi, int64_t wb_in, int64_t wb_out, int64_t wb_risk,
+                                              uint32_t* __restrict__ list, ListCounts& n) {
+  const int lane = threadIdx.x & 63;
+  const bool valid = lane < cnt;
+  const uint32_t k = valid ? q[lane] : 0u;
+  int inside = 0;
+  bool near = false;
+  if (valid) {
+    const double4 s = xs[k];
+#pragma unroll
+    for (int l = 0; l < kGroup; ++l) {
+      const double4 t = tg[l];
+      const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      const bool tv = t.w != 0.0;
+      inside += (tv && r2 <= rc2) ? 1 : 0;
+      near = near || (tv && r2 >= near_lo && r2 <= near_hi);
+    }
+  }
+  const bool is_in = valid && inside == nvalid;
+  const bool is_out = valid && inside > 0 && inside < nvalid;
+  const bool is_risk = is_out && near, is_safe = is_out && !near;
+  const uint64_t mi = ballot(is_in), mo = ballot(is_safe), mr = ballot(is_risk);
+  if (WRITE) {
+    if (is_in) list[wb_in + n.n_in + lanes_below(mi)] = k;
+    if (is_safe) list[wb_out + n.n_out + lanes_below(mo)] = k;
+    if (is_risk) list[wb_risk + n.n_risk + lanes_below(mr)] = k;
+  }
+  n.n_in += __popcll(mi);
+  n.n_out += __popcll(mo);
+  n.n_risk += __popcll(mr);
+  int64_t u = inside;
+  for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
+  n.use += u;
 }
 
-// Exact test of the first `cnt` queued shell sources.
-template <bool WRITE>
-__device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const double4* __restrict__ xs,
-                                              const double4& tme, bool tvalid, int nvalid, double rc2, double kscale,
-                                              double Tk, double risk, int64_t wb_in, int64_t wb_out,
-                                              int64_t wb_risk, uint32_t* __restrict__ list, ListCounts& n) {
-  const int lane = threadIdx.x & 63, row = lane >> 4;
-  for (int i0 = 0; i0 < cnt; i0 += 4) {
-    const bool svalid = i0 + row < cnt;
-    const uint32_t k = svalid ? q[i0 + row] : 0u;
-    bool inside = false, near = false;
-    if (svalid) {
-      const double4 s = xs[k];
-      const double dx = tme.x - s.x, dy = tme.y - s.y, dz = tme.z - s.z;
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      inside = tvalid && r2 <= rc2;
-      near = tvalid && fabs(r2 * kscale - Tk) <= risk;
-    }
-    const uint64_t mi = ballot(inside), mn = ballot(near);
-    // classify the four rows (wave-uniform), in row order
-    int64_t pos_row = -1;
-    for (int rr = 0; rr < 4; ++rr) {
-      if (i0 + rr >= cnt) break;
-      const int c = __popcll((mi >> (16 * rr)) & 0xffffull);
-      const bool nr = ((mn >> (16 * rr)) & 0xffffull) != 0;
-      int64_t p = -1;
-      if (c == nvalid) {
-        p = wb_in + n.n_in++;
-      } else if (c > 0) {
-        if (nr)
-          p = wb_risk + n.n_risk++;
-        else
-          p = wb_out + n.n_out++;
-      }
-      n.use += c;
-      if (row == rr) pos_row = p;
-    }
-    if (WRITE && (lane & 15) == 0 && svalid && pos_row >= 0) list[pos_row] = k;
-  }
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <bool WRITE>
@@ -428,13 +441,12 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= G) return;
   uint32_t* q = qbuf[wave];
-  // this lane's target (lane mod 16) and the group's box, anchor and radius
-  const double4 tme = tpts[g * kGroup + (lane & 15)];
-  const bool tvalid = tme.w != 0.0;
+  const double4* tg = tpts + g * kGroup;
+  // the group's box, anchor and radius (uniform)
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int nvalid = 0;
   for (int l = 0; l < kGroup; ++l) {
-    const double4 t = tpts[g * kGroup + l];
+    const double4 t = tg[l];
     if (t.w != 0.0) {
       ++nvalid;
       lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
@@ -465,35 +477,45 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]), az = 0.5 * (lo[2] + hi[2]);
   double rad = 0.0;
   for (int l = 0; l < kGroup; ++l) {
-    const double4 t = tpts[g * kGroup + l];
+    const double4 t = tg[l];
     if (t.w != 0.0) {
       const double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
       rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
     }
   }
+  // risky pairs: scaled squared distance within twice the float32 band of T,
+  // i.e. r^2 in [near_lo, near_hi]
   const double Tk = rc2 * kscale;
-  const double risk = isfinite(Tk) ? 2.0 * f32_cutoff_band(Tk, rad * sqrt(kscale)) : -1.0;
+  const double risk = 2.0 * f32_cutoff_band(Tk, rad * sqrt(kscale));
+  const double near_lo = (Tk - risk) / kscale, near_hi = (Tk + risk) / kscale;
   const double r_in = rc * (1.0 - 1e-12) - rad;   // |s - a| <= r_in: inside for every target
   const double r_out = rc * (1.0 + 1e-12) + rad;  // |s - a| >  r_out: inside for none
   const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
   const double r_out2 = r_out * r_out;
 
-  int cl[3], ch[3];
+  // candidate cube of coarse cells around the anchor
+  int cl[3], cn[3];
   const double ac[3] = {ax, ay, az};
   for (int d = 0; d < 3; ++d) {
     const double a = floor((ac[d] - r_out - lat.origin[d]) / lat.coarse) - 1.0;
     const double b = floor((ac[d] + r_out - lat.origin[d]) / lat.coarse) + 1.0;
-    cl[d] = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
-    ch[d] = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
+    const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
+    const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
+    cl[d] = ia;
+    cn[d] = ib - ia + 1;
   }
+  const int ncube = cn[0] * cn[1] * cn[2];
   ListCounts n{0, 0, 0, 0};
   int qn = 0;
-  for (int cz = cl[2]; cz <= ch[2]; ++cz)
-    for (int cy = cl[1]; cy <= ch[1]; ++cy)
-      for (int cx = cl[0]; cx <= ch[0]; ++cx) {
-        const int32_t cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
-        if (cid < 0) continue;
-        // nearest and farthest points of the cell box from the anchor
+  for (int c0 = 0; c0 < ncube; c0 += kWave) {
+    // one cell of the cube per lane: occupied? how far from the anchor?
+    const int ci = c0 + lane;
+    int32_t cid = -1;
+    bool whole = false;
+    if (ci < ncube) {
+      const int cx = cl[0] + ci % cn[0], cy = cl[1] + (ci / cn[0]) % cn[1], cz = cl[2] + ci / (cn[0] * cn[1]);
+      cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
+      if (cid >= 0) {
         const int cc[3] = {cx, cy, cz};
         double dmin2 = 0.0, dmax2 = 0.0;
         for (int d = 0; d < 3; ++d) {
@@ -503,50 +525,53 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
           dmin2 += gap * gap;
           dmax2 += far * far;
         }
-        if (dmin2 > r_out2 * (1.0 + 1e-9)) continue;
-        const bool cell_inner = dmax2 * (1.0 + 1e-9) <= r_in2;
-        const int32_t st = cstart[cid], ct = ccount[cid];
-        for (int b0 = 0; b0 < ct; b0 += kWave) {
-          const bool valid = b0 + lane < ct;
-          const uint32_t k = (uint32_t)(st + b0 + lane);
-          bool is_in = false, is_shell = false;
-          if (valid) {
-            if (cell_inner) {
-              is_in = true;
-            } else {
-              const double4 s = xs[k];
-              const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
-              const double d2 = (dx * dx + dy * dy) + dz * dz;
-              is_in = d2 <= r_in2;
-              is_shell = !is_in && d2 <= r_out2;
-            }
-          }
-          const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-          emit<WRITE>(list, wb_in, n.n_in, mi, is_in, k);
-          n.n_in += __popcll(mi);
-          n.use += (int64_t)__popcll(mi) * nvalid;
-          if (is_shell) q[qn + lanes_below(ms)] = k;
-          qn += __popcll(ms);
-          if (qn >= kWave) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            process_shell<WRITE>(q, kWave, xs, tme, tvalid, nvalid, rc2, kscale, Tk, risk, wb_in, wb_out, wb_risk,
-                                 list, n);
-            const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane + kWave < qn) q[lane] = rest;
-            qn -= kWave;
+        if (dmin2 > r_out2 * (1.0 + 1e-9)) cid = -1;
+        whole = dmax2 * (1.0 + 1e-9) <= r_in2;
+      }
+    }
+    uint64_t sel = ballot(cid >= 0);
+    const uint64_t wsel = ballot(cid >= 0 && whole);
+    while (sel) {
+      const int src_lane = __builtin_ctzll(sel);
+      sel &= sel - 1;
+      const int32_t cell = __builtin_amdgcn_readlane(cid, src_lane);
+      const bool cell_inner = (wsel >> src_lane) & 1ull;
+      const int32_t st = cstart[cell], ct = ccount[cell];
+      for (int b0 = 0; b0 < ct; b0 += kWave) {
+        const bool valid = b0 + lane < ct;
+        const uint32_t k = (uint32_t)(st + b0 + lane);
+        bool is_in = false, is_shell = false;
+        if (valid) {
+          if (cell_inner) {
+            is_in = true;
+          } else {
+            const double4 s = xs[k];
+            const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            is_in = d2 <= r_in2;
+            is_shell = !is_in && d2 <= r_out2;
           }
         }
+        const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
+        if (WRITE && is_in) list[wb_in + n.n_in + lanes_below(mi)] = k;
+        n.n_in += __popcll(mi);
+        n.use += (int64_t)__popcll(mi) * nvalid;
+        if (is_shell) q[qn + lanes_below(ms)] = k;
+        qn += __popcll(ms);
+        if (qn >= kWave) {
+          wave_sync_lds();
+          process_shell<WRITE>(q, kWave, tg, xs, nvalid, rc2, near_lo, near_hi, wb_in, wb_out, wb_risk, list, n);
+          const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
+          wave_sync_lds();
+          if (lane + kWave < qn) q[lane] = rest;
+          qn -= kWave;
+          wave_sync_lds();
+        }
       }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (qn > 0)
-    process_shell<WRITE>(q, qn, xs, tme, tvalid, nvalid, rc2, kscale, Tk, risk, wb_in, wb_out, wb_risk, list, n);
+    }
+  }
+  wave_sync_lds();
+  if (qn > 0) process_shell<WRITE>(q, qn, tg, xs, nvalid, rc2, near_lo, near_hi, wb_in, wb_out, wb_risk, list, n);
   if (!WRITE) {
     if (lane == 0) {
       cnt_in[g] = (int32_t)n.n_in;
@@ -617,31 +642,22 @@ __global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int6
   groups[g] = gi;
 }
 
+// Integer sum (out must start at 0): block sums added with atomics, exact and
+// independent of the order.
 __global__ void k_sum_i64(const int64_t* __restrict__ in, int64_t n, int64_t* __restrict__ out) {
   __shared__ int64_t s[kThreads];
   int64_t acc = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kThreads) acc += in[i];
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+    acc += in[i];
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = s[0];
+  if (threadIdx.x == 0) atomicAdd((unsigned long long*)out, (unsigned long long)s[0]);
 }
 
-__global__ void k_max_radius(const GroupInfo* __restrict__ groups, int64_t G, double* __restrict__ out) {
-  __shared__ double s[kThreads];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < G; i += kThreads) acc = fmax(acc, groups[i].radius);
-  s[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *out = s[0];
-}
 
 
 // ---------------------------------------------------------------------------
@@ -745,7 +761,7 @@ __global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_
 // kGroupSeg targets, one thread per segment: pass 1 counts the groups of
 // every segment, pass 2 (after a scan) assigns each target its slot.
 // ---------------------------------------------------------------------------
-constexpr int kGroupSeg = 512;
+constexpr int kGroupSeg = 256;
 
 template <bool ASSIGN>
 __global__ void k_group_greedy(const double4* __restrict__ sp, int64_t M, double E2, int64_t* __restrict__ gcount,
@@ -824,7 +840,7 @@ void bounding_box(const double* X, int64_t m, double* box6, double* scratch, hip
   int nb = (int)std::min<int64_t>(1024, ceil_div(m, kThreads));
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kThreads), 0, s, X, m, scratch);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, scratch, nb, box6);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kThreads), 0, s, scratch, nb, box6);
   RBF_HIP(hipGetLastError());
 }
 
@@ -981,7 +997,6 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
   ts.groups = set_alloc<GroupInfo>(ts, G);
   ts.owned.push_back(ts.groups);
   int64_t* tmp = talloc<int64_t>(1);
-  double* tmpd = talloc<double>(1);
   if (ts.dense) {
     hipLaunchKernelGGL(k_dense_groups, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.pts, G, c.m, ts.groups);
     RBF_HIP(hipGetLastError());
@@ -1005,7 +1020,9 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(len, off, G, s);
     hipLaunchKernelGGL(k_list_offsets, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, off);
-    hipLaunchKernelGGL(k_sum_i64, dim3(1), dim3(kThreads), 0, s, use, G, tmp);
+    RBF_HIP(hipMemsetAsync(tmp, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_sum_i64, dim3((unsigned)std::min<int64_t>(256, ceil_div(G, kThreads))), dim3(kThreads), 0,
+                       s, use, G, tmp);
     RBF_HIP(hipGetLastError());
     int64_t last_off = 0, last_len = 0;
     RBF_HIP(hipMemcpyAsync(&last_off, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1021,12 +1038,8 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     RBF_HIP(hipGetLastError());
     temp_free(cin); temp_free(cout); temp_free(crisk); temp_free(use); temp_free(len); temp_free(off);
   }
-  hipLaunchKernelGGL(k_max_radius, dim3(1), dim3(kThreads), 0, s, ts.groups, G, tmpd);
-  RBF_HIP(hipGetLastError());
-  RBF_HIP(hipMemcpyAsync(&ts.max_radius, tmpd, sizeof(double), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
   temp_free(tmp);
-  temp_free(tmpd);
 }
 
 void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s) {

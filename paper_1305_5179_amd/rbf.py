@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "RBF_OK", -1: "RBF_EINVAL", -2: "RBF_ENOMEM", -3: "RBF_EDEVIC
 
 # Every symbol include/rbf.h declares.
 EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "rbf_solve",
-           "rbf_eval_grid", "rbf_eval_points", "rbf_get_stats", "rbf_count_grid_pairs",
+           "rbf_eval_grid", "rbf_eval_points", "rbf_density", "rbf_get_stats", "rbf_count_grid_pairs",
            "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error"]
 
 
@@ -80,6 +80,7 @@ def load_library() -> C.CDLL:
     lib.rbf_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.rbf_eval_grid.argtypes = [vp, vp, C.POINTER(Grid), vp, i32, vp]
     lib.rbf_eval_points.argtypes = [vp, vp, vp, i64, vp, i32, vp]
+    lib.rbf_density.argtypes = [vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl), vp]
     lib.rbf_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
     lib.rbf_profile_begin.argtypes = []
@@ -231,6 +232,14 @@ class Rbf:
                                               int(prec), _stream()))
         return out
 
+    def density(self, samples=None):
+        """(q, h_max, h_fill) of the cloud (h_fill is NaN without samples)."""
+        q, hm, hf = C.c_double(), C.c_double(), C.c_double()
+        ns = 0 if samples is None else int(samples.shape[0])
+        self._check(self._lib.rbf_density(self.ctx, _ptr(samples) if samples is not None else None, ns,
+                                          C.byref(q), C.byref(hm), C.byref(hf), _stream()))
+        return q.value, hm.value, hf.value
+
     def stats(self) -> Stats:
         s = Stats()
         self._check(self._lib.rbf_get_stats(self.ctx, C.byref(s)))
@@ -241,3 +250,11 @@ class Rbf:
         u, e = C.c_int64(), C.c_int64()
         self._check(self._lib.rbf_count_grid_pairs(self.ctx, C.byref(g), C.byref(u), C.byref(e), _stream()))
         return u.value, e.value
+
+
+def sigma_heuristics(q: float, h_max: float, h_fill: float | None = None) -> dict:
+    """The paper's choices of sigma from the density measures (Sec. IV):
+    sigma = 2 q (eq. h1), sigma = sqrt(2) h (eq. h2) with h the fill distance,
+    or h estimated as sqrt(2) h_max (eq. hmax) when no fill distance is known."""
+    h = h_fill if h_fill is not None and math.isfinite(h_fill) else math.sqrt(2.0) * h_max
+    return {"sigma_sep": 2.0 * q, "sigma_fill": math.sqrt(2.0) * h, "h": h}

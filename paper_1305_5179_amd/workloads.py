@@ -141,6 +141,59 @@ def sphere_sdf(q: np.ndarray) -> np.ndarray:
     return np.sqrt(np.sum(q * q, axis=1)) - 1.0
 
 
+def _metaball_field(x: np.ndarray, c: np.ndarray, s: np.ndarray):
+    """F(x) = sum_k exp(-|x - c_k|^2 / (2 s_k^2)) - 1/2 and its gradient."""
+    F = np.full(x.shape[0], -0.5)
+    G = np.zeros_like(x)
+    for ck, sk in zip(c, s):
+        d = x - ck
+        e = np.exp(-np.sum(d * d, axis=1) / (2.0 * sk * sk))
+        F += e
+        G -= (e / (sk * sk))[:, None] * d
+    return F, G
+
+
+def metaballs(n: int = 2_000_000, seed: int = 2, k: int = 12, band: float = 0.1, hole: float = 0.15,
+              noise: float = 1e-3, batch: int = 4_000_000) -> Cloud:
+    """An incomplete, noisy scan-like cloud: the zero set of a sum of k
+    seeded Gaussian metaballs (centres U[-0.5, 0.5]^3, widths U(0.15, 0.30),
+    level 1/2).  Candidates uniform in the box with |F| < band are projected
+    onto the surface by three Newton steps x <- x - F grad F / |grad F|^2;
+    the outward normal is -grad F / |grad F| at the projected point; points
+    within `hole` of the first projected point are removed; exactly n are
+    kept (in generation order) and N(0, noise^2) is added to each coordinate."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-0.5, 0.5, size=(k, 3))
+    s = rng.uniform(0.15, 0.30, size=k)
+    lo = c.min(axis=0) - 3.0 * s.max()
+    hi = c.max(axis=0) + 3.0 * s.max()
+    pts, nrm = [], []
+    have = 0
+    first = None
+    while have < n:
+        x = rng.uniform(lo, hi, size=(batch, 3))
+        F, _ = _metaball_field(x, c, s)
+        x = x[np.abs(F) < band]
+        for _ in range(3):
+            F, G = _metaball_field(x, c, s)
+            x = x - (F / np.sum(G * G, axis=1))[:, None] * G
+        F, G = _metaball_field(x, c, s)
+        g = np.sqrt(np.sum(G * G, axis=1))
+        ok = (np.abs(F) < 1e-9) & (g > 1e-6)
+        x, G, g = x[ok], G[ok], g[ok]
+        if first is None and x.shape[0]:
+            first = x[0].copy()
+        keep = np.sum((x - first) ** 2, axis=1) > hole * hole
+        x, G, g = x[keep], G[keep], g[keep]
+        pts.append(x)
+        nrm.append(-G / g[:, None])
+        have += x.shape[0]
+    p = np.concatenate(pts)[:n]
+    q = np.concatenate(nrm)[:n]
+    p = p + rng.normal(0.0, noise, size=p.shape)
+    return Cloud(p, q, f"metaballs{n}")
+
+
 def patch(cloud: Cloud, n: int, seed: int = 5) -> Cloud:
     """The n points of ``cloud`` nearest to one of its points chosen at
     random: a compact piece at the cloud's own density."""
@@ -189,3 +242,7 @@ SPHERE_SMALL = dict(n=2000, seed=0, eps=0.01, sigma=0.05, cutoff=math.inf,
                     grid=lambda: Grid.cube(-1.2, 1.2, 32))
 TORUS_200K = dict(n=200_000, seed=1, eps=0.005, sigma=0.02, cutoff=0.08, restart=30,
                   grid_n=256)
+# The offset is not given for this cloud: eps = sigma / 4 keeps the torus
+# workload's ratio and stays above 2.5 times the noise.
+METABALLS_2M = dict(n=2_000_000, seed=2, eps=0.0025, sigma=0.01, cutoff=0.04, restart=30,
+                    grid_n=512)

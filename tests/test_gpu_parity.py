@@ -326,3 +326,36 @@ def test_torus_grid_sampled_nodes(torus_full, torch):
     _say(f"[torus grid] band nodes {nz.size}, max err/bound {np.max(err / bound):.3f}")
     assert np.all(err <= bound)
     assert np.all(out[idx][scale == 0] == 0)
+
+
+# ---------------------------------------------------------------------------
+# Density measures (Sec. IV: separation distance, fill distance, h_max).
+# ---------------------------------------------------------------------------
+def test_density_matches_paper_halton_example(torch, R):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "halton25.json")))
+    P = np.stack([w.halton(25, 2, 1), w.halton(25, 3, 1), np.zeros(25)], axis=1)
+    nrm = np.tile([0.0, 0.0, 1.0], (25, 1))
+    ctx = R.Rbf(dev(torch, P), dev(torch, nrm), 0.01, 0.1, 0.5)
+    s = np.linspace(0.0, 1.0, 1501)
+    gx, gy = np.meshgrid(s, s)
+    S = np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1)
+    q, hmax, h = ctx.density(dev(torch, S))
+    half_unit = 0.5 * 10.0 ** (-g["printed_digits"])
+    assert abs(q - g["q"]) <= half_unit and abs(h - g["h"]) <= half_unit
+    assert q == o.separation_distance(P)
+    assert hmax == o.h_max(P)
+    assert h == o.fill_distance(P, S)
+    ctx.close()
+
+
+def test_density_matches_oracle_on_a_patch(case):
+    c = case["cloud"]
+    q, hmax, hf = case["ctx"].density()
+    if c.n < 2:
+        assert math.isnan(q) and math.isnan(hmax)
+        return
+    assert q == o.separation_distance(c.points)
+    assert hmax == o.h_max(c.points)
+    assert math.isnan(hf)
