@@ -4,6 +4,8 @@
 #include <chrono>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 
 #include "common.h"
 
@@ -44,6 +46,8 @@ int guarded(Ctx* c, F&& f) {
 }
 
 // The library is built for gfx950 only.
+// The architecture check runs once per device (hipGetDeviceProperties takes
+// milliseconds); the verdict is kept for the life of the process.
 int check_device(Ctx* c, int* dev_out) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
@@ -51,10 +55,20 @@ int check_device(Ctx* c, int* dev_out) {
     return fail(c, RBF_EDEVICE, std::string("no HIP device available (") + hipGetErrorString(e) + ")");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(c, RBF_EDEVICE, "hipGetDevice failed");
-  hipDeviceProp_t p;
-  if (hipGetDeviceProperties(&p, dev) != hipSuccess) return fail(c, RBF_EDEVICE, "hipGetDeviceProperties failed");
-  if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0)
-    return fail(c, RBF_EDEVICE, std::string("device ") + p.gcnArchName + " is not gfx950");
+  static std::mutex mu;
+  static std::map<int, std::string> arch;   // device -> gcnArchName
+  std::string name;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = arch.find(dev);
+    if (it == arch.end()) {
+      hipDeviceProp_t p;
+      if (hipGetDeviceProperties(&p, dev) != hipSuccess) return fail(c, RBF_EDEVICE, "hipGetDeviceProperties failed");
+      it = arch.emplace(dev, std::string(p.gcnArchName)).first;
+    }
+    name = it->second;
+  }
+  if (name.compare(0, 6, "gfx950") != 0) return fail(c, RBF_EDEVICE, "device " + name + " is not gfx950");
   *dev_out = dev;
   return RBF_OK;
 }
@@ -82,12 +96,14 @@ void free_targets(TargetSet& ts) {
   ts.pts = nullptr;
   ts.groups = nullptr;
   ts.list = nullptr;
+  ts.mask = nullptr;
 }
 
 void free_ctx(Ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  SyncedRelease synced;   // the device is idle: the blocks may go to any stream
   free_targets(c->centres);
   for (void* p : {(void*)c->perm, (void*)c->keys, (void*)c->xs, (void*)c->xk, (void*)c->xpaper, (void*)c->cell_start,
                   (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->vin, (void*)c->vout,

@@ -35,28 +35,24 @@ constexpr int kFineMax = 1 << kCurveBits;
 constexpr double kFar = 1.0e6;
 
 // Per-group metadata of a target set.
-// The list of a group is [inner | outer-safe | outer-risky], padded to whole
-// chunks: inner sources are inside the cutoff for every target of the
-// group; outer ones for some; a risky source has a pair whose scaled squared
-// distance lies within twice the float32 error band of the cutoff, so the
-// float32 kernel must check those pairs against the float64 decision.
+// The list of a group is [inner | outer], padded to whole chunks: inner
+// sources are inside the cutoff for every target of the group, outer ones
+// for some (float64 decisions).  Every chunk from n_inner on carries, per
+// entry, the 16-bit mask of the targets it is inside for (see mask_slot).
 struct GroupInfo {
-  int64_t off;          // first list entry of the group
+  int64_t off;          // first list entry of the group (a multiple of 64)
   int32_t n_chunks;     // list length / 64
   int32_t n_inner;      // chunks [0, n_inner) hold inner sources only
-  int32_t first_risky;  // chunks [first_risky, n_chunks) may hold risky sources
-  int32_t pad_;
   double ax, ay, az;    // anchor (unscaled float64); float32 coordinates are taken relative to it
   double radius;        // max distance of a valid target from the anchor
 };
 
-// Half-width of the band around the scaled cutoff T inside which the float32
-// scaled squared distance may decide differently from float64, for a group
-// of scaled radius R: four times the bound u (10 T + 7 sqrt(T) R), u = 2^-24
-// (rounding of the anchor-relative coordinates, of the differences, of the
-// three products and of T itself).
-__host__ __device__ inline double f32_cutoff_band(double T, double R) {
-  return 4.0 * 5.9604644775390625e-08 * (10.0 * T + 7.0 * sqrt(T) * R);
+// Position in the mask array of list entry e of a group starting at `off`.
+// Entry e = 64 c + 16 r + k is the source that row r of a wave broadcasts at
+// step k of chunk c; its mask is stored at off + 64 c + 4 k + r, so that the
+// four masks of step k form one 64-bit lane mask (bit 16 r + t = target t).
+__host__ __device__ inline int64_t mask_slot(int64_t off, int64_t e) {
+  return off + (e & ~int64_t(63)) + ((e & 15) << 2) + ((e >> 4) & 3);
 }
 
 // A set of targets grouped by 16 (centres, grid nodes or evaluation points)
@@ -68,6 +64,7 @@ struct TargetSet {
   int64_t* index = nullptr; // output position of every target slot
   GroupInfo* groups = nullptr;
   uint32_t* list = nullptr; // sorted-source indices (M = padding source)
+  uint16_t* mask = nullptr; // per-entry target masks of the non-inner chunks (mask_slot)
   int64_t list_entries = 0;
   int64_t useful = 0;       // pairs with r^2 <= cutoff^2 (float64 decision)
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
@@ -150,16 +147,24 @@ const char* thread_error();
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+__host__ __device__ inline int64_t round_down(int64_t a, int64_t b) { return (a / b) * b; }
 
 
 // Temporaries: stream-ordered allocations on the stream of the current API
-// call (set by TempStream), served from the device's memory pool without a
-// device-wide synchronisation.
+// call (set by TempStream), served by the library's caching allocator
+// (alloc.hip) without a device-wide synchronisation.
 hipStream_t& temp_stream();
 struct TempStream {
   hipStream_t prev;
   explicit TempStream(hipStream_t s) : prev(temp_stream()) { temp_stream() = s; }
   ~TempStream() { temp_stream() = prev; }
+};
+// While one of these is alive on a thread, freed blocks may be reused by any
+// stream: only for code that has synchronised the device first.
+struct SyncedRelease {
+  bool prev;
+  SyncedRelease();
+  ~SyncedRelease();
 };
 void* temp_alloc_bytes(size_t bytes);
 void temp_free(void* p);
@@ -168,9 +173,9 @@ T* talloc(int64_t count) {
   if (count <= 0) count = 1;
   return static_cast<T*>(temp_alloc_bytes(sizeof(T) * (size_t)count));
 }
-// Context arrays come from the same pool (allocated on the stream of the
-// call that creates them; rbf_setup returns only after that stream is idle,
-// and rbf_destroy waits for the device before returning them).
+// Context arrays come from the same allocator (allocated on the stream of
+// the call that creates them; rbf_setup returns only after that stream is
+// idle, and rbf_destroy waits for the device before releasing them).
 template <class T>
 T* dalloc(int64_t count) {
   return talloc<T>(count);

@@ -7,14 +7,22 @@
 // phi = exp2(-d) with d the scaled squared distance, and taken relative to
 // the group's anchor before rounding to float32 (the rounding error then
 // scales with the distance to the anchor, not with the cloud's extent).
-// Per pair: 3 subtractions (source broadcast by DPP), 1 multiply, 2 FMAs,
-// one v_exp_f32 and one FMA of the broadcast weight.  "Inner" chunks (every
-// pair inside the cutoff) skip the truncation test; "outer" chunks add it:
-// v = H (T - d) with H = 2^30 has the exact sign of T - d, min(-d, v) keeps
-// -d inside the cutoff and sends the exponent to a huge negative value
-// outside.  When |T - d| is within the float32 error bound of d the lane
-// recomputes r^2 in float64 from the unscaled coordinates and takes the
-// float64 decision, so the truncation is the float64 one everywhere.
+// A wave holds the 16 targets of a group in each of its four 16-lane rows;
+// every lane loads one source of a 64-entry chunk of the group's list and a
+// DPP row_newbcast hands source k of each row to all 16 lanes at step k.
+//
+// Expanded form (lists of bounded extent): d = |t|^2 + |s|^2 - 2 t.s, so
+// phi = 2^{-|t|^2} 2^{2 t.s} 2^{-|s|^2}; the source factor is folded into the
+// weight once per chunk, the target factor into the result, and a pair costs
+// one DPP multiply and two DPP FMAs (2 t.s), one v_exp_f32 and the DPP FMA of
+// the weight.
+// Direct form (dense lists, and groups too wide for the expanded form's
+// exponent range): three DPP subtractions, a multiply and two FMAs, the
+// exponential and the weight FMA.
+// Truncation: chunks of inner sources (inside the cutoff for every target)
+// need no test; in every other chunk a v_cndmask with the 64-bit lane mask
+// of the step (the float64 decisions of the list builder, loaded by scalar
+// loads) zeroes the terms of the pairs outside the cutoff.
 //
 // float64 path: the same lists; sources broadcast through LDS; r^2 and the
 // cutoff test exactly as the float64 definition; exp from the device library.
@@ -24,22 +32,20 @@ namespace rbf {
 
 namespace {
 
-constexpr float kH = 1073741824.0f;  // 2^30
-
 struct PairArgs {
   const double4* tpts;
   const GroupInfo* groups;
   const uint32_t* list;
+  const uint64_t* mask;  // per-step lane masks of the non-inner chunks
   int64_t G;
-  const double4* xk;   // scaled sources (float32 path)
-  const double4* xs;   // unscaled sources
+  const double4* xk;     // scaled sources (float32 path)
+  const double4* xs;     // unscaled sources
   const double* w;
   int64_t m;
   double sqrt_k;
   double inv_two_s2;
   double rc2;
-  double Tk;           // scaled cutoff^2, k r_c^2 (float64)
-  float TH;            // T * H, T = scaled cutoff^2 in float32
+  double Tk;             // scaled cutoff^2, k r_c^2
   int dense;
   int out_f32;
   void* out;
@@ -60,30 +66,39 @@ __device__ __forceinline__ float bcast(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf, true));
 }
 
-// acc += (weight held by lane K of this row) * e as one v_fmac_f32 with a
+// acc += (src held by lane K of this row) * other as one v_fmac_f32 with a
 // DPP row_newbcast source.  The compiler does not look inside inline asm for
 // hazards, so the asm carries its own wait states:
-//   * a VALU reading the result of a transcendental (the v_exp_f32 that made
-//     e) needs one wait state on gfx950: s_nop 0 before every use;
 //   * a DPP source register needs two wait states after a VALU write; the
-//     weight is written once per chunk, before its first use, which gets
-//     s_nop 1 (covering both).
+//     per-chunk source values are written once per chunk, before their first
+//     use at K = 0, which gets s_nop 1;
+//   * a VALU reading the result of a transcendental (`other` may come
+//     straight from v_exp_f32) needs one wait state on gfx950: s_nop 0.
 template <int K>
-__device__ __forceinline__ void fmac_bcast(float& acc, float wt, float e) {
+__device__ __forceinline__ void fmac_bcast(float& acc, float src, float other) {
   if constexpr (K == 0) {
     asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-                 : "+v"(acc) : "v"(wt), "v"(e));
+                 : "+v"(acc) : "v"(src), "v"(other));
   } else {
     asm volatile("s_nop 0\n\tv_fmac_f32_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-                 : "+v"(acc) : "v"(wt), "v"(e), "i"(K));
+                 : "+v"(acc) : "v"(src), "v"(other), "i"(K));
   }
 }
 
+struct Tgt {
+  float x, y, z;   // direct: t; expanded: 2 t
+};
+struct Src {
+  float x, y, z;   // s (anchor-relative, scaled)
+  float w;         // direct: w; expanded: w 2^{-|s|^2}
+};
+
+// ---- direct form ----------------------------------------------------------
 template <int K>
-__device__ __forceinline__ float sqdist_bcast(float tx, float ty, float tz, float sx, float sy, float sz) {
-  const float dx = bcast<K>(sx) - tx;
-  const float dy = bcast<K>(sy) - ty;
-  const float dz = bcast<K>(sz) - tz;
+__device__ __forceinline__ float sqdist_bcast(const Tgt& t, const Src& s) {
+  const float dx = bcast<K>(s.x) - t.x;
+  const float dy = bcast<K>(s.y) - t.y;
+  const float dz = bcast<K>(s.z) - t.z;
   float d = dx * dx;
   d = __builtin_fmaf(dy, dy, d);
   d = __builtin_fmaf(dz, dz, d);
@@ -91,53 +106,33 @@ __device__ __forceinline__ float sqdist_bcast(float tx, float ty, float tz, floa
 }
 
 template <int K>
-__device__ __forceinline__ void step_inner(float& acc, float tx, float ty, float tz, float sx, float sy, float sz,
-                                           float sw) {
-  const float d = sqdist_bcast<K>(tx, ty, tz, sx, sy, sz);
-  const float e = __builtin_amdgcn_exp2f(-d);
-  fmac_bcast<K>(acc, sw, e);
+__device__ __forceinline__ void direct_inner(float& acc, const Tgt& t, const Src& s) {
+  const float d = sqdist_bcast<K>(t, s);
+  fmac_bcast<K>(acc, s.w, __builtin_amdgcn_exp2f(-d));
 }
 
-// float64 decision for the lanes whose float32 distance is too close to the
-// cutoff to decide.
-__device__ __forceinline__ float resolve_f64(const PairArgs& a, int64_t tid, uint32_t idx, int row, int K,
-                                                       float d) {
-  const uint32_t i0 = __builtin_amdgcn_readlane(idx, K);
-  const uint32_t i1 = __builtin_amdgcn_readlane(idx, 16 + K);
-  const uint32_t i2 = __builtin_amdgcn_readlane(idx, 32 + K);
-  const uint32_t i3 = __builtin_amdgcn_readlane(idx, 48 + K);
-  const uint32_t src = row == 0 ? i0 : row == 1 ? i1 : row == 2 ? i2 : i3;
-  const double4 t = a.tpts[tid];
-  const double4 s = a.xs[src];
-  const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
-  const double r2 = (dx * dx + dy * dy) + dz * dz;
-  return r2 <= a.rc2 ? -d : -INFINITY;
-}
-
-// Outer chunk without risky sources: every pair is farther than the band
-// from the cutoff, so the float32 test decides as float64 does.
-template <int K>
-__device__ __forceinline__ void step_outer(float& acc, float tx, float ty, float tz, float sx, float sy, float sz,
-                                           float sw, float th) {
-  const float d = sqdist_bcast<K>(tx, ty, tz, sx, sy, sz);
-  const float v = __builtin_fmaf(d, -kH, th);
-  const float e = __builtin_amdgcn_exp2f(__builtin_fminf(-d, v));
-  fmac_bcast<K>(acc, sw, e);
+// The 16 lane masks of a chunk in scalar registers.  They are read through
+// the constant address space (the list builder wrote them in an earlier
+// launch; nothing writes them during this one), which lets the compiler use
+// scalar loads for the uniform address.
+struct StepMasks {
+  uint64_t m[16];
+};
+typedef const __attribute__((address_space(4))) uint64_t* ConstU64;
+__device__ __forceinline__ StepMasks load_masks(const uint64_t* mk) {
+  const ConstU64 p = (ConstU64)mk;
+  StepMasks r;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) r.m[k] = p[k];
+  return r;
 }
 
 template <int K>
-__device__ __forceinline__ void step_risky(float& acc, float tx, float ty, float tz, float sx, float sy, float sz,
-                                           float sw, float th, float gh, const PairArgs& a, int64_t tid, uint32_t idx,
-                                           int row) {
-  const float d = sqdist_bcast<K>(tx, ty, tz, sx, sy, sz);
-  const float v = __builtin_fmaf(d, -kH, th);
-  float arg = __builtin_fminf(-d, v);
-  const bool amb = __builtin_fabsf(v) <= gh;
-  if (__builtin_expect(__builtin_amdgcn_ballot_w64(amb) != 0, 0)) {
-    if (amb) arg = resolve_f64(a, tid, idx, row, K, d);
-  }
-  const float e = __builtin_amdgcn_exp2f(arg);
-  fmac_bcast<K>(acc, sw, e);
+__device__ __forceinline__ void direct_masked(float& acc, const Tgt& t, const Src& s, const StepMasks& mk) {
+  const float d = sqdist_bcast<K>(t, s);
+  float e = __builtin_amdgcn_exp2f(-d);
+  asm volatile("s_nop 0\n\tv_cndmask_b32_e64 %0, 0, %0, %1" : "+v"(e) : "s"(mk.m[K]));
+  fmac_bcast<K>(acc, s.w, e);
 }
 
 #define RBF_STEPS(F, ...) \
@@ -145,6 +140,60 @@ __device__ __forceinline__ void step_risky(float& acc, float tx, float ty, float
   F<4>(__VA_ARGS__); F<5>(__VA_ARGS__); F<6>(__VA_ARGS__); F<7>(__VA_ARGS__); \
   F<8>(__VA_ARGS__); F<9>(__VA_ARGS__); F<10>(__VA_ARGS__); F<11>(__VA_ARGS__); \
   F<12>(__VA_ARGS__); F<13>(__VA_ARGS__); F<14>(__VA_ARGS__); F<15>(__VA_ARGS__)
+
+// ---- expanded form --------------------------------------------------------
+// The 16 steps of a chunk as one asm block, software pipelined: the next
+// pair's dot product separates each v_exp_f32 from the instruction that
+// reads its result (one wait state needed), and a single s_nop 1 at the
+// start covers the DPP sources written by the chunk set-up (two wait
+// states).  No other hazard applies inside: DPP reads only the per-chunk
+// source values, and the lane masks are scalar loads the compiler waits for.
+#define RBF_DPP(K) " row_newbcast:" #K " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define RBF_DOT(K)                                  \
+  "v_mul_f32_dpp %[va], %[sx], %[tx]" RBF_DPP(K)    \
+  "v_fmac_f32_dpp %[va], %[sy], %[ty]" RBF_DPP(K)   \
+  "v_fmac_f32_dpp %[va], %[sz], %[tz]" RBF_DPP(K)
+#define RBF_ACC(K) "v_fmac_f32_dpp %[acc], %[sw], %[ve]" RBF_DPP(K)
+#define RBF_EXP "v_exp_f32 %[ve], %[va]\n\t"
+#define RBF_SEL(K) "v_cndmask_b32_e64 %[ve], 0, %[ve], %[m" #K "]\n\t"
+#define RBF_IN_STEP(K, KP) RBF_DOT(K) RBF_ACC(KP) RBF_EXP
+#define RBF_MASKED_STEP(K, KP) RBF_DOT(K) RBF_SEL(KP) RBF_ACC(KP) RBF_EXP
+
+__device__ __forceinline__ void expanded_inner_chunk(float& acc, const Tgt& t, const Src& s) {
+  float va, ve;
+  asm volatile(
+      "s_nop 1\n\t"
+      RBF_DOT(0) RBF_EXP
+      RBF_IN_STEP(1, 0) RBF_IN_STEP(2, 1) RBF_IN_STEP(3, 2) RBF_IN_STEP(4, 3)
+      RBF_IN_STEP(5, 4) RBF_IN_STEP(6, 5) RBF_IN_STEP(7, 6) RBF_IN_STEP(8, 7)
+      RBF_IN_STEP(9, 8) RBF_IN_STEP(10, 9) RBF_IN_STEP(11, 10) RBF_IN_STEP(12, 11)
+      RBF_IN_STEP(13, 12) RBF_IN_STEP(14, 13) RBF_IN_STEP(15, 14)
+      "s_nop 0\n\t"
+      RBF_ACC(15)
+      : [acc] "+v"(acc), [va] "=&v"(va), [ve] "=&v"(ve)
+      : [sx] "v"(s.x), [sy] "v"(s.y), [sz] "v"(s.z), [sw] "v"(s.w), [tx] "v"(t.x), [ty] "v"(t.y),
+        [tz] "v"(t.z));
+}
+
+__device__ __forceinline__ void expanded_masked_chunk(float& acc, const Tgt& t, const Src& s,
+                                                      const StepMasks& mk) {
+  float va, ve;
+  asm volatile(
+      "s_nop 1\n\t"
+      RBF_DOT(0) RBF_EXP
+      RBF_MASKED_STEP(1, 0) RBF_MASKED_STEP(2, 1) RBF_MASKED_STEP(3, 2) RBF_MASKED_STEP(4, 3)
+      RBF_MASKED_STEP(5, 4) RBF_MASKED_STEP(6, 5) RBF_MASKED_STEP(7, 6) RBF_MASKED_STEP(8, 7)
+      RBF_MASKED_STEP(9, 8) RBF_MASKED_STEP(10, 9) RBF_MASKED_STEP(11, 10) RBF_MASKED_STEP(12, 11)
+      RBF_MASKED_STEP(13, 12) RBF_MASKED_STEP(14, 13) RBF_MASKED_STEP(15, 14)
+      "s_nop 0\n\t"
+      RBF_SEL(15) RBF_ACC(15)
+      : [acc] "+v"(acc), [va] "=&v"(va), [ve] "=&v"(ve)
+      : [sx] "v"(s.x), [sy] "v"(s.y), [sz] "v"(s.z), [sw] "v"(s.w), [tx] "v"(t.x), [ty] "v"(t.y),
+        [tz] "v"(t.z), [m0] "s"(mk.m[0]), [m1] "s"(mk.m[1]), [m2] "s"(mk.m[2]), [m3] "s"(mk.m[3]),
+        [m4] "s"(mk.m[4]), [m5] "s"(mk.m[5]), [m6] "s"(mk.m[6]), [m7] "s"(mk.m[7]), [m8] "s"(mk.m[8]),
+        [m9] "s"(mk.m[9]), [m10] "s"(mk.m[10]), [m11] "s"(mk.m[11]), [m12] "s"(mk.m[12]), [m13] "s"(mk.m[13]),
+        [m14] "s"(mk.m[14]), [m15] "s"(mk.m[15]));
+}
 
 __device__ __forceinline__ void store_result(const PairArgs& a, int64_t tid, double v) {
   if (a.out_f32)
@@ -161,6 +210,61 @@ __device__ __forceinline__ uint32_t list_entry(const PairArgs& a, const GroupInf
   return a.list[gi.off + (int64_t)c * kChunk + lane];
 }
 
+// Largest |s|^2 and 2|t||s| the expanded form admits (2^{-100} and 2^{100}
+// stay normal float32 numbers with room for the weights).
+constexpr double kExpandMax = 100.0;
+
+// The pair loop of one group: software pipeline over the chunks, the list
+// index two chunks ahead and the source gather one chunk ahead in flight
+// while a chunk computes.
+template <bool EXPAND>
+__device__ __forceinline__ float group_sum(const PairArgs& a, const GroupInfo& gi, const Tgt& t, int lane,
+                                           double akx, double aky, double akz) {
+  float acc = 0.0f;
+  const int nch = gi.n_chunks, nin = gi.n_inner;
+  const uint64_t* masks = a.mask + (gi.off >> 2);
+  uint32_t idx_next = nch > 0 ? list_entry(a, gi, 0, lane) : (uint32_t)a.m;
+  double4 s_next = a.xk[idx_next];
+  double w_next = a.w[idx_next];
+  uint32_t idx_after = nch > 1 ? list_entry(a, gi, 1, lane) : (uint32_t)a.m;
+  for (int c = 0; c < nch; ++c) {
+    Src s;
+    s.x = (float)(s_next.x - akx);
+    s.y = (float)(s_next.y - aky);
+    s.z = (float)(s_next.z - akz);
+    if constexpr (EXPAND) {
+      // |s|^2 of the rounded coordinates (exact in float64), so that
+      // |t|^2 + |s|^2 - 2 t.s is the squared distance of the very vectors
+      // whose dot product the steps form
+      const double q = ((double)s.x * s.x + (double)s.y * s.y) + (double)s.z * s.z;
+      s.w = (float)w_next * __builtin_amdgcn_exp2f(-(float)q);
+    } else {
+      s.w = (float)w_next;
+    }
+    if (c + 1 < nch) {
+      idx_next = idx_after;
+      s_next = a.xk[idx_next];
+      w_next = a.w[idx_next];
+    }
+    if (c + 2 < nch) idx_after = list_entry(a, gi, c + 2, lane);
+    if (c < nin) {
+      if constexpr (EXPAND) {
+        expanded_inner_chunk(acc, t, s);
+      } else {
+        RBF_STEPS(direct_inner, acc, t, s);
+      }
+    } else {
+      const StepMasks mk = load_masks(masks + (int64_t)c * 16);
+      if constexpr (EXPAND) {
+        expanded_masked_chunk(acc, t, s, mk);
+      } else {
+        RBF_STEPS(direct_masked, acc, t, s, mk);
+      }
+    }
+  }
+  return acc;
+}
+
 __global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -175,40 +279,27 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
   const float ty = (float)((tp.y - gi.ay) * a.sqrt_k);
   const float tz = (float)((tp.z - gi.az) * a.sqrt_k);
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
-  // the truncation threshold T*H held in a VGPR (v_fma_f32 takes it as its addend)
-  float th;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(th) : "s"(a.TH));
-  // ambiguity half-width of this group, times H
-  const float gh = (float)(f32_cutoff_band(a.Tk, gi.radius * a.sqrt_k) * (double)kH);
-  float acc = 0.0f;
-  const int nch = gi.n_chunks, nin = gi.n_inner, nrisk = gi.first_risky;
-  // Software pipeline over the chunks: the list index two chunks ahead and
-  // the source gather one chunk ahead are in flight while a chunk computes.
-  uint32_t idx_next = nch > 0 ? list_entry(a, gi, 0, lane) : (uint32_t)a.m;
-  double4 s_next = a.xk[idx_next];
-  double w_next = a.w[idx_next];
-  uint32_t idx_after = nch > 1 ? list_entry(a, gi, 1, lane) : (uint32_t)a.m;
-  for (int c = 0; c < nch; ++c) {
-    const uint32_t idx = idx_next;
-    const float sx = (float)(s_next.x - akx), sy = (float)(s_next.y - aky), sz = (float)(s_next.z - akz);
-    const float sw = (float)w_next;
-    if (c + 1 < nch) {
-      idx_next = idx_after;
-      s_next = a.xk[idx_next];
-      w_next = a.w[idx_next];
-    }
-    if (c + 2 < nch) idx_after = list_entry(a, gi, c + 2, lane);
-    if (c < nin) {
-      RBF_STEPS(step_inner, acc, tx, ty, tz, sx, sy, sz, sw);
-    } else if (c < nrisk) {
-      RBF_STEPS(step_outer, acc, tx, ty, tz, sx, sy, sz, sw, th);
-    } else {
-      RBF_STEPS(step_risky, acc, tx, ty, tz, sx, sy, sz, sw, th, gh, a, tid, idx, row);
-    }
+  // expanded form when the exponents stay in range: every listed source is
+  // within R + sqrt(T) of the anchor (scaled units)
+  const double rk = gi.radius * a.sqrt_k;
+  const double smax = rk + sqrt(a.Tk);
+  const bool expand = !a.dense && smax * smax <= kExpandMax && 2.0 * rk * smax <= kExpandMax;
+  double res;
+  if (expand) {
+    const Tgt t{2.0f * tx, 2.0f * ty, 2.0f * tz};
+    float acc = group_sum<true>(a, gi, t, lane, akx, aky, akz);
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    const double tq = ((double)tx * tx + (double)ty * ty) + (double)tz * tz;
+    res = (double)acc * exp2(-tq);
+  } else {
+    const Tgt t{tx, ty, tz};
+    float acc = group_sum<false>(a, gi, t, lane, akx, aky, akz);
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    res = (double)acc;
   }
-  acc += __shfl_xor(acc, 16);
-  acc += __shfl_xor(acc, 32);
-  if (row == 0 && tp.w != 0.0) store_result(a, tid, (double)acc);
+  if (row == 0 && tp.w != 0.0) store_result(a, tid, res);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
@@ -266,6 +357,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.tpts = ts.pts;
   a.groups = ts.groups;
   a.list = ts.list;
+  a.mask = reinterpret_cast<const uint64_t*>(ts.mask);
   a.G = ts.n_groups;
   a.xk = c.xk;
   a.xs = c.xs;
@@ -279,15 +371,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.out = out;
   a.out_index = ts.index;
   a.skip = skip;
-  // Scaled cutoff T = k r_c^2 (the per-group ambiguity band is
-  // f32_cutoff_band(T, scaled group radius)).
-  if (std::isfinite(c.rc2)) {
-    a.Tk = c.rc2 * c.sqrt_k * c.sqrt_k;
-    a.TH = (float)(a.Tk) * kH;
-  } else {
-    a.Tk = INFINITY;
-    a.TH = INFINITY;
-  }
+  a.Tk = std::isfinite(c.rc2) ? c.rc2 * c.sqrt_k * c.sqrt_k : INFINITY;
   return a;
 }
 

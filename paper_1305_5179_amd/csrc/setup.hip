@@ -359,10 +359,8 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 // bounding box) and radius R (largest distance of a target from a).  Every
 // source s of a coarse cell near the group is classified against the exact
 // float64 truncation test r^2 <= r_c^2 of every valid target:
-//   inside for all targets  -> "inner" (the pair kernels skip the test)
-//   inside for some targets -> "outer", split into "safe" and "risky" (a pair
-//                              within twice the float32 error band of the
-//                              cutoff: the float32 kernel checks those pairs)
+//   inside for all targets  -> "inner" (the pair kernels apply no test)
+//   inside for some targets -> "outer", with the mask of those targets
 //   inside for none         -> dropped.
 // By the triangle inequality |s - a| + R <= r_c (1 - 1e-12) makes s inner
 // and |s - a| - R > r_c (1 + 1e-12) drops it, without looking at the
@@ -374,24 +372,41 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 // at a time (targets in scalar registers).
 // Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
 // list order is deterministic.  Lists are padded to whole chunks with the
-// padding source m.
+// padding source m (mask 0).  Pass 2 also writes the masks of every entry
+// of the chunks from the first one that is not purely inner.
 // ---------------------------------------------------------------------------
 struct ListCounts {
-  int64_t n_in, n_out, n_risk, use;
+  int64_t n_in, n_out, use;
 };
+
+// Where pass 2 writes a group's entries.
+struct ListOut {
+  uint32_t* list;
+  uint16_t* mask;
+  int64_t base;     // first entry of the group
+  int64_t out0;     // relative position of the first outer entry (= number of inner entries)
+  int64_t in_full;  // inner entries below this position are in pure inner chunks (no mask)
+};
+
+__device__ __forceinline__ void put_inner(const ListOut& o, int64_t e, uint32_t k, uint32_t vmask) {
+  o.list[o.base + e] = k;
+  if (e >= o.in_full) o.mask[mask_slot(o.base, e)] = (uint16_t)vmask;
+}
+__device__ __forceinline__ void put_outer(const ListOut& o, int64_t e, uint32_t k, uint32_t bits) {
+  o.list[o.base + o.out0 + e] = k;
+  o.mask[mask_slot(o.base, o.out0 + e)] = (uint16_t)bits;
+}
 
 // Exact test of `cnt` (<= 64) queued shell sources, one per lane, against
 // the group's 16 targets (uniform loads: scalar registers).
 template <bool WRITE>
 __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const double4* __restrict__ tg,
-                                              const double4* __restrict__ xs, int nvalid, double rc2, double near_lo,
-                                              double near_hi, int64_t wb_in, int64_t wb_out, int64_t wb_risk,
-                                              uint32_t* __restrict__ list, ListCounts& n) {
+                                              const double4* __restrict__ xs, uint32_t vmask, double rc2,
+                                              const ListOut& o, ListCounts& n) {
   const int lane = threadIdx.x & 63;
   const bool valid = lane < cnt;
   const uint32_t k = valid ? q[lane] : 0u;
-  int inside = 0;
-  bool near = false;
+  uint32_t bits = 0;
   if (valid) {
     const double4 s = xs[k];
 #pragma unroll
@@ -399,24 +414,19 @@ __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const 
       const double4 t = tg[l];
       const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
       const double r2 = (dx * dx + dy * dy) + dz * dz;
-      const bool tv = t.w != 0.0;
-      inside += (tv && r2 <= rc2) ? 1 : 0;
-      near = near || (tv && r2 >= near_lo && r2 <= near_hi);
+      bits |= (t.w != 0.0 && r2 <= rc2) ? (1u << l) : 0u;
     }
   }
-  const bool is_in = valid && inside == nvalid;
-  const bool is_out = valid && inside > 0 && inside < nvalid;
-  const bool is_risk = is_out && near, is_safe = is_out && !near;
-  const uint64_t mi = ballot(is_in), mo = ballot(is_safe), mr = ballot(is_risk);
+  const bool is_in = valid && bits == vmask;
+  const bool is_out = valid && bits != 0u && !is_in;
+  const uint64_t mi = ballot(is_in), mo = ballot(is_out);
   if (WRITE) {
-    if (is_in) list[wb_in + n.n_in + lanes_below(mi)] = k;
-    if (is_safe) list[wb_out + n.n_out + lanes_below(mo)] = k;
-    if (is_risk) list[wb_risk + n.n_risk + lanes_below(mr)] = k;
+    if (is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
+    if (is_out) put_outer(o, n.n_out + lanes_below(mo), k, bits);
   }
   n.n_in += __popcll(mi);
   n.n_out += __popcll(mo);
-  n.n_risk += __popcll(mr);
-  int64_t u = inside;
+  int64_t u = __popc(bits);
   for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off);
   n.use += u;
 }
@@ -432,9 +442,9 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
                                                     const double4* __restrict__ xs, int64_t m,
                                                     const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
                                                     const int32_t* __restrict__ cmap, Lattice lat, double rc, double rc2,
-                                                    double kscale, int32_t* __restrict__ cnt_in,
-                                                    int32_t* __restrict__ cnt_out, int32_t* __restrict__ cnt_risk,
-                                                    int64_t* __restrict__ useful, uint32_t* __restrict__ list) {
+                                                    int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out,
+                                                    int64_t* __restrict__ useful, uint32_t* __restrict__ list,
+                                                    uint16_t* __restrict__ mask) {
   __shared__ uint32_t qbuf[kThreads / kWave][2 * kWave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -445,29 +455,30 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   // the group's box, anchor and radius (uniform)
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int nvalid = 0;
+  uint32_t vmask = 0;
   for (int l = 0; l < kGroup; ++l) {
     const double4 t = tg[l];
     if (t.w != 0.0) {
       ++nvalid;
+      vmask |= 1u << l;
       lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
       lo[1] = fmin(lo[1], t.y); hi[1] = fmax(hi[1], t.y);
       lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
     }
   }
-  int64_t wb_in = 0, wb_out = 0, wb_risk = 0;
+  ListOut o{list, mask, 0, 0, 0};
   if (WRITE) {
-    wb_in = groups[g].off;
-    wb_out = wb_in + cnt_in[g];
-    wb_risk = wb_out + cnt_out[g];
+    o.base = groups[g].off;
+    o.out0 = cnt_in[g];
+    o.in_full = round_down(o.out0, kChunk);
   }
   if (nvalid == 0) {
     if (!WRITE && lane == 0) {
       cnt_in[g] = 0;
       cnt_out[g] = 0;
-      cnt_risk[g] = 0;
       useful[g] = 0;
       GroupInfo gi;
-      gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0; gi.first_risky = 0; gi.pad_ = 0;
+      gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0;
       gi.ax = gi.ay = gi.az = 0.0;
       gi.radius = 0.0;
       groups[g] = gi;
@@ -483,11 +494,6 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
     }
   }
-  // risky pairs: scaled squared distance within twice the float32 band of T,
-  // i.e. r^2 in [near_lo, near_hi]
-  const double Tk = rc2 * kscale;
-  const double risk = 2.0 * f32_cutoff_band(Tk, rad * sqrt(kscale));
-  const double near_lo = (Tk - risk) / kscale, near_hi = (Tk + risk) / kscale;
   const double r_in = rc * (1.0 - 1e-12) - rad;   // |s - a| <= r_in: inside for every target
   const double r_out = rc * (1.0 + 1e-12) + rad;  // |s - a| >  r_out: inside for none
   const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
@@ -505,7 +511,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     cn[d] = ib - ia + 1;
   }
   const int ncube = cn[0] * cn[1] * cn[2];
-  ListCounts n{0, 0, 0, 0};
+  ListCounts n{0, 0, 0};
   int qn = 0;
   for (int c0 = 0; c0 < ncube; c0 += kWave) {
     // one cell of the cube per lane: occupied? how far from the anchor?
@@ -553,14 +559,14 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
           }
         }
         const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-        if (WRITE && is_in) list[wb_in + n.n_in + lanes_below(mi)] = k;
+        if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
         n.n_in += __popcll(mi);
         n.use += (int64_t)__popcll(mi) * nvalid;
         if (is_shell) q[qn + lanes_below(ms)] = k;
         qn += __popcll(ms);
         if (qn >= kWave) {
           wave_sync_lds();
-          process_shell<WRITE>(q, kWave, tg, xs, nvalid, rc2, near_lo, near_hi, wb_in, wb_out, wb_risk, list, n);
+          process_shell<WRITE>(q, kWave, tg, xs, vmask, rc2, o, n);
           const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
           wave_sync_lds();
           if (lane + kWave < qn) q[lane] = rest;
@@ -571,27 +577,27 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     }
   }
   wave_sync_lds();
-  if (qn > 0) process_shell<WRITE>(q, qn, tg, xs, nvalid, rc2, near_lo, near_hi, wb_in, wb_out, wb_risk, list, n);
+  if (qn > 0) process_shell<WRITE>(q, qn, tg, xs, vmask, rc2, o, n);
   if (!WRITE) {
     if (lane == 0) {
       cnt_in[g] = (int32_t)n.n_in;
       cnt_out[g] = (int32_t)n.n_out;
-      cnt_risk[g] = (int32_t)n.n_risk;
       useful[g] = n.use;
       GroupInfo gi;
       gi.off = 0;
-      gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out + n.n_risk, kChunk);
+      gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out, kChunk);
       gi.n_inner = (int32_t)(n.n_in / kChunk);
-      gi.first_risky = n.n_risk > 0 ? (int32_t)((n.n_in + n.n_out) / kChunk) : gi.n_chunks;
-      gi.pad_ = 0;
       gi.ax = ax; gi.ay = ay; gi.az = az;
       gi.radius = rad;
       groups[g] = gi;
     }
   } else {
-    const int64_t total = n.n_in + n.n_out + n.n_risk;
+    const int64_t total = n.n_in + n.n_out;
     const int64_t padded = round_up(total, kChunk);
-    for (int64_t e = total + lane; e < padded; e += kWave) list[wb_in + e] = (uint32_t)m;
+    for (int64_t e = total + lane; e < padded; e += kWave) {
+      list[o.base + e] = (uint32_t)m;
+      mask[mask_slot(o.base, e)] = 0;
+    }
   }
 }
 
@@ -622,8 +628,6 @@ __global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int6
   gi.off = 0;
   gi.n_chunks = nv ? (int32_t)ceil_div(m, kChunk) : 0;
   gi.n_inner = gi.n_chunks;
-  gi.first_risky = gi.n_chunks;
-  gi.pad_ = 0;
   if (nv) {
     gi.ax = 0.5 * (lo[0] + hi[0]); gi.ay = 0.5 * (lo[1] + hi[1]); gi.az = 0.5 * (lo[2] + hi[2]);
     double rad = 0.0;
@@ -951,35 +955,6 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   temp_free(slot_of);
 }
 
-hipStream_t& temp_stream() {
-  static thread_local hipStream_t s = nullptr;
-  return s;
-}
-
-void* temp_alloc_bytes(size_t bytes) {
-  static bool pool_ready = false;
-  if (!pool_ready) {
-    // keep freed blocks in the pool instead of returning them at every sync
-    int dev = 0;
-    hipMemPool_t pool;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-      uint64_t keep = UINT64_MAX;
-      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    pool_ready = true;
-  }
-  void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, temp_stream());
-  if (e != hipSuccess)
-    throw Error{e == hipErrorOutOfMemory ? RBF_ENOMEM : RBF_EDEVICE,
-                std::string("hipMallocAsync(") + std::to_string(bytes) + " bytes): " + hipGetErrorString(e)};
-  return p;
-}
-
-void temp_free(void* p) {
-  if (p) (void)hipFreeAsync(p, temp_stream());
-}
-
 void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
@@ -1001,20 +976,19 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     hipLaunchKernelGGL(k_dense_groups, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.pts, G, c.m, ts.groups);
     RBF_HIP(hipGetLastError());
     ts.list = nullptr;
+    ts.mask = nullptr;
     ts.list_entries = G * round_up(c.m, kChunk);
     ts.useful = ts.n_targets * c.m;
   } else {
     int32_t* cin = talloc<int32_t>(G);
     int32_t* cout = talloc<int32_t>(G);
-    int32_t* crisk = talloc<int32_t>(G);
-    const double kscale = c.sqrt_k * c.sqrt_k;
     int64_t* use = talloc<int64_t>(G);
     int64_t* len = talloc<int64_t>(G);
     int64_t* off = talloc<int64_t>(G);
     const unsigned nblk = (unsigned)ceil_div(G, 4);
     hipLaunchKernelGGL(k_lists<false>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, kscale, cin, cout, crisk,
-                       use, (uint32_t*)nullptr);
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use,
+                       (uint32_t*)nullptr, (uint16_t*)nullptr);
     RBF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
     RBF_HIP(hipGetLastError());
@@ -1032,11 +1006,13 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     ts.list_entries = last_off + last_len;
     ts.list = set_alloc<uint32_t>(ts, ts.list_entries);
     ts.owned.push_back(ts.list);
+    ts.mask = set_alloc<uint16_t>(ts, ts.list_entries);
+    ts.owned.push_back(ts.mask);
     hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, kscale, cin, cout, crisk,
-                       use, ts.list);
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use, ts.list,
+                       ts.mask);
     RBF_HIP(hipGetLastError());
-    temp_free(cin); temp_free(cout); temp_free(crisk); temp_free(use); temp_free(len); temp_free(off);
+    temp_free(cin); temp_free(cout); temp_free(use); temp_free(len); temp_free(off);
   }
   RBF_HIP(hipStreamSynchronize(s));
   temp_free(tmp);

@@ -1,14 +1,15 @@
 """Static checks on the gfx950 assembly of the float32 pair-sum kernel.
 
-The kernel's weight FMA is inline assembly (a v_fmac_f32 with a DPP
-row_newbcast source), which the compiler's hazard recognizer does not
-inspect.  Two hardware hazards apply to it and are covered by wait states
-inside the asm block:
-  * a VALU reading the result of a transcendental (v_exp_f32) needs one wait
-    state;
-  * a DPP source VGPR needs two wait states after a VALU writes it.
-This test compiles the kernel and checks every such instruction against the
-instructions the compiler placed before it."""
+Parts of the kernel's pair loop are inline assembly (DPP row_newbcast FMAs,
+and whole pipelined chunks), which the compiler's hazard recognizer does not
+look into.  Two hardware hazards apply to that code and must be covered by
+the instruction order or by s_nop wait states:
+  * a DPP instruction whose permuted source (src0) was written by a VALU
+    needs two wait states after that write;
+  * a (non-transcendental) VALU reading the result of a transcendental
+    (v_exp_f32 and the like) needs one wait state on gfx950.
+This test compiles the kernel and checks every instruction of it against
+the instructions that can precede it, following branches into labels."""
 import os
 import re
 import subprocess
@@ -17,6 +18,9 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_1305_5179_amd", "csrc", "pairsum.hip")
+KERNEL = "_ZN3rbf12_GLOBAL__N_113k_pairsum_f32ENS0_8PairArgsE"
+TRANS = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
+         "v_rcp_f64", "v_rsq_f64", "v_sqrt_f64", "v_rcp_iflag_f32")
 
 
 def _hipcc():
@@ -37,46 +41,160 @@ def f32_asm(tmp_path_factory):
     subprocess.run([hipcc, *flags, "--cuda-device-only", "-S", SRC, "-o", str(out)], check=True,
                    capture_output=True)
     text = out.read_text()
-    start = text.index("k_pairsum_f32ENS0_8PairArgsE:")
-    end = text.index("s_endpgm", start)
-    lines = [l.split(";")[0].strip() for l in text[start:end].splitlines()]
-    return [l for l in lines if l and not l.startswith(".") and not l.endswith(":")]
+    start = text.index(KERNEL + ":")
+    end = text.index(".Lfunc_end", start)
+    lines = []
+    for raw in text[start:end].splitlines()[1:]:
+        l = raw.split(";")[0].strip()
+        if not l or (l.startswith(".") and not l.endswith(":")):
+            continue
+        lines.append(l)
+    return lines
+
+
+def _regs(operand):
+    """VGPR numbers named by one operand (v7, -v7, |v7|, v[4:5])."""
+    m = re.search(r"v\[(\d+):(\d+)\]", operand)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    m = re.search(r"(?<![\w])v(\d+)\b", operand)
+    return {int(m.group(1))} if m else set()
+
+
+def _parse(instr):
+    parts = instr.split(None, 1)
+    op = parts[0]
+    args = [a.strip() for a in parts[1].split(",")] if len(parts) > 1 else []
+    # drop DPP/modifier words glued to the last operand
+    if args:
+        args[-1] = args[-1].split()[0]
+    return op, args
+
+
+def _is_valu(op):
+    return op.startswith("v_")
+
+
+def _writes(instr):
+    """VGPRs written by a VALU instruction."""
+    op, args = _parse(instr)
+    if not _is_valu(op) or not args or op.startswith(("v_cmp", "v_readlane", "v_readfirstlane")):
+        return set()
+    return _regs(args[0])
+
+
+def _reads(instr):
+    op, args = _parse(instr)
+    if not args:
+        return set()
+    srcs = args[1:]
+    r = set().union(*[_regs(a) for a in srcs]) if srcs else set()
+    if op.startswith(("v_fmac", "v_mac")):
+        r |= _regs(args[0])     # tied accumulator
+    return r
 
 
 def _wait_states(instr):
     m = re.match(r"s_nop\s+(\d+)", instr)
-    return int(m.group(1)) + 1 if m else 0
+    return int(m.group(1)) + 1 if m else 1
 
 
-def _dst(instr):
-    m = re.match(r"(v_\w+)\s+(v\[?\d+)", instr)
-    if not m or m.group(1).startswith(("v_cmp", "v_readlane", "v_readfirstlane")):
-        return None
-    return m.group(2).lstrip("v[")
+def _predecessors(lines):
+    """index of the line -> list of indices that may execute right before it."""
+    labels = {l[:-1]: i for i, l in enumerate(lines) if l.endswith(":")}
+    preds = {i: [] for i in range(len(lines))}
+    for i, l in enumerate(lines):
+        if i + 1 < len(lines) and not l.startswith(("s_branch", "s_endpgm", "s_setpc")):
+            preds[i + 1].append(i)
+        m = re.match(r"s_(?:cbranch_\w+|branch)\s+(\S+)", l)
+        if m and m.group(1) in labels:
+            preds[labels[m.group(1)]].append(i)
+    return preds
 
 
-def test_asm_fmac_is_preceded_by_enough_wait_states(f32_asm):
-    n = 0
-    for i, ins in enumerate(f32_asm):
-        m = re.match(r"v_fmac_f32_dpp\s+v(\d+),\s*v(\d+),\s*v(\d+)", ins)
-        if not m:
+def _violations(lines, i, regs, need, producer_ok):
+    """Producers of `regs` among the instructions within `need` wait states
+    before line i, on every path."""
+    preds = _predecessors.cache
+    found = []
+    stack = [(p, 0) for p in preds[i]]
+    seen = set()
+    while stack:
+        j, waited = stack.pop()
+        if (j, waited) in seen or waited >= need:
             continue
-        n += 1
-        src0, src1 = m.group(2), m.group(3)
-        # walk back over the wait states inside the asm block
-        j, waits = i - 1, 0
-        while j >= 0 and f32_asm[j].startswith("s_nop"):
-            waits += _wait_states(f32_asm[j])
-            j -= 1
-        assert waits >= 1, f"no wait state before {ins}"
-        # instructions the compiler placed before the block
-        prev = [f32_asm[k] for k in range(max(0, j - 2), j + 1)]
-        for dist, p in enumerate(reversed(prev)):
-            d = _dst(p)
-            if d is None:
-                continue
-            if d == src1 and p.startswith("v_exp_f32"):
-                assert waits + dist >= 1, (p, ins)
-            if d == src0:
-                assert waits + dist >= 2, f"DPP source v{src0} written by '{p}' right before '{ins}'"
-    assert n >= 32   # inner and outer bodies, 16 each
+        seen.add((j, waited))
+        l = lines[j]
+        if l.endswith(":"):
+            stack.extend((p, waited) for p in preds[j])
+            continue
+        if producer_ok(l) and _writes(l) & regs:
+            found.append((l, waited))
+        # regs written here are the newest value on this path: stop for them
+        rest = regs - _writes(l)
+        if rest:
+            stack.extend((p, waited + _wait_states(l)) for p in preds[j])
+    return found
+
+
+def test_no_dpp_or_transcendental_forwarding_hazard(f32_asm):
+    lines = f32_asm
+    _predecessors.cache = _predecessors(lines)
+    n_dpp = n_fmac_dpp = 0
+    problems = []
+    for i, l in enumerate(lines):
+        if l.endswith(":") or l.startswith("s_"):
+            continue
+        op, args = _parse(l)
+        if not _is_valu(op):
+            continue
+        if "_dpp" in op:
+            n_dpp += 1
+            n_fmac_dpp += op.startswith("v_fmac_f32_dpp")
+            src0 = _regs(args[1]) if len(args) > 1 else set()
+            for p, w in _violations(lines, i, src0, 2, lambda x: _is_valu(_parse(x)[0])):
+                problems.append(f"DPP source written {w} wait states before: '{p}' -> '{l}'")
+        if not op.startswith(TRANS):
+            for p, w in _violations(lines, i, _reads(l), 1, lambda x: _parse(x)[0].startswith(TRANS)):
+                problems.append(f"transcendental result read after {w} wait states: '{p}' -> '{l}'")
+    assert not problems, "\n".join(problems[:20])
+    # the pair loops of both forms are present
+    assert n_fmac_dpp >= 64, n_fmac_dpp
+    assert n_dpp >= 128, n_dpp
+
+
+def test_checker_sees_planted_hazards():
+    """The checker itself: two planted sequences must be reported."""
+    lines = [
+        "v_cvt_f32_f64_e32 v3, v[4:5]",
+        "v_mul_f32_dpp v1, v3, v2 row_newbcast:0 row_mask:0xf bank_mask:0xf bound_ctrl:1",
+        "v_exp_f32_e32 v6, v1",
+        "v_fmac_f32_e32 v7, v6, v8",
+        "s_endpgm",
+    ]
+    _predecessors.cache = _predecessors(lines)
+    dpp = _violations(lines, 1, {3}, 2, lambda x: _is_valu(_parse(x)[0]))
+    trans = _violations(lines, 3, _reads(lines[3]), 1, lambda x: _parse(x)[0].startswith(TRANS))
+    assert dpp and trans
+    # and with the waits in place, nothing
+    ok = ["v_cvt_f32_f64_e32 v3, v[4:5]", "s_nop 1",
+          "v_mul_f32_dpp v1, v3, v2 row_newbcast:0 row_mask:0xf bank_mask:0xf bound_ctrl:1",
+          "v_exp_f32_e32 v6, v1", "s_nop 0", "v_fmac_f32_e32 v7, v6, v8"]
+    _predecessors.cache = _predecessors(ok)
+    assert not _violations(ok, 2, {3}, 2, lambda x: _is_valu(_parse(x)[0]))
+    assert not _violations(ok, 5, _reads(ok[5]), 1, lambda x: _parse(x)[0].startswith(TRANS))
+
+
+def test_checker_follows_branches():
+    lines = [
+        "s_cbranch_vccnz .LBB0_9",
+        "v_mov_b32_e32 v3, 0",
+        "s_branch .LBB0_10",
+        ".LBB0_9:",
+        "v_exp_f32_e32 v3, v1",
+        ".LBB0_10:",
+        "v_mul_f32_dpp v1, v3, v2 row_newbcast:0 row_mask:0xf bank_mask:0xf bound_ctrl:1",
+    ]
+    _predecessors.cache = _predecessors(lines)
+    found = _violations(lines, 6, {3}, 2, lambda x: _is_valu(_parse(x)[0]))
+    assert len(found) == 2   # both paths write v3 right before the DPP read
