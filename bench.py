@@ -28,13 +28,15 @@ if ROOT not in sys.path:
 
 METRIC = "RBF kernel evals/s (% FP32 roofline); solve+grid time to resid 1e-8 vs plain"
 
-# Pair roofline of the float32 kernel (alu bound; derivation in the design doc):
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-slots/s.  One useful
-# pair is 7 float32 add/mul/FMA operations and one v_exp_f32.  At the
-# published vector FP32 peak (packed FMA, two operations per lane-slot) the
-# seven take 3.5 slots and the exponential one issue slot: 4.5 slots/pair.
+# Pair roofline of the float32 kernel (alu bound):
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-slots/s.  A useful
+# pair needs at least four float32 operations (2 t.s as one multiply and two
+# FMAs, and the FMA of the weighted sum) and one exponential.  At the
+# published vector FP32 peak (packed, two operations per lane-slot) the four
+# take 2 slots; v_exp_f32 issues at half the FMA rate on gfx950 (2 slots).
+# 4 slots per pair: 9.83e12 pairs/s.
 LANE_SLOTS = 256 * 4 * 16 * 2.4e9
-PEAK_PAIRS = LANE_SLOTS / 4.5
+PEAK_PAIRS = LANE_SLOTS / 4.0
 
 # HBM bytes per operator launch of the float32 kernel, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the same counters on a copy of

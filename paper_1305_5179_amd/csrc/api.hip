@@ -274,7 +274,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     // 6. the centres as targets, with their source lists
     TargetSet& ts = c->centres;
     ts.dense = !std::isfinite(cutoff);
-    group_targets(*c, c->xs, nullptr, c->m, ts, s);
+    centre_targets(*c, ts, s);
     build_lists(*c, ts, s);
     // 7. work vectors
     c->vin = dalloc<double>(c->mpad);

@@ -25,6 +25,9 @@ constexpr int kGroup = 16;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;
 constexpr int kBlock = 256;          // threads per block of the pair kernels (4 independent waves)
+// Padding entries after the last group's list: the pair kernels read the
+// list indices up to three chunks ahead without bounds tests.
+constexpr int kListTail = 3 * kChunk;
 
 // Curve keys (Hilbert order): 10 bits per axis on the fine lattice.
 constexpr int kCurveBits = 10;
@@ -203,9 +206,11 @@ int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const La
                     int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);
+void centre_targets(const Ctx& c, TargetSet& ts, hipStream_t s);
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void fill_f32(float* p, float v, int64_t n, hipStream_t s);
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
 // pairsum.hip
 // out[ts.index[t]] = sum over the source list of target t (float output when

@@ -214,53 +214,68 @@ __device__ __forceinline__ uint32_t list_entry(const PairArgs& a, const GroupInf
 // stay normal float32 numbers with room for the weights).
 constexpr double kExpandMax = 100.0;
 
-// The pair loop of one group: software pipeline over the chunks, the list
-// index two chunks ahead and the source gather one chunk ahead in flight
-// while a chunk computes.
+// One chunk: the anchor-relative float32 source of this lane, then the 16
+// steps (inner chunks without a test, the others with their lane masks).
+template <bool EXPAND>
+__device__ __forceinline__ void chunk_sum(float& acc, const PairArgs& a, const Tgt& t, const uint64_t* masks, int c,
+                                          int nin, const double4& sk, double wk, double akx, double aky,
+                                          double akz) {
+  Src s;
+  const double dx = sk.x - akx, dy = sk.y - aky, dz = sk.z - akz;
+  s.x = (float)dx;
+  s.y = (float)dy;
+  s.z = (float)dz;
+  if constexpr (EXPAND) {
+    // |s|^2 from the float64 differences: it differs from the squared norm
+    // of the rounded coordinates by at most u |s|^2, the size of the
+    // rounding of the dot product itself
+    const double q = fma(dx, dx, fma(dy, dy, dz * dz));
+    s.w = (float)wk * __builtin_amdgcn_exp2f(-(float)q);
+  } else {
+    s.w = (float)wk;
+  }
+  if (c < nin) {
+    if constexpr (EXPAND) {
+      expanded_inner_chunk(acc, t, s);
+    } else {
+      RBF_STEPS(direct_inner, acc, t, s);
+    }
+  } else {
+    const StepMasks mk = load_masks(masks + (int64_t)c * 16);
+    if constexpr (EXPAND) {
+      expanded_masked_chunk(acc, t, s, mk);
+    } else {
+      RBF_STEPS(direct_masked, acc, t, s, mk);
+    }
+  }
+}
+
+// The pair loop of one group, unrolled by two with fixed double buffers:
+// the source gather of chunk c + 1 and the list index of chunk c + 2 are in
+// flight while chunk c computes.  The loads are unconditional (the list
+// array ends with kListTail padding entries, so the indices read past a
+// group's last chunk are valid sources), which keeps every wait for a load
+// one chunk of work after its issue.
 template <bool EXPAND>
 __device__ __forceinline__ float group_sum(const PairArgs& a, const GroupInfo& gi, const Tgt& t, int lane,
                                            double akx, double aky, double akz) {
   float acc = 0.0f;
   const int nch = gi.n_chunks, nin = gi.n_inner;
   const uint64_t* masks = a.mask + (gi.off >> 2);
-  uint32_t idx_next = nch > 0 ? list_entry(a, gi, 0, lane) : (uint32_t)a.m;
-  double4 s_next = a.xk[idx_next];
-  double w_next = a.w[idx_next];
-  uint32_t idx_after = nch > 1 ? list_entry(a, gi, 1, lane) : (uint32_t)a.m;
-  for (int c = 0; c < nch; ++c) {
-    Src s;
-    s.x = (float)(s_next.x - akx);
-    s.y = (float)(s_next.y - aky);
-    s.z = (float)(s_next.z - akz);
-    if constexpr (EXPAND) {
-      // |s|^2 of the rounded coordinates (exact in float64), so that
-      // |t|^2 + |s|^2 - 2 t.s is the squared distance of the very vectors
-      // whose dot product the steps form
-      const double q = ((double)s.x * s.x + (double)s.y * s.y) + (double)s.z * s.z;
-      s.w = (float)w_next * __builtin_amdgcn_exp2f(-(float)q);
-    } else {
-      s.w = (float)w_next;
-    }
-    if (c + 1 < nch) {
-      idx_next = idx_after;
-      s_next = a.xk[idx_next];
-      w_next = a.w[idx_next];
-    }
-    if (c + 2 < nch) idx_after = list_entry(a, gi, c + 2, lane);
-    if (c < nin) {
-      if constexpr (EXPAND) {
-        expanded_inner_chunk(acc, t, s);
-      } else {
-        RBF_STEPS(direct_inner, acc, t, s);
-      }
-    } else {
-      const StepMasks mk = load_masks(masks + (int64_t)c * 16);
-      if constexpr (EXPAND) {
-        expanded_masked_chunk(acc, t, s, mk);
-      } else {
-        RBF_STEPS(direct_masked, acc, t, s, mk);
-      }
-    }
+  const uint32_t i0 = list_entry(a, gi, 0, lane);
+  uint32_t i1 = list_entry(a, gi, 1, lane);
+  double4 sA = a.xk[i0];
+  double wA = a.w[i0];
+  for (int c = 0; c < nch; c += 2) {
+    const double4 sB = a.xk[i1];
+    const double wB = a.w[i1];
+    const uint32_t i2 = list_entry(a, gi, c + 2, lane);
+    chunk_sum<EXPAND>(acc, a, t, masks, c, nin, sA, wA, akx, aky, akz);
+    if (c + 1 >= nch) break;
+    sA = a.xk[i2];
+    wA = a.w[i2];
+    i1 = list_entry(a, gi, c + 3, lane);
+    chunk_sum<EXPAND>(acc, a, t, masks, c + 1, nin, sB, wB, akx, aky, akz);
   }
   return acc;
 }

@@ -353,6 +353,10 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
 // ---------------------------------------------------------------------------
 // Source lists.  One wave per group of 16 targets, anchor a (centre of their
@@ -815,6 +819,36 @@ __global__ void k_place_targets(const double4* __restrict__ sp, const uint32_t* 
   oidx[t] = orig ? (int64_t)orig[k] : k;
 }
 
+// Target order of the centres: the surface points in curve order (their
+// on-surface centre, paper index i < n, in sorted order), each followed by
+// its two off-surface centres i + n and i + 2n, which lie within the offset
+// of it.  Groups of whole triples cover fewer surface points than groups of
+// centres in their own curve order, so their source lists are shorter.
+__global__ void k_invert_perm(const uint32_t* __restrict__ perm, int64_t m, uint32_t* __restrict__ inv) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) inv[perm[k]] = (uint32_t)k;
+}
+__global__ void k_surface_flags(const uint32_t* __restrict__ perm, int64_t m, int64_t n, int64_t* __restrict__ f) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) f[k] = perm[k] < (uint32_t)n ? 1 : 0;
+}
+__global__ void k_triple_order(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ inv,
+                               const int64_t* __restrict__ rank, int64_t m, int64_t n, const double4* __restrict__ xs,
+                               uint32_t* __restrict__ order, double4* __restrict__ sp) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const uint32_t i = perm[k];
+  if (i >= (uint32_t)n) return;
+  const int64_t r = rank[k];
+  const uint32_t k1 = inv[i + n], k2 = inv[i + 2 * n];
+  order[3 * r] = (uint32_t)k;
+  order[3 * r + 1] = k1;
+  order[3 * r + 2] = k2;
+  sp[3 * r] = xs[k];
+  sp[3 * r + 1] = xs[k1];
+  sp[3 * r + 2] = xs[k2];
+}
+
 // Points of an evaluation set in a given order, as double4.
 __global__ void k_gather_points(const double* __restrict__ P, const uint32_t* __restrict__ perm, int64_t n,
                                 double4* __restrict__ sp) {
@@ -955,6 +989,30 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   temp_free(slot_of);
 }
 
+// The centres as the operator's targets, grouped by surface-point triples
+// (m = 3 n centres, sorted by `perm`).
+void centre_targets(const Ctx& c, TargetSet& ts, hipStream_t s) {
+  const int64_t m = c.m, n = c.n;
+  uint32_t* inv = talloc<uint32_t>(m);
+  int64_t* flag = talloc<int64_t>(m);
+  int64_t* rank = talloc<int64_t>(m);
+  uint32_t* order = talloc<uint32_t>(m);
+  double4* sp = talloc<double4>(m);
+  hipLaunchKernelGGL(k_invert_perm, dim3(grid_for(m)), dim3(kThreads), 0, s, c.perm, m, inv);
+  hipLaunchKernelGGL(k_surface_flags, dim3(grid_for(m)), dim3(kThreads), 0, s, c.perm, m, n, flag);
+  RBF_HIP(hipGetLastError());
+  scan_exclusive_i64(flag, rank, m, s);
+  hipLaunchKernelGGL(k_triple_order, dim3(grid_for(m)), dim3(kThreads), 0, s, c.perm, inv, rank, m, n, c.xs, order,
+                     sp);
+  RBF_HIP(hipGetLastError());
+  group_targets(c, sp, order, m, ts, s);
+  temp_free(inv);
+  temp_free(flag);
+  temp_free(rank);
+  temp_free(order);
+  temp_free(sp);
+}
+
 void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
@@ -963,6 +1021,11 @@ void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
 void fill_f32(float* p, float v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
+  RBF_HIP(hipGetLastError());
+}
+void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
   RBF_HIP(hipGetLastError());
 }
 
@@ -1004,8 +1067,9 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     RBF_HIP(hipMemcpyAsync(&ts.useful, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
     ts.list_entries = last_off + last_len;
-    ts.list = set_alloc<uint32_t>(ts, ts.list_entries);
+    ts.list = set_alloc<uint32_t>(ts, ts.list_entries + kListTail);
     ts.owned.push_back(ts.list);
+    fill_u32(ts.list + ts.list_entries, (uint32_t)c.m, kListTail, s);
     ts.mask = set_alloc<uint16_t>(ts, ts.list_entries);
     ts.owned.push_back(ts.mask);
     hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
