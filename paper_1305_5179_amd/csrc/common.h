@@ -45,10 +45,18 @@ constexpr double kFar = 1.0e6;
 struct GroupInfo {
   int64_t off;          // first list entry of the group (a multiple of 64)
   int32_t n_chunks;     // list length / 64
-  int32_t n_inner;      // chunks [0, n_inner) hold inner sources only
+  int32_t n_inner;      // chunks [0, n_inner) hold inner sources only (an even count)
   double ax, ay, az;    // anchor (unscaled float64); float32 coordinates are taken relative to it
   double radius;        // max distance of a valid target from the anchor
 };
+
+// Number of leading chunks of a group's list that the pair kernels treat as
+// inner (no test): the whole chunks of inner sources, rounded down to an even
+// count (the kernels' chunk loop is unrolled by two; a chunk beyond it
+// carries masks like the outer chunks).
+__host__ __device__ inline int64_t inner_chunks(int64_t n_inner_sources) {
+  return (n_inner_sources / kChunk) & ~int64_t(1);
+}
 
 // Position in the mask array of list entry e of a group starting at `off`.
 // Entry e = 64 c + 16 r + k is the source that row r of a wave broadcasts at
@@ -56,6 +64,18 @@ struct GroupInfo {
 // four masks of step k form one 64-bit lane mask (bit 16 r + t = target t).
 __host__ __device__ inline int64_t mask_slot(int64_t off, int64_t e) {
   return off + (e & ~int64_t(63)) + ((e & 15) << 2) + ((e >> 4) & 3);
+}
+
+// Form of a group's float32 pair sums.  The expanded form writes the scaled
+// squared distance as |t|^2 + |s|^2 - 2 t.s (anchor-relative coordinates); it
+// applies when every listed source is within rk + sqrt(T) of the anchor with
+// (rk + sqrt(T))^2 <= 100 and 2 rk (rk + sqrt(T)) <= 100 (scaled units),
+// which keeps every exponent in range and the rounding of |s|^2 and 2 t.s at
+// a few float32 units of the term.  Other groups, and dense lists, take the
+// direct differences.
+__host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt_T) {
+  const double smax = rk + sqrt_T;
+  return !dense && smax * smax <= 100.0 && 2.0 * rk * smax <= 100.0;
 }
 
 // A set of targets grouped by 16 (centres, grid nodes or evaluation points)
@@ -189,6 +209,10 @@ template <class T>
 T* set_alloc(const TargetSet& ts, int64_t count) {
   return ts.temp ? talloc<T>(count) : dalloc<T>(count);
 }
+
+// sqrt(T), the scaled cutoff r_c sqrt(k), as the pair kernels give it to
+// expanded_form.
+inline double scaled_cutoff(const Ctx& c) { return std::isfinite(c.rc2) ? std::sqrt(c.rc2) * c.sqrt_k : INFINITY; }
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files).

@@ -46,6 +46,7 @@ struct PairArgs {
   double inv_two_s2;
   double rc2;
   double Tk;             // scaled cutoff^2, k r_c^2
+  double sqrt_T;         // scaled cutoff (as the list builder computes it)
   int dense;
   int out_f32;
   void* out;
@@ -85,12 +86,14 @@ __device__ __forceinline__ void fmac_bcast(float& acc, float src, float other) {
   }
 }
 
+// Direct form: a lane's target and the source it contributes to the chunk
+// (anchor-relative, scaled, float32).
 struct Tgt {
-  float x, y, z;   // direct: t; expanded: 2 t
+  float x, y, z;
 };
 struct Src {
-  float x, y, z;   // s (anchor-relative, scaled)
-  float w;         // direct: w; expanded: w 2^{-|s|^2}
+  float x, y, z;
+  float w;
 };
 
 // ---- direct form ----------------------------------------------------------
@@ -120,7 +123,14 @@ struct StepMasks {
 };
 typedef const __attribute__((address_space(4))) uint64_t* ConstU64;
 __device__ __forceinline__ StepMasks load_masks(const uint64_t* mk) {
-  const ConstU64 p = (ConstU64)mk;
+  // the address is uniform; read-first-lane states it, so that the loads are
+  // scalar whatever the compiler proves about where the pointer came from
+  // (read-first-lane returns int: go through uint32_t, or bit 31 of the low
+  // word would be sign-extended into the high word)
+  const uint64_t u = (uint64_t)mk;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  const ConstU64 p = (ConstU64)((hi << 32) | lo);
   StepMasks r;
 #pragma unroll
   for (int k = 0; k < 16; ++k) r.m[k] = p[k];
@@ -210,111 +220,154 @@ __device__ __forceinline__ uint32_t list_entry(const PairArgs& a, const GroupInf
   return a.list[gi.off + (int64_t)c * kChunk + lane];
 }
 
-// Largest |s|^2 and 2|t||s| the expanded form admits (2^{-100} and 2^{100}
-// stay normal float32 numbers with room for the weights).
-constexpr double kExpandMax = 100.0;
-
-// One chunk: the anchor-relative float32 source of this lane, then the 16
-// steps (inner chunks without a test, the others with their lane masks).
-template <bool EXPAND>
-__device__ __forceinline__ void chunk_sum(float& acc, const PairArgs& a, const Tgt& t, const uint64_t* masks, int c,
-                                          int nin, const double4& sk, double wk, double akx, double aky,
-                                          double akz) {
-  Src s;
-  const double dx = sk.x - akx, dy = sk.y - aky, dz = sk.z - akz;
-  s.x = (float)dx;
-  s.y = (float)dy;
-  s.z = (float)dz;
-  if constexpr (EXPAND) {
-    // |s|^2 from the float64 differences: it differs from the squared norm
-    // of the rounded coordinates by at most u |s|^2, the size of the
-    // rounding of the dot product itself
-    const double q = fma(dx, dx, fma(dy, dy, dz * dz));
-    s.w = (float)wk * __builtin_amdgcn_exp2f(-(float)q);
-  } else {
-    s.w = (float)wk;
-  }
-  if (c < nin) {
-    if constexpr (EXPAND) {
-      expanded_inner_chunk(acc, t, s);
-    } else {
-      RBF_STEPS(direct_inner, acc, t, s);
-    }
-  } else {
-    const StepMasks mk = load_masks(masks + (int64_t)c * 16);
-    if constexpr (EXPAND) {
-      expanded_masked_chunk(acc, t, s, mk);
-    } else {
-      RBF_STEPS(direct_masked, acc, t, s, mk);
-    }
-  }
-}
-
 // The pair loop of one group, unrolled by two with fixed double buffers:
 // the source gather of chunk c + 1 and the list index of chunk c + 2 are in
 // flight while chunk c computes.  The loads are unconditional (the list
 // array ends with kListTail padding entries, so the indices read past a
 // group's last chunk are valid sources), which keeps every wait for a load
-// one chunk of work after its issue.
-template <bool EXPAND>
-__device__ __forceinline__ float group_sum(const PairArgs& a, const GroupInfo& gi, const Tgt& t, int lane,
-                                           double akx, double aky, double akz) {
-  float acc = 0.0f;
+// one chunk of work after its issue.  The inner chunks (an even count) run
+// in one straight loop, the masked ones in a second loop on the same
+// pipeline, so neither body branches on the chunk kind.
+template <class Inner, class Masked>
+__device__ __forceinline__ void chunk_loop(const PairArgs& a, const GroupInfo& gi, int lane, Inner&& inner,
+                                           Masked&& masked) {
   const int nch = gi.n_chunks, nin = gi.n_inner;
-  const uint64_t* masks = a.mask + (gi.off >> 2);
   const uint32_t i0 = list_entry(a, gi, 0, lane);
   uint32_t i1 = list_entry(a, gi, 1, lane);
   double4 sA = a.xk[i0];
   double wA = a.w[i0];
-  for (int c = 0; c < nch; c += 2) {
+  int c = 0;
+  for (; c < nin; c += 2) {
     const double4 sB = a.xk[i1];
     const double wB = a.w[i1];
     const uint32_t i2 = list_entry(a, gi, c + 2, lane);
-    chunk_sum<EXPAND>(acc, a, t, masks, c, nin, sA, wA, akx, aky, akz);
+    inner(c, sA, wA);
+    sA = a.xk[i2];
+    wA = a.w[i2];
+    i1 = list_entry(a, gi, c + 3, lane);
+    inner(c + 1, sB, wB);
+  }
+  for (; c < nch; c += 2) {
+    const double4 sB = a.xk[i1];
+    const double wB = a.w[i1];
+    const uint32_t i2 = list_entry(a, gi, c + 2, lane);
+    masked(c, sA, wA);
     if (c + 1 >= nch) break;
     sA = a.xk[i2];
     wA = a.w[i2];
     i1 = list_entry(a, gi, c + 3, lane);
-    chunk_sum<EXPAND>(acc, a, t, masks, c + 1, nin, sB, wB, akx, aky, akz);
+    masked(c + 1, sB, wB);
   }
-  return acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
-  // the wave index is uniform across the wave: keep it (and all group data) scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63, row = lane >> 4, tl = lane & 15;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (g >= a.G) return;
-  if (a.skip && *a.skip) return;
-  const GroupInfo gi = a.groups[g];
+// ---- direct form ----------------------------------------------------------
+template <bool MASKED>
+__device__ __forceinline__ void direct_chunk(float& acc, const Tgt& t, const double4& sk, double wk, double akx,
+                                             double aky, double akz, const uint64_t* mk) {
+  Src s;
+  s.x = (float)(sk.x - akx);
+  s.y = (float)(sk.y - aky);
+  s.z = (float)(sk.z - akz);
+  s.w = (float)wk;
+  if constexpr (MASKED) {
+    const StepMasks m = load_masks(mk);
+    RBF_STEPS(direct_masked, acc, t, s, m);
+  } else {
+    RBF_STEPS(direct_inner, acc, t, s);
+  }
+}
+
+__device__ __forceinline__ void direct_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
+  const int row = lane >> 4, tl = lane & 15;
+  const int64_t tid = g * kGroup + tl;
+  const double4 tp = a.tpts[tid];
+  const Tgt t{(float)((tp.x - gi.ax) * a.sqrt_k), (float)((tp.y - gi.ay) * a.sqrt_k),
+              (float)((tp.z - gi.az) * a.sqrt_k)};
+  const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
+  const uint64_t* masks = a.mask + (gi.off >> 2);
+  float acc = 0.0f;
+  chunk_loop(
+      a, gi, lane,
+      [&](int, const double4& sk, double wk) { direct_chunk<false>(acc, t, sk, wk, akx, aky, akz, nullptr); },
+      [&](int c, const double4& sk, double wk) {
+        direct_chunk<true>(acc, t, sk, wk, akx, aky, akz, masks + (int64_t)c * 16);
+      });
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  if (row == 0 && tp.w != 0.0) store_result(a, tid, (double)acc);
+}
+
+// ---- expanded form --------------------------------------------------------
+__device__ __forceinline__ Src expanded_source(const double4& sk, double wk, double akx, double aky, double akz) {
+  Src s;
+  const double dx = sk.x - akx, dy = sk.y - aky, dz = sk.z - akz;
+  s.x = (float)dx;
+  s.y = (float)dy;
+  s.z = (float)dz;
+  // |s|^2 from the float64 differences: it differs from the squared norm of
+  // the rounded coordinates by at most u |s|^2, the size of the rounding of
+  // the dot product itself
+  const double q = fma(dx, dx, fma(dy, dy, dz * dz));
+  s.w = (float)wk * __builtin_amdgcn_exp2f(-(float)q);
+  return s;
+}
+
+__device__ __forceinline__ void expanded_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
+  const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
   const double4 tp = a.tpts[tid];
   const float tx = (float)((tp.x - gi.ax) * a.sqrt_k);
   const float ty = (float)((tp.y - gi.ay) * a.sqrt_k);
   const float tz = (float)((tp.z - gi.az) * a.sqrt_k);
+  const Tgt t{2.0f * tx, 2.0f * ty, 2.0f * tz};
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
-  // expanded form when the exponents stay in range: every listed source is
-  // within R + sqrt(T) of the anchor (scaled units)
-  const double rk = gi.radius * a.sqrt_k;
-  const double smax = rk + sqrt(a.Tk);
-  const bool expand = !a.dense && smax * smax <= kExpandMax && 2.0 * rk * smax <= kExpandMax;
-  double res;
-  if (expand) {
-    const Tgt t{2.0f * tx, 2.0f * ty, 2.0f * tz};
-    float acc = group_sum<true>(a, gi, t, lane, akx, aky, akz);
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    const double tq = ((double)tx * tx + (double)ty * ty) + (double)tz * tz;
-    res = (double)acc * exp2(-tq);
-  } else {
-    const Tgt t{tx, ty, tz};
-    float acc = group_sum<false>(a, gi, t, lane, akx, aky, akz);
-    acc += __shfl_xor(acc, 16);
-    acc += __shfl_xor(acc, 32);
-    res = (double)acc;
-  }
-  if (row == 0 && tp.w != 0.0) store_result(a, tid, res);
+  const uint64_t* masks = a.mask + (gi.off >> 2);
+  float acc = 0.0f;
+  chunk_loop(
+      a, gi, lane,
+      [&](int, const double4& sk, double wk) {
+        expanded_inner_chunk(acc, t, expanded_source(sk, wk, akx, aky, akz));
+      },
+      [&](int c, const double4& sk, double wk) {
+        const Src s = expanded_source(sk, wk, akx, aky, akz);
+        expanded_masked_chunk(acc, t, s, load_masks(masks + (int64_t)c * 16));
+      });
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  // |t|^2 of the rounded coordinates the steps used
+  const double tq = ((double)tx * tx + (double)ty * ty) + (double)tz * tz;
+  if (row == 0 && tp.w != 0.0) store_result(a, tid, (double)acc * exp2(-tq));
+}
+
+// A group record read field by field through the constant address space
+// (nothing writes it during the launch): scalar loads, so every field is
+// uniform for the compiler too.
+__device__ __forceinline__ GroupInfo load_group(const GroupInfo* gp) {
+  typedef const __attribute__((address_space(4))) GroupInfo* ConstGroup;
+  const ConstGroup p = (ConstGroup)gp;
+  GroupInfo gi;
+  gi.off = p->off;
+  gi.n_chunks = p->n_chunks;
+  gi.n_inner = p->n_inner;
+  gi.ax = p->ax;
+  gi.ay = p->ay;
+  gi.az = p->az;
+  gi.radius = p->radius;
+  return gi;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
+  // the wave index is uniform across the wave: keep it (and all group data) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (g >= a.G) return;
+  if (a.skip && *a.skip) return;
+  const GroupInfo gi = load_group(a.groups + g);
+  if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
+    expanded_group(a, gi, g, lane);
+  else
+    direct_group(a, gi, g, lane);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
@@ -387,6 +440,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.out_index = ts.index;
   a.skip = skip;
   a.Tk = std::isfinite(c.rc2) ? c.rc2 * c.sqrt_k * c.sqrt_k : INFINITY;
+  a.sqrt_T = scaled_cutoff(c);
   return a;
 }
 

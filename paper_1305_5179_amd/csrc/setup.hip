@@ -474,7 +474,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   if (WRITE) {
     o.base = groups[g].off;
     o.out0 = cnt_in[g];
-    o.in_full = round_down(o.out0, kChunk);
+    o.in_full = inner_chunks(o.out0) * kChunk;
   }
   if (nvalid == 0) {
     if (!WRITE && lane == 0) {
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       GroupInfo gi;
       gi.off = 0;
       gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out, kChunk);
-      gi.n_inner = (int32_t)(n.n_in / kChunk);
+      gi.n_inner = (int32_t)inner_chunks(n.n_in);
       gi.ax = ax; gi.ay = ay; gi.az = az;
       gi.radius = rad;
       groups[g] = gi;

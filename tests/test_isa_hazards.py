@@ -76,10 +76,12 @@ def _is_valu(op):
 
 
 def _writes(instr):
-    """VGPRs written by a VALU instruction."""
+    """VGPRs written by a VALU instruction (both operands of a lane swap)."""
     op, args = _parse(instr)
     if not _is_valu(op) or not args or op.startswith(("v_cmp", "v_readlane", "v_readfirstlane")):
         return set()
+    if op.startswith(("v_permlane16_swap", "v_permlane32_swap")) and len(args) > 1:
+        return _regs(args[0]) | _regs(args[1])
     return _regs(args[0])
 
 
