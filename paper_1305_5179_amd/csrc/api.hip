@@ -150,8 +150,11 @@ Lattice make_lattice(const double box[6], double cutoff) {
 void ensure_solver(Ctx* c, int m) {
   if (c->V && c->krylov_m >= m) return;
   dfree(c->V);
-  c->V = dalloc<double>((int64_t)(m + 1) * c->mpad);
-  RBF_HIP(hipMemsetAsync(c->V, 0, sizeof(double) * (size_t)(m + 1) * c->mpad, temp_stream()));
+  // m + 1 basis vectors, rounded up to whole blocks of the dot-product
+  // kernels' column loop (they read the extra columns, zero, unguarded)
+  const int64_t cols = round_up(m + 1, kKrylovColPad);
+  c->V = dalloc<double>(cols * c->mpad);
+  RBF_HIP(hipMemsetAsync(c->V, 0, sizeof(double) * (size_t)(cols * c->mpad), temp_stream()));
   c->krylov_m = m;
   if (!c->w) {
     c->w = dalloc<double>(c->mpad);

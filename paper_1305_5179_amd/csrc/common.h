@@ -28,6 +28,9 @@ constexpr int kBlock = 256;          // threads per block of the pair kernels (4
 // Padding entries after the last group's list: the pair kernels read the
 // list indices up to three chunks ahead without bounds tests.
 constexpr int kListTail = 3 * kChunk;
+// The Krylov basis is allocated with its column count rounded up to this
+// (extra columns zero): the dot-product kernels read columns in blocks of it.
+constexpr int kKrylovColPad = 8;
 
 // Curve keys (Hilbert order): 10 bits per axis on the fine lattice.
 constexpr int kCurveBits = 10;

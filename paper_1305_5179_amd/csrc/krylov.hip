@@ -54,6 +54,39 @@ __device__ __forceinline__ void block_store(double (*s)[kMaxRestart + 1], int nc
     partial[(int64_t)blockIdx.x * (kMaxRestart + 1) + i] = ((s[0][i] + s[1][i]) + s[2][i]) + s[3][i];
 }
 
+// Dot products of the block's rows of x with columns 0..ncols-1 of V, into
+// s[wave][i].  Columns go eight at a time with eight independent sums, so the
+// loads of a block of columns are all in flight together and the eight wave
+// reductions interleave.  The basis holds round_up(ncols, 8) finite columns
+// (kKrylovColPad; zeroed at allocation), so the block reads them unguarded
+// and keeps only the first ncols sums.
+constexpr int kColPad = kKrylovColPad;
+__device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t ldv, int ncols,
+                                           const double (&x)[kRowsPerThread], int64_t base, int64_t n,
+                                           double (*s)[kMaxRestart + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < ncols; i0 += kColPad) {
+    double a[kColPad];
+#pragma unroll
+    for (int c = 0; c < kColPad; ++c) a[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      const int64_t r = base + (int64_t)q * kVecThreads;
+      if (r < n) {
+#pragma unroll
+        for (int c = 0; c < kColPad; ++c) a[c] = fma(V[(int64_t)(i0 + c) * ldv + r], x[q], a[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kColPad; ++c) a[c] = wave_sum(a[c]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < kColPad; ++c)
+        if (i0 + c < ncols) s[wave][i0 + c] = a[c];
+    }
+  }
+}
+
 // pass 1: partial[b][i] = sum_{r in block b} V_i[r] w[r]
 __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__ V, int64_t ldv, int ncols,
                                                       const double* __restrict__ w, int64_t n,
@@ -67,15 +100,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
     const int64_t r = base + (int64_t)q * kVecThreads;
     wr[q] = r < n ? w[r] : 0.0;
   }
-  for (int i = 0; i < ncols; ++i) {
-    double a = 0.0;
-#pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
-      const int64_t r = base + (int64_t)q * kVecThreads;
-      if (r < n) a = fma(V[(int64_t)i * ldv + r], wr[q], a);
-    }
-    wave_partial(a, i, s);
-  }
+  block_dots(V, ldv, ncols, wr, base, n, s);
   block_store(s, ncols, partial);
 }
 
@@ -102,15 +127,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots(const double* __res
     }
   }
   __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
-  for (int i = 0; i < ncols; ++i) {
-    double a = 0.0;
-#pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) {
-      const int64_t r = base + (int64_t)q * kVecThreads;
-      if (r < n) a = fma(V[(int64_t)i * ldv + r], wr[q], a);
-    }
-    wave_partial(a, i, s);
-  }
+  block_dots(V, ldv, ncols, wr, base, n, s);
   block_store(s, ncols, partial);
 }
 
