@@ -356,11 +356,17 @@ __device__ __forceinline__ GroupInfo load_group(const GroupInfo* gp) {
   return gi;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairsum_f32(PairArgs a) {
+// Waves (groups) per workgroup.  One wave per workgroup lets the dispatcher
+// balance the uneven group costs wave by wave (occupancy 87 % against 82 %)
+// but measured 3 % slower: the kernel is bound by VALU issue, not by the
+// tail.
+constexpr int kPairWaves = 4;
+
+__global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kPairWaves + wave;
   if (g >= a.G) return;
   if (a.skip && *a.skip) return;
   const GroupInfo gi = load_group(a.groups + g);
@@ -517,9 +523,9 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
                  const int* skip) {
   if (ts.n_groups == 0) return;
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
-  const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
+  const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
   ProfScope prof(RBF_FP32, ts, s);
-  hipLaunchKernelGGL(k_pairsum_f32, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_pairsum_f32, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }

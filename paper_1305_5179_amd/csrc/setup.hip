@@ -370,8 +370,10 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 // and |s - a| - R > r_c (1 + 1e-12) drops it, without looking at the
 // targets (the relative margin covers the float64 rounding of the distances
 // and of the exact test), whole cells at a time when the cell box allows.
-// The cells near the anchor are examined one per lane; the sources of the
-// cells that remain are classified one per lane; the remaining "shell"
+// The cells near the anchor are examined one per lane (with their source
+// ranges); the sources of the cells that remain are then classified 64 at a
+// time, one per lane, across cell boundaries (a lane finds its cell by a
+// binary search of the block's count prefix in LDS); the remaining "shell"
 // sources are queued in LDS and tested exactly against the 16 targets, 64
 // at a time (targets in scalar registers).
 // Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
@@ -450,11 +452,16 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
                                                     int64_t* __restrict__ useful, uint32_t* __restrict__ list,
                                                     uint16_t* __restrict__ mask) {
   __shared__ uint32_t qbuf[kThreads / kWave][2 * kWave];
+  __shared__ int32_t cpre_s[kThreads / kWave][kWave], cst_s[kThreads / kWave][kWave];
+  __shared__ uint8_t cwhole_s[kThreads / kWave][kWave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= G) return;
   uint32_t* q = qbuf[wave];
+  int32_t* cpre = cpre_s[wave];
+  int32_t* cst = cst_s[wave];
+  uint8_t* cwhole = cwhole_s[wave];
   const double4* tg = tpts + g * kGroup;
   // the group's box, anchor and radius (uniform)
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -539,44 +546,63 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
         whole = dmax2 * (1.0 + 1e-9) <= r_in2;
       }
     }
-    uint64_t sel = ballot(cid >= 0);
-    const uint64_t wsel = ballot(cid >= 0 && whole);
-    while (sel) {
-      const int src_lane = __builtin_ctzll(sel);
-      sel &= sel - 1;
-      const int32_t cell = __builtin_amdgcn_readlane(cid, src_lane);
-      const bool cell_inner = (wsel >> src_lane) & 1ull;
-      const int32_t st = cstart[cell], ct = ccount[cell];
-      for (int b0 = 0; b0 < ct; b0 += kWave) {
-        const bool valid = b0 + lane < ct;
-        const uint32_t k = (uint32_t)(st + b0 + lane);
-        bool is_in = false, is_shell = false;
-        if (valid) {
-          if (cell_inner) {
-            is_in = true;
-          } else {
-            const double4 s = xs[k];
-            const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            is_in = d2 <= r_in2;
-            is_shell = !is_in && d2 <= r_out2;
-          }
+    // the occupied cells of this block, compacted in lane order, with the
+    // exclusive prefix of their source counts: the block's candidate
+    // sources are then taken 64 at a time across cell boundaries
+    const int32_t ct = cid >= 0 ? ccount[cid] : 0;
+    const int32_t st = cid >= 0 ? cstart[cid] : 0;
+    const bool occ = ct > 0;   // (empty cells would break the search below)
+    const uint64_t sel = ballot(occ);
+    const int nocc = __popcll(sel);
+    int32_t incl = ct;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int32_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int32_t total = __shfl(incl, kWave - 1);
+    wave_sync_lds();
+    if (occ) {
+      const int pos = lanes_below(sel);
+      cpre[pos] = incl - ct;
+      cst[pos] = st;
+      cwhole[pos] = whole ? 1 : 0;
+    }
+    wave_sync_lds();
+    for (int32_t b0 = 0; b0 < total; b0 += kWave) {
+      const int32_t f = b0 + lane;
+      const bool valid = f < total;
+      // the cell of flattened source f: the last j with cpre[j] <= f
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (j + step < nocc && cpre[j + step] <= f) j += step;
+      const uint32_t k = (uint32_t)(cst[j] + (f - cpre[j]));
+      bool is_in = false, is_shell = false;
+      if (valid) {
+        if (cwhole[j]) {
+          is_in = true;
+        } else {
+          const double4 s = xs[k];
+          const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
+          const double d2 = (dx * dx + dy * dy) + dz * dz;
+          is_in = d2 <= r_in2;
+          is_shell = !is_in && d2 <= r_out2;
         }
-        const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-        if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
-        n.n_in += __popcll(mi);
-        n.use += (int64_t)__popcll(mi) * nvalid;
-        if (is_shell) q[qn + lanes_below(ms)] = k;
-        qn += __popcll(ms);
-        if (qn >= kWave) {
-          wave_sync_lds();
-          process_shell<WRITE>(q, kWave, tg, xs, vmask, rc2, o, n);
-          const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
-          wave_sync_lds();
-          if (lane + kWave < qn) q[lane] = rest;
-          qn -= kWave;
-          wave_sync_lds();
-        }
+      }
+      const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
+      if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
+      n.n_in += __popcll(mi);
+      n.use += (int64_t)__popcll(mi) * nvalid;
+      if (is_shell) q[qn + lanes_below(ms)] = k;
+      qn += __popcll(ms);
+      if (qn >= kWave) {
+        wave_sync_lds();
+        process_shell<WRITE>(q, kWave, tg, xs, vmask, rc2, o, n);
+        const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
+        wave_sync_lds();
+        if (lane + kWave < qn) q[lane] = rest;
+        qn -= kWave;
+        wave_sync_lds();
       }
     }
   }

@@ -342,6 +342,69 @@ def test_torus_grid_sampled_nodes(torus_full, torch):
 
 
 # ---------------------------------------------------------------------------
+# The metaball workload's geometry (hole, position noise, sigma 0.01, cutoff
+# 4 sigma) at 100,000 points: sampled operator rows, sampled grid nodes and
+# the pair count of sampled rows.
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def metaballs_100k(torch, R):
+    cfg = dict(w.METABALLS_2M)
+    c = w.metaballs(100_000, cfg["seed"])
+    X, b = o.extended_centres(c.points, c.normals, cfg["eps"])
+    _say("[metaballs 100k] setup")
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), cfg["eps"], cfg["sigma"], cfg["cutoff"])
+    yield dict(c=c, X=X, b=b, ctx=ctx, cfg=cfg)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_metaballs_operator_sampled_rows(metaballs_100k, torch, prec):
+    t = metaballs_100k
+    X, cfg = t["X"], t["cfg"]
+    x = w.random_vector(X.shape[0], seed=4)
+    y = host(t["ctx"].matvec(dev(torch, x), prec=prec))
+    rows = np.random.default_rng(41).choice(X.shape[0], 400, replace=False)
+    ref = o.matvec_rows(X, x, rows, cfg["sigma"], cfg["cutoff"])
+    scale = abs_sums(X, x, rows, cfg["sigma"], cfg["cutoff"])
+    ratio = np.max(np.abs(y[rows] - ref) / scale)
+    _say(f"[metaballs operator prec={prec}] max ratio {ratio / U32:.2f} u32")
+    assert ratio <= (tol32(cfg["sigma"], cfg["cutoff"]) if prec == 0 else TOL64)
+
+
+def test_metaballs_pair_count_of_sampled_rows(metaballs_100k):
+    """The useful pairs of the whole operator against the oracle's count on
+    sampled rows, scaled: the row counts vary, so only a loose band."""
+    t = metaballs_100k
+    X, cfg = t["X"], t["cfg"]
+    st = t["ctx"].stats()
+    rows = np.random.default_rng(42).choice(X.shape[0], 300, replace=False)
+    r2 = np.stack([o.sqdist(X[i:i + 1], X)[0] for i in rows])
+    per_row = np.sum(r2 <= cfg["cutoff"] ** 2, axis=1)
+    est = per_row.mean() * X.shape[0]
+    _say(f"[metaballs pairs] device {st.useful_pairs}  sampled estimate {est:.4g}")
+    assert 0.8 * est < st.useful_pairs < 1.25 * est
+
+
+def test_metaballs_grid_sampled_nodes(metaballs_100k, torch):
+    t = metaballs_100k
+    X, cfg = t["X"], t["cfg"]
+    g = w.Grid.around(t["c"].points, 128)
+    coef = np.random.default_rng(43).uniform(-1, 1, X.shape[0])
+    out = host(t["ctx"].eval_grid(dev(torch, coef), g.origin, g.h, g.dims, prec=0))
+    rng = np.random.default_rng(44)
+    nz = np.flatnonzero(out)
+    idx = np.concatenate([rng.choice(nz, 300, replace=False), rng.choice(g.size, 100, replace=False)])
+    nodes = o.grid_nodes(g.origin, g.h, g.dims, idx)
+    ref = o.evaluate(X, coef, nodes, cfg["sigma"], cfg["cutoff"])
+    scale = abs_sums(X, coef, range(len(idx)), cfg["sigma"], cfg["cutoff"], targets=nodes)
+    err = np.abs(out[idx] - ref)
+    bound = tol32(cfg["sigma"], cfg["cutoff"]) * scale + U32 * np.abs(ref) + 1e-300
+    _say(f"[metaballs grid] band nodes {nz.size}, max err/bound {np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
+    assert np.all(out[idx][scale == 0] == 0)
+
+
+# ---------------------------------------------------------------------------
 # Density measures (Sec. IV: separation distance, fill distance, h_max).
 # ---------------------------------------------------------------------------
 def test_density_matches_paper_halton_example(torch, R):
