@@ -385,22 +385,29 @@ struct ListCounts {
   int64_t n_in, n_out, use;
 };
 
-// Where pass 2 writes a group's entries.
+// Where the classifying pass writes a group's entries: its staging region
+// [base, base + bound) holds the inner entries from the bottom up and the
+// outer entries, with their target masks, from the top down (both come from
+// the group's candidate sources, so they never meet).
 struct ListOut {
   uint32_t* list;
   uint16_t* mask;
-  int64_t base;     // first entry of the group
-  int64_t out0;     // relative position of the first outer entry (= number of inner entries)
-  int64_t in_full;  // inner entries below this position are in pure inner chunks (no mask)
+  int64_t base;
+  int64_t top;      // base + bound - 1
+  int64_t bound;
 };
 
-__device__ __forceinline__ void put_inner(const ListOut& o, int64_t e, uint32_t k, uint32_t vmask) {
-  o.list[o.base + e] = k;
-  if (e >= o.in_full) o.mask[mask_slot(o.base, e)] = (uint16_t)vmask;
+// (The two passes enumerate the same candidates, so e < bound always; the
+// tests keep a broken invariant from writing outside the region, and the
+// pass reports it.)
+__device__ __forceinline__ void put_inner(const ListOut& o, int64_t e, uint32_t k) {
+  if (e < o.bound) o.list[o.base + e] = k;
 }
 __device__ __forceinline__ void put_outer(const ListOut& o, int64_t e, uint32_t k, uint32_t bits) {
-  o.list[o.base + o.out0 + e] = k;
-  o.mask[mask_slot(o.base, o.out0 + e)] = (uint16_t)bits;
+  if (e < o.bound) {
+    o.list[o.top - e] = k;
+    o.mask[o.top - e] = (uint16_t)bits;
+  }
 }
 
 // Exact test of `cnt` (<= 64) queued shell sources, one per lane, against
@@ -427,7 +434,7 @@ __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const 
   const bool is_out = valid && bits != 0u && !is_in;
   const uint64_t mi = ballot(is_in), mo = ballot(is_out);
   if (WRITE) {
-    if (is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
+    if (is_in) put_inner(o, n.n_in + lanes_below(mi), k);
     if (is_out) put_outer(o, n.n_out + lanes_below(mo), k, bits);
   }
   n.n_in += __popcll(mi);
@@ -443,14 +450,23 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool WRITE>
+// MODE kBound: the cell phase only; bound[g] = the number of candidate
+// sources (those of the cells within r_out of the anchor), an upper bound of
+// the group's list.  MODE kStage: the classification, into the staging
+// region at soff[g] of size bound[g]; counts, useful pairs, the valid-target
+// mask and the group record (offset set later by k_list_compact).
+constexpr int kBound = 0, kStage = 1;
+template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
-                                                    const double4* __restrict__ xs, int64_t m,
+                                                    const double4* __restrict__ xs,
                                                     const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
                                                     const int32_t* __restrict__ cmap, Lattice lat, double rc, double rc2,
+                                                    int64_t* __restrict__ bound, const int64_t* __restrict__ soff,
                                                     int32_t* __restrict__ cnt_in, int32_t* __restrict__ cnt_out,
-                                                    int64_t* __restrict__ useful, uint32_t* __restrict__ list,
-                                                    uint16_t* __restrict__ mask) {
+                                                    int64_t* __restrict__ useful, uint32_t* __restrict__ vmasks,
+                                                    uint32_t* __restrict__ slist, uint16_t* __restrict__ smask,
+                                                    int* __restrict__ overflow) {
+  constexpr bool WRITE = MODE == kStage;
   __shared__ uint32_t qbuf[kThreads / kWave][2 * kWave];
   __shared__ int32_t cpre_s[kThreads / kWave][kWave], cst_s[kThreads / kWave][kWave];
   __shared__ uint8_t cwhole_s[kThreads / kWave][kWave];
@@ -477,22 +493,27 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
     }
   }
-  ListOut o{list, mask, 0, 0, 0};
+  ListOut o{slist, smask, 0, 0, 0};
   if (WRITE) {
-    o.base = groups[g].off;
-    o.out0 = cnt_in[g];
-    o.in_full = inner_chunks(o.out0) * kChunk;
+    o.base = soff[g];
+    o.bound = bound[g];
+    o.top = o.base + o.bound - 1;
   }
   if (nvalid == 0) {
-    if (!WRITE && lane == 0) {
-      cnt_in[g] = 0;
-      cnt_out[g] = 0;
-      useful[g] = 0;
-      GroupInfo gi;
-      gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0;
-      gi.ax = gi.ay = gi.az = 0.0;
-      gi.radius = 0.0;
-      groups[g] = gi;
+    if (lane == 0) {
+      if (MODE == kBound) {
+        bound[g] = 0;
+      } else {
+        cnt_in[g] = 0;
+        cnt_out[g] = 0;
+        useful[g] = 0;
+        vmasks[g] = 0;
+        GroupInfo gi;
+        gi.off = 0; gi.n_chunks = 0; gi.n_inner = 0;
+        gi.ax = gi.ay = gi.az = 0.0;
+        gi.radius = 0.0;
+        groups[g] = gi;
+      }
     }
     return;
   }
@@ -560,6 +581,10 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       if (lane >= off) incl += y;
     }
     const int32_t total = __shfl(incl, kWave - 1);
+    if (MODE == kBound) {
+      n.n_in += total;   // candidate count
+      continue;
+    }
     wave_sync_lds();
     if (occ) {
       const int pos = lanes_below(sel);
@@ -590,7 +615,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
         }
       }
       const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-      if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k, vmask);
+      if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k);
       n.n_in += __popcll(mi);
       n.use += (int64_t)__popcll(mi) * nvalid;
       if (is_shell) q[qn + lanes_below(ms)] = k;
@@ -606,38 +631,73 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       }
     }
   }
+  if (MODE == kBound) {
+    if (lane == 0) bound[g] = n.n_in;
+    return;
+  }
   wave_sync_lds();
   if (qn > 0) process_shell<WRITE>(q, qn, tg, xs, vmask, rc2, o, n);
-  if (!WRITE) {
-    if (lane == 0) {
-      cnt_in[g] = (int32_t)n.n_in;
-      cnt_out[g] = (int32_t)n.n_out;
-      useful[g] = n.use;
-      GroupInfo gi;
-      gi.off = 0;
-      gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out, kChunk);
-      gi.n_inner = (int32_t)inner_chunks(n.n_in);
-      gi.ax = ax; gi.ay = ay; gi.az = az;
-      gi.radius = rad;
-      groups[g] = gi;
+  if (lane == 0) {
+    if (n.n_in + n.n_out > o.bound) {
+      atomicOr(overflow, 1);
+      n.n_in = n.n_out = 0;
     }
-  } else {
-    const int64_t total = n.n_in + n.n_out;
-    const int64_t padded = round_up(total, kChunk);
-    for (int64_t e = total + lane; e < padded; e += kWave) {
-      list[o.base + e] = (uint32_t)m;
-      mask[mask_slot(o.base, e)] = 0;
+    cnt_in[g] = (int32_t)n.n_in;
+    cnt_out[g] = (int32_t)n.n_out;
+    useful[g] = n.use;
+    vmasks[g] = vmask;
+    GroupInfo gi;
+    gi.off = 0;
+    gi.n_chunks = (int32_t)ceil_div(n.n_in + n.n_out, kChunk);
+    gi.n_inner = (int32_t)inner_chunks(n.n_in);
+    gi.ax = ax; gi.ay = ay; gi.az = az;
+    gi.radius = rad;
+    groups[g] = gi;
+  }
+}
+
+// Final layout of a group's list at off[g] (one wave per group): the inner
+// entries in order, then the outer ones (read back from the top of the
+// staging region, restoring their order), padded to whole chunks with the
+// padding source m; the target masks of every chunk from n_inner on
+// (inner entries there: every valid target; padding: none).
+__global__ __launch_bounds__(kThreads) void k_list_compact(GroupInfo* __restrict__ groups, int64_t G,
+                                                           const int64_t* __restrict__ off,
+                                                           const int64_t* __restrict__ soff,
+                                                           const int64_t* __restrict__ bound,
+                                                           const int32_t* __restrict__ cnt_in,
+                                                           const int32_t* __restrict__ cnt_out,
+                                                           const uint32_t* __restrict__ vmasks,
+                                                           const uint32_t* __restrict__ slist,
+                                                           const uint16_t* __restrict__ smask, uint32_t m,
+                                                           uint32_t* __restrict__ list, uint16_t* __restrict__ mask) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  if (g >= G) return;
+  const int64_t base = off[g], sb = soff[g], top = soff[g] + bound[g] - 1;
+  const int64_t nin = cnt_in[g], nout = cnt_out[g];
+  const int64_t len = round_up(nin + nout, kChunk);
+  const int64_t in_full = inner_chunks(nin) * kChunk;
+  const uint32_t vm = vmasks[g];
+  if (lane == 0) groups[g].off = base;
+  for (int64_t e = lane; e < len; e += kWave) {
+    uint32_t k = m, bits = 0;
+    if (e < nin) {
+      k = slist[sb + e];
+      bits = vm;
+    } else if (e < nin + nout) {
+      k = slist[top - (e - nin)];
+      bits = smask[top - (e - nin)];
     }
+    list[base + e] = k;
+    if (e >= in_full) mask[mask_slot(base, e)] = (uint16_t)bits;
   }
 }
 
 __global__ void k_list_lengths(const GroupInfo* __restrict__ groups, int64_t G, int64_t* __restrict__ len) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g < G) len[g] = (int64_t)groups[g].n_chunks * kChunk;
-}
-__global__ void k_list_offsets(GroupInfo* __restrict__ groups, int64_t G, const int64_t* __restrict__ off) {
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g < G) groups[g].off = off[g];
 }
 // Dense sets: every group sees all m centres (padded to whole chunks).
 __global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int64_t m, GroupInfo* __restrict__ groups) {
@@ -1069,40 +1129,64 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     ts.list_entries = G * round_up(c.m, kChunk);
     ts.useful = ts.n_targets * c.m;
   } else {
+    int64_t* bnd = talloc<int64_t>(G);
+    int64_t* soff = talloc<int64_t>(G);
     int32_t* cin = talloc<int32_t>(G);
     int32_t* cout = talloc<int32_t>(G);
     int64_t* use = talloc<int64_t>(G);
+    uint32_t* vm = talloc<uint32_t>(G);
     int64_t* len = talloc<int64_t>(G);
     int64_t* off = talloc<int64_t>(G);
     const unsigned nblk = (unsigned)ceil_div(G, 4);
-    hipLaunchKernelGGL(k_lists<false>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use,
-                       (uint32_t*)nullptr, (uint16_t*)nullptr);
+    // 1. candidate counts (cell phase only): staging regions
+    hipLaunchKernelGGL(k_lists<kBound>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, (const int64_t*)nullptr,
+                       (int32_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr, (uint32_t*)nullptr,
+                       (uint32_t*)nullptr, (uint16_t*)nullptr, (int*)nullptr);
     RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(bnd, soff, G, s);
+    int64_t last_soff = 0, last_bnd = 0;
+    RBF_HIP(hipMemcpyAsync(&last_soff, soff + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(&last_bnd, bnd + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    const int64_t staged = last_soff + last_bnd;
+    uint32_t* slist = talloc<uint32_t>(staged);
+    uint16_t* smask = talloc<uint16_t>(staged);
+    int* overflow = talloc<int>(1);
+    RBF_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
+    // 2. the classification, once, into the staging regions
+    hipLaunchKernelGGL(k_lists<kStage>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, soff, cin, cout, use, vm,
+                       slist, smask, overflow);
+    RBF_HIP(hipGetLastError());
+    // 3. final offsets and the compact layout
     hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(len, off, G, s);
-    hipLaunchKernelGGL(k_list_offsets, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, off);
     RBF_HIP(hipMemsetAsync(tmp, 0, sizeof(int64_t), s));
     hipLaunchKernelGGL(k_sum_i64, dim3((unsigned)std::min<int64_t>(256, ceil_div(G, kThreads))), dim3(kThreads), 0,
                        s, use, G, tmp);
     RBF_HIP(hipGetLastError());
     int64_t last_off = 0, last_len = 0;
+    int overflowed = 0;
     RBF_HIP(hipMemcpyAsync(&last_off, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipMemcpyAsync(&last_len, len + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipMemcpyAsync(&ts.useful, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(&overflowed, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
+    temp_free(overflow);
+    if (overflowed) throw Error{RBF_EDEVICE, "source list larger than its candidate bound (internal error)"};
     ts.list_entries = last_off + last_len;
     ts.list = set_alloc<uint32_t>(ts, ts.list_entries + kListTail);
     ts.owned.push_back(ts.list);
     fill_u32(ts.list + ts.list_entries, (uint32_t)c.m, kListTail, s);
     ts.mask = set_alloc<uint16_t>(ts, ts.list_entries);
     ts.owned.push_back(ts.mask);
-    hipLaunchKernelGGL(k_lists<true>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs, c.m,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, cin, cout, use, ts.list,
-                       ts.mask);
+    hipLaunchKernelGGL(k_list_compact, dim3(nblk), dim3(kThreads), 0, s, ts.groups, G, off, soff, bnd, cin, cout, vm,
+                       slist, smask, (uint32_t)c.m, ts.list, ts.mask);
     RBF_HIP(hipGetLastError());
-    temp_free(cin); temp_free(cout); temp_free(use); temp_free(len); temp_free(off);
+    temp_free(slist); temp_free(smask); temp_free(bnd); temp_free(soff); temp_free(cin); temp_free(cout);
+    temp_free(use); temp_free(vm); temp_free(len); temp_free(off);
   }
   RBF_HIP(hipStreamSynchronize(s));
   temp_free(tmp);
