@@ -194,11 +194,15 @@ class GmresResult:
 
 
 def gmres(apply_A, b: np.ndarray, x0: np.ndarray | None = None, restart: int = 30,
-          max_iters: int = 1000, tol: float = 1e-8) -> GmresResult:
+          max_iters: int = 1000, tol: float = 1e-8, apply_M=None) -> GmresResult:
     """Restarted GMRES.  Stops when the relative residual (the rotated
     right-hand side's last entry inside a cycle, the true residual at a
     restart) is <= tol, or after max_iters operator applications inside
-    cycles."""
+    cycles.  With apply_M, right preconditioning (Sec. III.A uses the
+    Schwarz solves as a preconditioner of GMRES): the cycle builds its basis
+    on A M, and the correction is M V y."""
+    if apply_M is None:
+        apply_M = lambda v: v  # noqa: E731
     b = np.asarray(b, dtype=np.float64)
     n = b.size
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
@@ -229,7 +233,7 @@ def gmres(apply_A, b: np.ndarray, x0: np.ndarray | None = None, restart: int = 3
         V[0] = r / beta
         k = 0
         for j in range(m):
-            w = apply_A(V[j])
+            w = apply_A(apply_M(V[j]))
             res.iters += 1
             for i in range(j + 1):
                 H[i, j] = np.dot(w, V[i])
@@ -257,7 +261,7 @@ def gmres(apply_A, b: np.ndarray, x0: np.ndarray | None = None, restart: int = 3
         y = np.zeros(k)
         for i in range(k - 1, -1, -1):
             y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
-        x = x + V[:k].T @ y
+        x = x + apply_M(V[:k].T @ y)
         res.x = x
     res.x = x
     return res
