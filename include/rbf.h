@@ -58,14 +58,37 @@ typedef enum {
     RBF_SOLVE_IR_FP32 = 1      /* float64 outer refinement, GMRES cycles on the float32 operator */
 } rbf_mode;
 
+typedef enum {
+    RBF_PRECOND_NONE = 0,
+    RBF_PRECOND_SCHWARZ = 1    /* the context's Schwarz preconditioner (rbf_schwarz_setup), applied on the right */
+} rbf_precond;
+
 typedef struct {
     double tol;        /* stop when |b - A c|_2 / |b|_2 <= tol, float64 operator (default 1e-8) */
     int restart;       /* GMRES restart length m, 1..64 (default 30) */
     int max_outer;     /* maximum restarts / refinement steps (default 1000) */
     int max_iters;     /* maximum operator applications inside GMRES cycles (default 30000) */
     int mode;          /* rbf_mode (default RBF_SOLVE_IR_FP32) */
-    int reserved;      /* must be 0 */
+    int precond;       /* rbf_precond (default RBF_PRECOND_NONE) */
 } rbf_solve_opts;
+
+typedef struct {
+    int max_block;     /* largest subdomain, core + overlap centres, 3..192 (default 192) */
+    int overlap_pct;   /* overlap size in percent of the core, 0..100 (default 10) */
+    int restricted;    /* 1: restricted additive Schwarz (core rows of each local solution);
+                          0: additive (every row, summed) (default 0) */
+    int reserved;      /* must be 0 */
+    double shift;      /* added to the unit diagonal of every local block, >= 0 (default 0.1) */
+} rbf_schwarz_opts;
+
+typedef struct {
+    int64_t n_sub;         /* subdomains */
+    int64_t n_members;     /* sum of the subdomain sizes (core + overlap) */
+    int64_t max_members;   /* the largest subdomain */
+    int64_t inverse_bytes; /* device memory of the local inverses */
+    int retries;           /* local blocks redone with a larger shift */
+    double max_shift;      /* the largest shift a block ended with */
+} rbf_schwarz_info;
 
 typedef struct {
     int iters;               /* operator applications inside GMRES cycles */
@@ -128,6 +151,8 @@ int rbf_matvec(rbf_ctx* ctx, const double* x, double* y, int prec, void* stream)
  *   b: device 3n float64, or NULL for the default values (0, +eps, -eps).
  *   x0: device 3n initial guess, or NULL for zero.  c: device 3n output
  *   (may alias x0).  opts: NULL for defaults.  info: may be NULL.
+ *   opts->precond = RBF_PRECOND_SCHWARZ preconditions every GMRES cycle on the
+ *   right with the context's Schwarz preconditioner (RBF_EINVAL without one).
  * Blocks the host until done.  Returns RBF_OK when the float64 relative
  * residual reached opts->tol, RBF_ENOCONV when a limit stopped it (c and
  * info still hold the last iterate), RBF_EBREAKDOWN on non-finite values. */
@@ -157,6 +182,38 @@ int rbf_eval_points(rbf_ctx* ctx, const double* c, const double* pts, int64_t m,
  * pointers).  Synchronises with `stream`. */
 int rbf_density(rbf_ctx* ctx, const double* samples, int64_t n_samples, double* q, double* h_max,
                 double* h_fill, void* stream);
+
+/* Overlapping Schwarz preconditioner for rbf_solve (Sec. III.A: overlapping
+ * subdomains whose local systems are solved independently; their solutions
+ * added up (additive Schwarz) or kept on the non-overlapping parts only
+ * (restricted additive Schwarz) precondition GMRES).
+ *   Subdomains: the cores are the leaves of an octree over the surface
+ *   points (root cube at their componentwise minimum, side = their largest
+ *   extent, 10 levels), a cell being split while it holds more than p points,
+ *   p the largest count with 3p + ceil(3p overlap_pct / 100) <= max_block; a
+ *   core holds the three centres of each of its points.  The overlap adds
+ *   the ceil(overlap_pct |core| / 100) centres outside the core nearest to it
+ *   (squared float64 distance to the nearest core centre, ties by index).
+ *   Local matrices: the Gaussian of the subdomain without truncation plus
+ *   shift * I, inverted in float64 (a block found indefinite is redone with
+ *   ten times the shift, at most 8 times), kept in float32.
+ * opts: NULL for defaults.  Replaces the context's previous preconditioner.
+ * Synchronises with `stream`.  RBF_EBREAKDOWN when a block stays indefinite. */
+int rbf_default_schwarz_opts(rbf_schwarz_opts* opts);
+int rbf_schwarz_setup(rbf_ctx* ctx, const rbf_schwarz_opts* opts, void* stream);
+
+/* z = M^{-1} r with the context's Schwarz preconditioner.  r, z: device, 3n
+ * float64, paper order, not overlapping. */
+int rbf_schwarz_apply(rbf_ctx* ctx, const double* r, double* z, void* stream);
+
+/* Sizes of the context's Schwarz preconditioner (host call). */
+int rbf_schwarz_get_info(const rbf_ctx* ctx, rbf_schwarz_info* info);
+
+/* The subdomains, into HOST arrays: offsets (n_sub + 1), n_core (n_sub),
+ * members (n_members, paper centre indices).  Subdomain i holds
+ * members[offsets[i] .. offsets[i+1]): its n_core[i] core centres, then its
+ * overlap, nearest first. */
+int rbf_schwarz_subdomains(const rbf_ctx* ctx, int64_t* offsets, int32_t* n_core, int64_t* members);
 
 /* Sizes and pair counts of the context (host call, no device work). */
 int rbf_get_stats(const rbf_ctx* ctx, rbf_stats* stats);

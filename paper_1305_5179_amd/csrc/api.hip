@@ -105,6 +105,8 @@ void free_ctx(Ctx* c) {
   (void)hipDeviceSynchronize();
   SyncedRelease synced;   // the device is idle: the blocks may go to any stream
   free_targets(c->centres);
+  free_schwarz(c->schwarz);
+  c->schwarz = nullptr;
   for (void* p : {(void*)c->perm, (void*)c->keys, (void*)c->xs, (void*)c->xk, (void*)c->xpaper, (void*)c->cell_start,
                   (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->vin, (void*)c->vout,
                   (void*)c->V, (void*)c->w, (void*)c->r, (void*)c->csol, (void*)c->bsort, (void*)c->partial,
@@ -204,7 +206,7 @@ int rbf_default_solve_opts(rbf_solve_opts* o) {
   o->max_outer = 1000;
   o->max_iters = 30000;
   o->mode = RBF_SOLVE_IR_FP32;
-  o->reserved = 0;
+  o->precond = RBF_PRECOND_NONE;
   return RBF_OK;
 }
 
@@ -341,6 +343,10 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
   if (o.restart < 1 || o.restart > gm_max_restart()) return fail(c, RBF_EINVAL, "restart must be in 1..64");
   if (o.max_outer < 1 || o.max_iters < 0) return fail(c, RBF_EINVAL, "max_outer >= 1 and max_iters >= 0 required");
   if (o.mode != RBF_SOLVE_PLAIN_FP64 && o.mode != RBF_SOLVE_IR_FP32) return fail(c, RBF_EINVAL, "unknown mode");
+  if (o.precond != RBF_PRECOND_NONE && o.precond != RBF_PRECOND_SCHWARZ)
+    return fail(c, RBF_EINVAL, "unknown preconditioner");
+  if (o.precond == RBF_PRECOND_SCHWARZ && !c->schwarz)
+    return fail(c, RBF_EINVAL, "no Schwarz preconditioner on this context (rbf_schwarz_setup)");
   if ((b && !is_device_ptr(b)) || (x0 && !is_device_ptr(x0)) || !is_device_ptr(cout))
     return fail(c, RBF_EINVAL, "b, x0 and c must be device pointers");
   const int prec = o.mode == RBF_SOLVE_IR_FP32 ? RBF_FP32 : RBF_FP64;
@@ -414,11 +420,26 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         }
         const int steps = std::min<int64_t>(o.restart, (int64_t)o.max_iters - iters);
         const int* skip = gm_done_flag(c->state);
+        const SchwarzData* pre = o.precond == RBF_PRECOND_SCHWARZ ? c->schwarz : nullptr;
         for (int j = 0; j < steps; ++j) {
-          apply_sorted(c, c->V + (int64_t)j * ldv, c->w, prec, s, skip);
+          const double* vj = c->V + (int64_t)j * ldv;
+          if (pre) {
+            // right preconditioning: the basis is built on A M
+            schwarz_apply(*c, *pre, vj, pre->z, s, skip);
+            vj = pre->z;
+          }
+          apply_sorted(c, vj, c->w, prec, s, skip);
           gm_step(c->V, ldv, c->w, m, j, c->partial, c->state, s);
         }
-        gm_finish(c->V, ldv, c->csol, m, c->state, s);
+        if (pre) {
+          // c += M (V y)
+          fill_f64(pre->t, 0.0, c->mpad, s);
+          gm_finish(c->V, ldv, pre->t, m, c->state, s);
+          schwarz_apply(*c, *pre, pre->t, pre->z, s);
+          vec_add(c->csol, pre->z, m, s);
+        } else {
+          gm_finish(c->V, ldv, c->csol, m, c->state, s);
+        }
         gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
         iters += k;
         ++outer;
@@ -551,6 +572,80 @@ int rbf_density(rbf_ctx* c, const double* samples, int64_t ns, double* q, double
     density_measures(c->xpaper, c->n, samples, samples ? ns : 0, q, hmax, hfill, (hipStream_t)stream);
     return RBF_OK;
   });
+}
+
+int rbf_default_schwarz_opts(rbf_schwarz_opts* o) {
+  if (!o) return fail(nullptr, RBF_EINVAL, "opts is NULL");
+  o->max_block = kSchwarzMaxBlock;
+  o->overlap_pct = 10;
+  o->restricted = 0;
+  o->reserved = 0;
+  o->shift = 0.1;
+  return RBF_OK;
+}
+
+int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  rbf_schwarz_opts o;
+  rbf_default_schwarz_opts(&o);
+  if (opts_in) o = *opts_in;
+  if (o.max_block < 3 || o.max_block > kSchwarzMaxBlock)
+    return fail(c, RBF_EINVAL, "max_block must be in 3..192");
+  if (o.overlap_pct < 0 || o.overlap_pct > 100) return fail(c, RBF_EINVAL, "overlap_pct must be in 0..100");
+  if (o.restricted != 0 && o.restricted != 1) return fail(c, RBF_EINVAL, "restricted must be 0 or 1");
+  if (o.reserved != 0) return fail(c, RBF_EINVAL, "reserved must be 0");
+  if (!(o.shift >= 0.0) || !std::isfinite(o.shift)) return fail(c, RBF_EINVAL, "shift must be finite and >= 0");
+  if (3 + schwarz_overlap_count(3, o.overlap_pct) > o.max_block)
+    return fail(c, RBF_EINVAL, "max_block too small for one point and its overlap");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    free_schwarz(c->schwarz);   // stream-ordered release: queued work on this stream finishes first
+    c->schwarz = nullptr;
+    c->schwarz = schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.shift, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    return RBF_OK;
+  });
+}
+
+int rbf_schwarz_apply(rbf_ctx* c, const double* r, double* z, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!c->schwarz) return fail(c, RBF_EINVAL, "no Schwarz preconditioner on this context (rbf_schwarz_setup)");
+  if (!is_device_ptr(r) || !is_device_ptr(z)) return fail(c, RBF_EINVAL, "r and z must be device pointers");
+  if (r == z) return fail(c, RBF_EINVAL, "r and z must not overlap");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    gather_to_sorted(r, c->perm, c->m, c->vin, s);
+    schwarz_apply(*c, *c->schwarz, c->vin, c->vout, s);
+    scatter_from_sorted(c->vout, c->perm, c->m, z, s);
+    return RBF_OK;
+  });
+}
+
+int rbf_schwarz_get_info(const rbf_ctx* c, rbf_schwarz_info* out) {
+  if (!c || !out) return fail(nullptr, RBF_EINVAL, "ctx and info must not be NULL");
+  if (!c->schwarz) return fail(const_cast<rbf_ctx*>(c), RBF_EINVAL, "no Schwarz preconditioner on this context");
+  const SchwarzData& d = *c->schwarz;
+  out->n_sub = d.nsub;
+  out->n_members = d.nmem;
+  int64_t maxn = 0;
+  for (int64_t i = 0; i < d.nsub; ++i) maxn = std::max(maxn, d.h_mem_off[i + 1] - d.h_mem_off[i]);
+  out->max_members = maxn;
+  out->inverse_bytes = d.w_total * (int64_t)sizeof(float);
+  out->retries = d.retries;
+  out->max_shift = d.max_shift;
+  return RBF_OK;
+}
+
+int rbf_schwarz_subdomains(const rbf_ctx* c, int64_t* offsets, int32_t* n_core, int64_t* members) {
+  if (!c || !offsets || !n_core || !members) return fail(nullptr, RBF_EINVAL, "NULL argument");
+  if (!c->schwarz) return fail(const_cast<rbf_ctx*>(c), RBF_EINVAL, "no Schwarz preconditioner on this context");
+  const SchwarzData& d = *c->schwarz;
+  for (int64_t i = 0; i <= d.nsub; ++i) offsets[i] = d.h_mem_off[i];
+  for (int64_t i = 0; i < d.nsub; ++i) n_core[i] = d.h_ncore[i];
+  for (int64_t e = 0; e < d.nmem; ++e) members[e] = d.h_mem_paper[e];
+  return RBF_OK;
 }
 
 int rbf_get_stats(const rbf_ctx* c, rbf_stats* st) {

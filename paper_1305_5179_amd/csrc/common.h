@@ -81,6 +81,29 @@ __host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt
   return !dense && smax * smax <= 100.0 && 2.0 * rk * smax <= 100.0;
 }
 
+// The overlapping Schwarz preconditioner (schwarz.hip).  Subdomain i has
+// members mem[mem_off[i] .. mem_off[i+1]) (sorted positions), its ncore[i]
+// core centres first; its local inverse is W[woff[i] ..], float32, n x n.
+constexpr int kSchwarzMaxBlock = 192;   // a float64 packed triangle of this order fills the LDS of a CU
+struct SchwarzData {
+  int64_t nsub = 0, nmem = 0, w_total = 0;
+  int restricted = 0, max_block = 0, pct = 0, retries = 0;
+  double shift = 0, max_shift = 0;
+  int64_t* mem_off = nullptr;
+  int32_t* ncore = nullptr;
+  uint32_t* mem = nullptr;
+  int64_t* woff = nullptr;
+  float* W = nullptr;
+  double* Y = nullptr;          // additive form: the local solutions, by member slot
+  int64_t* occ_off = nullptr;   // additive form: the member slots of every centre
+  int64_t* occ_slot = nullptr;
+  double* z = nullptr;          // work vectors of the preconditioned solve (length mpad)
+  double* t = nullptr;
+  std::vector<int64_t> h_mem_off;
+  std::vector<int32_t> h_ncore;
+  std::vector<uint32_t> h_mem_paper;   // members as paper indices
+};
+
 // A set of targets grouped by 16 (centres, grid nodes or evaluation points)
 // together with the source list of every group.
 struct TargetSet {
@@ -134,6 +157,7 @@ struct Ctx {
   int32_t* cell_xyz = nullptr;  // coarse coordinates of every cell, x | y << 10 | z << 20
   int64_t n_cells = 0;
   TargetSet centres;            // the centres as targets of the operator
+  SchwarzData* schwarz = nullptr;
   // Work vectors (sorted order, length mpad, entry m kept 0).
   double* vin = nullptr;
   double* vout = nullptr;
@@ -255,7 +279,16 @@ void density_measures(const double* P, int64_t n, const double* samples, int64_t
 int profile_begin();
 int profile_end(rbf_profile* out);
 
+// schwarz.hip
+int schwarz_overlap_count(int ncore, int pct);
+int schwarz_core_cap(int max_block, int pct);
+SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, double shift, hipStream_t s);
+void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s,
+                   const int* skip = nullptr);
+void free_schwarz(SchwarzData* d);
+
 // krylov.hip
+void vec_add(double* x, const double* y, int64_t n, hipStream_t s);
 void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s);
 void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s);
 

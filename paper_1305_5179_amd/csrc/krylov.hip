@@ -298,6 +298,12 @@ __global__ __launch_bounds__(kVecThreads) void k_update_x(const double* __restri
   x[i] = v;
 }
 
+// x += y
+__global__ void k_vec_add(double* __restrict__ x, const double* __restrict__ y, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += y[i];
+}
+
 __global__ void k_gather(const double* __restrict__ src, const uint32_t* __restrict__ perm, int64_t m,
                          double* __restrict__ dst) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -316,6 +322,11 @@ __global__ void k_scatter(const double* __restrict__ src, const uint32_t* __rest
 // ===========================================================================
 static unsigned vec_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kRowsPerBlock)); }
 static unsigned elt_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kVecThreads)); }
+
+void vec_add(double* x, const double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_vec_add, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, x, y, n);
+  RBF_HIP(hipGetLastError());
+}
 
 void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(elt_blocks(m)), dim3(kVecThreads), 0, s, src, perm, m, dst_sorted);

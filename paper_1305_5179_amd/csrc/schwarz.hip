@@ -1,0 +1,651 @@
+// Overlapping Schwarz preconditioner (Sec. III.A: the domain is split into
+// overlapping subdomains, the local systems are solved independently and
+// their solutions combined, added up everywhere (additive Schwarz) or kept
+// only on the non-overlapping parts (restricted additive Schwarz), as the
+// preconditioner of GMRES).
+//
+// Subdomains.  Cores (the non-overlapping parts) are the leaves of an octree
+// over the surface points: root cube at the points' componentwise minimum,
+// side = their largest extent, 1024 finest cells per axis; a cell is split
+// while it holds more than `cap` points, and a core holds the three centres
+// of each of its points.  The points are sorted (stably) by the Hilbert
+// index of their finest cell; the cells of every level are then contiguous
+// ranges sharing a key prefix, and the host splits the ranges by key digits.
+// The overlap of a core is the k = ceil(pct |core| / 100) centres outside it
+// nearest to it (float64 squared distance to the nearest core centre, ties
+// by index), searched on the device one workgroup per subdomain.
+//
+// Local inverses.  The untruncated Gaussian of a subdomain plus shift I is
+// assembled and inverted in float64 inside the LDS of one compute unit
+// (packed lower triangle, n <= 192: 148 KB) by symmetric Gauss-Jordan
+// sweeps: sweeping every pivot of a symmetric positive definite matrix
+// leaves -A^{-1}, and every pivot is a Schur complement, so a pivot <= 0
+// means the shift is too small and the subdomain is redone with ten times
+// the shift.  One persistent launch takes the subdomains from a queue,
+// largest first.  The inverses are kept in float32, full n x n.
+//
+// Apply.  One workgroup per subdomain gathers the vector on its members into
+// LDS and forms W r, a lane per row (W is symmetric, so lane p reads column
+// p of each row b: consecutive lanes, consecutive addresses).  The
+// restricted form scatters the core rows (the cores partition the centres);
+// the additive form stores every row, and a second kernel sums, for every
+// centre, the rows of the subdomains that hold it, in subdomain order.
+#include <algorithm>
+#include <functional>
+#include <vector>
+
+#include "common.h"
+
+namespace rbf {
+
+namespace {
+
+constexpr int kOvThreads = 256;
+constexpr int kCandCap = 2048;                 // candidate buffer of the overlap search
+constexpr int kFacThreads = 512;
+constexpr int kPacked = kSchwarzMaxBlock * (kSchwarzMaxBlock + 1) / 2;
+constexpr int kApplyThreads = 256;
+static_assert(kSchwarzMaxBlock <= kApplyThreads, "one lane per row of a block");
+
+// ---------------------------------------------------------------------------
+// Bounding box of every core (one wave per subdomain).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_schwarz_box(const double* __restrict__ X, const int64_t* __restrict__ core_off,
+                                                    const uint32_t* __restrict__ core_mem, double* __restrict__ box) {
+  const int64_t sub = blockIdx.x;
+  const int64_t a = core_off[sub], b = core_off[sub + 1];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t e = a + threadIdx.x; e < b; e += 64) {
+    const uint32_t j = core_mem[e];
+    for (int d = 0; d < 3; ++d) {
+      const double v = X[3 * (int64_t)j + d];
+      lo[d] = fmin(lo[d], v);
+      hi[d] = fmax(hi[d], v);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], off));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], off));
+    }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) {
+      box[6 * sub + d] = lo[d];
+      box[6 * sub + 3 + d] = hi[d];
+    }
+}
+
+// Squared distance from a point to a box (0 inside).
+__device__ __forceinline__ double box_dist2(double x, double y, double z, const double* bx) {
+  const double gx = fmax(0.0, fmax(bx[0] - x, x - bx[3]));
+  const double gy = fmax(0.0, fmax(bx[1] - y, y - bx[4]));
+  const double gz = fmax(0.0, fmax(bx[2] - z, z - bx[5]));
+  return (gx * gx + gy * gy) + gz * gz;
+}
+__device__ __forceinline__ double box_box_dist2(const double* a, const double* b) {
+  double s = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double g = fmax(0.0, fmax(a[d] - b[3 + d], b[d] - a[3 + d]));
+    s += g * g;
+  }
+  return s;
+}
+
+__device__ __forceinline__ bool lex_less(double da, uint32_t ia, double db, uint32_t ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+struct OvArgs {
+  const double* X;          // paper-order centres, m x 3
+  int64_t nsub;
+  const int64_t* core_off;  // nsub + 1
+  const uint32_t* core_mem; // paper indices of the core centres
+  const double* box;        // 6 per subdomain
+  const int32_t* kcount;    // overlap size per subdomain
+  const int64_t* ov_off;    // nsub + 1
+  const double* rho;        // search radius per subdomain
+  const int32_t* list;      // subdomains to process (null: blockIdx.x)
+  int unbounded;            // 1: every centre is a candidate
+  uint32_t* ov_mem;         // out: paper indices, nearest first
+  int32_t* short_of;        // out: 1 where fewer than k centres lie within rho
+};
+
+// The k nearest centres outside one core.  Candidates (leaves whose box is
+// within rho of the core box, then centres within rho of it, then an exact
+// set distance <= rho^2) collect in an LDS buffer that also holds, at its
+// front, the best k found so far; when it fills, k rounds of a block-wide
+// lexicographic argmin keep the best k.  The selection depends only on the
+// (distance, index) pairs, not on the order in which candidates arrive.
+__global__ __launch_bounds__(kOvThreads) void k_schwarz_overlap(OvArgs a) {
+  __shared__ double cx[kSchwarzMaxBlock], cy[kSchwarzMaxBlock], cz[kSchwarzMaxBlock];
+  __shared__ double cd[kCandCap];
+  __shared__ uint32_t ci[kCandCap];
+  __shared__ double bd[kSchwarzMaxBlock];
+  __shared__ uint32_t bi[kSchwarzMaxBlock];
+  __shared__ int32_t leaves[kOvThreads];
+  __shared__ double wd[kOvThreads / 64];
+  __shared__ uint32_t wi[kOvThreads / 64];
+  __shared__ int32_t wp[kOvThreads / 64];
+  __shared__ double mybox[6];
+  __shared__ int s_nc, s_nl, s_found;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t sub = a.list ? a.list[blockIdx.x] : (int64_t)blockIdx.x;
+  const int64_t c0 = a.core_off[sub];
+  const int ncore = (int)(a.core_off[sub + 1] - c0);
+  const int k = a.kcount[sub];
+  const double rho = a.rho[sub];
+  const double rho2 = rho * rho;
+  const double margin = rho2 * (1.0 + 1e-9) + 1e-300;   // prefilters never drop a centre within rho
+  for (int p = tid; p < ncore; p += kOvThreads) {
+    const uint32_t j = a.core_mem[c0 + p];
+    cx[p] = a.X[3 * (int64_t)j];
+    cy[p] = a.X[3 * (int64_t)j + 1];
+    cz[p] = a.X[3 * (int64_t)j + 2];
+  }
+  if (tid < 6) mybox[tid] = a.box[6 * sub + tid];
+  if (tid == 0) s_nc = 0;
+  __syncthreads();
+
+  // keep the best k of cd/ci[0, nc) at its front, in increasing order
+  auto merge = [&]() {
+    const int nc = s_nc;
+    int taken = 0;
+    for (int r = 0; r < k; ++r) {
+      double d = INFINITY;
+      uint32_t id = 0xffffffffu;
+      int pos = -1;
+      for (int e = tid; e < nc; e += kOvThreads)
+        if (cd[e] != INFINITY && lex_less(cd[e], ci[e], d, id)) {
+          d = cd[e];
+          id = ci[e];
+          pos = e;
+        }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double d2 = __shfl_xor(d, off);
+        const uint32_t i2 = __shfl_xor(id, off);
+        const int p2 = __shfl_xor(pos, off);
+        if (lex_less(d2, i2, d, id)) {
+          d = d2;
+          id = i2;
+          pos = p2;
+        }
+      }
+      if (lane == 0) {
+        wd[wave] = d;
+        wi[wave] = id;
+        wp[wave] = pos;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double bdv = wd[0];
+        uint32_t biv = wi[0];
+        int bp = wp[0];
+        for (int w = 1; w < kOvThreads / 64; ++w)
+          if (lex_less(wd[w], wi[w], bdv, biv)) {
+            bdv = wd[w];
+            biv = wi[w];
+            bp = wp[w];
+          }
+        s_found = bp >= 0 ? 1 : 0;
+        if (bp >= 0) {
+          bd[r] = bdv;
+          bi[r] = biv;
+          cd[bp] = INFINITY;
+        }
+      }
+      __syncthreads();
+      if (!s_found) break;
+      ++taken;
+    }
+    for (int r = tid; r < taken; r += kOvThreads) {
+      cd[r] = bd[r];
+      ci[r] = bi[r];
+    }
+    if (tid == 0) s_nc = taken;
+    __syncthreads();
+  };
+
+  for (int64_t l0 = 0; l0 < a.nsub; l0 += kOvThreads) {
+    if (tid == 0) s_nl = 0;
+    __syncthreads();
+    const int64_t L = l0 + tid;
+    if (L < a.nsub && L != sub && (a.unbounded || box_box_dist2(a.box + 6 * L, mybox) <= margin))
+      leaves[atomicAdd(&s_nl, 1)] = (int32_t)L;
+    __syncthreads();
+    const int nl = s_nl;
+    for (int q = 0; q < nl; ++q) {
+      const int64_t L2 = leaves[q];
+      const int64_t b0 = a.core_off[L2];
+      const int cnt = (int)(a.core_off[L2 + 1] - b0);
+      if (tid < cnt) {
+        const uint32_t j = a.core_mem[b0 + tid];
+        const double x = a.X[3 * (int64_t)j], y = a.X[3 * (int64_t)j + 1], z = a.X[3 * (int64_t)j + 2];
+        if (a.unbounded || box_dist2(x, y, z, mybox) <= margin) {
+          double best = INFINITY;
+          for (int p = 0; p < ncore; ++p) {
+            const double dx = x - cx[p], dy = y - cy[p], dz = z - cz[p];
+            best = fmin(best, (dx * dx + dy * dy) + dz * dz);
+          }
+          if (a.unbounded || best <= rho2) {
+            const int slot = atomicAdd(&s_nc, 1);
+            cd[slot] = best;
+            ci[slot] = j;
+          }
+        }
+      }
+      __syncthreads();
+      if (s_nc > kCandCap - kSchwarzMaxBlock) merge();
+    }
+  }
+  merge();
+  const int found = s_nc;
+  for (int r = tid; r < found && r < k; r += kOvThreads) a.ov_mem[a.ov_off[sub] + r] = ci[r];
+  if (tid == 0) a.short_of[sub] = found < k ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Local inverses: one persistent launch, a subdomain per workgroup at a time.
+// ---------------------------------------------------------------------------
+struct FacArgs {
+  const double4* xs;        // sorted centres
+  const int64_t* mem_off;   // nsub + 1
+  const uint32_t* mem;      // sorted positions
+  const int32_t* order;     // subdomains, largest first
+  int64_t nsub;
+  const int64_t* woff;
+  double two_s2;            // 2 sigma^2
+  double shift;
+  int max_retry;
+  float* W;
+  double* shift_used;
+  int32_t* retries;
+  int* failed;
+  int* queue;
+};
+
+__device__ __forceinline__ int packed(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// The packed lower triangle is walked row by row: wave w takes the rows
+// i = w, w + 8, ..., its lanes the columns j = lane, lane + 64, ... <= i, so
+// that a wave touches consecutive LDS words and no thread keeps a table.
+template <class F>
+__device__ __forceinline__ void for_each_packed(int n, F&& f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < n; i += kFacThreads / 64) {
+    const int base = packed(i, 0);
+    for (int j = lane; j <= i; j += 64) f(i, j, base + j);
+  }
+}
+
+__global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
+  __shared__ double A[kPacked];
+  __shared__ double px[kSchwarzMaxBlock], py[kSchwarzMaxBlock], pz[kSchwarzMaxBlock];
+  __shared__ double col[kSchwarzMaxBlock];
+  __shared__ int s_task;
+  const int tid = threadIdx.x;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_task = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int64_t task = s_task;
+    if (task >= a.nsub) break;   // every workgroup reaches this once the queue is drained
+    const int64_t sub = a.order[task];
+    const int64_t off = a.mem_off[sub];
+    const int n = (int)(a.mem_off[sub + 1] - off);
+    for (int p = tid; p < n; p += kFacThreads) {
+      const double4 x = a.xs[a.mem[off + p]];
+      px[p] = x.x;
+      py[p] = x.y;
+      pz[p] = x.z;
+    }
+    double shift = a.shift;
+    int tries = 0;
+    bool ok = false;
+    for (;;) {
+      __syncthreads();
+      for_each_packed(n, [&](int i, int j, int u) {
+        double v;
+        if (i == j) {
+          v = 1.0 + shift;
+        } else {
+          const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+          v = exp(-((dx * dx + dy * dy) + dz * dz) / a.two_s2);
+        }
+        A[u] = v;
+      });
+      __syncthreads();
+      bool bad = false;
+      for (int k = 0; k < n; ++k) {
+        const double d = A[packed(k, k)];
+        if (!(d > 0.0) || !isfinite(d)) {   // the same value for every thread
+          bad = true;
+          break;
+        }
+        for (int i = tid; i < n; i += kFacThreads) col[i] = i >= k ? A[packed(i, k)] : A[packed(k, i)];
+        __syncthreads();
+        const double inv = 1.0 / d;
+        for_each_packed(n, [&](int i, int j, int u) {
+          if (i != k && j != k)
+            A[u] = fma(-(col[i] * inv), col[j], A[u]);
+          else if (i == k && j == k)
+            A[u] = -inv;
+          else
+            A[u] = (i == k ? col[j] : col[i]) * inv;
+        });
+        __syncthreads();
+      }
+      if (!bad) {
+        ok = true;
+        break;
+      }
+      if (++tries > a.max_retry) break;
+      shift = shift > 0.0 ? 10.0 * shift : 1e-10;
+    }
+    // W = -(swept matrix), full n x n
+    float* W = a.W + a.woff[sub];
+    for_each_packed(n, [&](int i, int j, int u) {
+      const float v = ok ? (float)(-A[u]) : 0.0f;
+      W[(int64_t)i * n + j] = v;
+      if (i != j) W[(int64_t)j * n + i] = v;
+    });
+    if (tid == 0) {
+      a.shift_used[sub] = shift;
+      a.retries[sub] = tries;
+      if (!ok) atomicOr(a.failed, 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Apply.
+// ---------------------------------------------------------------------------
+template <bool RESTRICTED>
+__global__ __launch_bounds__(kApplyThreads) void k_schwarz_local(const int64_t* __restrict__ mem_off,
+                                                                 const int32_t* __restrict__ ncore,
+                                                                 const uint32_t* __restrict__ mem,
+                                                                 const int64_t* __restrict__ woff,
+                                                                 const float* __restrict__ W,
+                                                                 const double* __restrict__ r,
+                                                                 double* __restrict__ out, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double rl[kSchwarzMaxBlock];
+  const int64_t sub = blockIdx.x;
+  const int64_t off = mem_off[sub];
+  const int n = (int)(mem_off[sub + 1] - off);
+  const int tid = threadIdx.x;
+  if (tid < n) rl[tid] = r[mem[off + tid]];
+  __syncthreads();
+  const int rows = RESTRICTED ? ncore[sub] : n;
+  if (tid >= rows) return;
+  const float* w = W + woff[sub] + tid;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = 0;
+  for (; b + 4 <= n; b += 4) {
+    a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
+    a1 = fma((double)w[(int64_t)(b + 1) * n], rl[b + 1], a1);
+    a2 = fma((double)w[(int64_t)(b + 2) * n], rl[b + 2], a2);
+    a3 = fma((double)w[(int64_t)(b + 3) * n], rl[b + 3], a3);
+  }
+  for (; b < n; ++b) a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
+  const double y = (a0 + a1) + (a2 + a3);
+  if (RESTRICTED)
+    out[mem[off + tid]] = y;
+  else
+    out[off + tid] = y;
+}
+
+__global__ void k_schwarz_sum(const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ_slot,
+                              const double* __restrict__ Y, int64_t m, double* __restrict__ z, const int* skip) {
+  if (skip && *skip) return;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double s = 0.0;
+  for (int64_t e = occ_off[j]; e < occ_off[j + 1]; ++e) s += Y[occ_slot[e]];
+  z[j] = s;
+}
+
+template <class T>
+T* upload(const std::vector<T>& h, hipStream_t s) {
+  T* d = dalloc<T>((int64_t)std::max<size_t>(h.size(), 1));
+  if (!h.empty()) RBF_HIP(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s));
+  return d;
+}
+template <class T>
+std::vector<T> download(const T* d, int64_t count, hipStream_t s) {
+  std::vector<T> h((size_t)std::max<int64_t>(count, 0));
+  if (count > 0) RBF_HIP(hipMemcpyAsync(h.data(), d, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, s));
+  return h;
+}
+
+}  // namespace
+
+int schwarz_overlap_count(int ncore, int pct) { return (ncore * pct + 99) / 100; }
+
+int schwarz_core_cap(int max_block, int pct) {
+  int p = max_block / 3;
+  while (p > 1 && 3 * p + schwarz_overlap_count(3 * p, pct) > max_block) --p;
+  return std::max(p, 1);
+}
+
+void free_schwarz(SchwarzData* d) {
+  if (!d) return;
+  for (void* p : {(void*)d->mem_off, (void*)d->ncore, (void*)d->mem, (void*)d->woff, (void*)d->W, (void*)d->Y,
+                  (void*)d->occ_off, (void*)d->occ_slot, (void*)d->z, (void*)d->t})
+    dfree(p);
+  delete d;
+}
+
+SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, double shift, hipStream_t s) {
+  const int64_t n = c.n, m = c.m;
+  const int cap = schwarz_core_cap(max_block, pct);
+  // 1. root cube of the surface points and their Hilbert order on it
+  double* box = talloc<double>(6);
+  double* scratch = talloc<double>(6 * 1024);
+  bounding_box(c.xpaper, n, box, scratch, s);
+  std::vector<double> hbox = download(box, 6, s);
+  RBF_HIP(hipStreamSynchronize(s));
+  temp_free(box);
+  temp_free(scratch);
+  double side = 0.0;
+  for (int d = 0; d < 3; ++d) side = std::max(side, hbox[3 + d] - hbox[d]);
+  if (!(side > 0.0)) side = 1.0;
+  Lattice L{};
+  for (int d = 0; d < 3; ++d) {
+    L.origin[d] = hbox[d];
+    L.fdims[d] = kFineMax;
+    L.cdims[d] = kFineMax;
+  }
+  L.fine = side / (double)kFineMax;
+  L.shift = 0;
+  L.coarse = L.fine;
+  uint32_t* sperm = talloc<uint32_t>(n);
+  uint32_t* skeys = talloc<uint32_t>(n);
+  sort_points(c.xpaper, n, L, sperm, skeys, s);
+  std::vector<uint32_t> hk = download(skeys, n, s), hp = download(sperm, n, s);
+  std::vector<uint32_t> perm = download(c.perm, m, s);
+  RBF_HIP(hipStreamSynchronize(s));
+  temp_free(sperm);
+  temp_free(skeys);
+
+  // 2. octree leaves: ranges of the sorted points
+  struct Leaf {
+    int64_t a, b;
+    int level;
+  };
+  std::vector<Leaf> leaves;
+  std::function<void(int64_t, int64_t, int)> visit = [&](int64_t a, int64_t b, int level) {
+    if (b - a <= cap || level == kCurveBits) {
+      for (int64_t q = a; q < b; q += cap) leaves.push_back({q, std::min<int64_t>(b, q + cap), level});
+      return;
+    }
+    const int sh = 3 * (kCurveBits - 1 - level);
+    int64_t q = a;
+    while (q < b) {
+      const uint32_t dig = (hk[q] >> sh) & 7u;
+      int64_t e = q;
+      while (e < b && ((hk[e] >> sh) & 7u) == dig) ++e;
+      visit(q, e, level + 1);
+      q = e;
+    }
+  };
+  if (n > 0) visit(0, n, 0);
+  const int64_t nsub = (int64_t)leaves.size();
+
+  // 3. cores (paper indices: the points in increasing order, then their +, - offsets)
+  std::vector<int64_t> core_off(nsub + 1, 0), ov_off(nsub + 1, 0);
+  std::vector<uint32_t> core_mem;
+  std::vector<int32_t> kcount(nsub);
+  std::vector<double> rho(nsub);
+  core_mem.reserve((size_t)m);
+  for (int64_t i = 0; i < nsub; ++i) {
+    std::vector<uint32_t> pts(hp.begin() + leaves[i].a, hp.begin() + leaves[i].b);
+    std::sort(pts.begin(), pts.end());
+    for (int t = 0; t < 3; ++t)
+      for (uint32_t p : pts) core_mem.push_back((uint32_t)(p + t * n));
+    const int nc = (int)(3 * pts.size());
+    core_off[i + 1] = core_off[i] + nc;
+    kcount[i] = (int32_t)std::min<int64_t>(schwarz_overlap_count(nc, pct), m - nc);
+    ov_off[i + 1] = ov_off[i] + kcount[i];
+    rho[i] = std::ldexp(side, -leaves[i].level);   // the side of the leaf's cell
+  }
+
+  // 4. overlaps on the device
+  int64_t* d_core_off = upload(core_off, s);
+  uint32_t* d_core_mem = upload(core_mem, s);
+  int32_t* d_k = upload(kcount, s);
+  int64_t* d_ov_off = upload(ov_off, s);
+  double* d_rho = upload(rho, s);
+  double* d_box = talloc<double>(6 * std::max<int64_t>(nsub, 1));
+  uint32_t* d_ov = talloc<uint32_t>(std::max<int64_t>(ov_off[nsub], 1));
+  int32_t* d_short = talloc<int32_t>(std::max<int64_t>(nsub, 1));
+  std::vector<uint32_t> ov;
+  if (nsub > 0) {
+    hipLaunchKernelGGL(k_schwarz_box, dim3((unsigned)nsub), dim3(64), 0, s, c.xpaper, d_core_off, d_core_mem, d_box);
+    RBF_HIP(hipGetLastError());
+    OvArgs oa{c.xpaper, nsub, d_core_off, d_core_mem, d_box, d_k, d_ov_off, d_rho, nullptr, 0, d_ov, d_short};
+    hipLaunchKernelGGL(k_schwarz_overlap, dim3((unsigned)nsub), dim3(kOvThreads), 0, s, oa);
+    RBF_HIP(hipGetLastError());
+    std::vector<int32_t> short_of = download(d_short, nsub, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> again;
+    for (int64_t i = 0; i < nsub; ++i)
+      if (short_of[i]) again.push_back((int32_t)i);
+    if (!again.empty()) {
+      // too few centres within the leaf-sized radius: search them all
+      int32_t* d_list = upload(again, s);
+      oa.list = d_list;
+      oa.unbounded = 1;
+      hipLaunchKernelGGL(k_schwarz_overlap, dim3((unsigned)again.size()), dim3(kOvThreads), 0, s, oa);
+      RBF_HIP(hipGetLastError());
+      RBF_HIP(hipStreamSynchronize(s));
+      dfree(d_list);
+    }
+    ov = download(d_ov, ov_off[nsub], s);
+    RBF_HIP(hipStreamSynchronize(s));
+  }
+  for (void* p : {(void*)d_core_off, (void*)d_core_mem, (void*)d_k, (void*)d_ov_off, (void*)d_rho, (void*)d_box,
+                  (void*)d_ov, (void*)d_short})
+    dfree(p);
+
+  // 5. members in sorted positions, layout of the inverses, occurrences
+  std::vector<uint32_t> inv(m);
+  for (int64_t q = 0; q < m; ++q) inv[perm[q]] = (uint32_t)q;
+  SchwarzData* d = new SchwarzData();
+  d->nsub = nsub;
+  d->restricted = restricted;
+  d->shift = shift;
+  d->max_block = max_block;
+  d->pct = pct;
+  d->h_mem_off.assign(nsub + 1, 0);
+  d->h_ncore.resize(nsub);
+  std::vector<uint32_t> mem;
+  std::vector<int64_t> woff(nsub, 0);
+  std::vector<int32_t> order(nsub);
+  int64_t wtotal = 0;
+  for (int64_t i = 0; i < nsub; ++i) {
+    const int nc = (int)(core_off[i + 1] - core_off[i]);
+    for (int64_t e = core_off[i]; e < core_off[i + 1]; ++e) d->h_mem_paper.push_back(core_mem[e]);
+    for (int64_t e = ov_off[i]; e < ov_off[i + 1]; ++e) d->h_mem_paper.push_back(ov[e]);
+    const int64_t nb = nc + (ov_off[i + 1] - ov_off[i]);
+    d->h_mem_off[i + 1] = d->h_mem_off[i] + nb;
+    d->h_ncore[i] = nc;
+    woff[i] = wtotal;
+    wtotal += nb * nb;
+    order[i] = (int32_t)i;
+  }
+  d->nmem = d->h_mem_off[nsub];
+  mem.resize(d->nmem);
+  for (int64_t e = 0; e < d->nmem; ++e) mem[e] = inv[d->h_mem_paper[e]];
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return d->h_mem_off[x + 1] - d->h_mem_off[x] > d->h_mem_off[y + 1] - d->h_mem_off[y];
+  });
+  d->mem_off = upload(d->h_mem_off, s);
+  d->ncore = upload(d->h_ncore, s);
+  d->mem = upload(mem, s);
+  d->woff = upload(woff, s);
+  d->W = dalloc<float>(std::max<int64_t>(wtotal, 1));
+  d->w_total = wtotal;
+  if (!restricted) {
+    std::vector<int64_t> occ_off(m + 1, 0), occ_slot(d->nmem);
+    for (int64_t e = 0; e < d->nmem; ++e) ++occ_off[mem[e] + 1];
+    for (int64_t j = 0; j < m; ++j) occ_off[j + 1] += occ_off[j];
+    std::vector<int64_t> fillp(occ_off.begin(), occ_off.end() - 1);
+    for (int64_t e = 0; e < d->nmem; ++e) occ_slot[fillp[mem[e]]++] = e;   // subdomain order
+    d->occ_off = upload(occ_off, s);
+    d->occ_slot = upload(occ_slot, s);
+    d->Y = dalloc<double>(std::max<int64_t>(d->nmem, 1));
+  }
+  d->z = dalloc<double>(c.mpad);
+  d->t = dalloc<double>(c.mpad);
+  fill_f64(d->z, 0.0, c.mpad, s);
+  fill_f64(d->t, 0.0, c.mpad, s);
+
+  // 6. local inverses
+  if (nsub > 0) {
+    int32_t* d_order = upload(order, s);
+    double* d_shift = talloc<double>(nsub);
+    int32_t* d_retries = talloc<int32_t>(nsub);
+    int* d_flags = talloc<int>(2);   // [0] queue, [1] failed
+    fill_u32(reinterpret_cast<uint32_t*>(d_flags), 0u, 2, s);
+    int cus = 0;
+    RBF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
+    const unsigned grid = (unsigned)std::min<int64_t>(nsub, std::max(cus, 1));
+    FacArgs fa{c.xs, d->mem_off, d->mem, d_order, nsub, d->woff, 2.0 * c.sigma * c.sigma, shift, 8,
+               d->W, d_shift, d_retries, d_flags + 1, d_flags};
+    hipLaunchKernelGGL(k_schwarz_factor, dim3(grid), dim3(kFacThreads), 0, s, fa);
+    RBF_HIP(hipGetLastError());
+    std::vector<double> hs = download(d_shift, nsub, s);
+    std::vector<int32_t> hr = download(d_retries, nsub, s);
+    std::vector<int> hf = download(d_flags, 2, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    for (void* p : {(void*)d_order, (void*)d_shift, (void*)d_retries, (void*)d_flags}) temp_free(p);
+    d->max_shift = 0.0;
+    d->retries = 0;
+    for (int64_t i = 0; i < nsub; ++i) {
+      d->max_shift = std::max(d->max_shift, hs[i]);
+      d->retries += hr[i];
+    }
+    if (hf[1]) {
+      free_schwarz(d);
+      throw Error{RBF_EBREAKDOWN, "a subdomain block stayed indefinite after the shift retries"};
+    }
+  }
+  return d;
+}
+
+// z = M^{-1} r (sorted order; z must not alias r; entries >= m untouched).
+void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s, const int* skip) {
+  if (d.nsub == 0) return;
+  if (d.restricted) {
+    hipLaunchKernelGGL(k_schwarz_local<true>, dim3((unsigned)d.nsub), dim3(kApplyThreads), 0, s, d.mem_off, d.ncore,
+                       d.mem, d.woff, d.W, r, z, skip);
+  } else {
+    hipLaunchKernelGGL(k_schwarz_local<false>, dim3((unsigned)d.nsub), dim3(kApplyThreads), 0, s, d.mem_off, d.ncore,
+                       d.mem, d.woff, d.W, r, d.Y, skip);
+    hipLaunchKernelGGL(k_schwarz_sum, dim3((unsigned)ceil_div(c.m, 256)), dim3(256), 0, s, d.occ_off, d.occ_slot,
+                       d.Y, c.m, z, skip);
+  }
+  RBF_HIP(hipGetLastError());
+}
+
+}  // namespace rbf

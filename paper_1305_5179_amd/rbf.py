@@ -18,18 +18,31 @@ LIB_PATH = os.path.join(HERE, "librbf.so")
 RBF_OK, RBF_EINVAL, RBF_ENOMEM, RBF_EDEVICE, RBF_ENOCONV, RBF_EBREAKDOWN = 0, -1, -2, -3, -4, -5
 RBF_FP32, RBF_FP64 = 0, 1
 RBF_SOLVE_PLAIN_FP64, RBF_SOLVE_IR_FP32 = 0, 1
+RBF_PRECOND_NONE, RBF_PRECOND_SCHWARZ = 0, 1
 STATUS_NAMES = {0: "RBF_OK", -1: "RBF_EINVAL", -2: "RBF_ENOMEM", -3: "RBF_EDEVICE",
                 -4: "RBF_ENOCONV", -5: "RBF_EBREAKDOWN"}
 
 # Every symbol include/rbf.h declares.
 EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "rbf_solve",
            "rbf_eval_grid", "rbf_eval_points", "rbf_density", "rbf_get_stats", "rbf_count_grid_pairs",
-           "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error"]
+           "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error",
+           "rbf_default_schwarz_opts", "rbf_schwarz_setup", "rbf_schwarz_apply", "rbf_schwarz_get_info",
+           "rbf_schwarz_subdomains"]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_outer", C.c_int),
-                ("max_iters", C.c_int), ("mode", C.c_int), ("reserved", C.c_int)]
+                ("max_iters", C.c_int), ("mode", C.c_int), ("precond", C.c_int)]
+
+
+class SchwarzOpts(C.Structure):
+    _fields_ = [("max_block", C.c_int), ("overlap_pct", C.c_int), ("restricted", C.c_int),
+                ("reserved", C.c_int), ("shift", C.c_double)]
+
+
+class SchwarzInfo(C.Structure):
+    _fields_ = [("n_sub", C.c_int64), ("n_members", C.c_int64), ("max_members", C.c_int64),
+                ("inverse_bytes", C.c_int64), ("retries", C.c_int), ("max_shift", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -85,6 +98,11 @@ def load_library() -> C.CDLL:
     lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
     lib.rbf_profile_begin.argtypes = []
     lib.rbf_profile_end.argtypes = [C.POINTER(Profile)]
+    lib.rbf_default_schwarz_opts.argtypes = [C.POINTER(SchwarzOpts)]
+    lib.rbf_schwarz_setup.argtypes = [vp, C.POINTER(SchwarzOpts), vp]
+    lib.rbf_schwarz_apply.argtypes = [vp, vp, vp, vp]
+    lib.rbf_schwarz_get_info.argtypes = [vp, C.POINTER(SchwarzInfo)]
+    lib.rbf_schwarz_subdomains.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(i64)]
     lib.rbf_destroy.argtypes = [vp]
     lib.rbf_destroy.restype = None
     lib.rbf_last_error.argtypes = [vp]
@@ -244,6 +262,43 @@ class Rbf:
         s = Stats()
         self._check(self._lib.rbf_get_stats(self.ctx, C.byref(s)))
         return s
+
+    def schwarz_setup(self, **opts) -> SchwarzInfo:
+        """Build the Schwarz preconditioner (rbf_schwarz_setup); returns its sizes."""
+        o = SchwarzOpts()
+        self._lib.rbf_default_schwarz_opts(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self._check(self._lib.rbf_schwarz_setup(self.ctx, C.byref(o), _stream()))
+        return self.schwarz_info()
+
+    def schwarz_info(self) -> SchwarzInfo:
+        info = SchwarzInfo()
+        self._check(self._lib.rbf_schwarz_get_info(self.ctx, C.byref(info)))
+        return info
+
+    def schwarz_apply(self, r, z=None):
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        self._check(self._lib.rbf_schwarz_apply(self.ctx, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def schwarz_subdomains(self) -> list:
+        """[(core centres, overlap centres)] as numpy int64 arrays (paper indices)."""
+        import numpy as np
+        info = self.schwarz_info()
+        offs = np.zeros(info.n_sub + 1, dtype=np.int64)
+        ncore = np.zeros(max(info.n_sub, 1), dtype=np.int32)
+        mem = np.zeros(max(info.n_members, 1), dtype=np.int64)
+        self._check(self._lib.rbf_schwarz_subdomains(
+            self.ctx, offs.ctypes.data_as(C.POINTER(C.c_int64)), ncore.ctypes.data_as(C.POINTER(C.c_int32)),
+            mem.ctypes.data_as(C.POINTER(C.c_int64))))
+        out = []
+        for i in range(info.n_sub):
+            seg = mem[offs[i]:offs[i + 1]]
+            out.append((seg[:ncore[i]].copy(), seg[ncore[i]:].copy()))
+        return out
 
     def count_grid_pairs(self, origin, h, dims):
         g = make_grid(origin, h, dims)

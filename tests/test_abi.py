@@ -43,8 +43,28 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_solve_options():
     o = rbf.default_opts()
-    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.reserved) == (1e-8, 30, 1000, 30000, 1, 0)
+    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.precond) == (1e-8, 30, 1000, 30000, 1, 0)
     assert rbf.load_library().rbf_default_solve_opts(None) == rbf.RBF_EINVAL
+
+
+def test_default_schwarz_options():
+    o = rbf.SchwarzOpts()
+    lib = rbf.load_library()
+    assert lib.rbf_default_schwarz_opts(C.byref(o)) == rbf.RBF_OK
+    assert (o.max_block, o.overlap_pct, o.restricted, o.reserved, o.shift) == (192, 10, 0, 0, 0.1)
+    assert lib.rbf_default_schwarz_opts(None) == rbf.RBF_EINVAL
+
+
+def test_schwarz_entry_points_reject_null_context():
+    lib = rbf.load_library()
+    o = rbf.SchwarzOpts()
+    lib.rbf_default_schwarz_opts(C.byref(o))
+    assert lib.rbf_schwarz_setup(None, C.byref(o), None) == rbf.RBF_EINVAL
+    p = C.c_void_p(0x1000)
+    assert lib.rbf_schwarz_apply(None, p, p, None) == rbf.RBF_EINVAL
+    info = rbf.SchwarzInfo()
+    assert lib.rbf_schwarz_get_info(None, C.byref(info)) == rbf.RBF_EINVAL
+    assert lib.rbf_schwarz_subdomains(None, None, None, None) == rbf.RBF_EINVAL
 
 
 @pytest.mark.parametrize("n,eps,sigma,cutoff,msg", [
