@@ -179,6 +179,7 @@ def main():
             ctx.matvec(x, y, prec=prec)
         torch.cuda.synchronize()
         phases[key] = 1e3 * (time.perf_counter() - t) / 5
+    schwarz = schwarz_measurement(rbf, ctx, torch, x)
     ctx.close()
 
     rbf.profile_begin()
@@ -226,6 +227,7 @@ def main():
                   "grid_useful": grid_useful, "grid_examined": grid_examined,
                   "applications_per_step": applications},
         "grid_kernel_f32": evaluation,
+        "schwarz": schwarz,
         "fp64_kernel": {"launches": prof.launches[OP][F64],
                         "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
                         "useful_rate": prof.useful_pairs[OP][F64] / max(prof.kernel_ms[OP][F64] * 1e-3, 1e-30) / 1e9},
@@ -245,20 +247,59 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def schwarz_measurement(rbf, ctx, torch, x):
+    """The Schwarz preconditioner with its default options: setup time, and
+    the time of one apply (gather, local products, sums, scatter) from torch
+    events on the stream the library runs on.  The apply streams the float32
+    local inverses once: its algorithmic bytes are those plus the vector
+    traffic (members gathered, local results written and summed, result
+    written), against the 8 TB/s of HBM."""
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info = ctx.schwarz_setup()
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t)
+    z = torch.empty_like(x)
+    ctx.schwarz_apply(x, z)
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.schwarz_apply(x, z)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / reps
+    m = x.numel()
+    alg_bytes = info.inverse_bytes + 8 * (3 * info.n_members + 4 * m)
+    return {"form": "additive", "max_block": 192, "overlap_pct": 10, "shift": 0.1,
+            "n_sub": info.n_sub, "n_members": info.n_members, "max_members": info.max_members,
+            "inverse_bytes": info.inverse_bytes, "retries": info.retries, "setup_ms": setup_ms,
+            "apply_ms": apply_ms,
+            "apply_roofline": {"bound": "hbm", "achieved": alg_bytes / (apply_ms * 1e-3) / 1e9, "peak": 8000.0,
+                               "unit": "GB/s", "frac": alg_bytes / (apply_ms * 1e-3) / 8e12,
+                               "bytes_per_apply": alg_bytes}}
+
+
 def solve_comparison(rbf, pts, nrm, cfg, g, iters):
-    """Chosen pipeline (float32 operator + float64 refinement) against the plain
-    float64 method, each from setup to grid.  When either stops above 1e-8,
-    both are compared at the lowest residual both reach (the common
-    residual): time to it = setup + solve up to that residual + grid."""
+    """Chosen pipeline (float32 operator + float64 refinement), the same with
+    the additive Schwarz preconditioner, and the plain float64 method, each
+    from setup to grid.  When one stops above 1e-8, they are compared at the
+    lowest residual all reach (the common residual): time to it = setup
+    (+ preconditioner setup) + solve up to that residual + grid."""
     import torch
     res = {}
-    for name, mode in (("ir_fp32", rbf.RBF_SOLVE_IR_FP32), ("plain_fp64", rbf.RBF_SOLVE_PLAIN_FP64)):
+    runs = (("ir_fp32", rbf.RBF_SOLVE_IR_FP32, False), ("ir_fp32_schwarz", rbf.RBF_SOLVE_IR_FP32, True),
+            ("plain_fp64", rbf.RBF_SOLVE_PLAIN_FP64, False))
+    for name, mode, pre in runs:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rbf.Rbf(pts, nrm, cfg["eps"], cfg["sigma"], cfg["cutoff"])
+        if pre:
+            ctx.schwarz_setup()
         torch.cuda.synchronize()
         setup_ms = 1e3 * (time.perf_counter() - t0)
-        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode)
+        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode,
+                               precond=rbf.RBF_PRECOND_SCHWARZ if pre else rbf.RBF_PRECOND_NONE)
         t1 = time.perf_counter()
         prec = rbf.RBF_FP32 if mode == rbf.RBF_SOLVE_IR_FP32 else rbf.RBF_FP64
         out = torch.empty(g.size, dtype=torch.float32 if prec == rbf.RBF_FP32 else torch.float64, device="cuda")
@@ -268,12 +309,14 @@ def solve_comparison(rbf, pts, nrm, cfg, g, iters):
         res[name] = {"setup_ms": setup_ms, "grid_ms": grid_ms, "status": info.status, "iters": info.iters,
                      "rel_resid": info.rel_resid, "history": info.history, "history_ms": info.history_ms}
         ctx.close()
-    common = max(min(res["ir_fp32"]["history"]), min(res["plain_fp64"]["history"]), 1e-8)
+    common = max(max(min(r["history"]) for r in res.values()), 1e-8)
     for r in res.values():
         t = next(ms for h, ms in zip(r["history"], r["history_ms"]) if h <= common)
         r["ms_to_common"] = r["setup_ms"] + t + r["grid_ms"]
+    plain = res["plain_fp64"]["ms_to_common"]
     return {"target": 1e-8, "common_resid": common,
-            "speedup_at_common": res["plain_fp64"]["ms_to_common"] / res["ir_fp32"]["ms_to_common"], **res}
+            "speedup_at_common": plain / res["ir_fp32"]["ms_to_common"],
+            "speedup_at_common_schwarz": plain / res["ir_fp32_schwarz"]["ms_to_common"], **res}
 
 
 if __name__ == "__main__":
