@@ -1,3 +1,3 @@
-"""CPU oracle (test infrastructure only; see rbf_oracle.py and schwarz.py)."""
+"""CPU oracle (test infrastructure only; see rbf_oracle.py, schwarz.py and mlp.py)."""
 from .rbf_oracle import *  # noqa: F401,F403
-from . import schwarz  # noqa: F401
+from . import mlp, schwarz  # noqa: F401
