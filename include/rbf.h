@@ -215,6 +215,53 @@ int rbf_schwarz_get_info(const rbf_ctx* ctx, rbf_schwarz_info* info);
  * overlap, nearest first. */
 int rbf_schwarz_subdomains(const rbf_ctx* ctx, int64_t* offsets, int32_t* n_core, int64_t* members);
 
+/* Learned narrow-band cull (Sec. II.A.3: the interpolant is needed only in a
+ * narrow volume around the surface).  A network
+ *   u = (x - centre) * scale -> 128 -> 128 -> 128 -> 128 -> y,
+ * SiLU after every hidden layer, predicts f(x) / tau.  Parameters, float32,
+ * RBF_NET_PARAMS of them in this order: W1 [128][3], b1 [128], W2 [128][128],
+ * b2, W3 [128][128], b3, W4 [128][128], b4, w5 [128], b5 [1] (W_l[out][in]).
+ * The three 128 x 128 layers run on the matrix cores in bf16 with float32
+ * accumulation, the others in float32. */
+#define RBF_NET_PARAMS 50177
+
+typedef struct {
+    int64_t support_bricks;   /* bricks of 4 x 2 x 2 nodes with a centre within the cutoff */
+    int64_t kept_bricks;      /* of those, evaluated exactly */
+    int64_t useful_pairs;     /* node-centre pairs with r^2 <= cutoff^2 of the kept bricks */
+    int64_t examined_pairs;   /* pairs the exact sum computed */
+} rbf_cull_stats;
+
+/* Install a network on the context (params: HOST array of RBF_NET_PARAMS
+ * floats; centre: host double[3]); resets the Adam state.  Synchronises. */
+int rbf_net_set(rbf_ctx* ctx, const float* params, const double centre[3], double scale, double tau,
+                void* stream);
+/* Current parameters into a HOST array of RBF_NET_PARAMS floats.  Synchronises. */
+int rbf_net_get(rbf_ctx* ctx, float* params, void* stream);
+/* y = network(x) for n positions x (device n x 3 float64); y: device n float32. */
+int rbf_net_forward(rbf_ctx* ctx, const double* x, int64_t n, float* y, void* stream);
+/* Gradient of the loss mean_i (y_i - f_i / tau)^2 over the n samples
+ * (x: device n x 3, f: device n float64 values of the interpolant) into grad
+ * (device, RBF_NET_PARAMS floats, the parameter order above); *loss (host,
+ * may be NULL) gets the loss.  Synchronises. */
+int rbf_net_gradient(rbf_ctx* ctx, const double* x, const double* f, int64_t n, float* grad, double* loss,
+                     void* stream);
+/* Adam (lr, b1 = 0.9, b2 = 0.999, eps = 1e-8) over `epochs` passes of the n
+ * samples in their given order, `batch` consecutive samples a step.
+ * *loss (host, may be NULL) gets the mean loss of the last pass.
+ * Synchronises. */
+int rbf_net_train(rbf_ctx* ctx, const double* x, const double* f, int64_t n, int batch, int epochs, double lr,
+                  double* loss, void* stream);
+/* f on a grid with the learned cull: nodes outside the support (no centre
+ * within the cutoff of their brick) get 0; the network runs on every node of
+ * the support; a support brick is evaluated exactly (float32 pair sums, as
+ * rbf_eval_grid) when one of its nodes has |y| < e_val or has a support node
+ * of the opposite sign of y within 3 grid steps along every axis; every other
+ * support node gets tau * y.  out: device float32, x fastest.  stats: host,
+ * may be NULL.  Synchronises. */
+int rbf_eval_grid_culled(rbf_ctx* ctx, const double* c, const rbf_grid* grid, float* out, double e_val,
+                         rbf_cull_stats* stats, void* stream);
+
 /* Sizes and pair counts of the context (host call, no device work). */
 int rbf_get_stats(const rbf_ctx* ctx, rbf_stats* stats);
 

@@ -83,21 +83,6 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
-void free_targets(TargetSet& ts) {
-  auto release = [&](void* p) {
-    if (ts.temp)
-      temp_free(p);
-    else
-      dfree(p);
-  };
-  for (void* p : ts.owned) release(p);
-  ts.owned.clear();
-  release(ts.pts);
-  ts.pts = nullptr;
-  ts.groups = nullptr;
-  ts.list = nullptr;
-  ts.mask = nullptr;
-}
 
 void free_ctx(Ctx* c) {
   if (!c) return;
@@ -107,6 +92,8 @@ void free_ctx(Ctx* c) {
   free_targets(c->centres);
   free_schwarz(c->schwarz);
   c->schwarz = nullptr;
+  free_net(c->net);
+  c->net = nullptr;
   for (void* p : {(void*)c->perm, (void*)c->keys, (void*)c->xs, (void*)c->xk, (void*)c->xpaper, (void*)c->cell_start,
                   (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->vin, (void*)c->vout,
                   (void*)c->V, (void*)c->w, (void*)c->r, (void*)c->csol, (void*)c->bsort, (void*)c->partial,
@@ -646,6 +633,116 @@ int rbf_schwarz_subdomains(const rbf_ctx* c, int64_t* offsets, int32_t* n_core, 
   for (int64_t i = 0; i < d.nsub; ++i) n_core[i] = d.h_ncore[i];
   for (int64_t e = 0; e < d.nmem; ++e) members[e] = d.h_mem_paper[e];
   return RBF_OK;
+}
+
+int rbf_net_set(rbf_ctx* c, const float* params, const double centre[3], double scale, double tau, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!params || !centre) return fail(c, RBF_EINVAL, "params and centre must not be NULL (host arrays)");
+  if (is_device_ptr(params)) return fail(c, RBF_EINVAL, "params must be a host array");
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(centre[d])) return fail(c, RBF_EINVAL, "centre must be finite");
+  if (!(scale > 0.0) || !std::isfinite(scale) || !(tau > 0.0) || !std::isfinite(tau))
+    return fail(c, RBF_EINVAL, "scale and tau must be finite and > 0");
+  for (int i = 0; i < RBF_NET_PARAMS; ++i)
+    if (!std::isfinite(params[i])) return fail(c, RBF_EINVAL, "params must be finite");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    free_net(c->net);
+    c->net = nullptr;
+    c->net = net_create(params, centre, scale, tau, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    return RBF_OK;
+  });
+}
+
+int rbf_net_get(rbf_ctx* c, float* params, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c || !params) return fail(c, RBF_EINVAL, "ctx and params must not be NULL");
+  if (!c->net) return fail(c, RBF_EINVAL, "no network on this context (rbf_net_set)");
+  if (is_device_ptr(params)) return fail(c, RBF_EINVAL, "params must be a host array");
+  return guarded(c, [&]() -> int {
+    net_get(*c->net, params, (hipStream_t)stream);
+    return RBF_OK;
+  });
+}
+
+int rbf_net_forward(rbf_ctx* c, const double* x, int64_t n, float* y, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!c->net) return fail(c, RBF_EINVAL, "no network on this context (rbf_net_set)");
+  if (n < 0) return fail(c, RBF_EINVAL, "n must be >= 0");
+  if (n > 0 && (!is_device_ptr(x) || !is_device_ptr(y))) return fail(c, RBF_EINVAL, "x and y must be device pointers");
+  return guarded(c, [&]() -> int {
+    net_forward(*c->net, x, n, y, (hipStream_t)stream);
+    return RBF_OK;
+  });
+}
+
+int rbf_net_gradient(rbf_ctx* c, const double* x, const double* f, int64_t n, float* grad, double* loss,
+                     void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!c->net) return fail(c, RBF_EINVAL, "no network on this context (rbf_net_set)");
+  if (n <= 0) return fail(c, RBF_EINVAL, "n must be > 0");
+  if (!is_device_ptr(x) || !is_device_ptr(f) || !is_device_ptr(grad))
+    return fail(c, RBF_EINVAL, "x, f and grad must be device pointers");
+  return guarded(c, [&]() -> int {
+    const double L = net_step(*c->net, x, f, n, grad, false, 0.0, (hipStream_t)stream);
+    if (loss) *loss = L;
+    return RBF_OK;
+  });
+}
+
+int rbf_net_train(rbf_ctx* c, const double* x, const double* f, int64_t n, int batch, int epochs, double lr,
+                  double* loss, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!c->net) return fail(c, RBF_EINVAL, "no network on this context (rbf_net_set)");
+  if (n <= 0 || batch <= 0 || epochs < 0) return fail(c, RBF_EINVAL, "n > 0, batch > 0 and epochs >= 0 required");
+  if (!(lr > 0.0) || !std::isfinite(lr)) return fail(c, RBF_EINVAL, "lr must be finite and > 0");
+  if (!is_device_ptr(x) || !is_device_ptr(f)) return fail(c, RBF_EINVAL, "x and f must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int e = 0; e < epochs; ++e) {
+      sum = 0.0;
+      cnt = 0;
+      for (int64_t b0 = 0; b0 < n; b0 += batch) {
+        const int64_t B = std::min<int64_t>(batch, n - b0);
+        sum += B * net_step(*c->net, x + 3 * b0, f + b0, B, nullptr, true, lr, s);
+        cnt += B;
+      }
+    }
+    if (loss) *loss = cnt > 0 ? sum / (double)cnt : 0.0;
+    return RBF_OK;
+  });
+}
+
+int rbf_eval_grid_culled(rbf_ctx* c, const double* cw, const rbf_grid* grid, float* out, double e_val,
+                         rbf_cull_stats* stats, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  int st = check_grid(c, grid);
+  if (st != RBF_OK) return st;
+  if (!c->net) return fail(c, RBF_EINVAL, "no network on this context (rbf_net_set)");
+  if (!(e_val >= 0.0) || !std::isfinite(e_val)) return fail(c, RBF_EINVAL, "e_val must be finite and >= 0");
+  if (!is_device_ptr(cw) || !is_device_ptr(out)) return fail(c, RBF_EINVAL, "c and out must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    gather_to_sorted(cw, c->perm, c->m, c->vin, s);
+    NetCullStats ns;
+    net_eval_grid_culled(*c, *c->net, c->vin, *grid, out, e_val, 3, &ns, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    if (stats) {
+      stats->support_bricks = ns.support_bricks;
+      stats->kept_bricks = ns.kept_bricks;
+      stats->useful_pairs = ns.useful_pairs;
+      stats->examined_pairs = ns.examined_pairs;
+    }
+    return RBF_OK;
+  });
 }
 
 int rbf_get_stats(const rbf_ctx* c, rbf_stats* st) {

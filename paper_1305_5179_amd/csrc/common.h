@@ -104,6 +104,23 @@ struct SchwarzData {
   std::vector<uint32_t> h_mem_paper;   // members as paper indices
 };
 
+// The network of the learned narrow-band cull (mlp.hip): float32 parameters
+// (layout of RBF_NET_PARAMS in rbf.h), Adam moments, bf16 copies of the
+// three wide layers and of their transposes, and the input normalisation.
+struct NetData {
+  float* P = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  __bf16* Wb = nullptr;
+  __bf16* WbT = nullptr;
+  double centre[3] = {0, 0, 0};
+  double scale = 1.0, tau = 1.0;
+  int64_t step = 0;
+};
+struct NetCullStats {
+  int64_t support_bricks = 0, kept_bricks = 0, useful_pairs = 0, examined_pairs = 0;
+};
+
 // A set of targets grouped by 16 (centres, grid nodes or evaluation points)
 // together with the source list of every group.
 struct TargetSet {
@@ -158,6 +175,7 @@ struct Ctx {
   int64_t n_cells = 0;
   TargetSet centres;            // the centres as targets of the operator
   SchwarzData* schwarz = nullptr;
+  NetData* net = nullptr;
   // Work vectors (sorted order, length mpad, entry m kept 0).
   double* vin = nullptr;
   double* vout = nullptr;
@@ -287,13 +305,37 @@ void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* 
                    const int* skip = nullptr);
 void free_schwarz(SchwarzData* d);
 
+// mlp.hip
+int net_param_count();
+NetData* net_create(const float* host_params, const double centre[3], double scale, double tau, hipStream_t s);
+void free_net(NetData* d);
+void net_get(const NetData& d, float* host_params, hipStream_t s);
+void net_forward(const NetData& d, const double* X, int64_t B, float* y, hipStream_t s);
+double net_step(NetData& d, const double* X, const double* f, int64_t B, float* grad, bool adam, double lr,
+                hipStream_t s);
+void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted, const rbf_grid& g, float* out,
+                          double e_val, int reach, NetCullStats* st, hipStream_t s);
+
 // krylov.hip
 void vec_add(double* x, const double* y, int64_t n, hipStream_t s);
 void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s);
 void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s);
 
-// setup.hip: targets of the evaluation entry points
+// setup.hip: targets of the evaluation entry points.  Grid nodes go by
+// bricks of 4 x 2 x 2 (x fastest), brick b = bx + nb[0] (by + nb[1] bz).
+struct GridDesc {
+  double o[3], h[3];
+  int64_t n[3];
+  int64_t nb[3];
+};
+GridDesc grid_desc(const rbf_grid& g);
+// Ids of the bricks with a centre within the cutoff of one of their nodes
+// (*ids = null and every brick without a cutoff); *ids is a temporary.
+int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids, hipStream_t s);
+void brick_targets(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, TargetSet& ts,
+                   hipStream_t s);
 void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s);
+void free_targets(TargetSet& ts);
 void point_targets(const Ctx& c, const double* pts, int64_t npts, TargetSet& ts, hipStream_t s);
 
 }  // namespace rbf

@@ -760,11 +760,6 @@ __global__ void k_sum_i64(const int64_t* __restrict__ in, int64_t n, int64_t* __
 // cutoff, reaches one of its nodes.  Nodes of inactive bricks have no centre
 // within the cutoff and keep the zero written beforehand.
 // ---------------------------------------------------------------------------
-struct GridDesc {
-  double o[3], h[3];
-  int64_t n[3];
-  int64_t nb[3];
-};
 __device__ __forceinline__ bool node_range(double lo, double hi, double o, double h, int64_t n, int64_t* a, int64_t* b) {
   if (h == 0.0) {
     if (o < lo || o > hi) return false;
@@ -1192,7 +1187,24 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
   temp_free(tmp);
 }
 
-void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s) {
+// Releases every array of a target set (stream-ordered for temporaries).
+void free_targets(TargetSet& ts) {
+  auto release = [&](void* p) {
+    if (ts.temp)
+      temp_free(p);
+    else
+      dfree(p);
+  };
+  for (void* p : ts.owned) release(p);
+  ts.owned.clear();
+  release(ts.pts);
+  ts.pts = nullptr;
+  ts.groups = nullptr;
+  ts.list = nullptr;
+  ts.mask = nullptr;
+}
+
+GridDesc grid_desc(const rbf_grid& g) {
   GridDesc gd;
   const int bs[3] = {4, 2, 2};
   for (int d = 0; d < 3; ++d) {
@@ -1201,31 +1213,41 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s)
     gd.n[d] = g.dims[d];
     gd.nb[d] = ceil_div(g.dims[d], bs[d]);
   }
+  return gd;
+}
+
+int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids_out, hipStream_t s) {
+  const GridDesc gd = grid_desc(g);
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
+  *ids_out = nullptr;
+  if (!std::isfinite(c.cutoff)) return nbricks;
+  int64_t* mark = talloc<int64_t>(nbricks);
+  int64_t* pos = talloc<int64_t>(nbricks);
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
+  hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
+                     c.cutoff, gd, mark);
+  RBF_HIP(hipGetLastError());
+  scan_exclusive_i64(mark, pos, nbricks, s);
+  int64_t last_pos = 0, last_mark = 0;
+  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  const int64_t nact = last_pos + last_mark;
+  int64_t* ids = talloc<int64_t>(nact);
+  hipLaunchKernelGGL(k_compact, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, pos, nbricks, ids);
+  RBF_HIP(hipGetLastError());
+  temp_free(mark);
+  temp_free(pos);
+  *ids_out = ids;
+  return nact;
+}
+
+void brick_targets(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, TargetSet& ts,
+                   hipStream_t s) {
+  const GridDesc gd = grid_desc(g);
   ts.temp = true;
   ts.kind = 1;
-  int64_t* ids = nullptr;
-  int64_t nact = nbricks;
   ts.dense = !std::isfinite(c.cutoff);
-  if (!ts.dense) {
-    int64_t* mark = talloc<int64_t>(nbricks);
-    int64_t* pos = talloc<int64_t>(nbricks);
-    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
-    hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
-                       c.cutoff, gd, mark);
-    RBF_HIP(hipGetLastError());
-    scan_exclusive_i64(mark, pos, nbricks, s);
-    int64_t last_pos = 0, last_mark = 0;
-    RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipStreamSynchronize(s));
-    nact = last_pos + last_mark;
-    ids = talloc<int64_t>(nact);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, pos, nbricks, ids);
-    RBF_HIP(hipGetLastError());
-    temp_free(mark);
-    temp_free(pos);
-  }
   ts.n_groups = nact;
   ts.pts = set_alloc<double4>(ts, nact * kGroup);
   ts.index = set_alloc<int64_t>(ts, nact * kGroup);
@@ -1244,6 +1266,12 @@ void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s)
     temp_free(cnt);
     build_lists(c, ts, s);
   }
+}
+
+void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s) {
+  int64_t* ids = nullptr;
+  const int64_t nact = support_bricks(c, g, &ids, s);
+  brick_targets(c, g, ids, nact, ts, s);
   temp_free(ids);
 }
 

@@ -27,7 +27,9 @@ EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "
            "rbf_eval_grid", "rbf_eval_points", "rbf_density", "rbf_get_stats", "rbf_count_grid_pairs",
            "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error",
            "rbf_default_schwarz_opts", "rbf_schwarz_setup", "rbf_schwarz_apply", "rbf_schwarz_get_info",
-           "rbf_schwarz_subdomains"]
+           "rbf_schwarz_subdomains", "rbf_net_set", "rbf_net_get", "rbf_net_forward", "rbf_net_gradient",
+           "rbf_net_train", "rbf_eval_grid_culled"]
+RBF_NET_PARAMS = 50177
 
 
 class SolveOpts(C.Structure):
@@ -68,6 +70,11 @@ class Profile(C.Structure):
                 ("useful_pairs", (C.c_int64 * 2) * 2), ("examined_pairs", (C.c_int64 * 2) * 2)]
 
 
+class CullStats(C.Structure):
+    _fields_ = [("support_bricks", C.c_int64), ("kept_bricks", C.c_int64), ("useful_pairs", C.c_int64),
+                ("examined_pairs", C.c_int64)]
+
+
 class RbfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -103,6 +110,12 @@ def load_library() -> C.CDLL:
     lib.rbf_schwarz_apply.argtypes = [vp, vp, vp, vp]
     lib.rbf_schwarz_get_info.argtypes = [vp, C.POINTER(SchwarzInfo)]
     lib.rbf_schwarz_subdomains.argtypes = [vp, C.POINTER(i64), C.POINTER(C.c_int32), C.POINTER(i64)]
+    lib.rbf_net_set.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(dbl), dbl, dbl, vp]
+    lib.rbf_net_get.argtypes = [vp, C.POINTER(C.c_float), vp]
+    lib.rbf_net_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.rbf_net_gradient.argtypes = [vp, vp, vp, i64, vp, C.POINTER(dbl), vp]
+    lib.rbf_net_train.argtypes = [vp, vp, vp, i64, i32, i32, dbl, C.POINTER(dbl), vp]
+    lib.rbf_eval_grid_culled.argtypes = [vp, vp, C.POINTER(Grid), vp, dbl, C.POINTER(CullStats), vp]
     lib.rbf_destroy.argtypes = [vp]
     lib.rbf_destroy.restype = None
     lib.rbf_last_error.argtypes = [vp]
@@ -299,6 +312,54 @@ class Rbf:
             seg = mem[offs[i]:offs[i + 1]]
             out.append((seg[:ncore[i]].copy(), seg[ncore[i]:].copy()))
         return out
+
+    def net_set(self, params, centre, scale: float, tau: float):
+        """Install the cull network (params: RBF_NET_PARAMS float32 values, host)."""
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != RBF_NET_PARAMS:
+            raise ValueError(f"expected {RBF_NET_PARAMS} parameters")
+        c3 = (C.c_double * 3)(*[float(v) for v in centre])
+        self._check(self._lib.rbf_net_set(self.ctx, p.ctypes.data_as(C.POINTER(C.c_float)), c3, float(scale),
+                                          float(tau), _stream()))
+
+    def net_get(self):
+        import numpy as np
+        p = np.zeros(RBF_NET_PARAMS, dtype=np.float32)
+        self._check(self._lib.rbf_net_get(self.ctx, p.ctypes.data_as(C.POINTER(C.c_float)), _stream()))
+        return p
+
+    def net_forward(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty(int(x.shape[0]), dtype=torch.float32, device="cuda")
+        self._check(self._lib.rbf_net_forward(self.ctx, _ptr(x), int(x.shape[0]), _ptr(y, "float32"), _stream()))
+        return y
+
+    def net_gradient(self, x, f):
+        import torch
+        g = torch.empty(RBF_NET_PARAMS, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        self._check(self._lib.rbf_net_gradient(self.ctx, _ptr(x), _ptr(f), int(x.shape[0]), _ptr(g, "float32"),
+                                               C.byref(loss), _stream()))
+        return g, loss.value
+
+    def net_train(self, x, f, batch: int, epochs: int, lr: float) -> float:
+        loss = C.c_double()
+        self._check(self._lib.rbf_net_train(self.ctx, _ptr(x), _ptr(f), int(x.shape[0]), int(batch), int(epochs),
+                                            float(lr), C.byref(loss), _stream()))
+        return loss.value
+
+    def eval_grid_culled(self, c, origin, h, dims, e_val: float, out=None):
+        import torch
+        g = make_grid(origin, h, dims)
+        total = int(dims[0]) * int(dims[1]) * int(dims[2])
+        if out is None:
+            out = torch.empty(total, dtype=torch.float32, device="cuda")
+        st = CullStats()
+        self._check(self._lib.rbf_eval_grid_culled(self.ctx, _ptr(c), C.byref(g), _ptr(out, "float32"),
+                                                   float(e_val), C.byref(st), _stream()))
+        return out, st
 
     def count_grid_pairs(self, origin, h, dims):
         g = make_grid(origin, h, dims)

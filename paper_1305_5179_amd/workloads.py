@@ -224,6 +224,50 @@ def lattice_cloud(nx: int, ny: int, spacing: float, seed: int = 6, jitter: float
     return Cloud(p, nrm, f"plane{nx}x{ny}")
 
 
+def net_init(seed: int = 8, width: int = 128, layers: int = 4) -> np.ndarray:
+    """Initial parameters of the cull network, flat float32 in the library's
+    order (W1, b1, W2, b2, W3, b3, W4, b4, w5, b5; W[out][in]): every entry
+    uniform in +-1/sqrt(fan_in) of its layer."""
+    rng = np.random.default_rng(seed)
+    sizes = [3] + [width] * layers + [1]
+    out = []
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        a = 1.0 / math.sqrt(fan_in)
+        out.append(rng.uniform(-a, a, size=fan_out * fan_in))
+        out.append(rng.uniform(-a, a, size=fan_out))
+    return np.concatenate(out).astype(np.float32)
+
+
+def net_unflatten(flat: np.ndarray, width: int = 128, layers: int = 4):
+    """[(W, b)] views of a flat parameter vector (float64 copies)."""
+    sizes = [3] + [width] * layers + [1]
+    out, o = [], 0
+    flat = np.asarray(flat, dtype=np.float64)
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        W = flat[o:o + fan_out * fan_in].reshape(fan_out, fan_in)
+        o += fan_out * fan_in
+        b = flat[o:o + fan_out]
+        o += fan_out
+        out.append((W.copy(), b.copy()))
+    return out
+
+
+def cull_samples(points: np.ndarray, radius: float, lo, hi, n: int, seed: int = 3) -> np.ndarray:
+    """Training positions of the cull network: half of them a random cloud
+    point plus a uniform offset in the ball of `radius` (the support of the
+    truncated interpolant), half uniform in the box [lo, hi]; shuffled."""
+    rng = np.random.default_rng(seed)
+    n_band = n // 2
+    base = points[rng.integers(0, len(points), n_band)]
+    d = rng.normal(size=(n_band, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    r = radius * rng.uniform(size=n_band) ** (1.0 / 3.0)
+    band = base + d * r[:, None]
+    box = rng.uniform(np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64), size=(n - n_band, 3))
+    X = np.concatenate([band, box])
+    return X[rng.permutation(n)]
+
+
 def halton(n: int, base: int, start: int = 1) -> np.ndarray:
     """Radical-inverse (van der Corput) sequence in ``base``, indices start..start+n-1."""
     out = np.empty(n)
