@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--solve", action="store_true",
                     help="also time full solves (float32+refinement vs plain float64) to a common residual")
     ap.add_argument("--solve-iters", type=int, default=3000)
+    ap.add_argument("--cull-samples", type=int, default=1_000_000,
+                    help="training positions of the learned narrow-band cull (0: skip that measurement)")
+    ap.add_argument("--cull-epochs", type=int, default=60)
     ap.add_argument("--calibrate", action="store_true",
                     help="after the timed steps, run one plain 256 MiB device copy (the reference a "
                          "hardware-counter run scales FETCH_SIZE / WRITE_SIZE by)")
@@ -232,6 +235,8 @@ def main():
                         "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
                         "useful_rate": prof.useful_pairs[OP][F64] / max(prof.kernel_ms[OP][F64] * 1e-3, 1e-30) / 1e9},
     }
+    if args.cull_samples > 0:
+        out["cull"] = cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, args.cull_samples, args.cull_epochs)
     if args.calibrate:
         src = torch.ones(1 << 25, dtype=torch.float64, device=dev)   # 256 MiB
         dst = torch.empty_like(src)
@@ -278,6 +283,70 @@ def schwarz_measurement(rbf, ctx, torch, x):
             "apply_roofline": {"bound": "hbm", "achieved": alg_bytes / (apply_ms * 1e-3) / 1e9, "peak": 8000.0,
                                "unit": "GB/s", "frac": alg_bytes / (apply_ms * 1e-3) / 8e12,
                                "bytes_per_apply": alg_bytes}}
+
+
+def cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, n_samples, epochs):
+    """The learned narrow-band cull on the workload's grid.  Weights from
+    three refinement steps (float32 operator); the network is trained (Adam,
+    lr 3e-3, batches of 16384) on positions in the support band (a cloud
+    point plus a uniform offset in the cutoff ball, seeded), on f / tau with
+    tau the RMS of f there; e_val is its largest error on a held-out set of
+    band positions.  Reported: the grid time plain and
+    culled (torch events, the network's inference included, training not),
+    the bricks kept, and the sign errors against the plain grid on nodes
+    with |f| > 1e-6 + 8 u32 |f|max."""
+    import numpy as np
+
+    from paper_1305_5179_amd import workloads as w
+    eps, sigma, rc = cfg["eps"], cfg["sigma"], cfg["cutoff"]
+    ctx = rbf.Rbf(pts, nrm, eps, sigma, rc)
+    coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=3 * cfg["restart"], max_outer=3)
+    lo = np.asarray(g.origin, dtype=np.float64)
+    hi = lo + (np.asarray(g.dims) - 1) * np.asarray(g.h)
+    X = w.band_samples(cloud.points, rc, n_samples, seed=3)
+    Xh = w.band_samples(cloud.points, rc, 100_000, seed=13)
+    Xd = torch.as_tensor(X, device="cuda")
+    Xhd = torch.as_tensor(Xh, device="cuda")
+    f = ctx.eval_points(coef, Xd, prec=rbf.RBF_FP32)
+    fh = ctx.eval_points(coef, Xhd, prec=rbf.RBF_FP32)
+    tau = float(torch.sqrt(torch.mean(f * f)))
+    centre = 0.5 * (lo + hi)
+    scale = 2.0 / float((hi - lo).max())
+    ctx.net_set(w.net_init(8), centre, scale, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = ctx.net_train(Xd, f, 16384, epochs, 3e-3)
+    torch.cuda.synchronize()
+    train_ms = 1e3 * (time.perf_counter() - t0)
+    yh = ctx.net_forward(Xhd).double()
+    e_val = float(torch.max(torch.abs(yh - fh / tau)))
+    total = g.size
+    plain = torch.empty(total, dtype=torch.float32, device="cuda")
+    culled = torch.empty_like(plain)
+    ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32, out=plain)
+    ctx.eval_grid_culled(coef, g.origin, g.h, g.dims, e_val, out=culled)
+    times = {}
+    for name, fn in (("plain", lambda: ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=rbf.RBF_FP32, out=plain)),
+                     ("culled", lambda: ctx.eval_grid_culled(coef, g.origin, g.h, g.dims, e_val, out=culled))):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            r = fn()
+        torch.cuda.synchronize()
+        times[name] = 1e3 * (time.perf_counter() - t) / 3
+    st = r[1]
+    fmax = float(torch.max(torch.abs(plain)))
+    tau_s = 1e-6 + 8 * 2.0 ** -24 * fmax
+    signed = torch.abs(plain) > tau_s
+    wrong = signed & (torch.sign(plain) != torch.sign(culled))
+    ctx.close()
+    return {"weights_resid": info.rel_resid, "samples": n_samples, "epochs": epochs, "batch": 16384, "lr": 3e-3,
+            "train_ms": train_ms, "final_loss": loss, "tau": tau, "e_val": e_val,
+            "support_bricks": st.support_bricks, "kept_bricks": st.kept_bricks,
+            "kept_fraction": st.kept_bricks / max(st.support_bricks, 1),
+            "grid_ms_plain": times["plain"], "grid_ms_culled": times["culled"],
+            "signed_nodes": int(signed.sum()), "sign_errors": int(wrong.sum()),
+            "sign_error_rate": float(wrong.sum()) / max(int(signed.sum()), 1)}
 
 
 def solve_comparison(rbf, pts, nrm, cfg, g, iters):

@@ -86,9 +86,12 @@ __device__ __forceinline__ bool sample_pos(const PosSrc& p, int64_t s, double* x
   return i < gd.n[0] && j < gd.n[1] && k < gd.n[2];
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU with the hardware exponential and reciprocal (about one ulp each:
+// far below the bf16 rounding the activations then take).
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + __expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -109,75 +112,90 @@ __device__ __forceinline__ void mma_rows16(const __bf16* A, int lda, const __bf1
   }
 }
 
-// Forward over 64 samples per workgroup: y (and, when Z is given, the
-// pre-activations Z[layer][sample][feature]).
-__global__ __launch_bounds__(kNetThreads) void k_net_forward(NetView nv, PosSrc ps, int64_t B, float* __restrict__ y,
-                                                             float* __restrict__ Z, int64_t zld) {
-  __shared__ __align__(16) __bf16 H[kTile * kLdh];
-  __shared__ float U[kTile][3];
-  __shared__ int valid_s[kTile];
+// Forward: a persistent launch, one workgroup of eight waves per compute
+// unit; the three bf16 weight matrices are copied into its LDS once (rows
+// padded like the activations) and the workgroup walks over tiles of 128
+// samples, a wave taking 16 of them through every layer.  y, and with SAVE
+// the pre-activations Z[layer][sample][feature].
+constexpr int kFwdWaves = 8;
+constexpr int kFwdTile = 16 * kFwdWaves;
+template <bool SAVE>
+__global__ __launch_bounds__(64 * kFwdWaves) void k_net_forward(NetView nv, PosSrc ps, int64_t B, float* __restrict__ y,
+                                                                float* __restrict__ Z, int64_t zld) {
+  __shared__ __align__(16) __bf16 Wl[3 * kW * kLdh];
+  __shared__ __align__(16) __bf16 H[kFwdTile * kLdh];
+  __shared__ float U[kFwdTile][3];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t s0 = (int64_t)blockIdx.x * kTile;
-  if (tid < kTile) {
-    const int64_t s = s0 + tid;
-    double x[3] = {0.0, 0.0, 0.0};
-    const bool ok = s < B && sample_pos(ps, s, x);
-    U[tid][0] = ok ? (float)((x[0] - nv.cx) * nv.scale) : 0.0f;
-    U[tid][1] = ok ? (float)((x[1] - nv.cy) * nv.scale) : 0.0f;
-    U[tid][2] = ok ? (float)((x[2] - nv.cz) * nv.scale) : 0.0f;
-    valid_s[tid] = s < B ? 1 : 0;
+  for (int e = tid; e < 3 * kW * kW / 8; e += 64 * kFwdWaves) {
+    const int row = e / (kW / 8), c8 = e % (kW / 8);   // row = layer * 128 + out
+    *reinterpret_cast<bf16x8*>(Wl + row * kLdh + 8 * c8) = *reinterpret_cast<const bf16x8*>(nv.Wb + row * kW + 8 * c8);
   }
-  __syncthreads();
-  {
-    const int j = tid & (kW - 1);
-    const float w0 = nv.P[kOffW1 + 3 * j], w1 = nv.P[kOffW1 + 3 * j + 1], w2 = nv.P[kOffW1 + 3 * j + 2];
-    const float bj = nv.P[kOffB1 + j];
-    for (int q = 0; q < kTile / 2; ++q) {
-      const int i = (tid >> 7) + 2 * q;
-      const float z = fmaf(w2, U[i][2], fmaf(w1, U[i][1], fmaf(w0, U[i][0], bj)));
-      if (Z && valid_s[i]) Z[(s0 + i) * kW + j] = z;
-      H[i * kLdh + j] = (__bf16)silu(z);
-    }
-  }
-  __syncthreads();
   const int r0 = 16 * wave + 4 * (lane >> 4), c0 = lane & 15;
-  f32x4 acc[8];
-  for (int L = 0; L < 3; ++L) {
+  const int64_t ntiles = ceil_div(B, kFwdTile);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t s0 = tile * kFwdTile;
+    __syncthreads();   // the previous tile is done with U and H (and the weights are in)
+    if (tid < kFwdTile) {
+      const int64_t s = s0 + tid;
+      double x[3] = {0.0, 0.0, 0.0};
+      const bool ok = s < B && sample_pos(ps, s, x);
+      U[tid][0] = ok ? (float)((x[0] - nv.cx) * nv.scale) : 0.0f;
+      U[tid][1] = ok ? (float)((x[1] - nv.cy) * nv.scale) : 0.0f;
+      U[tid][2] = ok ? (float)((x[2] - nv.cz) * nv.scale) : 0.0f;
+    }
+    __syncthreads();
+    {
+      const int j = tid & (kW - 1);
+      const float w0 = nv.P[kOffW1 + 3 * j], w1 = nv.P[kOffW1 + 3 * j + 1], w2 = nv.P[kOffW1 + 3 * j + 2];
+      const float bj = nv.P[kOffB1 + j];
+      constexpr int kRowsPer = 64 * kFwdWaves / kW;
+      for (int q = 0; q < kFwdTile / kRowsPer; ++q) {
+        const int i = (tid >> 7) + kRowsPer * q;
+        const float z = fmaf(w2, U[i][2], fmaf(w1, U[i][1], fmaf(w0, U[i][0], bj)));
+        if (SAVE && s0 + i < B) Z[(s0 + i) * kW + j] = z;
+        H[i * kLdh + j] = (__bf16)silu(z);
+      }
+    }
+    __syncthreads();
+    f32x4 acc[8];
+    for (int L = 0; L < 3; ++L) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float b = nv.P[kOffB[L] + 16 * t + c0];
+        acc[t] = f32x4{b, b, b, b};
+      }
+      mma_rows16(H + 16 * wave * kLdh, kLdh, Wl + L * kW * kLdh, kLdh, kW, acc);
+      // the wave's own rows: nothing else reads them, and its reads are done
+      // (every value stored below depends on all of them)
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int row = r0 + s, col = 16 * t + c0;
+          const float z = acc[t][s];
+          if (SAVE && s0 + row < B) Z[(int64_t)(L + 1) * zld + (s0 + row) * kW + col] = z;
+          const float h = silu(z);
+          if (L < 2) H[row * kLdh + col] = (__bf16)h;
+          acc[t][s] = h;
+        }
+    }
+    // output layer: the 16 lanes of a row hold its 128 features, 8 each
+    float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const float b = nv.P[kOffB[L] + 16 * t + c0];
-      acc[t] = f32x4{b, b, b, b};
+      const float w = nv.P[kOffW5 + 16 * t + c0];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) p[s] = fmaf(w, acc[t][s], p[s]);
     }
-    mma_rows16(H + 16 * wave * kLdh, kLdh, nv.Wb + L * kW * kW, kW, kW, acc);
-    // the wave's own rows: nothing else reads them, and its reads are done
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int row = r0 + s, col = 16 * t + c0;
-        const float z = acc[t][s];
-        if (Z && valid_s[row]) Z[(int64_t)(L + 1) * zld + (s0 + row) * kW + col] = z;
-        const float h = silu(z);
-        if (L < 2) H[row * kLdh + col] = (__bf16)h;
-        acc[t][s] = h;
-      }
-  }
-  // output layer: the 16 lanes of a row hold its 128 features, 8 each
-  float p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const float w = nv.P[kOffW5 + 16 * t + c0];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) p[s] = fmaf(w, acc[t][s], p[s]);
-  }
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-    for (int off = 8; off > 0; off >>= 1) p[s] += __shfl_xor(p[s], off);
-  if (c0 == 0) {
-    const float b5 = nv.P[kOffB5];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      if (valid_s[r0 + s]) y[s0 + r0 + s] = p[s] + b5;
+      for (int off = 8; off > 0; off >>= 1) p[s] += __shfl_xor(p[s], off);
+    if (c0 == 0) {
+      const float b5 = nv.P[kOffB5];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (s0 + r0 + s < B) y[s0 + r0 + s] = p[s] + b5;
+    }
   }
 }
 
@@ -356,10 +374,36 @@ __global__ void k_fill_nan(float* p, int64_t n) {
   if (i < n) p[i] = __builtin_nanf("");
 }
 
+// The keep test in three separable passes.  Signs of the support nodes as
+// bits (1 positive, 2 negative, 4 |y| < e_val; NaN nodes, outside the
+// support, carry none); then, along x, y and z in turn, every node ORs the
+// sign bits of the nodes within `reach` steps, so that after the three
+// passes it holds the signs of its (2 reach + 1)^3 neighbourhood.
+__global__ void k_sign_bits(const float* __restrict__ ygrid, int64_t total, float e_val, uint8_t* __restrict__ bits) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const float v = ygrid[i];
+  bits[i] = (uint8_t)((v > 0.0f ? 1 : 0) | (v < 0.0f ? 2 : 0) | (fabsf(v) < e_val ? 4 : 0));
+}
+
+// dir 0, 1, 2: x, y, z.  Only the two sign bits are spread.
+__global__ void k_spread_signs(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, GridDesc gd, int dir,
+                               int reach) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = gd.n[0] * gd.n[1] * gd.n[2];
+  if (idx >= total) return;
+  const int64_t stride = dir == 0 ? 1 : dir == 1 ? gd.n[0] : gd.n[0] * gd.n[1];
+  const int64_t c = dir == 0 ? idx % gd.n[0] : dir == 1 ? (idx / gd.n[0]) % gd.n[1] : idx / (gd.n[0] * gd.n[1]);
+  const int64_t lo = max<int64_t>(0, c - reach), hi = min<int64_t>(gd.n[dir] - 1, c + reach);
+  uint8_t acc = 0;
+  for (int64_t q = lo; q <= hi; ++q) acc |= in[idx + (q - c) * stride] & 3;
+  out[idx] = acc;
+}
+
 // One thread per node of the support bricks: kept when |y| < e_val or a
-// support node within `reach` steps along every axis has the opposite sign.
-__global__ void k_cull_keep(const float* __restrict__ ygrid, const int64_t* __restrict__ bricks, int64_t nact,
-                            GridDesc gd, float e_val, int reach, int64_t* __restrict__ keep) {
+// support node of the opposite sign lies in its neighbourhood.
+__global__ void k_cull_keep(const uint8_t* __restrict__ own, const uint8_t* __restrict__ hood,
+                            const int64_t* __restrict__ bricks, int64_t nact, GridDesc gd, int64_t* __restrict__ keep) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= nact * kGroup) return;
   const int64_t b = bricks[s / kGroup];
@@ -367,17 +411,9 @@ __global__ void k_cull_keep(const float* __restrict__ ygrid, const int64_t* __re
   const int64_t bx = b % gd.nb[0], by = (b / gd.nb[0]) % gd.nb[1], bz = b / (gd.nb[0] * gd.nb[1]);
   const int64_t i = bx * 4 + (l & 3), j = by * 2 + ((l >> 2) & 1), k = bz * 2 + (l >> 3);
   if (!(i < gd.n[0] && j < gd.n[1] && k < gd.n[2])) return;
-  const float v = ygrid[i + gd.n[0] * (j + gd.n[1] * k)];
-  bool hit = fabsf(v) < e_val;
-  for (int64_t c = max<int64_t>(0, k - reach); !hit && c <= min<int64_t>(gd.n[2] - 1, k + reach); ++c)
-    for (int64_t bb = max<int64_t>(0, j - reach); !hit && bb <= min<int64_t>(gd.n[1] - 1, j + reach); ++bb)
-      for (int64_t a = max<int64_t>(0, i - reach); a <= min<int64_t>(gd.n[0] - 1, i + reach); ++a) {
-        const float w = ygrid[a + gd.n[0] * (bb + gd.n[1] * c)];
-        if ((v > 0.0f && w < 0.0f) || (v < 0.0f && w > 0.0f)) {
-          hit = true;
-          break;
-        }
-      }
+  const int64_t n = i + gd.n[0] * (j + gd.n[1] * k);
+  const uint8_t o = own[n], h = hood[n];
+  const bool hit = (o & 4) || ((o & 1) && (h & 2)) || ((o & 2) && (h & 1));
   if (hit) keep[s / kGroup] = 1;   // benign race: every writer stores 1
 }
 
@@ -406,6 +442,18 @@ __global__ void k_fill_i64_m(int64_t* p, int64_t v, int64_t n) {
 }
 
 unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)std::max<int64_t>(1, ceil_div(n, t)); }
+
+// One forward workgroup per compute unit (its LDS holds the weights), or
+// fewer when there are fewer tiles.
+unsigned fwd_blocks(int64_t B) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    RBF_HIP(hipGetDevice(&dev));
+    RBF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(B, kFwdTile), std::max(cus, 1)));
+}
 
 NetView view(const NetData& d) { return NetView{d.P, d.Wb, d.WbT, d.centre[0], d.centre[1], d.centre[2], d.scale}; }
 
@@ -445,7 +493,7 @@ void net_get(const NetData& d, float* host_params, hipStream_t s) {
 void net_forward(const NetData& d, const double* X, int64_t B, float* y, hipStream_t s) {
   if (B <= 0) return;
   PosSrc ps{X, nullptr, GridDesc{}};
-  hipLaunchKernelGGL(k_net_forward, dim3(blocks_for(B, kTile)), dim3(kNetThreads), 0, s, view(d), ps, B, y,
+  hipLaunchKernelGGL(k_net_forward<false>, dim3(fwd_blocks(B)), dim3(64 * kFwdWaves), 0, s, view(d), ps, B, y,
                      (float*)nullptr, (int64_t)0);
   RBF_HIP(hipGetLastError());
 }
@@ -461,7 +509,7 @@ double net_step(NetData& d, const double* X, const double* f, int64_t B, float* 
   float* loss = talloc<float>(nblk);
   PosSrc ps{X, nullptr, GridDesc{}};
   const NetView nv = view(d);
-  hipLaunchKernelGGL(k_net_forward, dim3((unsigned)nblk), dim3(kNetThreads), 0, s, nv, ps, B, y, Z, B * kW);
+  hipLaunchKernelGGL(k_net_forward<true>, dim3(fwd_blocks(B)), dim3(64 * kFwdWaves), 0, s, nv, ps, B, y, Z, B * kW);
   hipLaunchKernelGGL(k_net_backward, dim3((unsigned)nblk), dim3(kNetThreads), 0, s, nv, ps, B, Z, B * kW, y, f,
                      1.0 / d.tau, (float)(1.0 / (double)B), G, loss);
   AdamArgs a{d.P, d.m, d.v, (float)lr, 0.9f, 0.999f, 1e-8f, 1.0f, 1.0f};
@@ -503,15 +551,21 @@ void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted
     // the network on every node of the support
     float* ysup = talloc<float>(nsup * kGroup);
     PosSrc ps{nullptr, sup, gd};
-    hipLaunchKernelGGL(k_net_forward, dim3(blocks_for(nsup * kGroup, kTile)), dim3(kNetThreads), 0, s, view(d), ps,
+    hipLaunchKernelGGL(k_net_forward<false>, dim3(fwd_blocks(nsup * kGroup)), dim3(64 * kFwdWaves), 0, s, view(d), ps,
                        nsup * kGroup, ysup, (float*)nullptr, (int64_t)0);
     float* ygrid = talloc<float>(total);
     hipLaunchKernelGGL(k_fill_nan, dim3(blocks_for(total)), dim3(256), 0, s, ygrid, total);
     hipLaunchKernelGGL(k_scatter_nodes, dim3(blocks_for(nsup * kGroup)), dim3(256), 0, s, ysup, sup, nsup, gd, ygrid);
+    uint8_t* own = talloc<uint8_t>(total);
+    uint8_t* t1 = talloc<uint8_t>(total);
+    uint8_t* t2 = talloc<uint8_t>(total);
+    hipLaunchKernelGGL(k_sign_bits, dim3(blocks_for(total)), dim3(256), 0, s, ygrid, total, (float)e_val, own);
+    hipLaunchKernelGGL(k_spread_signs, dim3(blocks_for(total)), dim3(256), 0, s, own, t1, gd, 0, reach);
+    hipLaunchKernelGGL(k_spread_signs, dim3(blocks_for(total)), dim3(256), 0, s, t1, t2, gd, 1, reach);
+    hipLaunchKernelGGL(k_spread_signs, dim3(blocks_for(total)), dim3(256), 0, s, t2, t1, gd, 2, reach);
     int64_t* keep = talloc<int64_t>(nsup);
     hipLaunchKernelGGL(k_fill_i64_m, dim3(blocks_for(nsup)), dim3(256), 0, s, keep, (int64_t)0, nsup);
-    hipLaunchKernelGGL(k_cull_keep, dim3(blocks_for(nsup * kGroup)), dim3(256), 0, s, ygrid, sup, nsup, gd,
-                       (float)e_val, reach, keep);
+    hipLaunchKernelGGL(k_cull_keep, dim3(blocks_for(nsup * kGroup)), dim3(256), 0, s, own, t1, sup, nsup, gd, keep);
     hipLaunchKernelGGL(k_cull_fill, dim3(blocks_for(nsup * kGroup)), dim3(256), 0, s, ysup, sup, keep, nsup, gd,
                        (float)d.tau, out);
     RBF_HIP(hipGetLastError());
@@ -534,7 +588,9 @@ void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted
     st->useful_pairs = ts.useful;
     st->examined_pairs = ts.list_entries * kGroup;
     free_targets(ts);
-    for (void* p : {(void*)ysup, (void*)ygrid, (void*)keep, (void*)pos, (void*)kept}) temp_free(p);
+    for (void* p : {(void*)ysup, (void*)ygrid, (void*)own, (void*)t1, (void*)t2, (void*)keep, (void*)pos,
+                    (void*)kept})
+      temp_free(p);
   }
   temp_free(sup);
 }

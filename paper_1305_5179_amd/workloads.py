@@ -252,6 +252,17 @@ def net_unflatten(flat: np.ndarray, width: int = 128, layers: int = 4):
     return out
 
 
+def band_samples(points: np.ndarray, radius: float, n: int, seed: int = 3) -> np.ndarray:
+    """n positions in the support band: a random cloud point plus a uniform
+    offset in the ball of `radius`."""
+    rng = np.random.default_rng(seed)
+    base = points[rng.integers(0, len(points), n)]
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    r = radius * rng.uniform(size=n) ** (1.0 / 3.0)
+    return base + d * r[:, None]
+
+
 def cull_samples(points: np.ndarray, radius: float, lo, hi, n: int, seed: int = 3) -> np.ndarray:
     """Training positions of the cull network: half of them a random cloud
     point plus a uniform offset in the ball of `radius` (the support of the
