@@ -190,45 +190,54 @@ __global__ __launch_bounds__(kVecThreads) void k_reduce_h2(const double* __restr
 }
 
 // Column j of the Hessenberg matrix, its Givens rotations and the residual
-// estimate |g_{j+1}|.
+// estimate |g_{j+1}|: the column and the rotations are staged in LDS by the
+// whole block, the rotation chain runs on one thread from there.
 __global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __restrict__ partial, int nb, int j,
                                                              GmState* __restrict__ st) {
   if (st->done) return;
-  const double beta = sqrt(block_fold(partial, nb, 0));
-  if (threadIdx.x != 0) return;
-  const int ld = kMaxRestart + 1;
-  double* Hc = st->H + (int64_t)j * ld;
-  for (int i = 0; i <= j; ++i) Hc[i] = st->h1[i] + st->h2[i];
-  Hc[j + 1] = beta;
-  for (int i = 0; i < j; ++i) {
-    const double a = Hc[i], b = Hc[i + 1];
-    Hc[i] = st->cs[i] * a + st->sn[i] * b;
-    Hc[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+  __shared__ double hc[kMaxRestart + 2], cs[kMaxRestart], sn[kMaxRestart];
+  const int t = threadIdx.x;
+  for (int i = t; i <= j; i += kVecThreads) hc[i] = st->h1[i] + st->h2[i];
+  for (int i = t; i < j; i += kVecThreads) {
+    cs[i] = st->cs[i];
+    sn[i] = st->sn[i];
   }
-  const double a = Hc[j], b = Hc[j + 1];
-  const double rho = hypot(a, b);
-  double c = 1.0, s = 0.0;
-  if (rho != 0.0) {
-    c = a / rho;
-    s = b / rho;
+  const double beta = sqrt(block_fold(partial, nb, 0));   // (synchronises the block)
+  if (t == 0) {
+    hc[j + 1] = beta;
+    for (int i = 0; i < j; ++i) {
+      const double a = hc[i], b = hc[i + 1];
+      hc[i] = cs[i] * a + sn[i] * b;
+      hc[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = hc[j], b = hc[j + 1];
+    const double rho = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (rho != 0.0) {
+      c = a / rho;
+      s = b / rho;
+    }
+    st->cs[j] = c;
+    st->sn[j] = s;
+    hc[j] = rho;
+    hc[j + 1] = 0.0;
+    const double gj = st->g[j];
+    st->g[j + 1] = -s * gj;
+    st->g[j] = c * gj;
+    st->k = j + 1;
+    st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+    const bool finite = isfinite(beta) && isfinite(rho) && isfinite(st->g[j + 1]);
+    if (!finite) {
+      st->breakdown = 1;
+      st->done = 1;
+      st->k = j;  // drop the column that went bad
+    } else if (fabs(st->g[j + 1]) <= st->tol_abs || beta == 0.0 || rho == 0.0) {
+      st->done = 1;
+    }
   }
-  st->cs[j] = c;
-  st->sn[j] = s;
-  Hc[j] = rho;
-  Hc[j + 1] = 0.0;
-  const double gj = st->g[j];
-  st->g[j + 1] = -s * gj;
-  st->g[j] = c * gj;
-  st->k = j + 1;
-  st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
-  const bool finite = isfinite(beta) && isfinite(rho) && isfinite(st->g[j + 1]);
-  if (!finite) {
-    st->breakdown = 1;
-    st->done = 1;
-    st->k = j;  // drop the column that went bad
-  } else if (fabs(st->g[j + 1]) <= st->tol_abs || beta == 0.0 || rho == 0.0) {
-    st->done = 1;
-  }
+  __syncthreads();
+  double* Hc = st->H + (int64_t)j * (kMaxRestart + 1);
+  for (int i = t; i <= j + 1; i += kVecThreads) Hc[i] = hc[i];
 }
 
 // v_{j+1} = w / |w|

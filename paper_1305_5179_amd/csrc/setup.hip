@@ -531,12 +531,17 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
   const double r_out2 = r_out * r_out;
 
-  // candidate cube of coarse cells around the anchor
+  // candidate cube of coarse cells around the anchor: the cells of every
+  // coordinate within r_out of it along each axis.  The relative pad keeps
+  // the float64 rounding of the cell index (here and in the sources' own
+  // cell keys, both floor((x - origin) / fine) up to a power of two) from
+  // dropping the cell of a source at the boundary.
   int cl[3], cn[3];
   const double ac[3] = {ax, ay, az};
   for (int d = 0; d < 3; ++d) {
-    const double a = floor((ac[d] - r_out - lat.origin[d]) / lat.coarse) - 1.0;
-    const double b = floor((ac[d] + r_out - lat.origin[d]) / lat.coarse) + 1.0;
+    const double pad = r_out * (1.0 + 1e-9) + 1e-12 * (fabs(ac[d]) + fabs(lat.origin[d]) + r_out);
+    const double a = floor((ac[d] - pad - lat.origin[d]) / lat.coarse);
+    const double b = floor((ac[d] + pad - lat.origin[d]) / lat.coarse);
     const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
     const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
     cl[d] = ia;
