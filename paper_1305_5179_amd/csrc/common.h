@@ -136,6 +136,7 @@ struct TargetSet {
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
   bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
   int kind = 0;             // 0: the centres (operator), 1: evaluation targets
+  bool lattice = false;     // groups are bricks of grid nodes (4 x 2 x 2, node order of k_brick_targets)
   std::vector<void*> owned; // device allocations to free with the set
 };
 

@@ -411,8 +411,12 @@ __device__ __forceinline__ void put_outer(const ListOut& o, int64_t e, uint32_t 
 }
 
 // Exact test of `cnt` (<= 64) queued shell sources, one per lane, against
-// the group's 16 targets (uniform loads: scalar registers).
-template <bool WRITE>
+// the group's 16 targets (uniform loads: scalar registers).  For a brick of
+// grid nodes (lattice), node l = (l & 3, (l >> 2) & 1, l >> 3) shares its x
+// with nodes l & 3, its y with node 4 ((l >> 2) & 1) and its z with node
+// 8 (l >> 3): the eight squared axis differences give all sixteen
+// r^2 = (dx dx + dy dy) + dz dz, bit for bit the same sums.
+template <bool WRITE, bool LATTICE>
 __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const double4* __restrict__ tg,
                                               const double4* __restrict__ xs, uint32_t vmask, double rc2,
                                               const ListOut& o, ListCounts& n) {
@@ -422,12 +426,33 @@ __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const 
   uint32_t bits = 0;
   if (valid) {
     const double4 s = xs[k];
+    if constexpr (LATTICE) {
+      double dx2[4], dy2[2], dz2[2];
 #pragma unroll
-    for (int l = 0; l < kGroup; ++l) {
-      const double4 t = tg[l];
-      const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
-      const double r2 = (dx * dx + dy * dy) + dz * dz;
-      bits |= (t.w != 0.0 && r2 <= rc2) ? (1u << l) : 0u;
+      for (int i = 0; i < 4; ++i) {
+        const double dx = tg[i].x - s.x;
+        dx2[i] = dx * dx;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const double dy = tg[4 * j].y - s.y, dz = tg[8 * j].z - s.z;
+        dy2[j] = dy * dy;
+        dz2[j] = dz * dz;
+      }
+#pragma unroll
+      for (int l = 0; l < kGroup; ++l) {
+        const double r2 = (dx2[l & 3] + dy2[(l >> 2) & 1]) + dz2[l >> 3];
+        bits |= r2 <= rc2 ? (1u << l) : 0u;
+      }
+      bits &= vmask;
+    } else {
+#pragma unroll
+      for (int l = 0; l < kGroup; ++l) {
+        const double4 t = tg[l];
+        const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        bits |= (t.w != 0.0 && r2 <= rc2) ? (1u << l) : 0u;
+      }
     }
   }
   const bool is_in = valid && bits == vmask;
@@ -456,7 +481,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // region at soff[g] of size bound[g]; counts, useful pairs, the valid-target
 // mask and the group record (offset set later by k_list_compact).
 constexpr int kBound = 0, kStage = 1;
-template <int MODE>
+template <int MODE, bool LATTICE>
 __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
                                                     const double4* __restrict__ xs,
                                                     const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
@@ -627,7 +652,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
       qn += __popcll(ms);
       if (qn >= kWave) {
         wave_sync_lds();
-        process_shell<WRITE>(q, kWave, tg, xs, vmask, rc2, o, n);
+        process_shell<WRITE, LATTICE>(q, kWave, tg, xs, vmask, rc2, o, n);
         const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
         wave_sync_lds();
         if (lane + kWave < qn) q[lane] = rest;
@@ -641,7 +666,7 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     return;
   }
   wave_sync_lds();
-  if (qn > 0) process_shell<WRITE>(q, qn, tg, xs, vmask, rc2, o, n);
+  if (qn > 0) process_shell<WRITE, LATTICE>(q, qn, tg, xs, vmask, rc2, o, n);
   if (lane == 0) {
     if (n.n_in + n.n_out > o.bound) {
       atomicOr(overflow, 1);
@@ -1139,7 +1164,7 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     int64_t* off = talloc<int64_t>(G);
     const unsigned nblk = (unsigned)ceil_div(G, 4);
     // 1. candidate counts (cell phase only): staging regions
-    hipLaunchKernelGGL(k_lists<kBound>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+    hipLaunchKernelGGL((k_lists<kBound, false>), dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
                        c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, (const int64_t*)nullptr,
                        (int32_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr, (uint32_t*)nullptr,
                        (uint32_t*)nullptr, (uint16_t*)nullptr, (int*)nullptr);
@@ -1155,9 +1180,14 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     int* overflow = talloc<int>(1);
     RBF_HIP(hipMemsetAsync(overflow, 0, sizeof(int), s));
     // 2. the classification, once, into the staging regions
-    hipLaunchKernelGGL(k_lists<kStage>, dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, soff, cin, cout, use, vm,
-                       slist, smask, overflow);
+    if (ts.lattice)
+      hipLaunchKernelGGL((k_lists<kStage, true>), dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+                         c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, soff, cin, cout, use, vm,
+                         slist, smask, overflow);
+    else
+      hipLaunchKernelGGL((k_lists<kStage, false>), dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+                         c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, soff, cin, cout, use, vm,
+                         slist, smask, overflow);
     RBF_HIP(hipGetLastError());
     // 3. final offsets and the compact layout
     hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
@@ -1252,6 +1282,7 @@ void brick_targets(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t 
   const GridDesc gd = grid_desc(g);
   ts.temp = true;
   ts.kind = 1;
+  ts.lattice = true;
   ts.dense = !std::isfinite(c.cutoff);
   ts.n_groups = nact;
   ts.pts = set_alloc<double4>(ts, nact * kGroup);
