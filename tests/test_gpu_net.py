@@ -226,3 +226,48 @@ def test_culled_grid(torch, R):
         _say(f"[net] oracle: must keep {must.sum()}, may keep {(hi & sup).sum()} of {sup.sum()} support bricks")
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (5, 3, 3), (9, 2, 7)])
+def test_culled_grid_small_shapes_and_no_cutoff(torch, R, dims):
+    """No cutoff (every brick in the support) and ragged or single-node
+    grids: every node is the exact sum or tau * y, bit for bit."""
+    c = w.sphere(200, 4)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), 0.05, 0.2, math.inf)
+    try:
+        X, _ = o.extended_centres(c.points, c.normals, 0.05)
+        origin, h = (-1.1, -1.0, -0.9), (2.2 / max(dims[0] - 1, 1), 2.0 / max(dims[1] - 1, 1), 1.8 / max(dims[2] - 1, 1))
+        flat = w.net_init(12)
+        ctx.net_set(flat, (0.0, 0.0, 0.0), 0.8, TAU)
+        cw = dev(torch, np.random.default_rng(6).uniform(-1, 1, len(X)))
+        _say(f"[net] culled grid {dims} without cutoff")
+        plain = host(ctx.eval_grid(cw, origin, h, dims, prec=R.RBF_FP32))
+        out, st = ctx.eval_grid_culled(cw, origin, h, dims, 0.05)
+        out = host(out)
+        nx, ny, nz = dims
+        i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+        nodes = np.stack([origin[0] + i * h[0], origin[1] + j * h[1], origin[2] + k * h[2]], -1)
+        nodes = nodes.transpose(2, 1, 0, 3).reshape(-1, 3)
+        y = host(ctx.net_forward(dev(torch, nodes)))
+        torch.cuda.synchronize()
+        culled_val = (np.float32(TAU) * y.astype(np.float32)).astype(np.float64)
+        assert np.all((out == plain) | (out == culled_val))
+        nb = (-(-nx // 4)) * (-(-ny // 2)) * (-(-nz // 2))
+        assert st.support_bricks == nb and 0 <= st.kept_bricks <= nb
+    finally:
+        ctx.close()
+
+
+def test_training_edge_cases(torch, R, net_ctx):
+    flat = w.net_init(13)
+    net_ctx.net_set(flat, CENTRE, SCALE, TAU)
+    X = np.random.default_rng(7).uniform(-1, 1, size=(100, 3))
+    f = np.random.default_rng(8).uniform(-0.01, 0.01, size=100)
+    assert net_ctx.net_train(dev(torch, X), dev(torch, f), 64, 0, 1e-3) == 0.0      # no epochs: no change
+    assert np.array_equal(net_ctx.net_get(), flat)
+    loss = net_ctx.net_train(dev(torch, X), dev(torch, f), 4096, 3, 1e-3)        # batch above n
+    assert math.isfinite(loss)
+    with pytest.raises(R.RbfError):
+        net_ctx.net_train(dev(torch, X), dev(torch, f), 0, 1, 1e-3)
+    with pytest.raises(R.RbfError):
+        net_ctx.net_set(np.full(R.RBF_NET_PARAMS, np.nan, dtype=np.float32), CENTRE, SCALE, TAU)

@@ -293,3 +293,24 @@ def test_one_point(torch, R):
         assert np.allclose(z, want, rtol=1e-6, atol=0)
     finally:
         ctx.close()
+
+
+def test_restricted_solve_and_setup_twice(torch, R):
+    """The restricted form preconditions the solve too, and a second setup
+    replaces the first."""
+    c = w.sphere(300, 3)
+    eps, sigma = 0.08, 0.06
+    X, b = o.extended_centres(c.points, c.normals, eps)
+    c_lu = np.linalg.solve(o.interpolation_matrix(X, sigma), b)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, math.inf)
+    try:
+        ctx.schwarz_setup(max_block=60, overlap_pct=20)
+        info = ctx.schwarz_setup(max_block=90, overlap_pct=30, restricted=1)
+        assert info.max_members <= 90
+        _say("[schwarz] restricted solve sphere300")
+        cw, res = ctx.solve(tol=1e-12, precond=R.RBF_PRECOND_SCHWARZ, max_iters=3000)
+        torch.cuda.synchronize()
+        assert res.status == R.RBF_OK, res
+        assert np.linalg.norm(host(cw) - c_lu) <= 1e-5 * np.linalg.norm(c_lu)
+    finally:
+        ctx.close()
