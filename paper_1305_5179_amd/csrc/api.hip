@@ -95,7 +95,8 @@ void free_ctx(Ctx* c) {
   free_net(c->net);
   c->net = nullptr;
   for (void* p : {(void*)c->perm, (void*)c->keys, (void*)c->xs, (void*)c->xk, (void*)c->xpaper, (void*)c->cell_start,
-                  (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->vin, (void*)c->vout,
+                  (void*)c->cell_count, (void*)c->cell_map, (void*)c->cell_xyz, (void*)c->cell_sat, (void*)c->vin,
+                  (void*)c->vout,
                   (void*)c->V, (void*)c->w, (void*)c->r, (void*)c->csol, (void*)c->bsort, (void*)c->partial,
                   (void*)c->state})
     dfree(p);
@@ -261,8 +262,10 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     c->xk = dalloc<double4>(c->m + 1);
     gather_sorted(c->xpaper, c->perm, c->m, c->sqrt_k, c->xs, c->xk, s);
     // 5. coarse cells
-    if (std::isfinite(cutoff))
+    if (std::isfinite(cutoff)) {
       c->n_cells = build_cells(c->keys, c->xs, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
+      c->cell_sat = build_cell_sat(*c, s);
+    }
     // 6. the centres as targets, with their source lists
     TargetSet& ts = c->centres;
     ts.dense = !std::isfinite(cutoff);

@@ -174,6 +174,7 @@ struct Ctx {
   int32_t* cell_map = nullptr;  // product of cdims entries, -1 = empty
   int32_t* cell_xyz = nullptr;  // coarse coordinates of every cell, x | y << 10 | z << 20
   int64_t n_cells = 0;
+  int64_t* cell_sat = nullptr;  // summed source counts of the coarse cells (null when too many cells)
   TargetSet centres;            // the centres as targets of the operator
   SchwarzData* schwarz = nullptr;
   NetData* net = nullptr;
@@ -275,6 +276,8 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
 int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
                     int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
+constexpr int64_t kCellSatMax = int64_t(1) << 26;   // entries of the summed cell counts (512 MB)
+int64_t* build_cell_sat(const Ctx& c, hipStream_t s);
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);
 void centre_targets(const Ctx& c, TargetSet& ts, hipStream_t s);
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);

@@ -475,6 +475,109 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A group's valid targets (mask), the centre of their bounding box (the
+// anchor) and their largest distance from it.
+struct Frame {
+  int nvalid;
+  uint32_t vmask;
+  double ax, ay, az, rad;
+};
+__device__ __forceinline__ Frame group_frame(const double4* __restrict__ tg) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  Frame f{0, 0u, 0.0, 0.0, 0.0, 0.0};
+  for (int l = 0; l < kGroup; ++l) {
+    const double4 t = tg[l];
+    if (t.w != 0.0) {
+      ++f.nvalid;
+      f.vmask |= 1u << l;
+      lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
+      lo[1] = fmin(lo[1], t.y); hi[1] = fmax(hi[1], t.y);
+      lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
+    }
+  }
+  if (f.nvalid == 0) return f;
+  f.ax = 0.5 * (lo[0] + hi[0]);
+  f.ay = 0.5 * (lo[1] + hi[1]);
+  f.az = 0.5 * (lo[2] + hi[2]);
+  for (int l = 0; l < kGroup; ++l) {
+    const double4 t = tg[l];
+    if (t.w != 0.0) {
+      const double dx = t.x - f.ax, dy = t.y - f.ay, dz = t.z - f.az;
+      f.rad = fmax(f.rad, sqrt((dx * dx + dy * dy) + dz * dz));
+    }
+  }
+  return f;
+}
+
+// The cube of coarse cells holding every coordinate within r_out of the
+// anchor along each axis.  The relative pad keeps the float64 rounding of
+// the cell index (here and in the sources' own cell keys, both
+// floor((x - origin) / fine) up to a power of two) from dropping the cell of
+// a source at the boundary.
+__device__ __forceinline__ void cell_cube(const double ac[3], double r_out, const Lattice& lat, int cl[3], int cn[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const double pad = r_out * (1.0 + 1e-9) + 1e-12 * (fabs(ac[d]) + fabs(lat.origin[d]) + r_out);
+    const double a = floor((ac[d] - pad - lat.origin[d]) / lat.coarse);
+    const double b = floor((ac[d] + pad - lat.origin[d]) / lat.coarse);
+    const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
+    const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
+    cl[d] = ia;
+    cn[d] = ib - ia + 1;
+  }
+}
+
+// Summed counts of the coarse cells: sat[(z * (ny + 1) + y) * (nx + 1) + x]
+// = the sources in the cells [0, x) x [0, y) x [0, z).
+__global__ void k_sat_counts(const int32_t* __restrict__ cmap, const int32_t* __restrict__ ccount, Lattice lat,
+                             int64_t* __restrict__ sat) {
+  const int64_t nx = lat.cdims[0] + 1, ny = lat.cdims[1] + 1, nz = lat.cdims[2] + 1;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nx * ny * nz) return;
+  const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+  int64_t v = 0;
+  if (x > 0 && y > 0 && z > 0) {
+    const int32_t cid = cmap[(x - 1) + (int64_t)lat.cdims[0] * ((y - 1) + (int64_t)lat.cdims[1] * (z - 1))];
+    v = cid >= 0 ? ccount[cid] : 0;
+  }
+  sat[i] = v;
+}
+// Prefix sums along one axis (0, 1, 2): one thread per line.
+__global__ void k_sat_scan(Lattice lat, int axis, int64_t* __restrict__ sat) {
+  const int64_t n[3] = {lat.cdims[0] + 1, lat.cdims[1] + 1, lat.cdims[2] + 1};
+  const int64_t stride[3] = {1, n[0], n[0] * n[1]};
+  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  const int64_t line = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (line >= n[a1] * n[a2]) return;
+  const int64_t base = (line % n[a1]) * stride[a1] + (line / n[a1]) * stride[a2];
+  int64_t acc = 0;
+  for (int64_t q = 0; q < n[axis]; ++q) {
+    acc += sat[base + q * stride[axis]];
+    sat[base + q * stride[axis]] = acc;
+  }
+}
+
+// Candidate bound of every group from the summed counts: the sources of its
+// whole cell cube (one thread per group).
+__global__ void k_list_bound_sat(const double4* __restrict__ tpts, int64_t G, const int64_t* __restrict__ sat, Lattice lat,
+                                 double rc, int64_t* __restrict__ bound) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const Frame f = group_frame(tpts + g * kGroup);
+  if (f.nvalid == 0) {
+    bound[g] = 0;
+    return;
+  }
+  const double r_out = rc * (1.0 + 1e-12) + f.rad;
+  const double ac[3] = {f.ax, f.ay, f.az};
+  int cl[3], cn[3];
+  cell_cube(ac, r_out, lat, cl, cn);
+  const int64_t nx = lat.cdims[0] + 1, ny = lat.cdims[1] + 1;
+  auto S = [&](int64_t x, int64_t y, int64_t z) { return sat[(z * ny + y) * nx + x]; };
+  const int64_t x0 = cl[0], y0 = cl[1], z0 = cl[2], x1 = cl[0] + cn[0], y1 = cl[1] + cn[1], z1 = cl[2] + cn[2];
+  bound[g] = S(x1, y1, z1) - S(x0, y1, z1) - S(x1, y0, z1) - S(x1, y1, z0) + S(x0, y0, z1) + S(x0, y1, z0) +
+             S(x1, y0, z0) - S(x0, y0, z0);
+}
+
 // MODE kBound: the cell phase only; bound[g] = the number of candidate
 // sources (those of the cells within r_out of the anchor), an upper bound of
 // the group's list.  MODE kStage: the classification, into the staging
@@ -504,20 +607,10 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   int32_t* cst = cst_s[wave];
   uint8_t* cwhole = cwhole_s[wave];
   const double4* tg = tpts + g * kGroup;
-  // the group's box, anchor and radius (uniform)
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  int nvalid = 0;
-  uint32_t vmask = 0;
-  for (int l = 0; l < kGroup; ++l) {
-    const double4 t = tg[l];
-    if (t.w != 0.0) {
-      ++nvalid;
-      vmask |= 1u << l;
-      lo[0] = fmin(lo[0], t.x); hi[0] = fmax(hi[0], t.x);
-      lo[1] = fmin(lo[1], t.y); hi[1] = fmax(hi[1], t.y);
-      lo[2] = fmin(lo[2], t.z); hi[2] = fmax(hi[2], t.z);
-    }
-  }
+  // the group's valid targets, anchor and radius (uniform)
+  const Frame fr = group_frame(tg);
+  const int nvalid = fr.nvalid;
+  const uint32_t vmask = fr.vmask;
   ListOut o{slist, smask, 0, 0, 0};
   if (WRITE) {
     o.base = soff[g];
@@ -542,36 +635,16 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
     }
     return;
   }
-  const double ax = 0.5 * (lo[0] + hi[0]), ay = 0.5 * (lo[1] + hi[1]), az = 0.5 * (lo[2] + hi[2]);
-  double rad = 0.0;
-  for (int l = 0; l < kGroup; ++l) {
-    const double4 t = tg[l];
-    if (t.w != 0.0) {
-      const double dx = t.x - ax, dy = t.y - ay, dz = t.z - az;
-      rad = fmax(rad, sqrt((dx * dx + dy * dy) + dz * dz));
-    }
-  }
+  const double ax = fr.ax, ay = fr.ay, az = fr.az, rad = fr.rad;
   const double r_in = rc * (1.0 - 1e-12) - rad;   // |s - a| <= r_in: inside for every target
   const double r_out = rc * (1.0 + 1e-12) + rad;  // |s - a| >  r_out: inside for none
   const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
   const double r_out2 = r_out * r_out;
 
-  // candidate cube of coarse cells around the anchor: the cells of every
-  // coordinate within r_out of it along each axis.  The relative pad keeps
-  // the float64 rounding of the cell index (here and in the sources' own
-  // cell keys, both floor((x - origin) / fine) up to a power of two) from
-  // dropping the cell of a source at the boundary.
+  // candidate cube of coarse cells around the anchor
   int cl[3], cn[3];
   const double ac[3] = {ax, ay, az};
-  for (int d = 0; d < 3; ++d) {
-    const double pad = r_out * (1.0 + 1e-9) + 1e-12 * (fabs(ac[d]) + fabs(lat.origin[d]) + r_out);
-    const double a = floor((ac[d] - pad - lat.origin[d]) / lat.coarse);
-    const double b = floor((ac[d] + pad - lat.origin[d]) / lat.coarse);
-    const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
-    const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
-    cl[d] = ia;
-    cn[d] = ib - ia + 1;
-  }
+  cell_cube(ac, r_out, lat, cl, cn);
   const int ncube = cn[0] * cn[1] * cn[2];
   ListCounts n{0, 0, 0};
   int qn = 0;
@@ -1163,11 +1236,17 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     int64_t* len = talloc<int64_t>(G);
     int64_t* off = talloc<int64_t>(G);
     const unsigned nblk = (unsigned)ceil_div(G, 4);
-    // 1. candidate counts (cell phase only): staging regions
-    hipLaunchKernelGGL((k_lists<kBound, false>), dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
-                       c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd, (const int64_t*)nullptr,
-                       (int32_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr, (uint32_t*)nullptr,
-                       (uint32_t*)nullptr, (uint16_t*)nullptr, (int*)nullptr);
+    // 1. candidate bounds: staging regions (the sources of each group's
+    // cell cube from the summed cell counts; without them, the cells of the
+    // cube within reach, one wave per group)
+    if (c.cell_sat)
+      hipLaunchKernelGGL(k_list_bound_sat, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.pts, G, c.cell_sat, c.lat,
+                         c.cutoff, bnd);
+    else
+      hipLaunchKernelGGL((k_lists<kBound, false>), dim3(nblk), dim3(kThreads), 0, s, ts.pts, G, ts.groups, c.xs,
+                         c.cell_start, c.cell_count, c.cell_map, c.lat, c.cutoff, c.rc2, bnd,
+                         (const int64_t*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr,
+                         (uint32_t*)nullptr, (uint32_t*)nullptr, (uint16_t*)nullptr, (int*)nullptr);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(bnd, soff, G, s);
     int64_t last_soff = 0, last_bnd = 0;
@@ -1237,6 +1316,19 @@ void free_targets(TargetSet& ts) {
   ts.groups = nullptr;
   ts.list = nullptr;
   ts.mask = nullptr;
+}
+
+int64_t* build_cell_sat(const Ctx& c, hipStream_t s) {
+  const int64_t n = (int64_t)(c.lat.cdims[0] + 1) * (c.lat.cdims[1] + 1) * (c.lat.cdims[2] + 1);
+  if (n > kCellSatMax) return nullptr;
+  int64_t* sat = dalloc<int64_t>(n);
+  hipLaunchKernelGGL(k_sat_counts, dim3(grid_for(n)), dim3(kThreads), 0, s, c.cell_map, c.cell_count, c.lat, sat);
+  for (int axis = 0; axis < 3; ++axis) {
+    const int64_t lines = n / (c.lat.cdims[axis] + 1);
+    hipLaunchKernelGGL(k_sat_scan, dim3(grid_for(lines)), dim3(kThreads), 0, s, c.lat, axis, sat);
+  }
+  RBF_HIP(hipGetLastError());
+  return sat;
 }
 
 GridDesc grid_desc(const rbf_grid& g) {
