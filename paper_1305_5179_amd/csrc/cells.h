@@ -1,0 +1,143 @@
+// Device helpers shared by the list builder (setup.hip) and the kernels that
+// walk the coarse cells or the target groups directly (pairsum.hip,
+// gridsum.hip).
+#pragma once
+
+#include "common.h"
+
+namespace rbf {
+
+// Lanes below this one whose bit is set in `mask`.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Orders the LDS accesses of one wave around this point (the wave's lanes
+// exchange data through LDS; no other wave takes part).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Block b of a launch runs on XCD b % 8; give every XCD a contiguous range of
+// blocks so that neighbouring groups (which share sources) share an L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8, x = b % 8;
+  const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return first + b / 8;
+}
+
+// The cube of coarse cells holding every coordinate within r_out of the
+// anchor along each axis.  The relative pad keeps the float64 rounding of
+// the cell index (here and in the sources' own cell keys, both
+// floor((x - origin) / fine) up to a power of two) from dropping the cell of
+// a source at the boundary.
+__device__ __forceinline__ void cell_cube(const double ac[3], double r_out, const Lattice& lat, int cl[3], int cn[3]) {
+  for (int d = 0; d < 3; ++d) {
+    const double pad = r_out * (1.0 + 1e-9) + 1e-12 * (fabs(ac[d]) + fabs(lat.origin[d]) + r_out);
+    const double a = floor((ac[d] - pad - lat.origin[d]) / lat.coarse);
+    const double b = floor((ac[d] + pad - lat.origin[d]) / lat.coarse);
+    const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
+    const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
+    cl[d] = ia;
+    cn[d] = ib - ia + 1;
+  }
+}
+
+// The candidate sources of a group with anchor `ac`: every source of the
+// occupied coarse cells of the cube [cl, cl + cn) whose box comes within
+// r_out of the anchor.  The cells are examined one per lane, 64 at a time;
+// the sources of the cells that remain are then taken 64 at a time across
+// cell boundaries (a lane finds its cell by a binary search of the count
+// prefix in LDS: cpre, cst and cwhole hold 64 entries of the calling wave).
+// visit(valid, k, is_in, is_shell) runs once per round of 64 candidates, in
+// the same order on every call: k is this lane's sorted source (when valid),
+// is_in marks a source within r_in of the anchor (a whole cell within r_in
+// counts without loading its sources), is_shell one within r_out but not
+// r_in.  r_in2 < 0 marks no inner sources.  Returns the number of
+// candidates; CELLS_ONLY stops after the cell phase (the count alone).
+template <bool CELLS_ONLY, class Visit>
+__device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_in2, double r_out2, const int cl[3],
+                                                   const int cn[3], const double4* __restrict__ xs,
+                                                   const int32_t* __restrict__ cstart,
+                                                   const int32_t* __restrict__ ccount,
+                                                   const int32_t* __restrict__ cmap, const Lattice& lat,
+                                                   int32_t* cpre, int32_t* cst, uint8_t* cwhole, Visit&& visit) {
+  const int lane = threadIdx.x & 63;
+  const int ncube = cn[0] * cn[1] * cn[2];
+  int64_t cand = 0;
+  for (int c0 = 0; c0 < ncube; c0 += kWave) {
+    // one cell of the cube per lane: occupied? how far from the anchor?
+    const int ci = c0 + lane;
+    int32_t cid = -1;
+    bool whole = false;
+    if (ci < ncube) {
+      const int cx = cl[0] + ci % cn[0], cy = cl[1] + (ci / cn[0]) % cn[1], cz = cl[2] + ci / (cn[0] * cn[1]);
+      cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
+      if (cid >= 0) {
+        const int cc[3] = {cx, cy, cz};
+        double dmin2 = 0.0, dmax2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double b0 = lat.origin[d] + cc[d] * lat.coarse, b1 = b0 + lat.coarse;
+          const double gap = fmax(0.0, fmax(b0 - ac[d], ac[d] - b1));
+          const double far = fmax(fabs(ac[d] - b0), fabs(ac[d] - b1));
+          dmin2 += gap * gap;
+          dmax2 += far * far;
+        }
+        if (dmin2 > r_out2 * (1.0 + 1e-9)) cid = -1;
+        whole = dmax2 * (1.0 + 1e-9) <= r_in2;
+      }
+    }
+    // the occupied cells of this block, compacted in lane order, with the
+    // exclusive prefix of their source counts
+    const int32_t ct = cid >= 0 ? ccount[cid] : 0;
+    const int32_t st = cid >= 0 ? cstart[cid] : 0;
+    const bool occ = ct > 0;   // (empty cells would break the search below)
+    const uint64_t sel = ballot(occ);
+    const int nocc = __popcll(sel);
+    int32_t incl = ct;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int32_t y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    const int32_t total = __shfl(incl, kWave - 1);
+    cand += total;
+    if (CELLS_ONLY) continue;
+    wave_sync_lds();
+    if (occ) {
+      const int pos = lanes_below(sel);
+      cpre[pos] = incl - ct;
+      cst[pos] = st;
+      cwhole[pos] = whole ? 1 : 0;
+    }
+    wave_sync_lds();
+    for (int32_t b0 = 0; b0 < total; b0 += kWave) {
+      const int32_t f = b0 + lane;
+      const bool valid = f < total;
+      // the cell of flattened source f: the last j with cpre[j] <= f
+      int j = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (j + step < nocc && cpre[j + step] <= f) j += step;
+      const uint32_t k = (uint32_t)(cst[j] + (f - cpre[j]));
+      bool is_in = false, is_shell = false;
+      if (valid) {
+        if (cwhole[j]) {
+          is_in = true;
+        } else {
+          const double4 s = xs[k];
+          const double dx = s.x - ac[0], dy = s.y - ac[1], dz = s.z - ac[2];
+          const double d2 = (dx * dx + dy * dy) + dz * dz;
+          is_in = d2 <= r_in2;
+          is_shell = !is_in && d2 <= r_out2;
+        }
+      }
+      visit(valid, k, is_in, is_shell);
+    }
+  }
+  return cand;
+}
+
+}  // namespace rbf

@@ -281,6 +281,7 @@ int64_t* build_cell_sat(const Ctx& c, hipStream_t s);
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);
 void centre_targets(const Ctx& c, TargetSet& ts, hipStream_t s);
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+void sum_i64(const int64_t* in, int64_t n, int64_t* out, hipStream_t s);   // *out = sum (device)
 void fill_f64(double* p, double v, int64_t n, hipStream_t s);
 void fill_f32(float* p, float v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -294,12 +295,32 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
 void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
                  const int* skip = nullptr);
 
+// gridsum.hip: float32 grid sums without source lists (bricks `ids`, or
+// every brick when ids is null; out is not cleared).  useful/examined: optional
+// per-brick pair counts.
+bool brick_sum_applies(const Ctx& c, const rbf_grid& g);
+void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
+                   float* out, int64_t* useful, int64_t* examined, hipStream_t s);
+
 // density.hip
 void density_measures(const double* P, int64_t n, const double* samples, int64_t ns, double* q, double* hmax,
                       double* hfill, hipStream_t s);
 
+// Launch timing (rbf_profile_begin / rbf_profile_end): while profiling is
+// on, a ProfScope brackets one launch with events on its stream (construct
+// before the launch, done() after it).  Pair counts known only later (read
+// back from the device) are given by set_pairs before rbf_profile_end.
+struct ProfScope {
+  ProfScope(int prec, int kind, int64_t useful, int64_t examined, hipStream_t s);
+  void done();
+  void set_pairs(int64_t useful, int64_t examined);
+  bool on;
+  hipStream_t s;
+  int rec = -1;
+};
 int profile_begin();
 int profile_end(rbf_profile* out);
+bool profiling();
 
 // schwarz.hip
 int schwarz_overlap_count(int ncore, int pct);

@@ -581,13 +581,27 @@ void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted
     int64_t* kept = talloc<int64_t>(nkeep);
     hipLaunchKernelGGL(k_gather_kept, dim3(blocks_for(nsup)), dim3(256), 0, s, sup, keep, pos, nsup, kept);
     RBF_HIP(hipGetLastError());
-    TargetSet ts;
-    brick_targets(c, g, kept, nkeep, ts, s);
-    if (ts.n_groups > 0) pairsum_f32(c, ts, w_sorted, true, out, s);
-    RBF_HIP(hipStreamSynchronize(s));
-    st->useful_pairs = ts.useful;
-    st->examined_pairs = ts.list_entries * kGroup;
-    free_targets(ts);
+    if (brick_sum_applies(c, g)) {
+      // the bricks walk their candidate sources directly, as in the plain grid
+      int64_t* cnt = talloc<int64_t>(2 * nkeep + 2);
+      brick_sum_f32(c, g, kept, nkeep, w_sorted, out, cnt, cnt + nkeep, s);
+      sum_i64(cnt, nkeep, cnt + 2 * nkeep, s);
+      sum_i64(cnt + nkeep, nkeep, cnt + 2 * nkeep + 1, s);
+      int64_t h[2] = {0, 0};
+      RBF_HIP(hipMemcpyAsync(h, cnt + 2 * nkeep, sizeof(h), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipStreamSynchronize(s));
+      st->useful_pairs = h[0];
+      st->examined_pairs = h[1];
+      temp_free(cnt);
+    } else {
+      TargetSet ts;
+      brick_targets(c, g, kept, nkeep, ts, s);
+      if (ts.n_groups > 0) pairsum_f32(c, ts, w_sorted, true, out, s);
+      RBF_HIP(hipStreamSynchronize(s));
+      st->useful_pairs = ts.useful;
+      st->examined_pairs = ts.list_entries * kGroup;
+      free_targets(ts);
+    }
     for (void* p : {(void*)ysup, (void*)ygrid, (void*)own, (void*)t1, (void*)t2, (void*)keep, (void*)pos,
                     (void*)kept})
       temp_free(p);

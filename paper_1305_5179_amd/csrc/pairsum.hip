@@ -26,7 +26,7 @@
 //
 // float64 path: the same lists; sources broadcast through LDS; r^2 and the
 // cutoff test exactly as the float64 definition; exp from the device library.
-#include "common.h"
+#include "cells.h"
 
 namespace rbf {
 
@@ -53,14 +53,6 @@ struct PairArgs {
   const int64_t* out_index;
   const int* skip;
 };
-
-// Block b of the launch runs on XCD b % 8; give every XCD a contiguous range
-// of groups so that neighbouring groups (which share sources) share an L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8, x = b % 8;
-  const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-  return first + b / 8;
-}
 
 template <int K>
 __device__ __forceinline__ float bcast(float v) {
@@ -450,11 +442,15 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   return a;
 }
 
+}  // namespace
+
 // Launch timing (rbf_profile_begin / rbf_profile_end).
+namespace {
 struct ProfRec {
   hipEvent_t a, b;
   int kind, prec;
   int64_t useful, examined;
+  bool ended;   // the end event was recorded
 };
 struct Profiler {
   bool on = false;
@@ -464,29 +460,36 @@ Profiler& profiler() {
   static Profiler p;
   return p;
 }
-
-struct ProfScope {
-  ProfRec rec{};
-  bool on;
-  hipStream_t s;
-  ProfScope(int prec, const TargetSet& ts, hipStream_t st) : on(profiler().on), s(st) {
-    if (!on) return;
-    rec.prec = prec;
-    rec.kind = ts.kind;
-    rec.useful = ts.useful;
-    rec.examined = ts.list_entries * kGroup;
-    RBF_HIP(hipEventCreate(&rec.a));
-    RBF_HIP(hipEventCreate(&rec.b));
-    RBF_HIP(hipEventRecord(rec.a, s));
-  }
-  void done() {
-    if (!on) return;
-    RBF_HIP(hipEventRecord(rec.b, s));
-    profiler().recs.push_back(rec);
-  }
-};
-
 }  // namespace
+
+ProfScope::ProfScope(int prec, int kind, int64_t useful, int64_t examined, hipStream_t st)
+    : on(profiler().on), s(st) {
+  if (!on) return;
+  ProfRec r{};
+  r.prec = prec;
+  r.kind = kind;
+  r.useful = useful;
+  r.examined = examined;
+  RBF_HIP(hipEventCreate(&r.a));
+  RBF_HIP(hipEventCreate(&r.b));
+  RBF_HIP(hipEventRecord(r.a, s));
+  profiler().recs.push_back(r);
+  rec = (int)profiler().recs.size() - 1;
+}
+
+void ProfScope::done() {
+  if (!on || rec < 0) return;
+  RBF_HIP(hipEventRecord(profiler().recs[rec].b, s));
+  profiler().recs[rec].ended = true;
+}
+
+void ProfScope::set_pairs(int64_t useful, int64_t examined) {
+  if (!on || rec < 0 || rec >= (int)profiler().recs.size()) return;
+  profiler().recs[rec].useful = useful;
+  profiler().recs[rec].examined = examined;
+}
+
+bool profiling() { return profiler().on; }
 
 int profile_begin() {
   Profiler& p = profiler();
@@ -504,6 +507,11 @@ int profile_end(rbf_profile* out) {
   p.on = false;
   rbf_profile r{};
   for (auto& q : p.recs) {
+    if (!q.ended) {   // a launch that failed
+      (void)hipEventDestroy(q.a);
+      (void)hipEventDestroy(q.b);
+      continue;
+    }
     RBF_HIP(hipEventSynchronize(q.b));
     float ms = 0.f;
     RBF_HIP(hipEventElapsedTime(&ms, q.a, q.b));
@@ -524,7 +532,7 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   if (ts.n_groups == 0) return;
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
-  ProfScope prof(RBF_FP32, ts, s);
+  ProfScope prof(RBF_FP32, ts.kind, ts.useful, ts.list_entries * kGroup, s);
   hipLaunchKernelGGL(k_pairsum_f32, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();
@@ -535,7 +543,7 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   if (ts.n_groups == 0) return;
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
-  ProfScope prof(RBF_FP64, ts, s);
+  ProfScope prof(RBF_FP64, ts.kind, ts.useful, ts.list_entries * kGroup, s);
   hipLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();

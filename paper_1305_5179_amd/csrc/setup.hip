@@ -1,17 +1,12 @@
 // Setup kernels: input checks, the extended centre set, Hilbert ordering
 // (wave-ballot LSD radix sort), coarse cells and per-group source lists.
-#include "common.h"
+#include "cells.h"
 
 namespace rbf {
 
 namespace {
 
 constexpr int kThreads = 256;
-
-__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 int grid_for(int64_t n, int threads = kThreads) {
   int64_t b = ceil_div(n, threads);
@@ -469,12 +464,6 @@ __device__ __forceinline__ void process_shell(const uint32_t* q, int cnt, const 
   n.use += u;
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // A group's valid targets (mask), the centre of their bounding box (the
 // anchor) and their largest distance from it.
 struct Frame {
@@ -507,23 +496,6 @@ __device__ __forceinline__ Frame group_frame(const double4* __restrict__ tg) {
     }
   }
   return f;
-}
-
-// The cube of coarse cells holding every coordinate within r_out of the
-// anchor along each axis.  The relative pad keeps the float64 rounding of
-// the cell index (here and in the sources' own cell keys, both
-// floor((x - origin) / fine) up to a power of two) from dropping the cell of
-// a source at the boundary.
-__device__ __forceinline__ void cell_cube(const double ac[3], double r_out, const Lattice& lat, int cl[3], int cn[3]) {
-  for (int d = 0; d < 3; ++d) {
-    const double pad = r_out * (1.0 + 1e-9) + 1e-12 * (fabs(ac[d]) + fabs(lat.origin[d]) + r_out);
-    const double a = floor((ac[d] - pad - lat.origin[d]) / lat.coarse);
-    const double b = floor((ac[d] + pad - lat.origin[d]) / lat.coarse);
-    const int ia = (int)fmax(0.0, fmin(a, (double)(lat.cdims[d] - 1)));
-    const int ib = (int)fmax(0.0, fmin(b, (double)(lat.cdims[d] - 1)));
-    cl[d] = ia;
-    cn[d] = ib - ia + 1;
-  }
 }
 
 // Summed counts of the coarse cells: sat[(z * (ny + 1) + y) * (nx + 1) + x]
@@ -603,9 +575,6 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   const int64_t g = (int64_t)blockIdx.x * 4 + wave;
   if (g >= G) return;
   uint32_t* q = qbuf[wave];
-  int32_t* cpre = cpre_s[wave];
-  int32_t* cst = cst_s[wave];
-  uint8_t* cwhole = cwhole_s[wave];
   const double4* tg = tpts + g * kGroup;
   // the group's valid targets, anchor and radius (uniform)
   const Frame fr = group_frame(tg);
@@ -645,97 +614,29 @@ __global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ 
   int cl[3], cn[3];
   const double ac[3] = {ax, ay, az};
   cell_cube(ac, r_out, lat, cl, cn);
-  const int ncube = cn[0] * cn[1] * cn[2];
   ListCounts n{0, 0, 0};
   int qn = 0;
-  for (int c0 = 0; c0 < ncube; c0 += kWave) {
-    // one cell of the cube per lane: occupied? how far from the anchor?
-    const int ci = c0 + lane;
-    int32_t cid = -1;
-    bool whole = false;
-    if (ci < ncube) {
-      const int cx = cl[0] + ci % cn[0], cy = cl[1] + (ci / cn[0]) % cn[1], cz = cl[2] + ci / (cn[0] * cn[1]);
-      cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
-      if (cid >= 0) {
-        const int cc[3] = {cx, cy, cz};
-        double dmin2 = 0.0, dmax2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-          const double b0 = lat.origin[d] + cc[d] * lat.coarse, b1 = b0 + lat.coarse;
-          const double gap = fmax(0.0, fmax(b0 - ac[d], ac[d] - b1));
-          const double far = fmax(fabs(ac[d] - b0), fabs(ac[d] - b1));
-          dmin2 += gap * gap;
-          dmax2 += far * far;
+  const int64_t cand = walk_candidates<MODE == kBound>(
+      ac, r_in2, r_out2, cl, cn, xs, cstart, ccount, cmap, lat, cpre_s[wave], cst_s[wave], cwhole_s[wave],
+      [&](bool, uint32_t k, bool is_in, bool is_shell) {
+        const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
+        if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k);
+        n.n_in += __popcll(mi);
+        n.use += (int64_t)__popcll(mi) * nvalid;
+        if (is_shell) q[qn + lanes_below(ms)] = k;
+        qn += __popcll(ms);
+        if (qn >= kWave) {
+          wave_sync_lds();
+          process_shell<WRITE, LATTICE>(q, kWave, tg, xs, vmask, rc2, o, n);
+          const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
+          wave_sync_lds();
+          if (lane + kWave < qn) q[lane] = rest;
+          qn -= kWave;
+          wave_sync_lds();
         }
-        if (dmin2 > r_out2 * (1.0 + 1e-9)) cid = -1;
-        whole = dmax2 * (1.0 + 1e-9) <= r_in2;
-      }
-    }
-    // the occupied cells of this block, compacted in lane order, with the
-    // exclusive prefix of their source counts: the block's candidate
-    // sources are then taken 64 at a time across cell boundaries
-    const int32_t ct = cid >= 0 ? ccount[cid] : 0;
-    const int32_t st = cid >= 0 ? cstart[cid] : 0;
-    const bool occ = ct > 0;   // (empty cells would break the search below)
-    const uint64_t sel = ballot(occ);
-    const int nocc = __popcll(sel);
-    int32_t incl = ct;
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int32_t y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    const int32_t total = __shfl(incl, kWave - 1);
-    if (MODE == kBound) {
-      n.n_in += total;   // candidate count
-      continue;
-    }
-    wave_sync_lds();
-    if (occ) {
-      const int pos = lanes_below(sel);
-      cpre[pos] = incl - ct;
-      cst[pos] = st;
-      cwhole[pos] = whole ? 1 : 0;
-    }
-    wave_sync_lds();
-    for (int32_t b0 = 0; b0 < total; b0 += kWave) {
-      const int32_t f = b0 + lane;
-      const bool valid = f < total;
-      // the cell of flattened source f: the last j with cpre[j] <= f
-      int j = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (j + step < nocc && cpre[j + step] <= f) j += step;
-      const uint32_t k = (uint32_t)(cst[j] + (f - cpre[j]));
-      bool is_in = false, is_shell = false;
-      if (valid) {
-        if (cwhole[j]) {
-          is_in = true;
-        } else {
-          const double4 s = xs[k];
-          const double dx = s.x - ax, dy = s.y - ay, dz = s.z - az;
-          const double d2 = (dx * dx + dy * dy) + dz * dz;
-          is_in = d2 <= r_in2;
-          is_shell = !is_in && d2 <= r_out2;
-        }
-      }
-      const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-      if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k);
-      n.n_in += __popcll(mi);
-      n.use += (int64_t)__popcll(mi) * nvalid;
-      if (is_shell) q[qn + lanes_below(ms)] = k;
-      qn += __popcll(ms);
-      if (qn >= kWave) {
-        wave_sync_lds();
-        process_shell<WRITE, LATTICE>(q, kWave, tg, xs, vmask, rc2, o, n);
-        const uint32_t rest = lane + kWave < qn ? q[kWave + lane] : 0u;
-        wave_sync_lds();
-        if (lane + kWave < qn) q[lane] = rest;
-        qn -= kWave;
-        wave_sync_lds();
-      }
-    }
-  }
+      });
   if (MODE == kBound) {
-    if (lane == 0) bound[g] = n.n_in;
+    if (lane == 0) bound[g] = cand;
     return;
   }
   wave_sync_lds();
@@ -1197,6 +1098,14 @@ void centre_targets(const Ctx& c, TargetSet& ts, hipStream_t s) {
   temp_free(sp);
 }
 
+void sum_i64(const int64_t* in, int64_t n, int64_t* out, hipStream_t s) {
+  RBF_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), s));
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_sum_i64, dim3((unsigned)std::min<int64_t>(256, ceil_div(n, kThreads))), dim3(kThreads), 0, s,
+                     in, n, out);
+  RBF_HIP(hipGetLastError());
+}
+
 void fill_f64(double* p, double v, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kThreads), 0, s, p, v, n);
@@ -1272,10 +1181,7 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     hipLaunchKernelGGL(k_list_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(len, off, G, s);
-    RBF_HIP(hipMemsetAsync(tmp, 0, sizeof(int64_t), s));
-    hipLaunchKernelGGL(k_sum_i64, dim3((unsigned)std::min<int64_t>(256, ceil_div(G, kThreads))), dim3(kThreads), 0,
-                       s, use, G, tmp);
-    RBF_HIP(hipGetLastError());
+    sum_i64(use, G, tmp, s);
     int64_t last_off = 0, last_len = 0;
     int overflowed = 0;
     RBF_HIP(hipMemcpyAsync(&last_off, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -165,6 +165,52 @@ def test_grid_evaluation_matches_oracle(case, torch, R, prec):
         assert np.all(out[scale == 0] == 0.0)
 
 
+def _brick_form(sigma, cutoff, h):
+    """Whether a float32 grid takes the list-free brick sums: the library's
+    range condition on the product form's exponents (scaled units)."""
+    sk = math.sqrt(math.log2(math.e) / (2 * sigma * sigma))
+    diag = math.sqrt((3 * h[0]) ** 2 + h[1] ** 2 + h[2] ** 2)
+    umax = sk * (cutoff + diag) * (1 + 1e-6)
+    return umax * umax + 2 * umax * sk * (3 * h[0] + h[1] + h[2]) <= 64
+
+
+@pytest.mark.parametrize("name", ["torus_patch_cut", "sphere333_cut"])
+def test_grid_brick_sums_match_oracle(name, torch, R):
+    """Float32 grids fine enough for the list-free brick sums: every node
+    against the oracle, bricks ragged on every axis, nodes without a centre
+    within the cutoff exactly zero, and the same values on a second call."""
+    make, eps, sigma, cutoff = CASES[name]
+    c = make()
+    X, _ = o.extended_centres(c.points, c.normals, eps)
+    h = (0.5 * sigma, 0.45 * sigma, 0.55 * sigma)
+    assert _brick_form(sigma, cutoff, h)
+    lo = X.min(axis=0) - 0.6 * cutoff
+    span = X.max(axis=0) + 0.6 * cutoff - lo
+    dims = [int(math.ceil(span[d] / h[d])) + 1 for d in range(3)]
+    dims = [d + (1 - d % 4) % 4 if i == 0 else d + (1 - d % 2) for i, d in enumerate(dims)]   # ragged bricks
+    g = w.Grid(tuple(float(v) for v in lo), h, tuple(dims))
+    _say(f"[brick grid {name}] dims {dims}")
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, cutoff)
+    try:
+        coef = np.random.default_rng(23).uniform(-2, 2, X.shape[0])
+        out = host(ctx.eval_grid(dev(torch, coef), g.origin, g.h, g.dims, prec=0))
+        again = host(ctx.eval_grid(dev(torch, coef), g.origin, g.h, g.dims, prec=0))
+    finally:
+        ctx.close()
+    nodes = o.grid_nodes(g.origin, g.h, g.dims)
+    ref = o.evaluate(X, coef, nodes, sigma, cutoff)
+    scale = abs_sums(X, coef, range(nodes.shape[0]), sigma, cutoff, targets=nodes)
+    err = np.abs(out - ref)
+    bound = tol32(sigma, cutoff) * scale + U32 * np.abs(ref) + 1e-300
+    band = scale > 0
+    _say(f"[brick grid {name}] band nodes {band.sum()} of {g.size}, max err/bound {np.max(err / bound):.3f}, "
+         f"max err {np.max(err[band] / scale[band]) / U32:.2f} u32 of sum |terms|")
+    assert band.sum() > 1000 and (~band).sum() > 1000
+    assert np.all(err <= bound)
+    assert np.all(out[~band] == 0.0)
+    assert np.array_equal(out, again)
+
+
 def test_cutoff_decision_is_the_float64_one(torch, R):
     """Pairs within a few ulps of the cutoff: the float32 kernel must take the
     float64 decision (inclusive) on both sides of it."""
