@@ -46,6 +46,18 @@ __device__ __forceinline__ void cell_cube(const double ac[3], double r_out, cons
   }
 }
 
+// n / d for 0 <= n < 2^20 and 1 <= d, with inv_d = 1 / d in float32: the
+// float quotient is within one of n / d (relative error below 2^-22), and
+// one integer product corrects it.
+__device__ __forceinline__ int div_small(int n, int d, float inv_d) {
+  int q = (int)((float)n * inv_d);
+  if (q * d > n)
+    --q;
+  else if ((q + 1) * d <= n)
+    ++q;
+  return q;
+}
+
 // The candidate sources of a group with anchor `ac`: every source of the
 // occupied coarse cells of the cube [cl, cl + cn) whose box comes within
 // r_out of the anchor.  The cells are examined one per lane, 64 at a time;
@@ -67,6 +79,8 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
                                                    int32_t* cpre, int32_t* cst, uint8_t* cwhole, Visit&& visit) {
   const int lane = threadIdx.x & 63;
   const int ncube = cn[0] * cn[1] * cn[2];
+  const bool small = ncube < (1 << 20);
+  const float inv0 = 1.0f / (float)cn[0], inv1 = 1.0f / (float)cn[1];
   int64_t cand = 0;
   for (int c0 = 0; c0 < ncube; c0 += kWave) {
     // one cell of the cube per lane: occupied? how far from the anchor?
@@ -74,7 +88,18 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
     int32_t cid = -1;
     bool whole = false;
     if (ci < ncube) {
-      const int cx = cl[0] + ci % cn[0], cy = cl[1] + (ci / cn[0]) % cn[1], cz = cl[2] + ci / (cn[0] * cn[1]);
+      int cx, cy, cz;
+      if (small) {
+        const int t = div_small(ci, cn[0], inv0);
+        cz = div_small(t, cn[1], inv1);
+        cx = cl[0] + (ci - t * cn[0]);
+        cy = cl[1] + (t - cz * cn[1]);
+        cz += cl[2];
+      } else {
+        cx = cl[0] + ci % cn[0];
+        cy = cl[1] + (ci / cn[0]) % cn[1];
+        cz = cl[2] + ci / (cn[0] * cn[1]);
+      }
       cid = cmap[(int64_t)cx + (int64_t)lat.cdims[0] * ((int64_t)cy + (int64_t)lat.cdims[1] * cz)];
       if (cid >= 0) {
         const int cc[3] = {cx, cy, cz};
@@ -102,7 +127,9 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
       const int32_t y = __shfl_up(incl, off);
       if (lane >= off) incl += y;
     }
-    const int32_t total = __shfl(incl, kWave - 1);
+    // (read-first-lane: the compiler cannot see that the shuffle is uniform,
+    // and a divergent trip count would make the whole walk divergent)
+    const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
     cand += total;
     if (CELLS_ONLY) continue;
     wave_sync_lds();

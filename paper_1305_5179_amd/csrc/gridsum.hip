@@ -45,8 +45,8 @@ struct BrickArgs {
   double rc, rc2, sqrt_k;
   double hk[3];          // scaled grid spacing h sqrt(k) per axis
   float* out;
-  int64_t* useful;       // per brick: pairs inside the cutoff (optional)
-  int64_t* examined;     // per brick: queued sources x 16 (optional)
+  int64_t* useful;       // per brick: pairs inside the cutoff (with `examined`, optional)
+  int64_t* examined;     // per brick: queued sources x 16
 };
 
 struct BrickNodes {
@@ -80,8 +80,8 @@ __device__ __forceinline__ BrickNodes brick_nodes(const GridDesc& gd, int64_t b)
 
 // Terms of `cnt` (<= 64) queued sources, one per lane, added to the lane's 16
 // node sums.  SHELL: each term only where the exact test puts the pair
-// inside the cutoff.
-template <bool SHELL>
+// inside the cutoff.  COUNT: add the pairs inside the cutoff to `use`.
+template <bool SHELL, bool COUNT>
 __device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes& bn, const uint32_t* q, int cnt,
                                             float acc[kGroup], int64_t& use) {
   const int lane = threadIdx.x & 63;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes
       acc[i + 8] = __builtin_fmaf(A[i], Z, acc[i + 8]);
       acc[i + 12] = __builtin_fmaf(B, Z, acc[i + 12]);
     }
-    use += (int64_t)cnt * bn.nvalid;
+    if (COUNT) use += (int64_t)cnt * bn.nvalid;
   } else {
     // the exact test, r^2 = (dx dx + dy dy) + dz dz with d = node - source
     double ex2[4], ey2[2], ez2[2];
@@ -140,13 +140,14 @@ __device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes
         const double r2 = (ex2[i] + ey2[jk & 1]) + ez2[jk >> 1];
         const bool in = valid && r2 <= a.rc2;
         acc[l] += in ? T[jk] : 0.0f;
-        if ((bn.vmask >> l) & 1u) use += __popcll(ballot(in));
+        if (COUNT) use += __popcll(ballot(in) & (((bn.vmask >> l) & 1u) ? ~0ull : 0ull));
       }
     }
   }
 }
 
-__global__ __launch_bounds__(kBrickWaves * kWave) void k_brick_sum_f32(BrickArgs a) {
+template <bool COUNT>
+__global__ __launch_bounds__(kBrickWaves * kWave, 5) void k_brick_sum_f32(BrickArgs a) {
   // per wave: the two source queues and the cell prefix of the walk, later
   // the cross-lane sums
   __shared__ uint32_t lds_s[kBrickWaves][kWave * kRedPitch];
@@ -197,7 +198,7 @@ __global__ __launch_bounds__(kBrickWaves * kWave) void k_brick_sum_f32(BrickArgs
     // take 64 queued sources from the front of a queue and move the rest down
     auto drain = [&](uint32_t* qq, int& nq, auto shell) {
       wave_sync_lds();
-      brick_batch<decltype(shell)::value>(a, bn, qq, kWave, acc, use);
+      brick_batch<decltype(shell)::value, COUNT>(a, bn, qq, kWave, acc, use);
       const uint32_t rest = lane + kWave < nq ? qq[kWave + lane] : 0u;
       wave_sync_lds();
       if (lane + kWave < nq) qq[lane] = rest;
@@ -216,8 +217,8 @@ __global__ __launch_bounds__(kBrickWaves * kWave) void k_brick_sum_f32(BrickArgs
                              if (nsh >= kWave) drain(qsh, nsh, std::true_type{});
                            });
     wave_sync_lds();
-    if (nin > 0) brick_batch<false>(a, bn, qin, nin, acc, use);
-    if (nsh > 0) brick_batch<true>(a, bn, qsh, nsh, acc, use);
+    if (nin > 0) brick_batch<false, COUNT>(a, bn, qin, nin, acc, use);
+    if (nsh > 0) brick_batch<true, COUNT>(a, bn, qsh, nsh, acc, use);
     queued += nin + nsh;
   }
   // node sums across the wave: lane L adds node L % 16 over the 16 lanes of
@@ -239,9 +240,9 @@ __global__ __launch_bounds__(kBrickWaves * kWave) void k_brick_sum_f32(BrickArgs
     const double nf = exp2(-((hx * hx + hy * hy) + hz * hz));
     a.out[(bn.i0 + i) + a.gd.n[0] * ((bn.j0 + j) + a.gd.n[1] * (bn.k0 + k))] = (float)((double)v * nf);
   }
-  if (lane == 0) {
-    if (a.useful) a.useful[g] = use;
-    if (a.examined) a.examined[g] = queued * kGroup;
+  if (COUNT && lane == 0) {
+    a.useful[g] = use;
+    a.examined[g] = queued * kGroup;
   }
 }
 
@@ -280,7 +281,10 @@ void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t 
   a.useful = useful;
   a.examined = examined;
   const int64_t nb = ceil_div(nact, kBrickWaves);
-  hipLaunchKernelGGL(k_brick_sum_f32, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, a);
+  if (useful && examined)
+    hipLaunchKernelGGL(k_brick_sum_f32<true>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_brick_sum_f32<false>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, a);
   RBF_HIP(hipGetLastError());
 }
 
