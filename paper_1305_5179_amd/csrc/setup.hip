@@ -983,6 +983,23 @@ void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t 
   temp_free(sums_scanned);
 }
 
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
+// 8 bits per pass; on return ki/vi point at the sorted arrays (the buffers
+// swap roles every pass).  hist/offs hold 256 entries per tile.
+static void radix_passes(uint32_t*& ki, uint32_t*& vi, uint32_t*& ko, uint32_t*& vo, int64_t m, int bits,
+                         int64_t* hist, int64_t* offs, hipStream_t s) {
+  const int nb = (int)ceil_div(m, kRsTile);
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, ki, m, shift, hist, nb);
+    RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(hist, offs, (int64_t)256 * nb, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, ko, vo, m, shift, offs, nb);
+    RBF_HIP(hipGetLastError());
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+}
+
 void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* perm, uint32_t* keys_out,
                  hipStream_t s) {
   const int nb = (int)ceil_div(m, kRsTile);
@@ -995,15 +1012,7 @@ void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* pe
   hipLaunchKernelGGL(k_curve_keys, dim3(grid_for(m)), dim3(kThreads), 0, s, pts3, m, lat, k0, v0);
   RBF_HIP(hipGetLastError());
   uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
-  for (int shift = 0; shift < 3 * kCurveBits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kThreads), 0, s, ki, m, shift, hist, nb);
-    RBF_HIP(hipGetLastError());
-    scan_exclusive_i64(hist, offs, (int64_t)256 * nb, s);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kThreads), 0, s, ki, vi, ko, vo, m, shift, offs, nb);
-    RBF_HIP(hipGetLastError());
-    std::swap(ki, ko);
-    std::swap(vi, vo);
-  }
+  radix_passes(ki, vi, ko, vo, m, 3 * kCurveBits, hist, offs, s);
   RBF_HIP(hipMemcpyAsync(perm, vi, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
   if (keys_out) RBF_HIP(hipMemcpyAsync(keys_out, ki, sizeof(uint32_t) * m, hipMemcpyDeviceToDevice, s));
   temp_free(k0); temp_free(v0); temp_free(k1); temp_free(v1); temp_free(hist); temp_free(offs);
