@@ -16,7 +16,7 @@ namespace rbf {
 
 constexpr int kMaxRestart = 64;
 constexpr int kVecThreads = 256;
-constexpr int kRowsPerThread = 4;
+constexpr int kRowsPerThread = 2;
 constexpr int kRowsPerBlock = kVecThreads * kRowsPerThread;
 
 struct GmState {

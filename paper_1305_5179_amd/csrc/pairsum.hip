@@ -24,8 +24,11 @@
 // of the step (the float64 decisions of the list builder, loaded by scalar
 // loads) zeroes the terms of the pairs outside the cutoff.
 //
-// float64 path: the same lists; sources broadcast through LDS; r^2 and the
-// cutoff test exactly as the float64 definition; exp from the device library.
+// float64 path: the same lists; sources broadcast through LDS.  Groups in
+// the expanded form's range take it in float64 with the same lane masks and
+// a Taylor-series exp2 (one FMA chain per pair); dense lists and wide groups
+// form r^2 and the cutoff test exactly as the float64 definition, with exp
+// from the device library.
 #include "cells.h"
 
 namespace rbf {
@@ -368,15 +371,94 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) 
     direct_group(a, gi, g, lane);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
-  __shared__ double4 sh[kBlock / kWave][kWave];
-  // the wave index is uniform across the wave: keep it (and all group data) scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63, row = lane >> 4, tl = lane & 15;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (g >= a.G) return;
-  if (a.skip && *a.skip) return;
-  const GroupInfo gi = a.groups[g];
+// ---- float64 ---------------------------------------------------------------
+// 2^y for |y| <= 1000: y = n + f with n the nearest integer (exact) and
+// |f| <= 1/2; 2^f = exp(f ln 2) by its Taylor series to degree 13 (the
+// first omitted term is below 2^-57 of the value), coefficients
+// (ln 2)^k / k! rounded to float64; then 2^n by ldexp.  Within 2 ulp.
+__device__ __forceinline__ double exp2_f64(double y) {
+  constexpr double C[14] = {
+      0x1.0000000000000p+0,  0x1.62e42fefa39efp-1, 0x1.ebfbdff82c58fp-3, 0x1.c6b08d704a0c0p-5,
+      0x1.3b2ab6fba4e77p-7,  0x1.5d87fe78a6731p-10, 0x1.430912f86c787p-13, 0x1.ffcbfc588b0c7p-17,
+      0x1.62c0223a5c824p-20, 0x1.b5253d395e7c4p-24, 0x1.e4cf5158b8ecap-28, 0x1.e8cac7351bb25p-32,
+      0x1.c3bd650fc2986p-36, 0x1.816193166d0f9p-40};
+  const double n = rint(y);
+  const double f = y - n;
+  double p = C[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) p = fma(p, f, C[k]);
+  return ldexp(p, (int)n);
+}
+
+// e where the step's lane mask has this lane's bit, else 0 (the mask in
+// scalar registers, as the float32 kernel applies it).
+__device__ __forceinline__ double mask_lane(double e, uint64_t m) {
+  uint32_t lo = (uint32_t)__builtin_bit_cast(uint64_t, e), hi = (uint32_t)(__builtin_bit_cast(uint64_t, e) >> 32);
+  asm volatile("v_cndmask_b32_e64 %0, 0, %0, %2\n\tv_cndmask_b32_e64 %1, 0, %1, %2"
+               : "+v"(lo), "+v"(hi) : "s"(m));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Expanded form in float64, with the list builder's lane masks: per chunk
+// every lane stages its source relative to the anchor (scaled) with the
+// weight folded with 2^{-|s|^2}; each pair then costs the dot product 2 t.s,
+// exp2_f64 and one FMA; the target factor 2^{-|t|^2} multiplies the sum.
+// (Within the expanded form's range |s|^2 <= 100 and 2 t.s <= 100; the
+// padding source, far away with weight 0 and always masked, is staged as 0.)
+__device__ __forceinline__ void expanded_group_f64(const PairArgs& a, const GroupInfo& gi, int64_t g, int wave,
+                                                   int lane, double4 (*sh)[kWave]) {
+  const int row = lane >> 4, tl = lane & 15;
+  const int64_t tid = g * kGroup + tl;
+  const double4 tp = a.tpts[tid];
+  const double tx = (tp.x - gi.ax) * a.sqrt_k, ty = (tp.y - gi.ay) * a.sqrt_k, tz = (tp.z - gi.az) * a.sqrt_k;
+  const double t2x = 2.0 * tx, t2y = 2.0 * ty, t2z = 2.0 * tz;
+  const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
+  const uint64_t* masks = a.mask + (gi.off >> 2);
+  const int nch = gi.n_chunks, nin = gi.n_inner;
+  double acc = 0.0;
+  for (int c = 0; c < nch; ++c) {
+    const uint32_t idx = list_entry(a, gi, c, lane);
+    const double4 sk = a.xk[idx];
+    const double sx = sk.x - akx, sy = sk.y - aky, sz = sk.z - akz;
+    const double q = fma(sx, sx, fma(sy, sy, sz * sz));
+    double4 st = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (q <= 1000.0) st = make_double4(sx, sy, sz, a.w[idx] * exp2_f64(-q));
+    sh[wave][lane] = st;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double4* src = &sh[wave][row * kGroup];
+    if (c < nin) {
+#pragma unroll 4
+      for (int k = 0; k < kGroup; ++k) {
+        const double4 s = src[k];
+        acc = fma(s.w, exp2_f64(fma(t2x, s.x, fma(t2y, s.y, t2z * s.z))), acc);
+      }
+    } else {
+      const StepMasks mk = load_masks(masks + (int64_t)c * 16);
+#pragma unroll
+      for (int k = 0; k < kGroup; ++k) {
+        const double4 s = src[k];
+        const double e = exp2_f64(fma(t2x, s.x, fma(t2y, s.y, t2z * s.z)));
+        acc = fma(s.w, mask_lane(e, mk.m[k]), acc);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  acc += __shfl_xor(acc, 16);
+  acc += __shfl_xor(acc, 32);
+  const double tq = fma(tx, tx, fma(ty, ty, tz * tz));
+  if (row == 0 && tp.w != 0.0) store_result(a, tid, acc * exp2_f64(-tq));
+}
+
+// Direct form in float64 (dense lists and groups too wide for the expanded
+// form): r^2 and the cutoff test exactly as the float64 definition, exp from
+// the device library.
+__device__ __forceinline__ void direct_group_f64(const PairArgs& a, const GroupInfo& gi, int64_t g, int wave,
+                                                 int lane, double4 (*sh)[kWave]) {
+  const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
   const double4 tp = a.tpts[tid];
   double acc = 0.0;
@@ -415,6 +497,21 @@ __global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
   acc += __shfl_xor(acc, 16);
   acc += __shfl_xor(acc, 32);
   if (row == 0 && tp.w != 0.0) store_result(a, tid, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
+  __shared__ double4 sh[kBlock / kWave][kWave];
+  // the wave index is uniform across the wave: keep it (and all group data) scalar
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (g >= a.G) return;
+  if (a.skip && *a.skip) return;
+  const GroupInfo gi = load_group(a.groups + g);
+  if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
+    expanded_group_f64(a, gi, g, wave, lane, sh);
+  else
+    direct_group_f64(a, gi, g, wave, lane, sh);
 }
 
 PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out,
