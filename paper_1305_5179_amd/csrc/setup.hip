@@ -851,27 +851,39 @@ __global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_
 // groups of at most 16 whose bounding box has a diagonal of at most E (the
 // float32 coordinates of a group are taken relative to its centre, so their
 // rounding error scales with E).  The packing is greedy inside segments of
-// kGroupSeg targets, one thread per segment: pass 1 counts the groups of
-// every segment, pass 2 (after a scan) assigns each target its slot.
+// kGroupSeg targets, one wave per segment (the segment staged in LDS, one
+// lane packing): pass 1 counts the groups of every segment, pass 2 (after a
+// scan) assigns each target its slot.
 // ---------------------------------------------------------------------------
 constexpr int kGroupSeg = 256;
 
 template <bool ASSIGN>
-__global__ void k_group_greedy(const double4* __restrict__ sp, int64_t M, double E2, int64_t* __restrict__ gcount,
-                               const int64_t* __restrict__ goff, int64_t* __restrict__ slot_of) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kThreads) void k_group_greedy(const double4* __restrict__ sp, int64_t M, double E2,
+                                                           int64_t* __restrict__ gcount,
+                                                           const int64_t* __restrict__ goff,
+                                                           int64_t* __restrict__ slot_of) {
+  // one wave per segment: the wave stages the segment in LDS, one lane runs
+  // the (sequential) greedy packing from there
+  __shared__ double4 seg_s[kThreads / kWave][kGroupSeg];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t s = (int64_t)blockIdx.x * (kThreads / kWave) + wave;
   const int64_t nseg = ceil_div(M, kGroupSeg);
   if (s >= nseg) return;
   const int64_t k0 = s * kGroupSeg, k1 = min(M, k0 + kGroupSeg);
+  double4* seg = seg_s[wave];
+  for (int64_t i = lane; i < k1 - k0; i += kWave) seg[i] = sp[k0 + i];
+  wave_sync_lds();
+  if (lane != 0) return;
   int64_t g = ASSIGN ? goff[s] : 0, ng = 0;
   int64_t k = k0;
   while (k < k1) {
-    const double4 p = sp[k];
+    const double4 p = seg[k - k0];
     double lx = p.x, ly = p.y, lz = p.z, hx = p.x, hy = p.y, hz = p.z;
     if (ASSIGN) slot_of[k] = g * kGroup;
     int64_t j = k + 1;
     for (; j < k1 && j - k < kGroup; ++j) {
-      const double4 q = sp[j];
+      const double4 q = seg[j - k0];
       const double nlx = fmin(lx, q.x), nly = fmin(ly, q.y), nlz = fmin(lz, q.z);
       const double nhx = fmax(hx, q.x), nhy = fmax(hy, q.y), nhz = fmax(hz, q.z);
       const double dx = nhx - nlx, dy = nhy - nly, dz = nhz - nlz;
@@ -1058,7 +1070,8 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   int64_t* gcount = talloc<int64_t>(nseg);
   int64_t* goff = talloc<int64_t>(nseg);
   int64_t* slot_of = talloc<int64_t>(M);
-  hipLaunchKernelGGL(k_group_greedy<false>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount,
+  const unsigned gblocks = (unsigned)ceil_div(nseg, kThreads / kWave);
+  hipLaunchKernelGGL(k_group_greedy<false>, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount,
                      (const int64_t*)nullptr, (int64_t*)nullptr);
   RBF_HIP(hipGetLastError());
   scan_exclusive_i64(gcount, goff, nseg, s);
@@ -1072,7 +1085,7 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   ts.pts = set_alloc<double4>(ts, total);
   ts.index = set_alloc<int64_t>(ts, total);
   ts.owned.push_back(ts.index);
-  hipLaunchKernelGGL(k_group_greedy<true>, dim3(grid_for(nseg, 64)), dim3(64), 0, s, sp, M, E * E, gcount, goff,
+  hipLaunchKernelGGL(k_group_greedy<true>, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount, goff,
                      slot_of);
   hipLaunchKernelGGL(k_pad_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, ts.pts, ts.index, total);
   hipLaunchKernelGGL(k_place_targets, dim3(grid_for(M)), dim3(kThreads), 0, s, sp, orig, M, slot_of, ts.pts,
