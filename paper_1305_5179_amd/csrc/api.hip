@@ -15,10 +15,12 @@ namespace rbf {
 int gm_max_restart();
 size_t gm_state_bytes();
 int64_t gm_partial_count(int64_t n);
-void gm_start(const double* b, const double* y, double* r, int64_t n, double* V, double* partial, int m,
+void gm_start(const double* b, const double* y, double* r, int64_t n, void* V, bool f32, double* partial, int m,
               double tol_abs, void* state, hipStream_t s);
-void gm_step(double* V, int64_t ldv, double* w, int64_t n, int j, double* partial, void* state, hipStream_t s);
-void gm_finish(double* V, int64_t ldv, double* x, int64_t n, void* state, hipStream_t s);
+void gm_step(void* V, int64_t ldv, void* w, bool f32, int64_t n, int j, double* partial, void* state,
+             hipStream_t s);
+void gm_finish(const void* V, int64_t ldv, bool f32, double* x, int64_t n, void* state, hipStream_t s);
+void to_f64(const float* x, double* y, int64_t n, hipStream_t s);
 void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s);
 const int* gm_done_flag(const void* state);
 
@@ -362,7 +364,17 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
     else
       fill_f64(c->csol, 0.0, c->mpad, s);
     // |b|
-    gm_start(c->bsort, nullptr, c->r, m, c->V, c->partial, o.restart, 0.0, c->state, s);
+    // the inner solve of the refinement keeps its Krylov basis (and w) in
+    // float32, in the same allocations; the plain method in float64
+    const bool f32 = o.mode == RBF_SOLVE_IR_FP32;
+    if (c->krylov_f32 != (int)f32) {
+      // the padding entry m of every basis vector is a weight of the operator
+      // and must read 0 in the new element type too
+      fill_f64(c->V, 0.0, round_up(c->krylov_m + 1, kKrylovColPad) * c->mpad, s);
+      fill_f64(c->w, 0.0, c->mpad, s);
+      c->krylov_f32 = (int)f32;
+    }
+    gm_start(c->bsort, nullptr, c->r, m, c->V, f32, c->partial, o.restart, 0.0, c->state, s);
     int k, done, bd;
     double bnorm, gk;
     gm_read(c->state, &k, &done, &bd, &bnorm, &gk, s);
@@ -391,7 +403,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
           apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
           y = c->vout;
         }
-        gm_start(c->bsort, y, c->r, m, c->V, c->partial, o.restart, o.tol * bnorm, c->state, s);
+        gm_start(c->bsort, y, c->r, m, c->V, f32, c->partial, o.restart, o.tol * bnorm, c->state, s);
         double beta;
         gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
         rel = beta / bnorm;
@@ -412,23 +424,35 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         const int* skip = gm_done_flag(c->state);
         const SchwarzData* pre = o.precond == RBF_PRECOND_SCHWARZ ? c->schwarz : nullptr;
         for (int j = 0; j < steps; ++j) {
-          const double* vj = c->V + (int64_t)j * ldv;
-          if (pre) {
-            // right preconditioning: the basis is built on A M
-            schwarz_apply(*c, *pre, vj, pre->z, s, skip);
-            vj = pre->z;
+          if (f32) {
+            const float* vj = reinterpret_cast<const float*>(c->V) + (int64_t)j * ldv;
+            float* w = reinterpret_cast<float*>(c->w);
+            if (pre) {
+              // right preconditioning: the basis is built on A M
+              to_f64(vj, c->vin, m, s);
+              schwarz_apply(*c, *pre, c->vin, pre->z, s, skip);
+              pairsum_f32(*c, c->centres, pre->z, true, w, s, skip);
+            } else {
+              pairsum_f32(*c, c->centres, nullptr, true, w, s, skip, vj);
+            }
+          } else {
+            const double* vj = c->V + (int64_t)j * ldv;
+            if (pre) {
+              schwarz_apply(*c, *pre, vj, pre->z, s, skip);
+              vj = pre->z;
+            }
+            apply_sorted(c, vj, c->w, prec, s, skip);
           }
-          apply_sorted(c, vj, c->w, prec, s, skip);
-          gm_step(c->V, ldv, c->w, m, j, c->partial, c->state, s);
+          gm_step(c->V, ldv, c->w, f32, m, j, c->partial, c->state, s);
         }
         if (pre) {
           // c += M (V y)
           fill_f64(pre->t, 0.0, c->mpad, s);
-          gm_finish(c->V, ldv, pre->t, m, c->state, s);
+          gm_finish(c->V, ldv, f32, pre->t, m, c->state, s);
           schwarz_apply(*c, *pre, pre->t, pre->z, s);
           vec_add(c->csol, pre->z, m, s);
         } else {
-          gm_finish(c->V, ldv, c->csol, m, c->state, s);
+          gm_finish(c->V, ldv, f32, c->csol, m, c->state, s);
         }
         gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
         iters += k;
@@ -438,7 +462,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
           status = RBF_EBREAKDOWN;
           // the true residual of the current iterate is still reported
           apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
-          gm_start(c->bsort, c->vout, c->r, m, c->V, c->partial, o.restart, 0.0, c->state, s);
+          gm_start(c->bsort, c->vout, c->r, m, c->V, f32, c->partial, o.restart, 0.0, c->state, s);
           gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
           rel = beta / bnorm;
           stamp(rel);

@@ -183,7 +183,8 @@ struct Ctx {
   double* vout = nullptr;
   // Solver storage, allocated on first use.
   int krylov_m = 0;
-  double* V = nullptr;          // (m+1) basis vectors of length mpad
+  int krylov_f32 = -1;          // element type the basis was last used with (1 float32, 0 float64)
+  double* V = nullptr;          // (m+1) basis vectors of length mpad (float64, or float32 in the same space)
   double* w = nullptr;
   double* r = nullptr;
   double* csol = nullptr;
@@ -289,9 +290,9 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 // pairsum.hip
 // out[ts.index[t]] = sum over the source list of target t (float output when
 // out_f32, else double).  `skip`: optional device flag; when it is nonzero the
-// kernel returns at once.
+// kernel returns at once.  w32: float32 weights used instead of w.
 void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
-                 const int* skip = nullptr);
+                 const int* skip = nullptr, const float* w32 = nullptr);
 void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
                  const int* skip = nullptr);
 

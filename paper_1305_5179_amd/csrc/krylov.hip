@@ -10,6 +10,11 @@
 // Every kernel of a step first reads the device flag `done`, set when the
 // residual estimate |g_{j+1}| reaches the tolerance (or on breakdown), so the
 // host can enqueue a whole cycle without waiting on it.
+// The basis (and the operator's output w) is stored as T: float64, or
+// float32 for the inner solve of the refinement, whose operator is float32
+// anyway (half the traffic of these memory-bound passes); dot products,
+// norms and updates are formed in float64 either way, and the rounding to T
+// happens once per stored element.
 #include "common.h"
 
 namespace rbf {
@@ -61,7 +66,8 @@ __device__ __forceinline__ void block_store(double (*s)[kMaxRestart + 1], int nc
 // (kKrylovColPad; zeroed at allocation), so the block reads them unguarded
 // and keeps only the first ncols sums.
 constexpr int kColPad = kKrylovColPad;
-__device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t ldv, int ncols,
+template <class T>
+__device__ __forceinline__ void block_dots(const T* __restrict__ V, int64_t ldv, int ncols,
                                            const double (&x)[kRowsPerThread], int64_t base, int64_t n,
                                            double (*s)[kMaxRestart + 1]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -74,7 +80,7 @@ __device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t
       const int64_t r = base + (int64_t)q * kVecThreads;
       if (r < n) {
 #pragma unroll
-        for (int c = 0; c < kColPad; ++c) a[c] = fma(V[(int64_t)(i0 + c) * ldv + r], x[q], a[c]);
+        for (int c = 0; c < kColPad; ++c) a[c] = fma((double)V[(int64_t)(i0 + c) * ldv + r], x[q], a[c]);
       }
     }
 #pragma unroll
@@ -88,8 +94,9 @@ __device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t
 }
 
 // pass 1: partial[b][i] = sum_{r in block b} V_i[r] w[r]
-__global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                      const double* __restrict__ w, int64_t n,
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_dots(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                      const T* __restrict__ w, int64_t n,
                                                       const GmState* __restrict__ st, double* __restrict__ partial) {
   if (st->done) return;
   __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
@@ -98,15 +105,16 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const double* __restrict__
 #pragma unroll
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t r = base + (int64_t)q * kVecThreads;
-    wr[q] = r < n ? w[r] : 0.0;
+    wr[q] = r < n ? (double)w[r] : 0.0;
   }
   block_dots(V, ldv, ncols, wr, base, n, s);
   block_store(s, ncols, partial);
 }
 
 // pass 2: w <- w - V h1 ; partial = V^T w
-__global__ __launch_bounds__(kVecThreads) void k_update_dots(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                             double* __restrict__ w, int64_t n,
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_update_dots(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                             T* __restrict__ w, int64_t n,
                                                              const GmState* __restrict__ st,
                                                              double* __restrict__ partial) {
   if (st->done) return;
@@ -118,10 +126,11 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots(const double* __res
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t r = base + (int64_t)q * kVecThreads;
     if (r < n) {
-      double v = w[r];
-      for (int i = 0; i < ncols; ++i) v = fma(-h[i], V[(int64_t)i * ldv + r], v);
-      w[r] = v;
-      wr[q] = v;
+      double v = (double)w[r];
+      for (int i = 0; i < ncols; ++i) v = fma(-h[i], (double)V[(int64_t)i * ldv + r], v);
+      const T vt = (T)v;
+      w[r] = vt;
+      wr[q] = (double)vt;
     } else {
       wr[q] = 0.0;
     }
@@ -132,8 +141,9 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots(const double* __res
 }
 
 // pass 3: w <- w - V h2 ; partial = |w|^2
-__global__ __launch_bounds__(kVecThreads) void k_update_norm(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                             double* __restrict__ w, int64_t n,
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_update_norm(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                             T* __restrict__ w, int64_t n,
                                                              const GmState* __restrict__ st,
                                                              double* __restrict__ partial) {
   if (st->done) return;
@@ -145,10 +155,11 @@ __global__ __launch_bounds__(kVecThreads) void k_update_norm(const double* __res
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t r = base + (int64_t)q * kVecThreads;
     if (r < n) {
-      double v = w[r];
-      for (int i = 0; i < ncols; ++i) v = fma(-h[i], V[(int64_t)i * ldv + r], v);
-      w[r] = v;
-      a = fma(v, v, a);
+      double v = (double)w[r];
+      for (int i = 0; i < ncols; ++i) v = fma(-h[i], (double)V[(int64_t)i * ldv + r], v);
+      const T vt = (T)v;
+      w[r] = vt;
+      a = fma((double)vt, (double)vt, a);
     }
   }
   __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
@@ -241,12 +252,13 @@ __global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __res
 }
 
 // v_{j+1} = w / |w|
-__global__ __launch_bounds__(kVecThreads) void k_scale(const double* __restrict__ w, int64_t n,
-                                                       const GmState* __restrict__ st, double* __restrict__ out) {
+template <class Tin, class Tout>
+__global__ __launch_bounds__(kVecThreads) void k_scale(const Tin* __restrict__ w, int64_t n,
+                                                       const GmState* __restrict__ st, Tout* __restrict__ out) {
   if (st->done) return;
   const double s = st->inv_beta;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = w[i] * s;
+  if (i < n) out[i] = (Tout)((double)w[i] * s);
 }
 
 // r = b - y and |r|^2 partials (y may be null: r = b)
@@ -296,15 +308,21 @@ __global__ void k_solve_y(GmState* __restrict__ st) {
 }
 
 // x <- x + V y  (k columns, k read from the state)
-__global__ __launch_bounds__(kVecThreads) void k_update_x(const double* __restrict__ V, int64_t ldv,
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_update_x(const T* __restrict__ V, int64_t ldv,
                                                           const GmState* __restrict__ st, double* __restrict__ x,
                                                           int64_t n) {
   const int k = st->k;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n || k == 0) return;
   double v = x[i];
-  for (int l = 0; l < k; ++l) v = fma(st->y[l], V[(int64_t)l * ldv + i], v);
+  for (int l = 0; l < k; ++l) v = fma(st->y[l], (double)V[(int64_t)l * ldv + i], v);
   x[i] = v;
+}
+
+__global__ void k_to_f64(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (double)x[i];
 }
 
 // x += y
@@ -351,36 +369,64 @@ size_t gm_state_bytes() { return sizeof(GmState); }
 int64_t gm_partial_count(int64_t n) { return (int64_t)vec_blocks(n) * (kMaxRestart + 1); }
 
 // r = b - y (y may be null); starts a cycle: beta0 = |r|, v_0 = r / beta0.
-void gm_start(const double* b, const double* y, double* r, int64_t n, double* V, double* partial, int m,
-              double tol_abs, void* state, hipStream_t s) {
-  GmState* st = static_cast<GmState*>(state);
+template <class T>
+static void gm_start_t(const double* b, const double* y, double* r, int64_t n, T* V, double* partial, int m,
+                       double tol_abs, GmState* st, hipStream_t s) {
   const unsigned nb = vec_blocks(n);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kVecThreads), 0, s, b, y, r, n, partial);
   hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, m, tol_abs, st);
-  hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, r, n, st, V);
+  hipLaunchKernelGGL((k_scale<double, T>), dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, r, n, st, V);
   RBF_HIP(hipGetLastError());
+}
+void gm_start(const double* b, const double* y, double* r, int64_t n, void* V, bool f32, double* partial, int m,
+              double tol_abs, void* state, hipStream_t s) {
+  GmState* st = static_cast<GmState*>(state);
+  if (f32)
+    gm_start_t(b, y, r, n, static_cast<float*>(V), partial, m, tol_abs, st, s);
+  else
+    gm_start_t(b, y, r, n, static_cast<double*>(V), partial, m, tol_abs, st, s);
 }
 
 // Orthogonalisation and bookkeeping of step j after w = A v_j.
-void gm_step(double* V, int64_t ldv, double* w, int64_t n, int j, double* partial, void* state, hipStream_t s) {
-  GmState* st = static_cast<GmState*>(state);
+template <class T>
+static void gm_step_t(T* V, int64_t ldv, T* w, int64_t n, int j, double* partial, GmState* st, hipStream_t s) {
   const unsigned nb = vec_blocks(n);
   const int ncols = j + 1;
-  hipLaunchKernelGGL(k_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_dots<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
   hipLaunchKernelGGL(k_reduce_h1, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
-  hipLaunchKernelGGL(k_update_dots, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_update_dots<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
   hipLaunchKernelGGL(k_reduce_h2, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
-  hipLaunchKernelGGL(k_update_norm, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
+  hipLaunchKernelGGL(k_update_norm<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
   hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, j, st);
-  hipLaunchKernelGGL(k_scale, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, w, n, st, V + (int64_t)(j + 1) * ldv);
+  hipLaunchKernelGGL((k_scale<T, T>), dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, w, n, st,
+                     V + (int64_t)(j + 1) * ldv);
   RBF_HIP(hipGetLastError());
+}
+void gm_step(void* V, int64_t ldv, void* w, bool f32, int64_t n, int j, double* partial, void* state,
+             hipStream_t s) {
+  GmState* st = static_cast<GmState*>(state);
+  if (f32)
+    gm_step_t(static_cast<float*>(V), ldv, static_cast<float*>(w), n, j, partial, st, s);
+  else
+    gm_step_t(static_cast<double*>(V), ldv, static_cast<double*>(w), n, j, partial, st, s);
 }
 
 // x += V y after the cycle.
-void gm_finish(double* V, int64_t ldv, double* x, int64_t n, void* state, hipStream_t s) {
+void gm_finish(const void* V, int64_t ldv, bool f32, double* x, int64_t n, void* state, hipStream_t s) {
   GmState* st = static_cast<GmState*>(state);
   hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, s, st);
-  hipLaunchKernelGGL(k_update_x, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, V, ldv, st, x, n);
+  if (f32)
+    hipLaunchKernelGGL(k_update_x<float>, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, static_cast<const float*>(V),
+                       ldv, st, x, n);
+  else
+    hipLaunchKernelGGL(k_update_x<double>, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s,
+                       static_cast<const double*>(V), ldv, st, x, n);
+  RBF_HIP(hipGetLastError());
+}
+
+// float32 -> float64 copy (a basis vector handed to the preconditioner)
+void to_f64(const float* x, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f64, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, x, y, n);
   RBF_HIP(hipGetLastError());
 }
 

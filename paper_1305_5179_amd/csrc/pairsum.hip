@@ -44,6 +44,7 @@ struct PairArgs {
   const double4* xk;     // scaled sources (float32 path)
   const double4* xs;     // unscaled sources
   const double* w;
+  const float* w32;      // float32 weights instead of w (float32 path), or null
   int64_t m;
   double sqrt_k;
   double inv_two_s2;
@@ -223,33 +224,41 @@ __device__ __forceinline__ uint32_t list_entry(const PairArgs& a, const GroupInf
 // one chunk of work after its issue.  The inner chunks (an even count) run
 // in one straight loop, the masked ones in a second loop on the same
 // pipeline, so neither body branches on the chunk kind.
-template <class Inner, class Masked>
+template <bool W32>
+__device__ __forceinline__ double weight(const PairArgs& a, uint32_t i) {
+  if constexpr (W32)
+    return (double)a.w32[i];
+  else
+    return a.w[i];
+}
+
+template <bool W32, class Inner, class Masked>
 __device__ __forceinline__ void chunk_loop(const PairArgs& a, const GroupInfo& gi, int lane, Inner&& inner,
                                            Masked&& masked) {
   const int nch = gi.n_chunks, nin = gi.n_inner;
   const uint32_t i0 = list_entry(a, gi, 0, lane);
   uint32_t i1 = list_entry(a, gi, 1, lane);
   double4 sA = a.xk[i0];
-  double wA = a.w[i0];
+  double wA = weight<W32>(a, i0);
   int c = 0;
   for (; c < nin; c += 2) {
     const double4 sB = a.xk[i1];
-    const double wB = a.w[i1];
+    const double wB = weight<W32>(a, i1);
     const uint32_t i2 = list_entry(a, gi, c + 2, lane);
     inner(c, sA, wA);
     sA = a.xk[i2];
-    wA = a.w[i2];
+    wA = weight<W32>(a, i2);
     i1 = list_entry(a, gi, c + 3, lane);
     inner(c + 1, sB, wB);
   }
   for (; c < nch; c += 2) {
     const double4 sB = a.xk[i1];
-    const double wB = a.w[i1];
+    const double wB = weight<W32>(a, i1);
     const uint32_t i2 = list_entry(a, gi, c + 2, lane);
     masked(c, sA, wA);
     if (c + 1 >= nch) break;
     sA = a.xk[i2];
-    wA = a.w[i2];
+    wA = weight<W32>(a, i2);
     i1 = list_entry(a, gi, c + 3, lane);
     masked(c + 1, sB, wB);
   }
@@ -272,6 +281,7 @@ __device__ __forceinline__ void direct_chunk(float& acc, const Tgt& t, const dou
   }
 }
 
+template <bool W32>
 __device__ __forceinline__ void direct_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
   const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
@@ -281,7 +291,7 @@ __device__ __forceinline__ void direct_group(const PairArgs& a, const GroupInfo&
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
   const uint64_t* masks = a.mask + (gi.off >> 2);
   float acc = 0.0f;
-  chunk_loop(
+  chunk_loop<W32>(
       a, gi, lane,
       [&](int, const double4& sk, double wk) { direct_chunk<false>(acc, t, sk, wk, akx, aky, akz, nullptr); },
       [&](int c, const double4& sk, double wk) {
@@ -307,6 +317,7 @@ __device__ __forceinline__ Src expanded_source(const double4& sk, double wk, dou
   return s;
 }
 
+template <bool W32>
 __device__ __forceinline__ void expanded_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
   const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
@@ -318,7 +329,7 @@ __device__ __forceinline__ void expanded_group(const PairArgs& a, const GroupInf
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
   const uint64_t* masks = a.mask + (gi.off >> 2);
   float acc = 0.0f;
-  chunk_loop(
+  chunk_loop<W32>(
       a, gi, lane,
       [&](int, const double4& sk, double wk) {
         expanded_inner_chunk(acc, t, expanded_source(sk, wk, akx, aky, akz));
@@ -357,6 +368,7 @@ __device__ __forceinline__ GroupInfo load_group(const GroupInfo* gp) {
 // tail.
 constexpr int kPairWaves = 4;
 
+template <bool W32>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -366,9 +378,9 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) 
   if (a.skip && *a.skip) return;
   const GroupInfo gi = load_group(a.groups + g);
   if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
-    expanded_group(a, gi, g, lane);
+    expanded_group<W32>(a, gi, g, lane);
   else
-    direct_group(a, gi, g, lane);
+    direct_group<W32>(a, gi, g, lane);
 }
 
 // ---- float64 ---------------------------------------------------------------
@@ -525,6 +537,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.xk = c.xk;
   a.xs = c.xs;
   a.w = w;
+  a.w32 = nullptr;
   a.m = c.m;
   a.sqrt_k = c.sqrt_k;
   a.inv_two_s2 = c.inv_two_s2;
@@ -625,12 +638,16 @@ int profile_end(rbf_profile* out) {
 }
 
 void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
-                 const int* skip) {
+                 const int* skip, const float* w32) {
   if (ts.n_groups == 0) return;
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
+  a.w32 = w32;
   const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
   ProfScope prof(RBF_FP32, ts.kind, ts.useful, ts.list_entries * kGroup, s);
-  hipLaunchKernelGGL(k_pairsum_f32, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+  if (w32)
+    hipLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }

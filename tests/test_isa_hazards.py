@@ -18,7 +18,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_1305_5179_amd", "csrc", "pairsum.hip")
-KERNEL = "_ZN3rbf12_GLOBAL__N_113k_pairsum_f32ENS0_8PairArgsE"
+# every instantiation of the kernel (float64 or float32 weights)
+KERNEL = "_ZN3rbf12_GLOBAL__N_113k_pairsum_f32"
 TRANS = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
          "v_rcp_f64", "v_rsq_f64", "v_sqrt_f64", "v_rcp_iflag_f32")
 
@@ -41,15 +42,18 @@ def f32_asm(tmp_path_factory):
     subprocess.run([hipcc, *flags, "--cuda-device-only", "-S", SRC, "-o", str(out)], check=True,
                    capture_output=True)
     text = out.read_text()
-    start = text.index(KERNEL + ":")
-    end = text.index(".Lfunc_end", start)
-    lines = []
-    for raw in text[start:end].splitlines()[1:]:
-        l = raw.split(";")[0].strip()
-        if not l or (l.startswith(".") and not l.endswith(":")):
-            continue
-        lines.append(l)
-    return lines
+    bodies = []
+    for m in re.finditer(r"^(" + KERNEL + r"\w*):", text, re.M):
+        end = text.index(".Lfunc_end", m.end())
+        lines = []
+        for raw in text[m.end():end].splitlines()[1:]:
+            l = raw.split(";")[0].strip()
+            if not l or (l.startswith(".") and not l.endswith(":")):
+                continue
+            lines.append(l)
+        bodies.append((m.group(1), lines))
+    assert len(bodies) == 2, [b[0] for b in bodies]
+    return bodies
 
 
 def _regs(operand):
@@ -140,7 +144,11 @@ def _violations(lines, i, regs, need, producer_ok):
 
 
 def test_no_dpp_or_transcendental_forwarding_hazard(f32_asm):
-    lines = f32_asm
+    for name, lines in f32_asm:
+        _check_kernel(name, lines)
+
+
+def _check_kernel(name, lines):
     _predecessors.cache = _predecessors(lines)
     n_dpp = n_fmac_dpp = 0
     problems = []
@@ -159,10 +167,10 @@ def test_no_dpp_or_transcendental_forwarding_hazard(f32_asm):
         if not op.startswith(TRANS):
             for p, w in _violations(lines, i, _reads(l), 1, lambda x: _parse(x)[0].startswith(TRANS)):
                 problems.append(f"transcendental result read after {w} wait states: '{p}' -> '{l}'")
-    assert not problems, "\n".join(problems[:20])
+    assert not problems, name + "\n" + "\n".join(problems[:20])
     # the pair loops of both forms are present
-    assert n_fmac_dpp >= 64, n_fmac_dpp
-    assert n_dpp >= 128, n_dpp
+    assert n_fmac_dpp >= 64, (name, n_fmac_dpp)
+    assert n_dpp >= 128, (name, n_dpp)
 
 
 def test_checker_sees_planted_hazards():
