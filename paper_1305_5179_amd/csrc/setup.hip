@@ -521,10 +521,23 @@ __global__ void k_sat_scan(Lattice lat, int axis, int64_t* __restrict__ sat) {
   const int64_t line = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (line >= n[a1] * n[a2]) return;
   const int64_t base = (line % n[a1]) * stride[a1] + (line / n[a1]) * stride[a2];
+  const int64_t st = stride[axis], len = n[axis];
   int64_t acc = 0;
-  for (int64_t q = 0; q < n[axis]; ++q) {
-    acc += sat[base + q * stride[axis]];
-    sat[base + q * stride[axis]] = acc;
+  // eight entries at a time: their loads are in flight together
+  int64_t q = 0;
+  for (; q + 8 <= len; q += 8) {
+    int64_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = sat[base + (q + u) * st];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      acc += v[u];
+      sat[base + (q + u) * st] = acc;
+    }
+  }
+  for (; q < len; ++q) {
+    acc += sat[base + q * st];
+    sat[base + q * st] = acc;
   }
 }
 
@@ -852,18 +865,18 @@ __global__ void k_count_valid(const double4* __restrict__ pts, int64_t n, int64_
 // float32 coordinates of a group are taken relative to its centre, so their
 // rounding error scales with E).  The packing is greedy inside segments of
 // kGroupSeg targets, one wave per segment (the segment staged in LDS, one
-// lane packing): pass 1 counts the groups of every segment, pass 2 (after a
-// scan) assigns each target its slot.
+// lane packing), which counts the groups of every segment and records each
+// target's slot within its segment; after a scan of the counts a parallel
+// pass gives every target its global slot.
 // ---------------------------------------------------------------------------
 constexpr int kGroupSeg = 256;
 
-template <bool ASSIGN>
 __global__ __launch_bounds__(kThreads) void k_group_greedy(const double4* __restrict__ sp, int64_t M, double E2,
                                                            int64_t* __restrict__ gcount,
-                                                           const int64_t* __restrict__ goff,
-                                                           int64_t* __restrict__ slot_of) {
+                                                           int32_t* __restrict__ local_slot) {
   // one wave per segment: the wave stages the segment in LDS, one lane runs
-  // the (sequential) greedy packing from there
+  // the (sequential) greedy packing from there and records every target's
+  // slot relative to the segment's first group
   __shared__ double4 seg_s[kThreads / kWave][kGroupSeg];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -875,12 +888,12 @@ __global__ __launch_bounds__(kThreads) void k_group_greedy(const double4* __rest
   for (int64_t i = lane; i < k1 - k0; i += kWave) seg[i] = sp[k0 + i];
   wave_sync_lds();
   if (lane != 0) return;
-  int64_t g = ASSIGN ? goff[s] : 0, ng = 0;
+  int32_t g = 0;
   int64_t k = k0;
   while (k < k1) {
     const double4 p = seg[k - k0];
     double lx = p.x, ly = p.y, lz = p.z, hx = p.x, hy = p.y, hz = p.z;
-    if (ASSIGN) slot_of[k] = g * kGroup;
+    local_slot[k] = g * kGroup;
     int64_t j = k + 1;
     for (; j < k1 && j - k < kGroup; ++j) {
       const double4 q = seg[j - k0];
@@ -889,13 +902,20 @@ __global__ __launch_bounds__(kThreads) void k_group_greedy(const double4* __rest
       const double dx = nhx - nlx, dy = nhy - nly, dz = nhz - nlz;
       if ((dx * dx + dy * dy) + dz * dz > E2) break;
       lx = nlx; ly = nly; lz = nlz; hx = nhx; hy = nhy; hz = nhz;
-      if (ASSIGN) slot_of[j] = g * kGroup + (j - k);
+      local_slot[j] = g * kGroup + (int32_t)(j - k);
     }
     k = j;
     ++g;
-    ++ng;
   }
-  if (!ASSIGN) gcount[s] = ng;
+  gcount[s] = g;
+}
+
+// slot of every target: its segment's first group (scanned counts) plus its
+// slot within the segment
+__global__ void k_group_slots(const int32_t* __restrict__ local_slot, const int64_t* __restrict__ goff, int64_t M,
+                              int64_t* __restrict__ slot_of) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < M) slot_of[k] = goff[k / kGroupSeg] * kGroup + local_slot[k];
 }
 
 __global__ void k_pad_targets(double4* __restrict__ pts, int64_t* __restrict__ oidx, int64_t total) {
@@ -1070,9 +1090,9 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   int64_t* gcount = talloc<int64_t>(nseg);
   int64_t* goff = talloc<int64_t>(nseg);
   int64_t* slot_of = talloc<int64_t>(M);
+  int32_t* local_slot = talloc<int32_t>(M);
   const unsigned gblocks = (unsigned)ceil_div(nseg, kThreads / kWave);
-  hipLaunchKernelGGL(k_group_greedy<false>, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount,
-                     (const int64_t*)nullptr, (int64_t*)nullptr);
+  hipLaunchKernelGGL(k_group_greedy, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount, local_slot);
   RBF_HIP(hipGetLastError());
   scan_exclusive_i64(gcount, goff, nseg, s);
   int64_t last_off = 0, last_cnt = 0;
@@ -1085,8 +1105,7 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   ts.pts = set_alloc<double4>(ts, total);
   ts.index = set_alloc<int64_t>(ts, total);
   ts.owned.push_back(ts.index);
-  hipLaunchKernelGGL(k_group_greedy<true>, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount, goff,
-                     slot_of);
+  hipLaunchKernelGGL(k_group_slots, dim3(grid_for(M)), dim3(kThreads), 0, s, local_slot, goff, M, slot_of);
   hipLaunchKernelGGL(k_pad_targets, dim3(grid_for(total)), dim3(kThreads), 0, s, ts.pts, ts.index, total);
   hipLaunchKernelGGL(k_place_targets, dim3(grid_for(M)), dim3(kThreads), 0, s, sp, orig, M, slot_of, ts.pts,
                      ts.index);
@@ -1094,6 +1113,7 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   temp_free(gcount);
   temp_free(goff);
   temp_free(slot_of);
+  temp_free(local_slot);
 }
 
 // The centres as the operator's targets, grouped by surface-point triples

@@ -290,6 +290,39 @@ def test_solve_limits_and_resume(torch, R):
     ctx.close()
 
 
+def test_solve_modes_alternate_on_one_context(torch, R):
+    """The refinement's inner solve keeps its Krylov basis in float32 in the
+    same storage the plain method uses in float64: alternating the modes on
+    one context gives, bit for bit, what fresh contexts give."""
+    make, eps, sigma, cutoff = CASES["torus_patch_cut"]
+    c = make()
+    P, N = dev(torch, c.points), dev(torch, c.normals)
+    kw = dict(tol=1e-12, restart=20, max_iters=40)
+    plain, ir = R.RBF_SOLVE_PLAIN_FP64, R.RBF_SOLVE_IR_FP32
+
+    def fresh(mode):
+        ctx = R.Rbf(P, N, eps, sigma, cutoff)
+        try:
+            x, info = ctx.solve(mode=mode, **kw)
+            return host(x), info.rel_resid
+        finally:
+            ctx.close()
+
+    ref_plain, ref_ir = fresh(plain), fresh(ir)
+    ctx = R.Rbf(P, N, eps, sigma, cutoff)
+    try:
+        seq = []
+        for mode in (plain, ir, plain, ir):
+            x, info = ctx.solve(mode=mode, **kw)
+            seq.append((host(x), info.rel_resid))
+    finally:
+        ctx.close()
+    _say(f"[modes] plain {ref_plain[1]:.3e} refined {ref_ir[1]:.3e}")
+    for (x, r), ref in zip(seq, (ref_plain, ref_ir, ref_plain, ref_ir)):
+        assert np.array_equal(x, ref[0]) and r == ref[1]
+    assert ref_ir[1] < 0.1 and ref_plain[1] < 0.1
+
+
 # ---------------------------------------------------------------------------
 # The sphere workload (2,000 points, no cutoff) at full size.
 # ---------------------------------------------------------------------------
