@@ -42,9 +42,31 @@ struct GmState {
 
 namespace {
 
+// v plus lane `ctrl` of the DPP pattern (a double moved as two 32-bit halves);
+// lanes the row mask leaves out add 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROW_MASK, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the wave's 64 lanes, the same in every lane, in a fixed order:
+// quads, half-rows and rows by DPP (quad_perm, row_half_mirror, row_mirror),
+// then rows 0+1 and 2+3 (row_bcast:15), then all (row_bcast:31) into lane
+// 63, read back as a uniform value.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v = dpp_add<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);   // row_mirror
+  v = dpp_add<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Block sums: every wave folds its lanes (fixed butterfly order) into
@@ -295,16 +317,29 @@ __global__ __launch_bounds__(kVecThreads) void k_start_cycle(const double* __res
   st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
 }
 
-// Least squares: back substitution with the rotated Hessenberg matrix.
-__global__ void k_solve_y(GmState* __restrict__ st) {
-  if (threadIdx.x != 0) return;
+// Least squares: back substitution with the rotated Hessenberg matrix, by
+// one wave: the triangle and g are staged in LDS by all lanes, then row i's
+// sum over l > i is spread over the lanes and added in a fixed order.
+__global__ __launch_bounds__(64) void k_solve_y(GmState* __restrict__ st) {
+  __shared__ double Hs[kMaxRestart * kMaxRestart];   // Hs[l * k + i] = H(i, l), i <= l
+  __shared__ double ys[kMaxRestart + 1];
+  const int lane = threadIdx.x;
   const int ld = kMaxRestart + 1;
   const int k = st->k;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = st->g[i];
-    for (int l = i + 1; l < k; ++l) s -= st->H[(int64_t)l * ld + i] * st->y[l];
-    st->y[i] = s / st->H[(int64_t)i * ld + i];
+  for (int e = lane; e < k * k; e += 64) {
+    const int l = e / k, i = e % k;
+    Hs[e] = i <= l ? st->H[(int64_t)l * ld + i] : 0.0;
   }
+  for (int i = lane; i < k; i += 64) ys[i] = st->g[i];
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    double part = 0.0;
+    for (int l = i + 1 + lane; l < k; l += 64) part = fma(Hs[l * k + i], ys[l], part);
+    part = wave_sum(part);
+    if (lane == 0) ys[i] = (ys[i] - part) / Hs[i * k + i];
+    __syncthreads();
+  }
+  for (int i = lane; i < k; i += 64) st->y[i] = ys[i];
 }
 
 // x <- x + V y  (k columns, k read from the state)
@@ -414,7 +449,7 @@ void gm_step(void* V, int64_t ldv, void* w, bool f32, int64_t n, int j, double* 
 // x += V y after the cycle.
 void gm_finish(const void* V, int64_t ldv, bool f32, double* x, int64_t n, void* state, hipStream_t s) {
   GmState* st = static_cast<GmState*>(state);
-  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, s, st);
+  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, s, st);  // one wave
   if (f32)
     hipLaunchKernelGGL(k_update_x<float>, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, static_cast<const float*>(V),
                        ldv, st, x, n);
