@@ -190,20 +190,18 @@ __global__ __launch_bounds__(kVecThreads) void k_update_norm(const T* __restrict
 }
 
 // Sum of the block partials of one column by a whole block: thread t adds
-// partials t, t+256, ... in order, then a fixed tree adds the 256 sums, so
-// the result does not depend on scheduling.  Every thread gets the sum.
+// partials t, t+256, ... in order, each wave adds its lanes (wave_sum), and
+// the four wave sums are added in order, so the result does not depend on
+// scheduling.  Every thread gets the sum.
 __device__ double block_fold(const double* __restrict__ partial, int nb, int col) {
-  __shared__ double s[kVecThreads];
+  __shared__ double s[kVecThreads / 64];
   const int t = threadIdx.x;
   double acc = 0.0;
   for (int b = t; b < nb; b += kVecThreads) acc += partial[(int64_t)b * (kMaxRestart + 1) + col];
-  s[t] = acc;
+  acc = wave_sum(acc);
+  if ((t & 63) == 0) s[t >> 6] = acc;
   __syncthreads();
-  for (int w = kVecThreads / 2; w > 0; w >>= 1) {
-    if (t < w) s[t] += s[t + w];
-    __syncthreads();
-  }
-  const double r = s[0];
+  const double r = ((s[0] + s[1]) + s[2]) + s[3];
   __syncthreads();
   return r;
 }
