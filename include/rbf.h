@@ -272,16 +272,19 @@ int rbf_count_grid_pairs(rbf_ctx* ctx, const rbf_grid* grid, int64_t* useful,
                          int64_t* examined, void* stream);
 
 /* Kernel timing for measurement tools (process-wide, off by default).
- * Between rbf_profile_begin() and rbf_profile_end() every pair-sum kernel
- * launch is bracketed by HIP events on the stream it runs on;
- * rbf_profile_end() waits for them and reports, per launch kind (operator
- * = rbf_matvec and the solves, evaluation = grid and point evaluation) and
- * precision, the launches, their summed device time and the pairs they
- * evaluated.  Not thread-safe; adds two event records per launch. */
+ * Between rbf_profile_begin() and rbf_profile_end() pair-sum kernel launches
+ * carry HIP start/stop events in their dispatch on the stream they run on:
+ * every launch, except float32 operator launches, of which one in three is
+ * timed (the first, fourth, ...).  rbf_profile_end() waits for them and
+ * reports, per launch kind (operator = rbf_matvec and the solves,
+ * evaluation = grid and point evaluation) and precision, the timed launches,
+ * their summed device time and the pairs they evaluated.  Not thread-safe. */
 typedef struct {
-    int64_t launches[2][2];        /* [kind: 0 operator, 1 evaluation][RBF_FP32 / RBF_FP64] */
+    int64_t launches[2][2];        /* timed launches [kind: 0 operator, 1 evaluation][RBF_FP32 / RBF_FP64] */
     double kernel_ms[2][2];        /* summed event-to-event time of those launches */
-    int64_t useful_pairs[2][2];    /* pairs with r^2 <= cutoff^2 they evaluated */
+    int64_t useful_pairs[2][2];    /* pairs with r^2 <= cutoff^2 they evaluated (float32 grids
+                                      with a cutoff, summed without lists, count none:
+                                      rbf_count_grid_pairs gives their pairs) */
     int64_t examined_pairs[2][2];  /* pairs they computed (list entries x 16) */
 } rbf_profile;
 

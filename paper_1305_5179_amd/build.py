@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librbf.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "alloc.hip", "setup.hip", "pairsum.hip", "gridsum.hip", "krylov.hip", "density.hip", "schwarz.hip",
+SOURCES = ["api.hip", "alloc.hip", "setup.hip", "pairsum.hip", "profile.hip", "gridsum.hip", "krylov.hip", "density.hip", "schwarz.hip",
            "mlp.hip"]
 
 # -ffp-contract=off: no implicit FMA contraction, so float64 expressions that

@@ -525,24 +525,12 @@ int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out,
       // float32 with a cutoff: the bricks walk their candidate sources directly
       int64_t* ids = nullptr;
       const int64_t nact = support_bricks(*c, *grid, &ids, s);
-      const bool prof = profiling();
-      int64_t* use = prof ? talloc<int64_t>(nact) : nullptr;
-      int64_t* exam = prof ? talloc<int64_t>(nact) : nullptr;
+      // (timed like the pair kernels; it counts no pairs: the counts of a
+      // grid come from rbf_count_grid_pairs)
       ProfScope ps(RBF_FP32, 1, 0, 0, s);
-      brick_sum_f32(*c, *grid, ids, nact, c->vin, static_cast<float*>(out), use, exam, s);
+      brick_sum_f32(*c, *grid, ids, nact, c->vin, static_cast<float*>(out), nullptr, nullptr, s, ps.start(),
+                    ps.stop());
       ps.done();
-      if (prof) {
-        int64_t* tot = talloc<int64_t>(2);
-        sum_i64(use, nact, tot, s);
-        sum_i64(exam, nact, tot + 1, s);
-        int64_t h[2] = {0, 0};
-        RBF_HIP(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
-        RBF_HIP(hipStreamSynchronize(s));
-        ps.set_pairs(h[0], h[1]);
-        temp_free(tot);
-        temp_free(use);
-        temp_free(exam);
-      }
       RBF_HIP(hipStreamSynchronize(s));
       temp_free(ids);
       return RBF_OK;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the librbf sources (gfx950, wave64).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -301,18 +302,22 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
 // per-brick pair counts.
 bool brick_sum_applies(const Ctx& c, const rbf_grid& g);
 void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
-                   float* out, int64_t* useful, int64_t* examined, hipStream_t s);
+                   float* out, int64_t* useful, int64_t* examined, hipStream_t s, hipEvent_t t0 = nullptr,
+                   hipEvent_t t1 = nullptr);   // t0, t1: start/stop events the launch carries (optional)
 
 // density.hip
 void density_measures(const double* P, int64_t n, const double* samples, int64_t ns, double* q, double* hmax,
                       double* hfill, hipStream_t s);
 
 // Launch timing (rbf_profile_begin / rbf_profile_end): while profiling is
-// on, a ProfScope brackets one launch with events on its stream (construct
-// before the launch, done() after it).  Pair counts known only later (read
-// back from the device) are given by set_pairs before rbf_profile_end.
+// on, a ProfScope holds the start and stop events one launch carries
+// (hipExtLaunchKernelGGL with start() and stop(), both null when profiling
+// is off); done() after the launch.  Pair counts known only later (read back
+// from the device) are given by set_pairs before rbf_profile_end.
 struct ProfScope {
   ProfScope(int prec, int kind, int64_t useful, int64_t examined, hipStream_t s);
+  hipEvent_t start() const;
+  hipEvent_t stop() const;
   void done();
   void set_pairs(int64_t useful, int64_t examined);
   bool on;

@@ -261,7 +261,7 @@ bool brick_sum_applies(const Ctx& c, const rbf_grid& g) {
 }
 
 void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
-                   float* out, int64_t* useful, int64_t* examined, hipStream_t s) {
+                   float* out, int64_t* useful, int64_t* examined, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   if (nact <= 0) return;
   BrickArgs a;
   a.gd = grid_desc(g);
@@ -282,9 +282,9 @@ void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t 
   a.examined = examined;
   const int64_t nb = ceil_div(nact, kBrickWaves);
   if (useful && examined)
-    hipLaunchKernelGGL(k_brick_sum_f32<true>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, a);
+    hipExtLaunchKernelGGL(k_brick_sum_f32<true>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, t0, t1, 0, a);
   else
-    hipLaunchKernelGGL(k_brick_sum_f32<false>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, a);
+    hipExtLaunchKernelGGL(k_brick_sum_f32<false>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, t0, t1, 0, a);
   RBF_HIP(hipGetLastError());
 }
 

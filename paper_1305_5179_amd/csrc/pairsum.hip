@@ -554,89 +554,6 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
 
 }  // namespace
 
-// Launch timing (rbf_profile_begin / rbf_profile_end).
-namespace {
-struct ProfRec {
-  hipEvent_t a, b;
-  int kind, prec;
-  int64_t useful, examined;
-  bool ended;   // the end event was recorded
-};
-struct Profiler {
-  bool on = false;
-  std::vector<ProfRec> recs;
-};
-Profiler& profiler() {
-  static Profiler p;
-  return p;
-}
-}  // namespace
-
-ProfScope::ProfScope(int prec, int kind, int64_t useful, int64_t examined, hipStream_t st)
-    : on(profiler().on), s(st) {
-  if (!on) return;
-  ProfRec r{};
-  r.prec = prec;
-  r.kind = kind;
-  r.useful = useful;
-  r.examined = examined;
-  RBF_HIP(hipEventCreate(&r.a));
-  RBF_HIP(hipEventCreate(&r.b));
-  RBF_HIP(hipEventRecord(r.a, s));
-  profiler().recs.push_back(r);
-  rec = (int)profiler().recs.size() - 1;
-}
-
-void ProfScope::done() {
-  if (!on || rec < 0) return;
-  RBF_HIP(hipEventRecord(profiler().recs[rec].b, s));
-  profiler().recs[rec].ended = true;
-}
-
-void ProfScope::set_pairs(int64_t useful, int64_t examined) {
-  if (!on || rec < 0 || rec >= (int)profiler().recs.size()) return;
-  profiler().recs[rec].useful = useful;
-  profiler().recs[rec].examined = examined;
-}
-
-bool profiling() { return profiler().on; }
-
-int profile_begin() {
-  Profiler& p = profiler();
-  for (auto& r : p.recs) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
-  }
-  p.recs.clear();
-  p.on = true;
-  return RBF_OK;
-}
-
-int profile_end(rbf_profile* out) {
-  Profiler& p = profiler();
-  p.on = false;
-  rbf_profile r{};
-  for (auto& q : p.recs) {
-    if (!q.ended) {   // a launch that failed
-      (void)hipEventDestroy(q.a);
-      (void)hipEventDestroy(q.b);
-      continue;
-    }
-    RBF_HIP(hipEventSynchronize(q.b));
-    float ms = 0.f;
-    RBF_HIP(hipEventElapsedTime(&ms, q.a, q.b));
-    r.launches[q.kind][q.prec] += 1;
-    r.kernel_ms[q.kind][q.prec] += ms;
-    r.useful_pairs[q.kind][q.prec] += q.useful;
-    r.examined_pairs[q.kind][q.prec] += q.examined;
-    (void)hipEventDestroy(q.a);
-    (void)hipEventDestroy(q.b);
-  }
-  p.recs.clear();
-  if (out) *out = r;
-  return RBF_OK;
-}
-
 void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
                  const int* skip, const float* w32) {
   if (ts.n_groups == 0) return;
@@ -645,9 +562,11 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
   ProfScope prof(RBF_FP32, ts.kind, ts.useful, ts.list_entries * kGroup, s);
   if (w32)
-    hipLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+    hipExtLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
+                          prof.stop(), 0, a);
   else
-    hipLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+    hipExtLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
+                          prof.stop(), 0, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }
@@ -658,7 +577,7 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
   ProfScope prof(RBF_FP64, ts.kind, ts.useful, ts.list_entries * kGroup, s);
-  hipLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  hipExtLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, prof.start(), prof.stop(), 0, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }
