@@ -144,7 +144,9 @@ int rbf_centres(rbf_ctx* ctx, double* centres, double* values, void* stream);
 
 /* y = A x (Sec. II.B eq. RBFsys), matrix-free.  x, y: device, 3n float64.
  * RBF_FP32 evaluates the pair sums in float32 (cutoff still decided as in
- * float64); RBF_FP64 entirely in float64.  x and y may not overlap. */
+ * float64); RBF_FP64 entirely in float64.  x and y may not overlap.
+ * (Inside rbf_solve's refinement mode the inner GMRES keeps its Krylov
+ * basis in float32; its products and updates are formed in float64.) */
 int rbf_matvec(rbf_ctx* ctx, const double* x, double* y, int prec, void* stream);
 
 /* Weights c with A c = b (Sec. III.A: GMRES on the interpolation system).
@@ -162,7 +164,10 @@ int rbf_solve(rbf_ctx* ctx, const double* b, const double* x0, double* c,
 /* f on a regular grid (Sec. II.A.3; Sec. II.B eq. matxvet).
  *   c: device 3n float64 weights.  out: device, dims[0]*dims[1]*dims[2]
  *   values, float32 when prec == RBF_FP32, float64 when RBF_FP64.
- * Nodes farther than cutoff from every centre get exactly 0. */
+ * Nodes farther than cutoff from every centre get exactly 0.  With a
+ * cutoff, float32 grids whose spacing is fine against sigma are summed
+ * brick by brick from the neighbour cells without source lists (same
+ * truncation, decided in float64); other grids go through lists. */
 int rbf_eval_grid(rbf_ctx* ctx, const double* c, const rbf_grid* grid, void* out,
                   int prec, void* stream);
 
