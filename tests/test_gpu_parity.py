@@ -211,6 +211,38 @@ def test_grid_brick_sums_match_oracle(name, torch, R):
     assert np.array_equal(out, again)
 
 
+def test_grid_brick_sums_edge_cases(torch, R):
+    """List-free brick sums on degenerate grids: a zero spacing on one axis
+    (every node of a row at the same place), a single node, and a grid out
+    of reach of every centre (all exact zeros)."""
+    make, eps, sigma, cutoff = CASES["torus_patch_cut"]
+    c = make()
+    X, _ = o.extended_centres(c.points, c.normals, eps)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, cutoff)
+    try:
+        coef = np.random.default_rng(24).uniform(-2, 2, X.shape[0])
+        cen = X.mean(axis=0)
+        grids = [
+            w.Grid(tuple(float(v) for v in cen - 0.05), (0.5 * sigma, 0.0, 0.5 * sigma), (21, 5, 19)),
+            w.Grid(tuple(float(v) for v in X[7]), (0.5 * sigma,) * 3, (1, 1, 1)),
+            w.Grid(tuple(float(v) for v in X.max(axis=0) + 2 * cutoff), (0.5 * sigma,) * 3, (9, 7, 5)),
+        ]
+        for g in grids:
+            assert _brick_form(sigma, cutoff, g.h)
+            out = host(ctx.eval_grid(dev(torch, coef), g.origin, g.h, g.dims, prec=0))
+            nodes = o.grid_nodes(g.origin, g.h, g.dims)
+            ref = o.evaluate(X, coef, nodes, sigma, cutoff)
+            scale = abs_sums(X, coef, range(nodes.shape[0]), sigma, cutoff, targets=nodes)
+            bound = tol32(sigma, cutoff) * scale + U32 * np.abs(ref) + 1e-300
+            _say(f"[brick edge] dims {g.dims} h {g.h}: band {int((scale > 0).sum())}, "
+                 f"max err/bound {np.max(np.abs(out - ref) / bound):.3f}")
+            assert np.all(np.abs(out - ref) <= bound)
+            assert np.all(out[scale == 0] == 0.0)
+        assert np.count_nonzero(out) == 0   # the last grid is out of reach
+    finally:
+        ctx.close()
+
+
 def test_cutoff_decision_is_the_float64_one(torch, R):
     """Pairs within a few ulps of the cutoff: the float32 kernel must take the
     float64 decision (inclusive) on both sides of it."""
