@@ -5,8 +5,8 @@
 //   pass 2  w <- w - V h1,  h2 = V^T w       (one sweep: update, then dots)
 //   pass 3  w <- w - V h2,  |w|^2            (classical Gram-Schmidt applied
 //                                             twice, "twice is enough")
-//   finish  H(:,j) = h1 + h2, H(j+1,j) = |w|, Givens rotations, |g_{j+1}|
-//   scale   v_{j+1} = w / |w|
+//   finish  H(:,j) = h1 + h2, H(j+1,j) = |w|, Givens rotations, |g_{j+1}|,
+//           and v_{j+1} = w / |w| (one launch)
 // Every kernel of a step first reads the device flag `done`, set when the
 // residual estimate |g_{j+1}| reaches the tolerance (or on breakdown), so the
 // host can enqueue a whole cycle without waiting on it.
@@ -70,7 +70,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block sums: every wave folds its lanes (fixed butterfly order) into
-// s[wave][i]; thread i then adds the four waves in order.
+// s[wave][i]; thread i then adds the four waves in order.  The partials are
+// stored column by column (partial[i * nb + b] for block b of nb), so that
+// the fold of one column reads contiguous memory.
 __device__ __forceinline__ void wave_partial(double v, int i, double (*s)[kMaxRestart + 1]) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6][i] = v;
@@ -78,7 +80,7 @@ __device__ __forceinline__ void wave_partial(double v, int i, double (*s)[kMaxRe
 __device__ __forceinline__ void block_store(double (*s)[kMaxRestart + 1], int ncols, double* partial) {
   __syncthreads();
   for (int i = threadIdx.x; i < ncols; i += kVecThreads)
-    partial[(int64_t)blockIdx.x * (kMaxRestart + 1) + i] = ((s[0][i] + s[1][i]) + s[2][i]) + s[3][i];
+    partial[(int64_t)i * gridDim.x + blockIdx.x] = ((s[0][i] + s[1][i]) + s[2][i]) + s[3][i];
 }
 
 // Dot products of the block's rows of x with columns 0..ncols-1 of V, into
@@ -255,7 +257,8 @@ __device__ double block_fold(const double* __restrict__ partial, int nb, int col
   __shared__ double s[kVecThreads / 64];
   const int t = threadIdx.x;
   double acc = 0.0;
-  for (int b = t; b < nb; b += kVecThreads) acc += partial[(int64_t)b * (kMaxRestart + 1) + col];
+  const double* p = partial + (int64_t)col * nb;
+  for (int b = t; b < nb; b += kVecThreads) acc += p[b];
   acc = wave_sum(acc);
   if ((t & 63) == 0) s[t >> 6] = acc;
   __syncthreads();
@@ -279,11 +282,9 @@ __global__ __launch_bounds__(kVecThreads) void k_reduce_h2(const double* __restr
 }
 
 // Column j of the Hessenberg matrix, its Givens rotations and the residual
-// estimate |g_{j+1}|: the column and the rotations are staged in LDS by the
-// whole block, the rotation chain runs on one thread from there.
-__global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __restrict__ partial, int nb, int j,
-                                                             GmState* __restrict__ st) {
-  if (st->done) return;
+// estimate |g_{j+1}| from beta = |w|: the column and the rotations are staged
+// in LDS by the whole block, the rotation chain runs on one thread from there.
+__device__ void finish_step(double beta, int j, GmState* __restrict__ st) {
   __shared__ double hc[kMaxRestart + 2], cs[kMaxRestart], sn[kMaxRestart];
   const int t = threadIdx.x;
   for (int i = t; i <= j; i += kVecThreads) hc[i] = st->h1[i] + st->h2[i];
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __res
     cs[i] = st->cs[i];
     sn[i] = st->sn[i];
   }
-  const double beta = sqrt(block_fold(partial, nb, 0));   // (synchronises the block)
+  __syncthreads();
   if (t == 0) {
     hc[j + 1] = beta;
     for (int i = 0; i < j; ++i) {
@@ -327,6 +328,28 @@ __global__ __launch_bounds__(kVecThreads) void k_finish_step(const double* __res
   __syncthreads();
   double* Hc = st->H + (int64_t)j * (kMaxRestart + 1);
   for (int i = t; i <= j + 1; i += kVecThreads) Hc[i] = hc[i];
+}
+
+// End of step j: v_{j+1} = w / |w|, with the step's bookkeeping.  Every
+// block folds the norm partials itself (in the same fixed order, so all get
+// the same |w| to the bit); block 0 also runs finish_step.  A block that
+// already sees the stop flag block 0 may set skips the scaling: the column
+// past the last step of a cycle is never read.
+constexpr int kScaleRows = 4;   // elements per thread
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_finish_scale(const double* __restrict__ partial, int nb, int j,
+                                                              GmState* __restrict__ st, const T* __restrict__ w,
+                                                              int64_t n, T* __restrict__ out) {
+  if (st->done) return;
+  const double beta = sqrt(block_fold(partial, nb, 0));
+  if (blockIdx.x == 0) finish_step(beta, j, st);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t base = (int64_t)blockIdx.x * (kVecThreads * kScaleRows) + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kScaleRows; ++q) {
+    const int64_t i = base + (int64_t)q * kVecThreads;
+    if (i < n) out[i] = (T)((double)w[i] * inv);
+  }
 }
 
 // v_{j+1} = w / |w|
@@ -498,8 +521,8 @@ static void gm_step_t(T* V, int64_t ldv, T* w, int64_t n, int j, double* partial
   }
   hipLaunchKernelGGL(k_reduce_h2, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
   hipLaunchKernelGGL(k_update_norm<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
-  hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, j, st);
-  hipLaunchKernelGGL((k_scale<T, T>), dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, w, n, st,
+  const unsigned sb = (unsigned)std::max<int64_t>(1, ceil_div(n, (int64_t)kVecThreads * kScaleRows));
+  hipLaunchKernelGGL(k_finish_scale<T>, dim3(sb), dim3(kVecThreads), 0, s, partial, (int)nb, j, st, w, n,
                      V + (int64_t)(j + 1) * ldv);
   RBF_HIP(hipGetLastError());
 }
