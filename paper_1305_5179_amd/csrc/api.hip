@@ -22,6 +22,7 @@ void gm_step(void* V, int64_t ldv, void* w, bool f32, int64_t n, int j, double* 
 void gm_finish(const void* V, int64_t ldv, bool f32, double* x, int64_t n, void* state, hipStream_t s);
 void to_f64(const float* x, double* y, int64_t n, hipStream_t s);
 void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s);
+void gm_set_tol(void* state, double tol_abs, hipStream_t s);
 const int* gm_done_flag(const void* state);
 
 namespace {
@@ -230,26 +231,27 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     c->rc2 = std::isfinite(cutoff) ? cutoff * cutoff : INFINITY;
     c->sqrt_k = std::sqrt(1.4426950408889634 / (2.0 * sigma * sigma));
     c->inv_two_s2 = 1.0 / (2.0 * sigma * sigma);
-    // 1. inputs
+    // 1. inputs (the flags are read back with the bounding box, one wait
+    // for both; the two kernels in between only combine values elementwise,
+    // so bad inputs make bad values there and nothing else)
     int* flags = talloc<int>(2);
     RBF_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
     check_inputs(points, normals, n, flags, s);
-    int hf[2] = {0, 0};
-    RBF_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipStreamSynchronize(s));
-    temp_free(flags);
-    if (hf[0]) return fail(c, RBF_EINVAL, "points or normals contain NaN or Inf");
-    if (hf[1]) return fail(c, RBF_EINVAL, "a normal is shorter than 1e-12");
     // 2. extended set (paper order)
     c->xpaper = dalloc<double>(3 * c->m);
     build_centres(points, normals, n, off_surface_eps, c->xpaper, s);
     // 3. lattice from the bounding box
     double* box = talloc<double>(6 + 6 * 1024);
     bounding_box(c->xpaper, c->m, box, box + 6, s);
+    int hf[2] = {0, 0};
     double hb[6];
+    RBF_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
+    temp_free(flags);
     temp_free(box);
+    if (hf[0]) return fail(c, RBF_EINVAL, "points or normals contain NaN or Inf");
+    if (hf[1]) return fail(c, RBF_EINVAL, "a normal is shorter than 1e-12");
     c->lat = make_lattice(hb, cutoff);
     if (std::isfinite(cutoff)) {
       const double cells = (double)c->lat.cdims[0] * c->lat.cdims[1] * c->lat.cdims[2];
@@ -396,16 +398,28 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
       stamp(0.0);
       status = RBF_OK;
     } else {
+      // without a starting guess the cycle started above (r = b) is the
+      // first one: it only needs its stopping tolerance
+      bool first_started = !have_x;
+      if (first_started) gm_set_tol(c->state, o.tol * bnorm, s);
+      bool residual_queued = false;
       for (;;) {
-        // true residual with the float64 operator
-        const double* y = nullptr;
-        if (have_x) {
-          apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
-          y = c->vout;
-        }
-        gm_start(c->bsort, y, c->r, m, c->V, f32, c->partial, o.restart, o.tol * bnorm, c->state, s);
         double beta;
-        gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
+        if (first_started) {
+          beta = bnorm;
+          first_started = false;
+        } else {
+          // true residual with the float64 operator (queued already when a
+          // cycle has just ended)
+          const double* y = nullptr;
+          if (have_x) {
+            if (!residual_queued) apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
+            y = c->vout;
+          }
+          residual_queued = false;
+          gm_start(c->bsort, y, c->r, m, c->V, f32, c->partial, o.restart, o.tol * bnorm, c->state, s);
+          gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
+        }
         rel = beta / bnorm;
         stamp(rel);
         if (!std::isfinite(rel)) {
@@ -454,6 +468,10 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         } else {
           gm_finish(c->V, ldv, f32, c->csol, m, c->state, s);
         }
+        // the next true residual goes into the queue before the host waits
+        // for the cycle's state, so that the device is not idle meanwhile
+        apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
+        residual_queued = true;
         gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
         iters += k;
         ++outer;
@@ -461,7 +479,6 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         if (bd) {
           status = RBF_EBREAKDOWN;
           // the true residual of the current iterate is still reported
-          apply_sorted(c, c->csol, c->vout, RBF_FP64, s);
           gm_start(c->bsort, c->vout, c->r, m, c->V, f32, c->partial, o.restart, 0.0, c->state, s);
           gm_read(c->state, &k, &done, &bd, &beta, &gk, s);
           rel = beta / bnorm;

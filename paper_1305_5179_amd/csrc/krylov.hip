@@ -421,6 +421,10 @@ __global__ __launch_bounds__(64) void k_solve_y(GmState* __restrict__ st) {
   for (int i = lane; i < k; i += 64) st->y[i] = ys[i];
 }
 
+__global__ void k_set_tol(GmState* __restrict__ st, double tol_abs) {
+  if (threadIdx.x == 0) st->tol_abs = tol_abs;
+}
+
 // x <- x + V y  (k columns, k read from the state)
 template <class T>
 __global__ __launch_bounds__(kVecThreads) void k_update_x(const T* __restrict__ V, int64_t ldv,
@@ -551,6 +555,12 @@ void gm_finish(const void* V, int64_t ldv, bool f32, double* x, int64_t n, void*
 // float32 -> float64 copy (a basis vector handed to the preconditioner)
 void to_f64(const float* x, double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_to_f64, dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, x, y, n);
+  RBF_HIP(hipGetLastError());
+}
+
+// Sets the stopping tolerance of the cycle gm_start began (stream-ordered).
+void gm_set_tol(void* state, double tol_abs, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, s, static_cast<GmState*>(state), tol_abs);
   RBF_HIP(hipGetLastError());
 }
 
