@@ -13,6 +13,25 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
+// Inclusive prefix sum over the wave's 64 lanes by DPP moves: shifts by 1,
+// 2, 4 and 8 lanes within each 16-lane row (a lane shifted in from outside
+// the row adds 0) give the row scans; then the last lane of rows 0 and 2 is
+// added to rows 1 and 3 (row_bcast:15), and lane 31 to rows 2 and 3
+// (row_bcast:31).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_or_zero(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+  v += dpp_or_zero<0x111, 0xf>(v);   // row_shr:1
+  v += dpp_or_zero<0x112, 0xf>(v);   // row_shr:2
+  v += dpp_or_zero<0x114, 0xf>(v);   // row_shr:4
+  v += dpp_or_zero<0x118, 0xf>(v);   // row_shr:8
+  v += dpp_or_zero<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_or_zero<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Orders the LDS accesses of one wave around this point (the wave's lanes
 // exchange data through LDS; no other wave takes part).
 __device__ __forceinline__ void wave_sync_lds() {
@@ -122,14 +141,9 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
     const bool occ = ct > 0;   // (empty cells would break the search below)
     const uint64_t sel = ballot(occ);
     const int nocc = __popcll(sel);
-    int32_t incl = ct;
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int32_t y = __shfl_up(incl, off);
-      if (lane >= off) incl += y;
-    }
-    // (read-first-lane: the compiler cannot see that the shuffle is uniform,
-    // and a divergent trip count would make the whole walk divergent)
-    const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1));
+    const int32_t incl = wave_incl_scan(ct);
+    // (read-lane: a uniform value, so the trip count below is uniform too)
+    const int32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
     cand += total;
     if (CELLS_ONLY) continue;
     wave_sync_lds();
