@@ -32,6 +32,21 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
   return v;
 }
 
+// Bitwise OR over the wave's 64 lanes, the same in every lane: quads,
+// half-rows and rows by DPP (quad_perm, row_half_mirror, row_mirror), then
+// rows 0+1 and 2+3 (row_bcast:15) and all four (row_bcast:31) into lane 63,
+// read back as a uniform value.
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+  const int32_t x = (int32_t)v;
+  int32_t y = x | dpp_or_zero<0xB1, 0xf>(x);    // quad_perm [1,0,3,2]
+  y |= dpp_or_zero<0x4E, 0xf>(y);               // quad_perm [2,3,0,1]
+  y |= dpp_or_zero<0x141, 0xf>(y);              // row_half_mirror
+  y |= dpp_or_zero<0x140, 0xf>(y);              // row_mirror
+  y |= dpp_or_zero<0x142, 0xa>(y);              // row_bcast:15 into rows 1 and 3
+  y |= dpp_or_zero<0x143, 0xc>(y);              // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane(y, 63);
+}
+
 // Orders the LDS accesses of one wave around this point (the wave's lanes
 // exchange data through LDS; no other wave takes part).
 __device__ __forceinline__ void wave_sync_lds() {
@@ -81,8 +96,10 @@ __device__ __forceinline__ int div_small(int n, int d, float inv_d) {
 // occupied coarse cells of the cube [cl, cl + cn) whose box comes within
 // r_out of the anchor.  The cells are examined one per lane, 64 at a time;
 // the sources of the cells that remain are then taken 64 at a time across
-// cell boundaries (a lane finds its cell by a binary search of the count
-// prefix in LDS: cpre, cst and cwhole hold 64 entries of the calling wave).
+// cell boundaries (cpre, cst and cwhole in LDS hold the start, first source
+// and whole-cell flag of the occupied cells, 64 entries of the calling wave;
+// a lane finds its cell from a count of the cells that start before the
+// round and a mask of those that start within it).
 // visit(valid, k, is_in, is_shell) runs once per round of 64 candidates, in
 // the same order on every call: k is this lane's sorted source (when valid),
 // is_in marks a source within r_in of the anchor (a whole cell within r_in
@@ -154,14 +171,21 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
       cwhole[pos] = whole ? 1 : 0;
     }
     wave_sync_lds();
+    const int32_t start = incl - ct;   // of this lane's cell, when occupied
+    const uint64_t below_lane = lane == kWave - 1 ? ~0ull : (2ull << lane) - 1;
     for (int32_t b0 = 0; b0 < total; b0 += kWave) {
       const int32_t f = b0 + lane;
       const bool valid = f < total;
-      // the cell of flattened source f: the last j with cpre[j] <= f
-      int j = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1)
-        if (j + step < nocc && cpre[j + step] <= f) j += step;
+      // the cell of flattened source f is the last occupied cell that starts
+      // at or before f (the starts rise with the compacted index): its index
+      // is the number of cells starting before b0, plus those starting in
+      // [b0, f], minus one
+      const int32_t r = start - b0;
+      const int before = __popcll(ballot(occ && r < 0));
+      const uint32_t lo = wave_or(occ && r >= 0 && r < 32 ? 1u << r : 0u);
+      const uint32_t hi = wave_or(occ && r >= 32 && r < 64 ? 1u << (r - 32) : 0u);
+      const uint64_t starts = ((uint64_t)hi << 32) | lo;
+      const int j = min(max(before + __popcll(starts & below_lane) - 1, 0), nocc - 1);
       const uint32_t k = (uint32_t)(cst[j] + (f - cpre[j]));
       bool is_in = false, is_shell = false;
       if (valid) {
