@@ -266,8 +266,11 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     c->xk = dalloc<double4>(c->m + 1);
     gather_sorted(c->xpaper, c->perm, c->m, c->sqrt_k, c->xs, c->xk, s);
     // 5. coarse cells
+    int64_t* ncell_parts = pinned_slots();
+    ncell_parts[0] = ncell_parts[1] = 0;
     if (std::isfinite(cutoff)) {
-      c->n_cells = build_cells(c->keys, c->xs, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz, s);
+      build_cells(c->keys, c->xs, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz,
+                  ncell_parts, s);
       c->cell_sat = build_cell_sat(*c, s);
     }
     // 6. the centres as targets, with their source lists
@@ -281,6 +284,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     RBF_HIP(hipMemsetAsync(c->vin, 0, sizeof(double) * c->mpad, s));
     RBF_HIP(hipMemsetAsync(c->vout, 0, sizeof(double) * c->mpad, s));
     RBF_HIP(hipStreamSynchronize(s));
+    c->n_cells = ncell_parts[0] + ncell_parts[1];
     return RBF_OK;
   });
   if (st != RBF_OK) {

@@ -275,8 +275,12 @@ void sort_points(const double* pts3, int64_t m, const Lattice& lat, uint32_t* pe
                  hipStream_t s);
 void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double sqrt_k, double4* xs,
                    double4* xk, hipStream_t s);
-int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
-                    int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s);
+// The occupied cells' arrays (sized by the bound m); their count arrives
+// in ncell_parts[0] + ncell_parts[1] (pinned host memory) once the stream
+// has been synchronised.
+void build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
+                 int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, int64_t* ncell_parts, hipStream_t s);
+int64_t* pinned_slots();
 void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
 constexpr int64_t kCellSatMax = int64_t(1) << 26;   // entries of the summed cell counts (512 MB)
 int64_t* build_cell_sat(const Ctx& c, hipStream_t s);

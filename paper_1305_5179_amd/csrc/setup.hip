@@ -1056,31 +1056,38 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
   RBF_HIP(hipGetLastError());
 }
 
-int64_t build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
-                    int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, hipStream_t s) {
+// Pinned host slots of the calling thread for values read back without a
+// wait of their own: the copy is queued, and the value is there once the
+// stream has been synchronised.
+int64_t* pinned_slots() {
+  static thread_local int64_t* p = nullptr;
+  if (!p) RBF_HIP(hipHostMalloc((void**)&p, 8 * sizeof(int64_t), hipHostMallocDefault));
+  return p;
+}
+
+void build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
+                 int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, int64_t* ncell_parts, hipStream_t s) {
   const int cshift = 3 * lat.shift;
   int64_t* flag = talloc<int64_t>(m);
   int64_t* cid = talloc<int64_t>(m);
   hipLaunchKernelGGL(k_cell_flags, dim3(grid_for(m)), dim3(kThreads), 0, s, keys, m, cshift, flag);
   RBF_HIP(hipGetLastError());
   scan_exclusive_i64(flag, cid, m, s);
-  int64_t last_cid = 0, last_flag = 0;
-  RBF_HIP(hipMemcpyAsync(&last_cid, cid + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipStreamSynchronize(s));
-  const int64_t ncell = last_cid + last_flag;
+  // the number of occupied cells is cid[m-1] + flag[m-1]: queued into the
+  // caller's pinned slots, not waited for (the arrays take the bound m)
+  RBF_HIP(hipMemcpyAsync(ncell_parts, cid + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(ncell_parts + 1, flag + (m - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   const int64_t nmap = (int64_t)lat.cdims[0] * lat.cdims[1] * lat.cdims[2];
-  *cell_start = dalloc<int32_t>(ncell);
-  *cell_count = dalloc<int32_t>(ncell);
+  *cell_start = dalloc<int32_t>(m);
+  *cell_count = dalloc<int32_t>(m);
   *cell_map = dalloc<int32_t>(nmap);
-  *cell_xyz = dalloc<int32_t>(ncell);
+  *cell_xyz = dalloc<int32_t>(m);
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nmap)), dim3(kThreads), 0, s, *cell_map, -1, nmap);
   hipLaunchKernelGGL(k_cell_fill, dim3(grid_for(m)), dim3(kThreads), 0, s, xs, m, flag, cid, lat,
                      *cell_start, *cell_count, *cell_map, *cell_xyz);
   RBF_HIP(hipGetLastError());
   temp_free(flag);
   temp_free(cid);
-  return ncell;
 }
 
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts,
