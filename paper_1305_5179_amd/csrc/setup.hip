@@ -569,8 +569,10 @@ __global__ void k_list_bound_sat(const double4* __restrict__ tpts, int64_t G, co
 // region at soff[g] of size bound[g]; counts, useful pairs, the valid-target
 // mask and the group record (offset set later by k_list_compact).
 constexpr int kBound = 0, kStage = 1;
+// The centres' classification fits 64 VGPRs, eight waves per SIMD for the
+// walk's latency; the lattice form (grid nodes) keeps its registers.
 template <int MODE, bool LATTICE>
-__global__ __launch_bounds__(kThreads) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
+__global__ __launch_bounds__(kThreads, LATTICE ? 1 : 8) void k_lists(const double4* __restrict__ tpts, int64_t G, GroupInfo* __restrict__ groups,
                                                     const double4* __restrict__ xs,
                                                     const int32_t* __restrict__ cstart, const int32_t* __restrict__ ccount,
                                                     const int32_t* __restrict__ cmap, Lattice lat, double rc, double rc2,
