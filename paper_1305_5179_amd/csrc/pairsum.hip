@@ -511,7 +511,10 @@ __device__ __forceinline__ void direct_group_f64(const PairArgs& a, const GroupI
   if (row == 0 && tp.w != 0.0) store_result(a, tid, acc);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairsum_f64(PairArgs a) {
+// Six waves per SIMD (76 VGPRs, no spills): the LDS broadcasts of the
+// sources wait less with more waves in flight (102 VGPRs and four waves
+// took 6 % longer; seven or eight waves spill).
+__global__ __launch_bounds__(kBlock, 6) void k_pairsum_f64(PairArgs a) {
   __shared__ double4 sh[kBlock / kWave][kWave];
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
