@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kVecThreads) void k_finish_scale(const double* __re
   }
 }
 
-// v_{j+1} = w / |w|
+// v_0 = r / |r| at the start of a cycle
 template <class Tin, class Tout>
 __global__ __launch_bounds__(kVecThreads) void k_scale(const Tin* __restrict__ w, int64_t n,
                                                        const GmState* __restrict__ st, Tout* __restrict__ out) {

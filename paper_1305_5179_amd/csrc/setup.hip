@@ -367,8 +367,8 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
 // and of the exact test), whole cells at a time when the cell box allows.
 // The cells near the anchor are examined one per lane (with their source
 // ranges); the sources of the cells that remain are then classified 64 at a
-// time, one per lane, across cell boundaries (a lane finds its cell by a
-// binary search of the block's count prefix in LDS); the remaining "shell"
+// time, one per lane, across cell boundaries (a lane finds its cell from
+// ballots over the cells' starts, cells.h); the remaining "shell"
 // sources are queued in LDS and tested exactly against the 16 targets, 64
 // at a time (targets in scalar registers).
 // Pass 1 counts, pass 2 writes; both enumerate in the same order, so the
