@@ -700,17 +700,31 @@ __global__ __launch_bounds__(kThreads) void k_list_compact(GroupInfo* __restrict
   const int64_t in_full = inner_chunks(nin) * kChunk;
   const uint32_t vm = vmasks[g];
   if (lane == 0) groups[g].off = base;
-  for (int64_t e = lane; e < len; e += kWave) {
-    uint32_t k = m, bits = 0;
-    if (e < nin) {
-      k = slist[sb + e];
-      bits = vm;
-    } else if (e < nin + nout) {
-      k = slist[top - (e - nin)];
-      bits = smask[top - (e - nin)];
+  // four entries per lane per pass, their loads issued together
+  constexpr int kU = 4;
+  for (int64_t e0 = lane; e0 < len; e0 += kU * kWave) {
+    uint32_t k[kU], bits[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = e0 + (int64_t)u * kWave;
+      k[u] = m;
+      bits[u] = 0;
+      if (e < nin) {
+        k[u] = slist[sb + e];
+        bits[u] = vm;
+      } else if (e < nin + nout) {
+        k[u] = slist[top - (e - nin)];
+        bits[u] = smask[top - (e - nin)];
+      }
     }
-    list[base + e] = k;
-    if (e >= in_full) mask[mask_slot(base, e)] = (uint16_t)bits;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t e = e0 + (int64_t)u * kWave;
+      if (e < len) {
+        list[base + e] = k[u];
+        if (e >= in_full) mask[mask_slot(base, e)] = (uint16_t)bits[u];
+      }
+    }
   }
 }
 
