@@ -160,7 +160,11 @@ void ensure_solver(Ctx* c, int m) {
     RBF_HIP(hipMemsetAsync(c->bsort, 0, sizeof(double) * c->mpad, temp_stream()));
     c->state = dalloc<char>((int64_t)gm_state_bytes());
     RBF_HIP(hipMemsetAsync(c->state, 0, gm_state_bytes(), temp_stream()));
+  } else {
+    RBF_HIP(hipMemsetAsync(c->w, 0, sizeof(double) * c->mpad, temp_stream()));
   }
+  // the basis and w are all zero bits: 0 read as float32 or as float64
+  c->krylov_f32 = -1;
   const int64_t pc = gm_partial_count(c->m);
   if (c->partial_cap < pc) {
     dfree(c->partial);
@@ -373,13 +377,13 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
     // the inner solve of the refinement keeps its Krylov basis (and w) in
     // float32, in the same allocations; the plain method in float64
     const bool f32 = o.mode == RBF_SOLVE_IR_FP32;
-    if (c->krylov_f32 != (int)f32) {
+    if (c->krylov_f32 != (int)f32 && c->krylov_f32 != -1) {
       // the padding entry m of every basis vector is a weight of the operator
       // and must read 0 in the new element type too
       fill_f64(c->V, 0.0, round_up(c->krylov_m + 1, kKrylovColPad) * c->mpad, s);
       fill_f64(c->w, 0.0, c->mpad, s);
-      c->krylov_f32 = (int)f32;
     }
+    c->krylov_f32 = (int)f32;
     gm_start(c->bsort, nullptr, c->r, m, c->V, f32, c->partial, o.restart, 0.0, c->state, s);
     int k, done, bd;
     double bnorm, gk;

@@ -184,7 +184,8 @@ struct Ctx {
   double* vout = nullptr;
   // Solver storage, allocated on first use.
   int krylov_m = 0;
-  int krylov_f32 = -1;          // element type the basis was last used with (1 float32, 0 float64)
+  int krylov_f32 = -1;          // element type the basis was last used with (1 float32, 0 float64;
+                                // -1: all zero since its allocation, either type)
   double* V = nullptr;          // (m+1) basis vectors of length mpad (float64, or float32 in the same space)
   double* w = nullptr;
   double* r = nullptr;
