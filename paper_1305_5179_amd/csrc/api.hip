@@ -361,12 +361,8 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
     if (b) {
       gather_to_sorted(b, c->perm, m, c->bsort, s);
     } else {
-      // values 0 / +eps / -eps in paper order, then sorted
-      fill_f64(c->w, 0.0, c->n, s);
-      fill_f64(c->w + c->n, c->eps, c->n, s);
-      fill_f64(c->w + 2 * c->n, -c->eps, c->n, s);
-      gather_to_sorted(c->w, c->perm, m, c->bsort, s);
-      fill_f64(c->w, 0.0, c->mpad, s);
+      // values 0 / +eps / -eps of the paper order, written in sorted order
+      rhs_sorted(c->perm, m, c->n, c->eps, c->bsort, s);
     }
     bool have_x = x0 != nullptr;
     if (x0)

@@ -355,6 +355,8 @@ void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted
 // krylov.hip
 void vec_add(double* x, const double* y, int64_t n, hipStream_t s);
 void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s);
+// 0 / +eps / -eps of the paper-order centres (n points each), in sorted order
+void rhs_sorted(const uint32_t* perm, int64_t m, int64_t n, double eps, double* dst_sorted, hipStream_t s);
 void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s);
 
 // setup.hip: targets of the evaluation entry points.  Grid nodes go by

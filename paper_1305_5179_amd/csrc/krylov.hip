@@ -454,6 +454,17 @@ __global__ void k_gather(const double* __restrict__ src, const uint32_t* __restr
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k < m) dst[k] = src[perm[k]];
 }
+// The right-hand side of the interpolation system in sorted order: centre
+// perm[k] of the paper order is an on-surface point (value 0) for index < n,
+// an outer off-surface point (+eps) below 2n, an inner one (-eps) above.
+__global__ void k_rhs_sorted(const uint32_t* __restrict__ perm, int64_t m, int64_t n, double eps,
+                             double* __restrict__ dst) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) {
+    const int64_t i = perm[k];
+    dst[k] = i < n ? 0.0 : (i < 2 * n ? eps : -eps);
+  }
+}
 __global__ void k_scatter(const double* __restrict__ src, const uint32_t* __restrict__ perm, int64_t m,
                           double* __restrict__ dst) {
   const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -475,6 +486,10 @@ void vec_add(double* x, const double* y, int64_t n, hipStream_t s) {
 
 void gather_to_sorted(const double* src, const uint32_t* perm, int64_t m, double* dst_sorted, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(elt_blocks(m)), dim3(kVecThreads), 0, s, src, perm, m, dst_sorted);
+  RBF_HIP(hipGetLastError());
+}
+void rhs_sorted(const uint32_t* perm, int64_t m, int64_t n, double eps, double* dst_sorted, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_sorted, dim3(elt_blocks(m)), dim3(kVecThreads), 0, s, perm, m, n, eps, dst_sorted);
   RBF_HIP(hipGetLastError());
 }
 void scatter_from_sorted(const double* src_sorted, const uint32_t* perm, int64_t m, double* dst, hipStream_t s) {
