@@ -352,16 +352,6 @@ __global__ __launch_bounds__(kVecThreads) void k_finish_scale(const double* __re
   }
 }
 
-// v_0 = r / |r| at the start of a cycle
-template <class Tin, class Tout>
-__global__ __launch_bounds__(kVecThreads) void k_scale(const Tin* __restrict__ w, int64_t n,
-                                                       const GmState* __restrict__ st, Tout* __restrict__ out) {
-  if (st->done) return;
-  const double s = st->inv_beta;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (Tout)((double)w[i] * s);
-}
-
 // r = b - y and |r|^2 partials (y may be null: r = b)
 __global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restrict__ b, const double* __restrict__ y,
                                                           double* __restrict__ r, int64_t n,
@@ -381,19 +371,35 @@ __global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restri
   block_store(s, 1, partial);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_start_cycle(const double* __restrict__ partial, int nb, int m,
-                                                             double tol_abs, GmState* __restrict__ st) {
+// Start of a cycle from the residual partials: beta = |r|, the state, and
+// v_0 = r / beta.  Every block folds the partials itself (the same fixed
+// order: the same beta in all of them); block 0 writes the state.  Nothing
+// is scaled when beta is 0 or not finite (the cycle is done at once).
+template <class T>
+__global__ __launch_bounds__(kVecThreads) void k_start_scale(const double* __restrict__ partial, int nb, int m,
+                                                             double tol_abs, GmState* __restrict__ st,
+                                                             const double* __restrict__ r, int64_t n,
+                                                             T* __restrict__ out) {
   const double beta = sqrt(block_fold(partial, nb, 0));
-  if (threadIdx.x != 0) return;
-  st->m = m;
-  st->k = 0;
-  st->tol_abs = tol_abs;
-  st->beta0 = beta;
-  st->g[0] = beta;
-  for (int i = 1; i <= kMaxRestart; ++i) st->g[i] = 0.0;
-  st->breakdown = isfinite(beta) ? 0 : 1;
-  st->done = (beta == 0.0 || !isfinite(beta)) ? 1 : 0;
-  st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->m = m;
+    st->k = 0;
+    st->tol_abs = tol_abs;
+    st->beta0 = beta;
+    st->g[0] = beta;
+    for (int i = 1; i <= kMaxRestart; ++i) st->g[i] = 0.0;
+    st->breakdown = isfinite(beta) ? 0 : 1;
+    st->done = (beta == 0.0 || !isfinite(beta)) ? 1 : 0;
+    st->inv_beta = beta > 0.0 ? 1.0 / beta : 0.0;
+  }
+  if (beta == 0.0 || !isfinite(beta)) return;
+  const double inv = 1.0 / beta;
+  const int64_t base = (int64_t)blockIdx.x * (kVecThreads * kScaleRows) + threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < kScaleRows; ++q) {
+    const int64_t i = base + (int64_t)q * kVecThreads;
+    if (i < n) out[i] = (T)(r[i] * inv);
+  }
 }
 
 // Least squares: back substitution with the rotated Hessenberg matrix, by
@@ -507,8 +513,8 @@ static void gm_start_t(const double* b, const double* y, double* r, int64_t n, T
                        double tol_abs, GmState* st, hipStream_t s) {
   const unsigned nb = vec_blocks(n);
   hipLaunchKernelGGL(k_residual, dim3(nb), dim3(kVecThreads), 0, s, b, y, r, n, partial);
-  hipLaunchKernelGGL(k_start_cycle, dim3(1), dim3(kVecThreads), 0, s, partial, (int)nb, m, tol_abs, st);
-  hipLaunchKernelGGL((k_scale<double, T>), dim3(elt_blocks(n)), dim3(kVecThreads), 0, s, r, n, st, V);
+  const unsigned sb = (unsigned)std::max<int64_t>(1, ceil_div(n, (int64_t)kVecThreads * kScaleRows));
+  hipLaunchKernelGGL(k_start_scale<T>, dim3(sb), dim3(kVecThreads), 0, s, partial, (int)nb, m, tol_abs, st, r, n, V);
   RBF_HIP(hipGetLastError());
 }
 void gm_start(const double* b, const double* y, double* r, int64_t n, void* V, bool f32, double* partial, int m,
