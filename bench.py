@@ -110,8 +110,8 @@ def cpu_baseline(X, sigma, cutoff, rows_n):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no multi-GPU "
-              f"implementation in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              f"multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
