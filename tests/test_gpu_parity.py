@@ -287,6 +287,28 @@ def test_solve_well_conditioned_matches_lu(torch, R):
     ctx.close()
 
 
+def test_default_rhs_equals_explicit_rhs(torch, R):
+    """A solve without b builds the system's right-hand side (0 on the
+    surface, +eps / -eps off it, Sec. II.B) on the device; it must give the
+    same coefficients, to the bit, as the oracle's b passed explicitly."""
+    make, eps, sigma, cutoff = CASES["torus_patch_cut"]
+    c = make()
+    X, b = o.extended_centres(c.points, c.normals, eps)
+    for mode in (R.RBF_SOLVE_IR_FP32, R.RBF_SOLVE_PLAIN_FP64):
+        out = []
+        for explicit in (False, True):
+            ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, cutoff)
+            try:
+                kw = dict(tol=1e-10, mode=mode, restart=30, max_iters=60, max_outer=2)
+                coef, info = ctx.solve(b=dev(torch, b), **kw) if explicit else ctx.solve(**kw)
+                out.append((host(coef), info.rel_resid, info.iters))
+            finally:
+                ctx.close()
+        _say(f"[default rhs mode={mode}] iters {out[0][2]} resid {out[0][1]:.3e}")
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+
+
 def test_gmres_iterates_match_oracle(torch, R):
     """After exactly k steps from zero, the device GMRES iterate equals the
     oracle's GMRES(k) iterate (same Krylov space, same minimiser)."""
