@@ -70,10 +70,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rows", type=int, default=1200, help="operator rows the CPU oracle evaluates")
-    ap.add_argument("--solve", action="store_true",
-                    help="also time full solves (float32+refinement vs plain float64) to a common residual")
-    ap.add_argument("--solve-iters", type=int, default=3000)
+    ap.add_argument("--cpu-row-frac", type=float, default=0.08,
+                    help="share of the operator rows the one-thread CPU oracle run evaluates")
+    ap.add_argument("--cpu-points", type=int, default=800_000,
+                    help="band points the CPU oracle evaluates the interpolant at (all threads; 1/10 on one)")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the solves to a common residual (chosen pipelines vs plain float64) and the "
+                         "grid-sign comparison")
+    ap.add_argument("--solve-iters", type=int, default=3000,
+                    help="operator applications each solve may take before it is compared at the common residual")
     ap.add_argument("--cull-samples", type=int, default=1_000_000,
                     help="training positions of the learned narrow-band cull (0: skip that measurement)")
     ap.add_argument("--cull-epochs", type=int, default=60)
@@ -83,28 +88,61 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(X, sigma, cutoff, rows_n):
-    """The oracle's float64 operator rows on the host, one thread."""
+def cpu_baseline(cloud, eps, sigma, cutoff, row_frac, eval_points, solve_apps):
+    """The C cell-list oracle (float64, oracle/cellsum.c) on the host: one
+    operator application over every row on all threads, the same on one
+    thread over a seeded sample of the rows, and the interpolant at points of
+    the support band (a cloud point plus a uniform offset in the cutoff ball,
+    seeded) on all threads and on one.  The solve is not run on the host (its
+    thousands of applications would take hours): its time is extrapolated as
+    the all-thread application time x the applications the plain float64
+    method needed to reach the common residual."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
+    from oracle import cells
     from oracle import rbf_oracle as o
     from paper_1305_5179_amd import workloads as w
 
+    X, _ = o.extended_centres(cloud.points, cloud.normals, eps)
+    t0 = time.perf_counter()
+    L = cells.CellOracle(X, cutoff)
+    build_s = time.perf_counter() - t0
+    nthr = cells.max_threads()
     x = w.random_vector(X.shape[0], seed=4)
-    rows = np.random.default_rng(7).choice(X.shape[0], rows_n, replace=False)
-    with threadpool_limits(limits=1):
-        o.matvec_rows(X, x, rows[:8], sigma, cutoff)
+    res = {}
+    # operator, all threads, every row
+    t0 = time.perf_counter()
+    L.matvec_rows(x, sigma, threads=nthr)
+    dt = time.perf_counter() - t0
+    res["matvec_all"] = {"threads": nthr, "rows": X.shape[0], "s": dt, "useful": L.useful,
+                         "examined": L.examined, "useful_per_s": L.useful / dt}
+    # operator, one thread, a sample of the rows
+    rows = np.sort(np.random.default_rng(7).choice(X.shape[0], int(row_frac * X.shape[0]), replace=False))
+    t0 = time.perf_counter()
+    L.matvec_rows(x, sigma, rows=rows, threads=1)
+    dt = time.perf_counter() - t0
+    res["matvec_1"] = {"threads": 1, "rows": int(rows.size), "s": dt, "useful": L.useful,
+                       "examined": L.examined, "useful_per_s": L.useful / dt}
+    # interpolant at band points
+    pts = w.band_samples(cloud.points, cutoff, eval_points, seed=21)
+    coef = w.random_vector(X.shape[0], seed=22)
+    for key, thr, npts in (("eval_all", nthr, eval_points), ("eval_1", 1, eval_points // 10)):
         t0 = time.perf_counter()
-        o.matvec_rows(X, x, rows, sigma, cutoff)
+        L.evaluate(coef, pts[:npts], sigma, threads=thr)
         dt = time.perf_counter() - t0
-        r2_in = 0
-        for i in rows:
-            r2 = o.sqdist(X[i:i + 1], X)[0]
-            r2_in += int(np.count_nonzero(r2 <= cutoff * cutoff))
-    return {"value": r2_in / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows_n} random rows of the float64 operator (brute force over all {X.shape[0]} "
-                      f"centres, {r2_in} useful pairs, {dt:.1f} s)"}
+        res[key] = {"threads": thr, "points": npts, "s": dt, "useful": L.useful, "examined": L.examined,
+                    "useful_per_s": L.useful / dt}
+    L.close()
+    out = {"value": res["matvec_all"]["useful_per_s"], "unit": "evals/s", "cores": nthr, "kind": "oracle",
+           "sample": (f"C cell-list float64 oracle: one full operator application ({X.shape[0]} rows) on {nthr} "
+                      f"threads; {rows.size} sampled rows on 1 thread; the interpolant at {eval_points} band "
+                      f"points on {nthr} threads and {eval_points // 10} on 1"),
+           "host_cpus": os.cpu_count(), "cell_list_s": build_s, **res}
+    if solve_apps:
+        out["solve_extrapolated_s"] = res["matvec_all"]["s"] * solve_apps
+        out["solve_extrapolated_note"] = (f"{solve_apps} float64 operator applications (the plain method's count to "
+                                          f"the common residual) x the all-thread application time")
+    return out
 
 
 def main():
@@ -192,6 +230,10 @@ def main():
         torch.cuda.synchronize()
         phases[key] = 1e3 * (time.perf_counter() - t) / 5
     schwarz = schwarz_measurement(rbf, ctx, torch, x)
+    dens = ctx.density()
+    density = {"q": dens.q, "h_max": dens.h_max, "h": dens.h, "h_from": "sqrt(2) h_max (eq. hmax)",
+               "sigma_sep": dens.sigma_sep, "sigma_fill": dens.sigma_fill, "sigma": sigma,
+               "sigma_over_h": sigma / dens.h}
     ctx.close()
 
 
@@ -235,6 +277,7 @@ def main():
                   "applications_per_step": applications},
         "grid_kernel_f32": evaluation,
         "schwarz": schwarz,
+        "density": density,
         "fp64_kernel": {"launches": prof.launches[OP][F64],
                         "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
                         "useful_rate": prof.useful_pairs[OP][F64] / max(prof.kernel_ms[OP][F64] * 1e-3, 1e-30) / 1e9},
@@ -247,12 +290,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = int(src.numel() * 8)
-    if args.solve:
-        out["solve"] = solve_comparison(rbf, pts, nrm, cfg, g, args.solve_iters)
+    if not args.no_solve:
+        out["solve"], grids = solve_comparison(rbf, torch, pts, nrm, cfg, g, args.solve_iters)
+        radii = (cfg["R"], cfg["r"], 2 * cutoff) if args.workload == "torus" else None
+        out["signs"] = sign_comparison(torch, grids, g, args.workload, radii)
+        del grids
     if not args.no_cpu:
-        from oracle import rbf_oracle as o
-        X, _ = o.extended_centres(cloud.points, cloud.normals, eps)
-        out["cpu_baseline"] = cpu_baseline(X, sigma, cutoff, args.cpu_rows)
+        apps = None
+        if "solve" in out:
+            p = out["solve"]["plain_fp64"]
+            # operator applications of the plain method up to the common residual (30 per cycle + 1 residual)
+            k = next(i for i, h in enumerate(p["history"]) if h <= out["solve"]["common_resid"])
+            apps = k * (restart + 1)
+        out["cpu_baseline"] = cpu_baseline(cloud, eps, sigma, cutoff, args.cpu_row_frac, args.cpu_points, apps)
     print(json.dumps(out), flush=True)
 
 
@@ -353,17 +403,27 @@ def cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, n_samples, epochs):
             "sign_error_rate": float(wrong.sum()) / max(int(signed.sum()), 1)}
 
 
-def solve_comparison(rbf, pts, nrm, cfg, g, iters):
-    """Chosen pipeline (float32 operator + float64 refinement), the same with
-    the additive Schwarz preconditioner, and the plain float64 method, each
-    from setup to grid.  When one stops above 1e-8, they are compared at the
-    lowest residual all reach (the common residual): time to it = setup
-    (+ preconditioner setup) + solve up to that residual + grid."""
-    import torch
-    res = {}
-    runs = (("ir_fp32", rbf.RBF_SOLVE_IR_FP32, False), ("ir_fp32_schwarz", rbf.RBF_SOLVE_IR_FP32, True),
-            ("plain_fp64", rbf.RBF_SOLVE_PLAIN_FP64, False))
-    for name, mode, pre in runs:
+SOLVE_RUNS = (
+    # name, mode, basis, Schwarz preconditioner
+    ("ir_fp32", "ir", "fp32", False),
+    ("ir_fp32_basis64", "ir", "fp64", False),
+    ("ir_fp32_schwarz", "ir", "fp32", True),
+    ("plain_fp64", "plain", "fp64", False),
+)
+
+
+def solve_comparison(rbf, torch, pts, nrm, cfg, g, iters):
+    """Setup -> solve -> grid for the chosen pipeline (float32 operator inside
+    float64 refinement; its Krylov basis in float32, and in float64 for
+    comparison), the same with the additive Schwarz preconditioner, and the
+    plain float64 method (float64 operator, basis and grid), each to relative
+    residual 1e-8 or `iters` operator applications.  When one stops above
+    1e-8 they are compared at the lowest residual all reach (the common
+    residual): time to it = setup (+ preconditioner setup) + solve up to the
+    first true residual at or below it + grid.  Returns the summary and the
+    grids of the final iterates (for the sign comparison)."""
+    res, grids = {}, {}
+    for name, mode, basis, pre in SOLVE_RUNS:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rbf.Rbf(pts, nrm, cfg["eps"], cfg["sigma"], cfg["cutoff"])
@@ -371,25 +431,79 @@ def solve_comparison(rbf, pts, nrm, cfg, g, iters):
             ctx.schwarz_setup()
         torch.cuda.synchronize()
         setup_ms = 1e3 * (time.perf_counter() - t0)
-        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=mode,
-                               precond=rbf.RBF_PRECOND_SCHWARZ if pre else rbf.RBF_PRECOND_NONE)
+        m = rbf.RBF_SOLVE_IR_FP32 if mode == "ir" else rbf.RBF_SOLVE_PLAIN_FP64
+        coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=m,
+                               precond=rbf.RBF_PRECOND_SCHWARZ if pre else rbf.RBF_PRECOND_NONE,
+                               basis=rbf.RBF_FP32 if basis == "fp32" else rbf.RBF_FP64)
         t1 = time.perf_counter()
-        prec = rbf.RBF_FP32 if mode == rbf.RBF_SOLVE_IR_FP32 else rbf.RBF_FP64
+        prec = rbf.RBF_FP32 if mode == "ir" else rbf.RBF_FP64
         out = torch.empty(g.size, dtype=torch.float32 if prec == rbf.RBF_FP32 else torch.float64, device="cuda")
         ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=prec, out=out)
         torch.cuda.synchronize()
         grid_ms = 1e3 * (time.perf_counter() - t1)
-        res[name] = {"setup_ms": setup_ms, "grid_ms": grid_ms, "status": info.status, "iters": info.iters,
-                     "rel_resid": info.rel_resid, "history": info.history, "history_ms": info.history_ms}
+        if name == "plain_fp64":
+            # sum_j |c_j phi_j| per node, for the sign threshold
+            grids["abs_sum"] = ctx.eval_grid(torch.abs(coef), g.origin, g.h, g.dims, prec=rbf.RBF_FP64)
+        grids[name] = out
+        res[name] = {"operator": "float32" if mode == "ir" else "float64", "basis": basis,
+                     "precond": "schwarz" if pre else "none", "grid": "float32" if prec == rbf.RBF_FP32 else "float64",
+                     "setup_ms": setup_ms, "grid_ms": grid_ms, "status": rbf.STATUS_NAMES[info.status],
+                     "iters": info.iters, "rel_resid": info.rel_resid, "stall": min(info.history),
+                     "solve_ms": info.history_ms[-1] if info.history_ms else 0.0,
+                     "history": info.history, "history_ms": info.history_ms}
         ctx.close()
-    common = max(max(min(r["history"]) for r in res.values()), 1e-8)
+    common = max(max(r["stall"] for r in res.values()), 1e-8)
     for r in res.values():
         t = next(ms for h, ms in zip(r["history"], r["history_ms"]) if h <= common)
         r["ms_to_common"] = r["setup_ms"] + t + r["grid_ms"]
     plain = res["plain_fp64"]["ms_to_common"]
-    return {"target": 1e-8, "common_resid": common,
-            "speedup_at_common": plain / res["ir_fp32"]["ms_to_common"],
-            "speedup_at_common_schwarz": plain / res["ir_fp32_schwarz"]["ms_to_common"], **res}
+    summary = {"target": 1e-8, "max_applications": iters, "reached_target": {k: r["stall"] <= 1e-8 for k, r in
+                                                                             res.items()},
+               "common_resid": common,
+               "speedup_at_common": {k: plain / r["ms_to_common"] for k, r in res.items() if k != "plain_fp64"},
+               **res}
+    return summary, grids
+
+
+def sign_comparison(torch, grids, g, cloud_kind, torus_radii=None):
+    """Grid signs of each pipeline's final iterate against the plain float64
+    method's grid.  A node has a sign when |f_plain| > tau = 1e-6 +
+    8 u32 sum_j |c_j phi_j| (the float32 evaluation bound on top of the
+    absolute 1e-6); the others (zero outside the support, or too small) are
+    excluded.  For the torus, the signs are also compared with the signed
+    distance to the torus on nodes within 2 cutoffs of it."""
+    ref = grids["plain_fp64"]
+    tau = 1e-6 + 8 * 2.0 ** -24 * grids["abs_sum"]
+    signed = torch.abs(ref) > tau
+    n_signed = int(signed.sum())
+    zero = int((ref == 0).sum())
+    out = {"reference": "plain_fp64", "tau": "1e-6 + 8 u32 sum_j |c_j phi_j(node)|", "nodes": g.size,
+           "signed": n_signed, "excluded_zero": zero, "excluded_small": g.size - n_signed - zero,
+           "disagree": {}, "agreement": {}}
+    sref = torch.sign(ref)
+    for name, f in grids.items():
+        if name in ("plain_fp64", "abs_sum"):
+            continue
+        bad = int((signed & (torch.sign(f.double()) != sref)).sum())
+        out["disagree"][name] = bad
+        out["agreement"][name] = 1.0 - bad / max(n_signed, 1)
+    if cloud_kind == "torus" and torus_radii is not None:
+        R, r, band = torus_radii
+        k = torch.arange(g.size, device=ref.device, dtype=torch.int64)
+        nx, ny = g.dims[0], g.dims[1]
+        ix, iy, iz = k % nx, (k // nx) % ny, k // (nx * ny)
+        x = g.origin[0] + ix.double() * g.h[0]
+        y = g.origin[1] + iy.double() * g.h[1]
+        z = g.origin[2] + iz.double() * g.h[2]
+        sdf = torch.sqrt((torch.sqrt(x * x + y * y) - R) ** 2 + z * z) - r
+        near = signed & (torch.abs(sdf) <= band)
+        n_near = int(near.sum())
+        geo = {"band": band, "nodes": n_near}
+        for name in ("plain_fp64", "ir_fp32"):
+            f = grids[name].double()
+            geo[name] = 1.0 - int((near & (torch.sign(f) != torch.sign(sdf))).sum()) / max(n_near, 1)
+        out["torus_sdf_agreement"] = geo
+    return out
 
 
 if __name__ == "__main__":

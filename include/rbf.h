@@ -70,6 +70,10 @@ typedef struct {
     int max_iters;     /* maximum operator applications inside GMRES cycles (default 30000) */
     int mode;          /* rbf_mode (default RBF_SOLVE_IR_FP32) */
     int precond;       /* rbf_precond (default RBF_PRECOND_NONE) */
+    int basis;         /* rbf_prec in which the refinement's inner GMRES stores its Krylov basis and
+                          the operator's output: RBF_FP32 (default) or RBF_FP64.  Its dot products,
+                          norms, updates and least squares are float64 either way.  The plain method
+                          always stores float64 and ignores this field. */
 } rbf_solve_opts;
 
 typedef struct {
@@ -171,22 +175,53 @@ int rbf_solve(rbf_ctx* ctx, const double* b, const double* x0, double* c,
 int rbf_eval_grid(rbf_ctx* ctx, const double* c, const rbf_grid* grid, void* out,
                   int prec, void* stream);
 
-/* f at m arbitrary points.  pts: device m x 3 float64; out: device m float64. */
+/* f at m arbitrary points (Sec. II.B eq. matxvet: the interpolant at
+ * evaluation points is the rectangular matrix phi(|xi_k - x_j|), truncated as
+ * the operator, times the weights).
+ *   c: device 3n float64 weights (paper order).
+ *   pts: device m x 3 float64, row-major; out: device m float64.
+ *   prec: RBF_FP32 sums in float32 (truncation decided in float64),
+ *   RBF_FP64 entirely in float64.  m = 0 does nothing.  Points farther than
+ *   cutoff from every centre get exactly 0. */
 int rbf_eval_points(rbf_ctx* ctx, const double* c, const double* pts, int64_t m,
                     double* out, int prec, void* stream);
 
 /* Density measures of the point cloud the context was built from (Sec. IV,
- * eqs. sepDist, fillDist, hmax), used by the paper to choose sigma
- * (sigma ~ 2q, eq. h1; sigma ~ sqrt(2) h, eq. h2; h ~ sqrt(2) h_max):
- *   q      = 1/2 min_{i != j} |x_i - x_j| over the n cloud points;
- *   h_max  = max_j min_{i != j} |x_i - x_j|;
- *   h_fill = max over the `samples` (device, n_samples x 3 float64, points of
- *            the domain chosen by the caller) of min_j |s - x_j|, the
- *            sampled fill distance; NaN when samples is NULL.
- * Exact float64 minima (all pairs).  Any output pointer may be NULL (host
- * pointers).  Synchronises with `stream`. */
-int rbf_density(rbf_ctx* ctx, const double* samples, int64_t n_samples, double* q, double* h_max,
-                double* h_fill, void* stream);
+ * eqs. sepDist, fillDist, hmax) and the choices of sigma the paper derives
+ * from them (eqs. h1, h2):
+ *   q          = 1/2 min_{i != j} |x_i - x_j| over the n cloud points;
+ *   h_max      = max_j min_{i != j} |x_i - x_j|;
+ *   h_fill     = max over the `samples` (device, n_samples x 3 float64, points
+ *                of the domain chosen by the caller) of min_j |s - x_j|, the
+ *                sampled fill distance; NaN when samples is NULL;
+ *   h          = h_fill, or sqrt(2) h_max (eq. hmax) without samples;
+ *   sigma_sep  = 2 q (eq. h1);
+ *   sigma_fill = sqrt(2) h (eq. h2).
+ * Exact float64 minima (all pairs); q, h_max are NaN for n < 2.
+ * out: HOST pointer.  Synchronises with `stream`. */
+typedef struct {
+    double q, h_max, h_fill, h, sigma_sep, sigma_fill;
+} rbf_density_info;
+
+int rbf_density(rbf_ctx* ctx, const double* samples, int64_t n_samples, rbf_density_info* out, void* stream);
+
+/* The Arnoldi process of rbf_solve's GMRES (Sec. III.A) for m steps from v0,
+ * with no restart and no stopping test, so that its invariants can be
+ * inspected: V_{k+1}^T V_{k+1} = I and A V_k = V_{k+1} H_k.
+ *   v0: device 3n float64 (paper order), not zero.
+ *   op_prec: the operator's precision (RBF_FP32 / RBF_FP64); basis: the
+ *   storage of the basis and of the operator's output (RBF_FP32 / RBF_FP64),
+ *   as rbf_solve_opts.basis.  The orthogonalisation is rbf_solve's: classical
+ *   Gram-Schmidt applied twice, products in float64.
+ *   V: device (m+1) x 3n float64, row k = basis vector k in paper order.
+ *   H: HOST (m+1) x m float64, row-major, the Hessenberg matrix before any
+ *   Givens rotation (zero below the subdiagonal).
+ *   *steps: columns computed.  It is m unless |w| became exactly 0 at step
+ *   *steps - 1 (an invariant Krylov space); then rows 0 .. *steps - 1 of V
+ *   are the basis and the rest of V and H is 0.
+ * 1 <= m <= 64.  RBF_EBREAKDOWN on a non-finite value.  Synchronises. */
+int rbf_arnoldi(rbf_ctx* ctx, const double* v0, int m, int op_prec, int basis, double* V, double* H, int* steps,
+                void* stream);
 
 /* Overlapping Schwarz preconditioner for rbf_solve (Sec. III.A: overlapping
  * subdomains whose local systems are solved independently; their solutions

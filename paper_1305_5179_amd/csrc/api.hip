@@ -24,6 +24,7 @@ void to_f64(const float* x, double* y, int64_t n, hipStream_t s);
 void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s);
 void gm_set_tol(void* state, double tol_abs, hipStream_t s);
 const int* gm_done_flag(const void* state);
+int gm_read_hessenberg(const void* state, int m, double* H, int* breakdown, hipStream_t s);
 
 namespace {
 
@@ -173,6 +174,17 @@ void ensure_solver(Ctx* c, int m) {
   }
 }
 
+// The basis and w are reinterpreted as float32 or float64 storage: on a
+// change of type the padding entry m of every basis vector (a weight of the
+// operator) must read 0 in the new element type too.
+void set_basis_type(Ctx* c, bool f32, hipStream_t s) {
+  if (c->krylov_f32 != (int)f32 && c->krylov_f32 != -1) {
+    fill_f64(c->V, 0.0, round_up(c->krylov_m + 1, kKrylovColPad) * c->mpad, s);
+    fill_f64(c->w, 0.0, c->mpad, s);
+  }
+  c->krylov_f32 = (int)f32;
+}
+
 // y_sorted = A x_sorted (x_sorted has a zero at index m).
 void apply_sorted(Ctx* c, const double* x, double* y, int prec, hipStream_t s, const int* skip = nullptr) {
   if (prec == RBF_FP32)
@@ -202,6 +214,7 @@ int rbf_default_solve_opts(rbf_solve_opts* o) {
   o->max_iters = 30000;
   o->mode = RBF_SOLVE_IR_FP32;
   o->precond = RBF_PRECOND_NONE;
+  o->basis = RBF_FP32;
   return RBF_OK;
 }
 
@@ -347,6 +360,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
   if (o.mode != RBF_SOLVE_PLAIN_FP64 && o.mode != RBF_SOLVE_IR_FP32) return fail(c, RBF_EINVAL, "unknown mode");
   if (o.precond != RBF_PRECOND_NONE && o.precond != RBF_PRECOND_SCHWARZ)
     return fail(c, RBF_EINVAL, "unknown preconditioner");
+  if (o.basis != RBF_FP32 && o.basis != RBF_FP64) return fail(c, RBF_EINVAL, "basis must be RBF_FP32 or RBF_FP64");
   if (o.precond == RBF_PRECOND_SCHWARZ && !c->schwarz)
     return fail(c, RBF_EINVAL, "no Schwarz preconditioner on this context (rbf_schwarz_setup)");
   if ((b && !is_device_ptr(b)) || (x0 && !is_device_ptr(x0)) || !is_device_ptr(cout))
@@ -369,17 +383,11 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
       gather_to_sorted(x0, c->perm, m, c->csol, s);
     else
       fill_f64(c->csol, 0.0, c->mpad, s);
-    // |b|
     // the inner solve of the refinement keeps its Krylov basis (and w) in
-    // float32, in the same allocations; the plain method in float64
-    const bool f32 = o.mode == RBF_SOLVE_IR_FP32;
-    if (c->krylov_f32 != (int)f32 && c->krylov_f32 != -1) {
-      // the padding entry m of every basis vector is a weight of the operator
-      // and must read 0 in the new element type too
-      fill_f64(c->V, 0.0, round_up(c->krylov_m + 1, kKrylovColPad) * c->mpad, s);
-      fill_f64(c->w, 0.0, c->mpad, s);
-    }
-    c->krylov_f32 = (int)f32;
+    // float32 unless asked otherwise, in the same allocations; the plain
+    // method in float64
+    const bool f32 = o.mode == RBF_SOLVE_IR_FP32 && o.basis == RBF_FP32;
+    set_basis_type(c, f32, s);
     gm_start(c->bsort, nullptr, c->r, m, c->V, f32, c->partial, o.restart, 0.0, c->state, s);
     int k, done, bd;
     double bnorm, gk;
@@ -611,14 +619,72 @@ int rbf_eval_points(rbf_ctx* c, const double* cw, const double* pts, int64_t npt
   });
 }
 
-int rbf_density(rbf_ctx* c, const double* samples, int64_t ns, double* q, double* hmax, double* hfill,
-                void* stream) {
+int rbf_density(rbf_ctx* c, const double* samples, int64_t ns, rbf_density_info* out, void* stream) {
   TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (!out) return fail(c, RBF_EINVAL, "out is NULL");
   if (ns < 0) return fail(c, RBF_EINVAL, "n_samples must be >= 0");
   if (samples && ns > 0 && !is_device_ptr(samples)) return fail(c, RBF_EINVAL, "samples must be a device pointer");
   return guarded(c, [&]() -> int {
-    density_measures(c->xpaper, c->n, samples, samples ? ns : 0, q, hmax, hfill, (hipStream_t)stream);
+    double q, hmax, hfill;
+    density_measures(c->xpaper, c->n, samples, samples ? ns : 0, &q, &hmax, &hfill, (hipStream_t)stream);
+    out->q = q;
+    out->h_max = hmax;
+    out->h_fill = hfill;
+    // eq. hmax stands in for the fill distance when no domain sample is given
+    out->h = std::isnan(hfill) ? std::sqrt(2.0) * hmax : hfill;
+    out->sigma_sep = 2.0 * q;                    // eq. h1
+    out->sigma_fill = std::sqrt(2.0) * out->h;   // eq. h2
+    return RBF_OK;
+  });
+}
+
+int rbf_arnoldi(rbf_ctx* c, const double* v0, int m, int op_prec, int basis, double* V, double* H, int* steps,
+                void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  if (m < 1 || m > gm_max_restart()) return fail(c, RBF_EINVAL, "m must be in 1..64");
+  if (op_prec != RBF_FP32 && op_prec != RBF_FP64) return fail(c, RBF_EINVAL, "op_prec must be RBF_FP32 or RBF_FP64");
+  if (basis != RBF_FP32 && basis != RBF_FP64) return fail(c, RBF_EINVAL, "basis must be RBF_FP32 or RBF_FP64");
+  if (!H || !steps) return fail(c, RBF_EINVAL, "H and steps must not be NULL (host)");
+  if (is_device_ptr(H)) return fail(c, RBF_EINVAL, "H must be a host array");
+  if (!is_device_ptr(v0) || !is_device_ptr(V)) return fail(c, RBF_EINVAL, "v0 and V must be device pointers");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    ensure_solver(c, m);
+    const int64_t n = c->m, ldv = c->mpad;
+    const bool f32 = basis == RBF_FP32;
+    set_basis_type(c, f32, s);
+    gather_to_sorted(v0, c->perm, n, c->bsort, s);
+    // v_0 = v0 / |v0|, no stopping tolerance
+    gm_start(c->bsort, nullptr, c->r, n, c->V, f32, c->partial, m, 0.0, c->state, s);
+    const int* skip = gm_done_flag(c->state);
+    for (int j = 0; j < m; ++j) {
+      if (f32)
+        pairsum_f32(*c, c->centres, nullptr, true, c->w, s, skip, reinterpret_cast<const float*>(c->V) + j * ldv);
+      else if (op_prec == RBF_FP32)
+        pairsum_f32(*c, c->centres, c->V + j * ldv, false, c->w, s, skip);
+      else
+        pairsum_f64(*c, c->centres, c->V + j * ldv, false, c->w, s, skip);
+      gm_step(c->V, ldv, c->w, f32, n, j, c->partial, c->state, s);
+    }
+    int bd = 0;
+    const int k = gm_read_hessenberg(c->state, m, H, &bd, s);
+    *steps = k;
+    // basis vectors in paper order (float64); the last one exists only when
+    // every step ran to the end
+    const int rows = k == m && !bd ? m + 1 : k;
+    fill_f64(V, 0.0, (int64_t)(m + 1) * n, s);
+    for (int r = 0; r < rows; ++r) {
+      const double* col = c->V + r * ldv;
+      if (f32) {
+        to_f64(reinterpret_cast<const float*>(c->V) + r * ldv, c->vin, n, s);
+        col = c->vin;
+      }
+      scatter_from_sorted(col, c->perm, n, V + (int64_t)r * n, s);
+    }
+    RBF_HIP(hipStreamSynchronize(s));
+    if (bd) return fail(c, RBF_EBREAKDOWN, "non-finite value in the Arnoldi process");
     return RBF_OK;
   });
 }

@@ -15,6 +15,8 @@
 // anyway (half the traffic of these memory-bound passes); dot products,
 // norms and updates are formed in float64 either way, and the rounding to T
 // happens once per stored element.
+#include <cstddef>
+
 #include "common.h"
 
 namespace rbf {
@@ -32,11 +34,13 @@ struct GmState {
   double tol_abs;
   double beta0;
   double inv_beta;
+  double g[kMaxRestart + 1];
+  // (the host reads the fields above after every cycle; those below stay on the device)
   double h1[kMaxRestart + 1];
   double h2[kMaxRestart + 1];
-  double H[(kMaxRestart + 1) * kMaxRestart];  // column j at H[j*(kMaxRestart+1) + i]
+  double H[(kMaxRestart + 1) * kMaxRestart];     // column j at H[j*(kMaxRestart+1) + i], rotated
+  double Hraw[(kMaxRestart + 1) * kMaxRestart];  // the same columns before the rotations
   double cs[kMaxRestart], sn[kMaxRestart];
-  double g[kMaxRestart + 1];
   double y[kMaxRestart];
 };
 
@@ -293,7 +297,10 @@ __device__ void finish_step(double beta, int j, GmState* __restrict__ st) {
     sn[i] = st->sn[i];
   }
   __syncthreads();
+  double* Hr = st->Hraw + (int64_t)j * (kMaxRestart + 1);
+  for (int i = t; i <= j; i += kVecThreads) Hr[i] = hc[i];
   if (t == 0) {
+    Hr[j + 1] = beta;
     hc[j + 1] = beta;
     for (int i = 0; i < j; ++i) {
       const double a = hc[i], b = hc[i + 1];
@@ -588,7 +595,7 @@ void gm_set_tol(void* state, double tol_abs, hipStream_t s) {
 // Host copy of the fields the driver loop needs.
 void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0, double* gk, hipStream_t s) {
   GmState h;
-  RBF_HIP(hipMemcpyAsync(&h, state, sizeof(GmState), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&h, state, offsetof(GmState, h1), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
   *k = h.k;
   *done = h.done;
@@ -598,5 +605,19 @@ void gm_read(const void* state, int* k, int* done, int* breakdown, double* beta0
 }
 
 const int* gm_done_flag(const void* state) { return &static_cast<const GmState*>(state)->done; }
+
+// The unrotated Hessenberg matrix of the last cycle into H (host, (m+1) x m,
+// row-major, zero outside the computed columns' upper Hessenberg part);
+// returns the columns computed and whether a non-finite value stopped it.
+int gm_read_hessenberg(const void* state, int m, double* H, int* breakdown, hipStream_t s) {
+  GmState h;
+  RBF_HIP(hipMemcpyAsync(&h, state, sizeof(GmState), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  const int ld = kMaxRestart + 1;
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < m; ++j) H[(int64_t)i * m + j] = (j < h.k && i <= j + 1) ? h.Hraw[(int64_t)j * ld + i] : 0.0;
+  *breakdown = h.breakdown;
+  return h.k;
+}
 
 }  // namespace rbf

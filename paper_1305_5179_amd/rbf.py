@@ -28,13 +28,13 @@ EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "
            "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error",
            "rbf_default_schwarz_opts", "rbf_schwarz_setup", "rbf_schwarz_apply", "rbf_schwarz_get_info",
            "rbf_schwarz_subdomains", "rbf_net_set", "rbf_net_get", "rbf_net_forward", "rbf_net_gradient",
-           "rbf_net_train", "rbf_eval_grid_culled"]
+           "rbf_net_train", "rbf_eval_grid_culled", "rbf_arnoldi"]
 RBF_NET_PARAMS = 50177
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_outer", C.c_int),
-                ("max_iters", C.c_int), ("mode", C.c_int), ("precond", C.c_int)]
+                ("max_iters", C.c_int), ("mode", C.c_int), ("precond", C.c_int), ("basis", C.c_int)]
 
 
 class SchwarzOpts(C.Structure):
@@ -51,6 +51,11 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("rel_resid", C.c_double), ("status", C.c_int),
                 ("n_history", C.c_int), ("history", C.POINTER(C.c_double)),
                 ("history_ms", C.POINTER(C.c_double))]
+
+
+class DensityInfo(C.Structure):
+    _fields_ = [("q", C.c_double), ("h_max", C.c_double), ("h_fill", C.c_double), ("h", C.c_double),
+                ("sigma_sep", C.c_double), ("sigma_fill", C.c_double)]
 
 
 class Grid(C.Structure):
@@ -100,7 +105,8 @@ def load_library() -> C.CDLL:
     lib.rbf_solve.argtypes = [vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
     lib.rbf_eval_grid.argtypes = [vp, vp, C.POINTER(Grid), vp, i32, vp]
     lib.rbf_eval_points.argtypes = [vp, vp, vp, i64, vp, i32, vp]
-    lib.rbf_density.argtypes = [vp, vp, i64, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl), vp]
+    lib.rbf_density.argtypes = [vp, vp, i64, C.POINTER(DensityInfo), vp]
+    lib.rbf_arnoldi.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(dbl), C.POINTER(i32), vp]
     lib.rbf_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
     lib.rbf_profile_begin.argtypes = []
@@ -173,14 +179,25 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t, dtype_name: str = "float64"):
+def _ptr(t, dtype_name: str = "float64", numel: int | None = None, rows3: bool = False, device=None,
+         name: str = "tensor"):
+    """Device address of a torch tensor after the checks the C side cannot
+    make from a raw pointer: a CUDA (HIP) tensor of the given dtype,
+    contiguous, on the context's device, with `numel` elements or, with
+    rows3, of shape (k, 3)."""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a CUDA (HIP) torch tensor")
+        raise TypeError(f"{name}: expected a CUDA (HIP) torch tensor")
     if str(t.dtype) != f"torch.{dtype_name}":
-        raise TypeError(f"expected dtype {dtype_name}, got {t.dtype}")
+        raise TypeError(f"{name}: expected dtype {dtype_name}, got {t.dtype}")
     if not t.is_contiguous():
-        raise ValueError("tensor must be contiguous")
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: tensor is on {t.device}, the context on {device}")
+    if rows3 and (t.dim() != 2 or t.shape[1] != 3):
+        raise ValueError(f"{name}: expected shape (k, 3), got {tuple(t.shape)}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -192,8 +209,10 @@ class Rbf:
         self._lib = lib
         self.ctx = C.c_void_p()
         n = int(points.shape[0])
-        st = lib.rbf_setup(_ptr(points), _ptr(normals), n, float(eps), float(sigma), float(cutoff), _stream(),
-                           C.byref(self.ctx))
+        self.device = points.device
+        pp = _ptr(points, rows3=True, name="points")
+        pn = _ptr(normals, rows3=True, numel=3 * n, device=self.device, name="normals")
+        st = lib.rbf_setup(pp, pn, n, float(eps), float(sigma), float(cutoff), _stream(), C.byref(self.ctx))
         if st != RBF_OK:
             raise RbfError(st, lib.rbf_last_error(None).decode())
         self.n = n
@@ -202,6 +221,10 @@ class Rbf:
     def _check(self, st):
         if st != RBF_OK:
             raise RbfError(st, self._lib.rbf_last_error(self.ctx).decode())
+
+    def _vec(self, t, name, dtype_name="float64", numel=None):
+        """Checked address of a length-3n (or `numel`) vector on the context's device."""
+        return _ptr(t, dtype_name, numel=self.m if numel is None else numel, device=self.device, name=name)
 
     def close(self):
         if self.ctx:
@@ -216,8 +239,8 @@ class Rbf:
 
     def centres(self):
         import torch
-        X = torch.empty((self.m, 3), dtype=torch.float64, device="cuda")
-        b = torch.empty(self.m, dtype=torch.float64, device="cuda")
+        X = torch.empty((self.m, 3), dtype=torch.float64, device=self.device)
+        b = torch.empty(self.m, dtype=torch.float64, device=self.device)
         self._check(self._lib.rbf_centres(self.ctx, _ptr(X), _ptr(b), _stream()))
         return X, b
 
@@ -225,18 +248,18 @@ class Rbf:
         import torch
         if y is None:
             y = torch.empty_like(x)
-        self._check(self._lib.rbf_matvec(self.ctx, _ptr(x), _ptr(y), int(prec), _stream()))
+        self._check(self._lib.rbf_matvec(self.ctx, self._vec(x, "x"), self._vec(y, "y"), int(prec), _stream()))
         return y
 
     def solve(self, b=None, x0=None, c=None, **opts) -> tuple:
         import torch
         if c is None:
-            c = torch.empty(self.m, dtype=torch.float64, device="cuda")
+            c = torch.empty(self.m, dtype=torch.float64, device=self.device)
         o = default_opts(**opts)
         info = SolveInfo()
-        st = self._lib.rbf_solve(self.ctx, _ptr(b) if b is not None else None,
-                                 _ptr(x0) if x0 is not None else None, _ptr(c), C.byref(o), C.byref(info),
-                                 _stream())
+        st = self._lib.rbf_solve(self.ctx, self._vec(b, "b") if b is not None else None,
+                                 self._vec(x0, "x0") if x0 is not None else None, self._vec(c, "c"), C.byref(o),
+                                 C.byref(info), _stream())
         if st not in (RBF_OK, RBF_ENOCONV):
             raise RbfError(st, self._lib.rbf_last_error(self.ctx).decode())
         hist = [info.history[i] for i in range(info.n_history)]
@@ -249,27 +272,44 @@ class Rbf:
         total = int(dims[0]) * int(dims[1]) * int(dims[2])
         dt = torch.float32 if prec == RBF_FP32 else torch.float64
         if out is None:
-            out = torch.empty(total, dtype=dt, device="cuda")
-        self._check(self._lib.rbf_eval_grid(self.ctx, _ptr(c), C.byref(g),
-                                            _ptr(out, "float32" if prec == RBF_FP32 else "float64"),
+            out = torch.empty(total, dtype=dt, device=self.device)
+        self._check(self._lib.rbf_eval_grid(self.ctx, self._vec(c, "c"), C.byref(g),
+                                            self._vec(out, "out", "float32" if prec == RBF_FP32 else "float64",
+                                                      total),
                                             int(prec), _stream()))
         return out
 
     def eval_points(self, c, pts, prec: int = RBF_FP32, out=None):
         import torch
+        k = int(pts.shape[0])
         if out is None:
-            out = torch.empty(int(pts.shape[0]), dtype=torch.float64, device="cuda")
-        self._check(self._lib.rbf_eval_points(self.ctx, _ptr(c), _ptr(pts), int(pts.shape[0]), _ptr(out),
+            out = torch.empty(k, dtype=torch.float64, device=self.device)
+        pp = _ptr(pts, rows3=True, device=self.device, name="pts")
+        self._check(self._lib.rbf_eval_points(self.ctx, self._vec(c, "c"), pp, k, self._vec(out, "out", numel=k),
                                               int(prec), _stream()))
         return out
 
-    def density(self, samples=None):
-        """(q, h_max, h_fill) of the cloud (h_fill is NaN without samples)."""
-        q, hm, hf = C.c_double(), C.c_double(), C.c_double()
+    def density(self, samples=None) -> DensityInfo:
+        """q, h_max, h_fill (NaN without samples), h and the sigma choices of
+        eqs. h1 / h2 for the cloud (rbf_density)."""
+        d = DensityInfo()
         ns = 0 if samples is None else int(samples.shape[0])
-        self._check(self._lib.rbf_density(self.ctx, _ptr(samples) if samples is not None else None, ns,
-                                          C.byref(q), C.byref(hm), C.byref(hf), _stream()))
-        return q.value, hm.value, hf.value
+        ps = _ptr(samples, rows3=True, device=self.device, name="samples") if samples is not None else None
+        self._check(self._lib.rbf_density(self.ctx, ps, ns, C.byref(d), _stream()))
+        return d
+
+    def arnoldi(self, v0, m: int, op_prec: int = RBF_FP64, basis: int = RBF_FP64):
+        """m Arnoldi steps of the solver from v0 (rbf_arnoldi): (V (m+1) x 3n,
+        H (m+1) x m as numpy, steps)."""
+        import numpy as np
+        import torch
+        V = torch.empty((m + 1, self.m), dtype=torch.float64, device=self.device)
+        H = np.zeros((m + 1) * m, dtype=np.float64)
+        k = C.c_int()
+        self._check(self._lib.rbf_arnoldi(self.ctx, self._vec(v0, "v0"), int(m), int(op_prec), int(basis),
+                                          _ptr(V, device=self.device, name="V"),
+                                          H.ctypes.data_as(C.POINTER(C.c_double)), C.byref(k), _stream()))
+        return V, H.reshape(m + 1, m), k.value
 
     def stats(self) -> Stats:
         s = Stats()
@@ -294,7 +334,7 @@ class Rbf:
         import torch
         if z is None:
             z = torch.empty_like(r)
-        self._check(self._lib.rbf_schwarz_apply(self.ctx, _ptr(r), _ptr(z), _stream()))
+        self._check(self._lib.rbf_schwarz_apply(self.ctx, self._vec(r, "r"), self._vec(z, "z"), _stream()))
         return z
 
     def schwarz_subdomains(self) -> list:
@@ -331,22 +371,28 @@ class Rbf:
 
     def net_forward(self, x, y=None):
         import torch
+        k = int(x.shape[0])
         if y is None:
-            y = torch.empty(int(x.shape[0]), dtype=torch.float32, device="cuda")
-        self._check(self._lib.rbf_net_forward(self.ctx, _ptr(x), int(x.shape[0]), _ptr(y, "float32"), _stream()))
+            y = torch.empty(k, dtype=torch.float32, device=self.device)
+        self._check(self._lib.rbf_net_forward(self.ctx, _ptr(x, rows3=True, device=self.device, name="x"), k,
+                                              self._vec(y, "y", "float32", k), _stream()))
         return y
 
     def net_gradient(self, x, f):
         import torch
-        g = torch.empty(RBF_NET_PARAMS, dtype=torch.float32, device="cuda")
+        k = int(x.shape[0])
+        g = torch.empty(RBF_NET_PARAMS, dtype=torch.float32, device=self.device)
         loss = C.c_double()
-        self._check(self._lib.rbf_net_gradient(self.ctx, _ptr(x), _ptr(f), int(x.shape[0]), _ptr(g, "float32"),
+        self._check(self._lib.rbf_net_gradient(self.ctx, _ptr(x, rows3=True, device=self.device, name="x"),
+                                               self._vec(f, "f", numel=k), k, _ptr(g, "float32"),
                                                C.byref(loss), _stream()))
         return g, loss.value
 
     def net_train(self, x, f, batch: int, epochs: int, lr: float) -> float:
+        k = int(x.shape[0])
         loss = C.c_double()
-        self._check(self._lib.rbf_net_train(self.ctx, _ptr(x), _ptr(f), int(x.shape[0]), int(batch), int(epochs),
+        self._check(self._lib.rbf_net_train(self.ctx, _ptr(x, rows3=True, device=self.device, name="x"),
+                                            self._vec(f, "f", numel=k), k, int(batch), int(epochs),
                                             float(lr), C.byref(loss), _stream()))
         return loss.value
 
@@ -355,9 +401,10 @@ class Rbf:
         g = make_grid(origin, h, dims)
         total = int(dims[0]) * int(dims[1]) * int(dims[2])
         if out is None:
-            out = torch.empty(total, dtype=torch.float32, device="cuda")
+            out = torch.empty(total, dtype=torch.float32, device=self.device)
         st = CullStats()
-        self._check(self._lib.rbf_eval_grid_culled(self.ctx, _ptr(c), C.byref(g), _ptr(out, "float32"),
+        self._check(self._lib.rbf_eval_grid_culled(self.ctx, self._vec(c, "c"), C.byref(g),
+                                                   self._vec(out, "out", "float32", total),
                                                    float(e_val), C.byref(st), _stream()))
         return out, st
 
@@ -367,10 +414,3 @@ class Rbf:
         self._check(self._lib.rbf_count_grid_pairs(self.ctx, C.byref(g), C.byref(u), C.byref(e), _stream()))
         return u.value, e.value
 
-
-def sigma_heuristics(q: float, h_max: float, h_fill: float | None = None) -> dict:
-    """The paper's choices of sigma from the density measures (Sec. IV):
-    sigma = 2 q (eq. h1), sigma = sqrt(2) h (eq. h2) with h the fill distance,
-    or h estimated as sqrt(2) h_max (eq. hmax) when no fill distance is known."""
-    h = h_fill if h_fill is not None and math.isfinite(h_fill) else math.sqrt(2.0) * h_max
-    return {"sigma_sep": 2.0 * q, "sigma_fill": math.sqrt(2.0) * h, "h": h}

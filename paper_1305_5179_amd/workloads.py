@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import hashlib
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -153,6 +154,19 @@ def _metaball_field(x: np.ndarray, c: np.ndarray, s: np.ndarray):
     return F, G
 
 
+def _metaball_field_threads(x: np.ndarray, c: np.ndarray, s: np.ndarray, parts: int = 16):
+    """_metaball_field over row blocks of x on a thread pool.  Every row's
+    values depend on that row alone, so the result is the same, bit for bit,
+    as one call over all of x."""
+    if x.shape[0] < 65536:
+        return _metaball_field(x, c, s)
+    from concurrent.futures import ThreadPoolExecutor
+    blocks = np.array_split(np.arange(x.shape[0]), parts)
+    with ThreadPoolExecutor(max_workers=min(parts, os.cpu_count() or 1)) as ex:
+        res = list(ex.map(lambda ix: _metaball_field(x[ix[0]:ix[-1] + 1], c, s), blocks))
+    return np.concatenate([r[0] for r in res]), np.concatenate([r[1] for r in res])
+
+
 def metaballs(n: int = 2_000_000, seed: int = 2, k: int = 12, band: float = 0.1, hole: float = 0.15,
               noise: float = 1e-3, batch: int = 4_000_000) -> Cloud:
     """An incomplete, noisy scan-like cloud: the zero set of a sum of k
@@ -172,12 +186,12 @@ def metaballs(n: int = 2_000_000, seed: int = 2, k: int = 12, band: float = 0.1,
     first = None
     while have < n:
         x = rng.uniform(lo, hi, size=(batch, 3))
-        F, _ = _metaball_field(x, c, s)
+        F, _ = _metaball_field_threads(x, c, s)
         x = x[np.abs(F) < band]
         for _ in range(3):
-            F, G = _metaball_field(x, c, s)
+            F, G = _metaball_field_threads(x, c, s)
             x = x - (F / np.sum(G * G, axis=1))[:, None] * G
-        F, G = _metaball_field(x, c, s)
+        F, G = _metaball_field_threads(x, c, s)
         g = np.sqrt(np.sum(G * G, axis=1))
         ok = (np.abs(F) < 1e-9) & (g > 1e-6)
         x, G, g = x[ok], G[ok], g[ok]
@@ -296,7 +310,7 @@ def halton(n: int, base: int, start: int = 1) -> np.ndarray:
 SPHERE_SMALL = dict(n=2000, seed=0, eps=0.01, sigma=0.05, cutoff=math.inf,
                     grid=lambda: Grid.cube(-1.2, 1.2, 32))
 TORUS_200K = dict(n=200_000, seed=1, eps=0.005, sigma=0.02, cutoff=0.08, restart=30,
-                  grid_n=256)
+                  grid_n=256, R=1.0, r=0.35)
 # The offset is not given for this cloud: eps = sigma / 4 keeps the torus
 # workload's ratio and stays above 2.5 times the noise.
 METABALLS_2M = dict(n=2_000_000, seed=2, eps=0.0025, sigma=0.01, cutoff=0.04, restart=30,

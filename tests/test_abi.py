@@ -43,7 +43,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_solve_options():
     o = rbf.default_opts()
-    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.precond) == (1e-8, 30, 1000, 30000, 1, 0)
+    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.precond, o.basis) == \
+        (1e-8, 30, 1000, 30000, 1, 0, rbf.RBF_FP32)
+    assert C.sizeof(rbf.SolveOpts) == 32
     assert rbf.load_library().rbf_default_solve_opts(None) == rbf.RBF_EINVAL
 
 
@@ -114,6 +116,11 @@ def test_null_context_calls_are_einval():
     assert lib.rbf_centres(None, v, v, None) == rbf.RBF_EINVAL
     assert lib.rbf_get_stats(None, None) == rbf.RBF_EINVAL
     assert lib.rbf_count_grid_pairs(None, C.byref(g), None, None, None) == rbf.RBF_EINVAL
+    d = rbf.DensityInfo()
+    assert lib.rbf_density(None, None, 0, C.byref(d), None) == rbf.RBF_EINVAL
+    H = (C.c_double * 6)()
+    k = C.c_int()
+    assert lib.rbf_arnoldi(None, v, 2, 1, 1, v, H, C.byref(k), None) == rbf.RBF_EINVAL
     lib.rbf_destroy(None)
     assert lib.rbf_last_error(None)
 
@@ -122,3 +129,57 @@ def test_binding_refuses_host_tensors():
     import torch
     with pytest.raises(TypeError):
         rbf._ptr(torch.zeros(3, dtype=torch.float64))
+
+
+@pytest.mark.gpu
+def test_binding_checks_sizes_shapes_and_devices():
+    """The C side cannot check array lengths behind raw pointers: the binding
+    refuses wrongly sized or shaped tensors before calling it."""
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1305_5179_amd import workloads as w
+    c = w.sphere(50, seed=1)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")  # noqa: E731
+    with pytest.raises(ValueError):
+        rbf.Rbf(d(c.points).reshape(-1), d(c.normals), 0.01, 0.2, 0.6)      # points not (n, 3)
+    with pytest.raises(ValueError):
+        rbf.Rbf(d(c.points), d(c.normals[:-1]), 0.01, 0.2, 0.6)             # normals of n - 1 rows
+    ctx = rbf.Rbf(d(c.points), d(c.normals), 0.01, 0.2, 0.6)
+    m = ctx.m
+    good, short = torch.zeros(m, dtype=torch.float64, device="cuda"), torch.zeros(m - 1, dtype=torch.float64,
+                                                                               device="cuda")
+    with pytest.raises(ValueError):
+        ctx.matvec(short)
+    with pytest.raises(ValueError):
+        ctx.matvec(good, short)
+    with pytest.raises(ValueError):
+        ctx.solve(b=short)
+    with pytest.raises(ValueError):
+        ctx.solve(x0=short)
+    with pytest.raises(ValueError):
+        ctx.solve(c=short)
+    with pytest.raises(ValueError):
+        ctx.eval_grid(short, (0, 0, 0), (0.1, 0.1, 0.1), (4, 4, 4))
+    with pytest.raises(ValueError):
+        ctx.eval_grid(good, (0, 0, 0), (0.1, 0.1, 0.1), (4, 4, 4),
+                      out=torch.zeros(63, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.eval_points(good, torch.zeros(12, dtype=torch.float64, device="cuda"))   # pts not (k, 3)
+    with pytest.raises(ValueError):
+        ctx.eval_points(good, torch.zeros((4, 3), dtype=torch.float64, device="cuda"),
+                        out=torch.zeros(3, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.density(torch.zeros(9, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.arnoldi(short, 3)
+    with pytest.raises(TypeError):
+        ctx.matvec(torch.zeros(m, dtype=torch.float32, device="cuda"))
+    with pytest.raises(TypeError):
+        ctx.matvec(torch.zeros(m, dtype=torch.float64))                    # host tensor
+    # a well-formed call still works after the refusals
+    y = ctx.matvec(good)
+    torch.cuda.synchronize()
+    assert float(torch.abs(y).max()) == 0.0
+    ctx.close()

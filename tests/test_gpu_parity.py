@@ -550,21 +550,31 @@ def test_density_matches_paper_halton_example(torch, R):
     s = np.linspace(0.0, 1.0, 1501)
     gx, gy = np.meshgrid(s, s)
     S = np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1)
-    q, hmax, h = ctx.density(dev(torch, S))
+    d = ctx.density(dev(torch, S))
+    q, hmax, h = d.q, d.h_max, d.h_fill
     half_unit = 0.5 * 10.0 ** (-g["printed_digits"])
     assert abs(q - g["q"]) <= half_unit and abs(h - g["h"]) <= half_unit
     assert q == o.separation_distance(P)
     assert hmax == o.h_max(P)
     assert h == o.fill_distance(P, S)
+    # the sigma choices of eqs. h1 and h2 with the sampled fill distance
+    assert d.h == h
+    assert d.sigma_sep == 2.0 * o.separation_distance(P)
+    assert d.sigma_fill == math.sqrt(2.0) * o.fill_distance(P, S)
     ctx.close()
 
 
 def test_density_matches_oracle_on_a_patch(case):
     c = case["cloud"]
-    q, hmax, hf = case["ctx"].density()
+    d = case["ctx"].density()
+    q, hmax, hf = d.q, d.h_max, d.h_fill
     if c.n < 2:
-        assert math.isnan(q) and math.isnan(hmax)
+        assert math.isnan(q) and math.isnan(hmax) and math.isnan(d.sigma_sep)
         return
     assert q == o.separation_distance(c.points)
     assert hmax == o.h_max(c.points)
     assert math.isnan(hf)
+    # without a domain sample the fill distance is estimated by eq. hmax
+    assert d.h == math.sqrt(2.0) * o.h_max(c.points)
+    assert d.sigma_sep == 2.0 * q
+    assert d.sigma_fill == math.sqrt(2.0) * (math.sqrt(2.0) * o.h_max(c.points))

@@ -1,0 +1,261 @@
+"""GPU solver checks beyond parity with the oracle's iterates: the Arnoldi
+process's invariants in every precision combination the solver uses, the
+breakdown status on non-finite inputs, the refinement with a float32 and a
+float64 Krylov basis, and the grid signs of the chosen pipelines against the
+plain float64 method and against the known geometry (Sec. III.A GMRES;
+Sec. IV.A sphere)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import rbf_oracle as o
+from paper_1305_5179_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1305_5179_amd import rbf
+    rbf.load_library()
+    return rbf
+
+
+def dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+# A torus patch whose truncated system is well conditioned (condition number
+# about 150 by the oracle's eigenvalues): GMRES(30) reaches 1e-10 on it.
+WELL = dict(ntorus=20000, npatch=1500, seed=2, eps=0.01, sigma=0.013)
+
+
+def well_patch():
+    c = w.patch(w.torus(WELL["ntorus"], seed=1), WELL["npatch"], seed=WELL["seed"])
+    return c, WELL["eps"], WELL["sigma"], 4 * WELL["sigma"]
+
+
+# ---------------------------------------------------------------------------
+# Arnoldi invariants
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_system(torch, R):
+    c = w.patch(w.torus(20000, seed=1), 300, seed=4)
+    eps, sigma, rc = 0.01, 0.03, 0.12
+    X, b = o.extended_centres(c.points, c.normals, eps)
+    A = o.interpolation_matrix(X, sigma, rc)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, rc)
+    yield dict(X=X, b=b, A=A, ctx=ctx)
+    ctx.close()
+
+
+@pytest.mark.parametrize("op,basis", [(1, 1), (0, 1), (0, 0)], ids=["op64-basis64", "op32-basis64", "op32-basis32"])
+def test_arnoldi_invariants(small_system, torch, R, op, basis):
+    """V_{m+1}^T V_{m+1} = I and A V_m = V_{m+1} H_m (A the oracle's float64
+    truncated matrix).  Bounds: float64 storage and operator keep both to
+    1e-12 of the magnitudes involved; a float32 operator differs from A by at
+    most 64 u32 sum_j |A_ij v_j| (the operator's parity bound); float32
+    storage rounds every stored basis entry and operator output once (u32
+    relative), which bounds |V^T V - I| by 8 u32 and adds 8 u32 |V||H| to the
+    relation."""
+    s = small_system
+    A, m = s["A"], 30
+    v0 = w.random_vector(A.shape[0], seed=11)
+    Vd, H, k = s["ctx"].arnoldi(dev(torch, v0), m, op_prec=op, basis=basis)
+    V = host(Vd)
+    assert k == m
+    # upper Hessenberg, positive subdiagonal
+    assert np.all(np.tril(H, -2) == 0.0)
+    assert np.all(np.diag(H, -1) > 0.0)
+    orth = np.max(np.abs(V @ V.T - np.eye(m + 1)))
+    Rel = A @ V[:m].T - V.T @ H
+    mag_A = np.abs(A) @ np.abs(V[:m].T)
+    mag_H = np.abs(V.T) @ np.abs(H)
+    if op == 1:
+        bound = 1e-12 * (mag_A + mag_H)
+    else:
+        bound = 64 * U32 * mag_A + (8 * U32 if basis == 0 else 1e-12) * mag_H
+    ratio = np.max(np.abs(Rel) / bound)
+    first = np.max(np.abs(V[0] - v0 / np.linalg.norm(v0)))
+    _say(f"[arnoldi op={op} basis={basis}] |V^T V - I| = {orth:.2e}  relation/bound = {ratio:.3f}  "
+         f"|v_0 - v0/|v0|| = {first:.2e}")
+    assert orth <= (8 * U32 if basis == 0 else 1e-12)
+    assert ratio <= 1.0
+    assert first <= (U32 if basis == 0 else 1e-15)
+
+
+def test_arnoldi_hessenberg_matches_projection(small_system, torch, R):
+    """H's entries are the projections h_ij = v_i^T A v_j of the computed basis
+    (float64 operator and storage)."""
+    s = small_system
+    A, m = s["A"], 12
+    v0 = w.random_vector(A.shape[0], seed=12)
+    Vd, H, k = s["ctx"].arnoldi(dev(torch, v0), m, op_prec=1, basis=1)
+    V = host(Vd)
+    P = V @ A @ V[:m].T
+    err = np.max(np.abs(P - H))
+    _say(f"[arnoldi projection] max |V^T A V - H| = {err:.2e}")
+    assert err <= 1e-12 * np.max(np.abs(H))
+
+
+def test_arnoldi_rejects_bad_arguments(small_system, torch, R):
+    """m outside 1..64 and unknown precisions are RBF_EINVAL before any
+    device work."""
+    import ctypes as C
+    ctx = small_system["ctx"]
+    v0 = dev(torch, np.ones(ctx.m))
+    H = (C.c_double * 16)()
+    k = C.c_int()
+    for m, op, basis in ((0, 1, 1), (65, 1, 1), (4, 2, 1), (4, 1, 3)):
+        st = ctx._lib.rbf_arnoldi(ctx.ctx, R._ptr(v0), m, op, basis, R._ptr(v0), H, C.byref(k), R._stream())
+        assert st == R.RBF_EINVAL, (m, op, basis)
+
+
+# ---------------------------------------------------------------------------
+# Breakdown: non-finite inputs end the solve with RBF_EBREAKDOWN (no hang)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1], ids=["plain", "refined"])
+@pytest.mark.parametrize("where", ["b_nan", "b_inf", "x0_nan"])
+def test_solve_non_finite_input_is_breakdown(small_system, torch, R, mode, where):
+    ctx, b = small_system["ctx"], small_system["b"].copy()
+    x0 = None
+    if where == "b_nan":
+        b[7] = math.nan
+    elif where == "b_inf":
+        b[123] = math.inf
+    else:
+        x0 = np.zeros_like(b)
+        x0[5] = math.nan
+    with pytest.raises(R.RbfError) as e:
+        ctx.solve(b=dev(torch, b), x0=None if x0 is None else dev(torch, x0), tol=1e-10, mode=mode, restart=30,
+                  max_iters=300)
+    assert e.value.status == R.RBF_EBREAKDOWN
+    # the context still solves a finite system afterwards
+    coef, info = ctx.solve(b=dev(torch, small_system["b"]), tol=1e-3, mode=mode, restart=30, max_iters=300)
+    assert info.status in (R.RBF_OK, R.RBF_ENOCONV) and math.isfinite(info.rel_resid)
+
+
+# ---------------------------------------------------------------------------
+# Refinement with a float32 and a float64 Krylov basis
+# ---------------------------------------------------------------------------
+def test_refinement_basis_fp32_and_fp64_reach_the_same_weights(torch, R):
+    c, eps, sigma, rc = well_patch()
+    X, b = o.extended_centres(c.points, c.normals, eps)
+    A = o.interpolation_matrix(X, sigma, rc)
+    ref = np.linalg.solve(A, b)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, rc)
+    try:
+        out = {}
+        for basis in (R.RBF_FP32, R.RBF_FP64):
+            coef, info = ctx.solve(tol=1e-12, mode=R.RBF_SOLVE_IR_FP32, restart=30, basis=basis)
+            out[basis] = (host(coef), info)
+            rel = np.linalg.norm(out[basis][0] - ref) / np.linalg.norm(ref)
+            _say(f"[refinement basis={basis}] status {info.status} iters {info.iters} outer {info.outer} "
+                 f"resid {info.rel_resid:.2e} |c - c_LU|/|c_LU| {rel:.2e}")
+            assert info.status == R.RBF_OK and info.rel_resid <= 1e-12
+            assert o.relative_residual(X, out[basis][0], b, sigma, rc) <= 1e-11
+            assert rel <= 1e-5
+        # the float32 basis costs no more than a few extra operator applications
+        assert out[R.RBF_FP32][1].iters <= out[R.RBF_FP64][1].iters + 30
+    finally:
+        ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Grid signs: chosen pipelines against the plain float64 method and the
+# geometry.  A node has a sign when |f_ref| > 1e-6 + 8 u32 sum_j |c_j phi_j|.
+# ---------------------------------------------------------------------------
+def _pipelines(R):
+    return (("plain_fp64", R.RBF_SOLVE_PLAIN_FP64, R.RBF_FP64, False),
+            ("ir_fp32", R.RBF_SOLVE_IR_FP32, R.RBF_FP32, False),
+            ("ir_fp32_basis64", R.RBF_SOLVE_IR_FP32, R.RBF_FP64, False),
+            ("ir_fp32_schwarz", R.RBF_SOLVE_IR_FP32, R.RBF_FP32, True))
+
+
+def _solve_and_grid(torch, R, c, eps, sigma, rc, g, tol, max_iters):
+    P, N = dev(torch, c.points), dev(torch, c.normals)
+    grids, infos, tau = {}, {}, None
+    for name, mode, basis, pre in _pipelines(R):
+        ctx = R.Rbf(P, N, eps, sigma, rc)
+        try:
+            if pre:
+                ctx.schwarz_setup()
+            coef, info = ctx.solve(tol=tol, mode=mode, restart=30, max_iters=max_iters, basis=basis,
+                                   precond=R.RBF_PRECOND_SCHWARZ if pre else R.RBF_PRECOND_NONE)
+            prec = R.RBF_FP64 if mode == R.RBF_SOLVE_PLAIN_FP64 else R.RBF_FP32
+            grids[name] = host(ctx.eval_grid(coef, g.origin, g.h, g.dims, prec=prec))
+            infos[name] = info
+            if name == "plain_fp64":
+                S = host(ctx.eval_grid(torch.abs(coef), g.origin, g.h, g.dims, prec=R.RBF_FP64))
+                tau = 1e-6 + 8 * U32 * S
+        finally:
+            ctx.close()
+    return grids, infos, tau
+
+
+def test_pipeline_signs_agree_on_a_well_conditioned_torus_patch(torch, R):
+    """Every pipeline reaches 1e-8; on every node with a sign the float32
+    pipelines' grids have the plain float64 method's sign."""
+    c, eps, sigma, rc = well_patch()
+    g = w.Grid.around(c.points, 96)
+    grids, infos, tau = _solve_and_grid(torch, R, c, eps, sigma, rc, g, 1e-8, 3000)
+    ref = grids["plain_fp64"]
+    signed = np.abs(ref) > tau
+    for name, info in infos.items():
+        assert info.status == R.RBF_OK and info.rel_resid <= 1e-8, name
+    # (the patch's support band is a thin shell of its bounding cube)
+    assert signed.sum() > 30000
+    for name, f in grids.items():
+        bad = int(np.sum(signed & (np.sign(f) != np.sign(ref))))
+        _say(f"[patch signs {name}] iters {infos[name].iters} resid {infos[name].rel_resid:.2e} "
+             f"signed {signed.sum()} excluded {g.size - signed.sum()} disagree {bad}")
+        assert bad == 0
+    # the geometry: on band nodes the sign is that of the torus's signed
+    # distance (reported; the patch's edges make it fall short of 100 %)
+    nodes = o.grid_nodes(g.origin, g.h, g.dims)
+    sdf = w.torus_sdf(nodes)
+    near = signed & (np.abs(sdf) <= 2 * rc) & (np.abs(sdf) > 0.5 * eps)
+    geo = np.mean(np.sign(ref[near]) == np.sign(sdf[near]))
+    _say(f"[patch geometry] sign(f) = sign(sdf) on {geo:.4f} of {near.sum()} band nodes")
+
+
+def test_sphere_signs_match_the_geometry(torch, R):
+    """P6 on the sphere workload (2,000 points, no cutoff, condition number
+    ~3.5e9: neither pipeline reaches 1e-8 in 1,500 applications): on nodes
+    0.01 < ||xi| - 1| < 0.1 with a sign, sign f = sign(|xi| - 1) for the
+    chosen pipelines and the plain method."""
+    cfg = w.SPHERE_SMALL
+    c = w.sphere(cfg["n"], cfg["seed"])
+    g = cfg["grid"]()
+    grids, infos, tau = _solve_and_grid(torch, R, c, cfg["eps"], cfg["sigma"], cfg["cutoff"], g, 1e-8, 1500)
+    nodes = o.grid_nodes(g.origin, g.h, g.dims)
+    d = np.linalg.norm(nodes, axis=1) - 1.0
+    band = (np.abs(d) > 0.01) & (np.abs(d) < 0.1)
+    for name, f in grids.items():
+        sel = band & (np.abs(f) > tau)
+        bad = int(np.sum(np.sign(f[sel]) != np.sign(d[sel])))
+        _say(f"[sphere signs {name}] resid {infos[name].rel_resid:.2e} band {band.sum()} signed {sel.sum()} "
+             f"wrong {bad}")
+        assert sel.sum() > 0.9 * band.sum()
+        assert bad == 0
