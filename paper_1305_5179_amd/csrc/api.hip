@@ -551,17 +551,19 @@ int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out,
     else
       fill_f64(static_cast<double*>(out), 0.0, total, s);
     if (prec == RBF_FP32 && brick_sum_applies(*c, *grid)) {
-      // float32 with a cutoff: the bricks walk their candidate sources directly
-      int64_t* ids = nullptr;
-      const int64_t nact = support_bricks(*c, *grid, &ids, s);
+      // float32 with a cutoff: tiles of bricks walk their candidate sources
+      // directly
+      int64_t* ws = talloc<int64_t>(support_tiles_ws_elems(*grid));
+      const int64_t *tiles = nullptr, *masks = nullptr;
+      const int64_t nt = support_tiles(*c, *grid, ws, &tiles, &masks, s);
       // (timed like the pair kernels; it counts no pairs: the counts of a
       // grid come from rbf_count_grid_pairs)
       ProfScope ps(RBF_FP32, 1, 0, 0, s);
-      brick_sum_f32(*c, *grid, ids, nact, c->vin, static_cast<float*>(out), nullptr, nullptr, s, ps.start(),
-                    ps.stop());
+      brick_sum_tiles(*c, *grid, tiles, masks, nt, c->vin, static_cast<float*>(out), nullptr, nullptr, s,
+                      ps.start(), ps.stop());
       ps.done();
       RBF_HIP(hipStreamSynchronize(s));
-      temp_free(ids);
+      temp_free(ws);
       return RBF_OK;
     }
     TargetSet ts;

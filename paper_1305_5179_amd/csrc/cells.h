@@ -100,12 +100,14 @@ __device__ __forceinline__ int div_small(int n, int d, float inv_d) {
 // and whole-cell flag of the occupied cells, 64 entries of the calling wave;
 // a lane finds its cell from a count of the cells that start before the
 // round and a mask of those that start within it).
-// visit(valid, k, is_in, is_shell) runs once per round of 64 candidates, in
-// the same order on every call: k is this lane's sorted source (when valid),
-// is_in marks a source within r_in of the anchor (a whole cell within r_in
-// counts without loading its sources), is_shell one within r_out but not
-// r_in.  r_in2 < 0 marks no inner sources.  Returns the number of
-// candidates; CELLS_ONLY stops after the cell phase (the count alone).
+// visit(valid, k, is_in, is_shell, whole, s) runs once per round of 64
+// candidates, in the same order on every call: k is this lane's sorted source
+// (when valid), is_in marks a source within r_in of the anchor (a whole cell
+// within r_in counts without loading its sources: then `whole` is set and s
+// is not loaded), is_shell one within r_out but not r_in, s the source's
+// (unscaled) coordinates when loaded.  r_in2 < 0 marks no inner sources.
+// Returns the number of candidates; CELLS_ONLY stops after the cell phase
+// (the count alone).
 template <bool CELLS_ONLY, class Visit>
 __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_in2, double r_out2, const int cl[3],
                                                    const int cn[3], const double4* __restrict__ xs,
@@ -188,18 +190,20 @@ __device__ __forceinline__ int64_t walk_candidates(const double ac[3], double r_
       const int j = min(max(before + __popcll(starts & below_lane) - 1, 0), nocc - 1);
       const uint32_t k = (uint32_t)(cst[j] + (f - cpre[j]));
       bool is_in = false, is_shell = false;
+      const bool whole = valid && cwhole[j];
+      double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
       if (valid) {
-        if (cwhole[j]) {
+        if (whole) {
           is_in = true;
         } else {
-          const double4 s = xs[k];
+          s = xs[k];
           const double dx = s.x - ac[0], dy = s.y - ac[1], dz = s.z - ac[2];
           const double d2 = (dx * dx + dy * dy) + dz * dz;
           is_in = d2 <= r_in2;
           is_shell = !is_in && d2 <= r_out2;
         }
       }
-      visit(valid, k, is_in, is_shell);
+      visit(valid, k, is_in, is_shell, whole, s);
     }
   }
   return cand;

@@ -302,13 +302,27 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
 void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,
                  const int* skip = nullptr);
 
-// gridsum.hip: float32 grid sums without source lists (bricks `ids`, or
-// every brick when ids is null; out is not cleared).  useful/examined: optional
-// per-brick pair counts.
+// gridsum.hip: float32 grid sums without source lists, by tiles of bricks
+// (a wave per tile of 1 x 2 x 1 bricks of 4 x 2 x 2 nodes; a tile's mask
+// selects the bricks it evaluates; nodes of other bricks are not written, out
+// is not cleared).
+//   support_tiles: the tiles of the support and their masks, carved from a
+//   workspace of support_tiles_ws_elems(g) int64 entries; returns the count
+//   (waits for it).  Needs a cutoff.
+//   brick_sum_tiles: the sums over such a tile list; t0, t1: start/stop
+//   events the launch carries (optional).  useful/examined: optional HOST
+//   totals of the pairs inside the cutoff and of the pairs computed (then the
+//   call waits for them).
+//   brick_sum_f32: the same over a list of brick ids (nact of them).
 bool brick_sum_applies(const Ctx& c, const rbf_grid& g);
+int64_t support_tiles_ws_elems(const rbf_grid& g);
+int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_t** tiles, const int64_t** masks,
+                      hipStream_t s);
+void brick_sum_tiles(const Ctx& c, const rbf_grid& g, const int64_t* tiles, const int64_t* masks, int64_t nt,
+                     const double* w_sorted, float* out, int64_t* useful, int64_t* examined, hipStream_t s,
+                     hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
-                   float* out, int64_t* useful, int64_t* examined, hipStream_t s, hipEvent_t t0 = nullptr,
-                   hipEvent_t t1 = nullptr);   // t0, t1: start/stop events the launch carries (optional)
+                   float* out, int64_t* useful, int64_t* examined, hipStream_t s);
 
 // density.hip
 void density_measures(const double* P, int64_t n, const double* samples, int64_t ns, double* q, double* hmax,
@@ -370,6 +384,8 @@ GridDesc grid_desc(const rbf_grid& g);
 // Ids of the bricks with a centre within the cutoff of one of their nodes
 // (*ids = null and every brick without a cutoff); *ids is a temporary.
 int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids, hipStream_t s);
+// mark[b] = 1 for the bricks of the support (those support_bricks lists).
+void mark_support(const Ctx& c, const GridDesc& gd, int64_t* mark, int64_t nbricks, hipStream_t s);
 void brick_targets(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, TargetSet& ts,
                    hipStream_t s);
 void grid_targets(const Ctx& c, const rbf_grid& g, TargetSet& ts, hipStream_t s);

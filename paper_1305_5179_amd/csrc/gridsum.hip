@@ -3,14 +3,17 @@
 //
 // A grid's lists are used once, so building them (classify every candidate,
 // write the list and the masks, read them back in the pair kernel) costs
-// more than the sums themselves.  Here one wave owns a brick of 4 x 2 x 2
-// nodes and walks the brick's candidate sources directly, with the list
-// builder's classification: sources within r_in of the brick's anchor are
+// more than the sums themselves.  Here one wave owns a tile of 4 x 4 x 2
+// nodes, two bricks of 4 x 2 x 2 (one along x and z, two along y), walks
+// the tile's candidate sources once and classifies each for every brick with
+// the list builder's rule: sources within r_in of the brick's anchor are
 // inside the cutoff of every node, sources beyond r_out of none, and the
 // shell in between gets the exact float64 test of every node.  Kept sources
-// are queued in LDS and summed 64 at a time, one source per lane.
+// go to the brick's two LDS queues and are summed 64 at a time, one source
+// per lane.  Sharing the walk (cell cube, candidate loads) between bricks is
+// the point of the tile: the walk cost more than the sums.
 //
-// Terms (lane = source s, 16 nodes n = c + h (i, j, k) of the brick, c its
+// Terms (lane = source s, 16 nodes n = c + h (i, j, k) of a brick, c its
 // corner node, coordinates scaled by sqrt(k) so that phi = exp2(-d)):
 //   d = |u|^2 - 2 u.Hn + |Hn|^2,   u = s - c,
 //   phi_n = 2^{-|u|^2} X^i Y^j Z^k 2^{-|Hn|^2},   X = 2^{2 h_x u_x} (and y, z),
@@ -27,15 +30,25 @@
 
 namespace rbf {
 
+// setup.hip
+int64_t scan_ws_elems(int64_t n);
+void scan_exclusive_i64_ws(const int64_t* in, int64_t* out, int64_t n, int64_t* ws, hipStream_t s);
+
 namespace {
 
-constexpr int kBrickWaves = 4;
-constexpr int kRedPitch = kGroup + 1;   // LDS row pitch of the cross-lane sums (odd: no bank conflicts)
+constexpr int kTileWaves = 4;          // tiles (waves) per workgroup
+constexpr int kTileY = 2, kTileZ = 1;  // bricks of a tile along y and z (one along x)
+constexpr int kTileBricks = kTileY * kTileZ;
+constexpr int kRedPitch = kGroup + 1;  // LDS row pitch of the cross-lane sums (odd: no bank conflicts)
+constexpr int kQueue = 2 * kWave;      // entries of a source queue (drained at 64)
+constexpr int kThreadsT = 256;
 
-struct BrickArgs {
+struct TileArgs {
   GridDesc gd;
-  const int64_t* ids;    // brick ids (null: brick g is id g)
-  int64_t nb;            // bricks
+  const int64_t* tiles;  // tile ids t = tx + nt0 (ty + nt1 tz)
+  const int64_t* masks;  // per tile: bit b (b = dy + kTileY dz) for each brick to evaluate
+  int64_t nt;            // tiles in the list
+  int64_t nt0, nt1;      // tiles along x and y
   const double4* xs;     // unscaled sorted sources
   const double* w;       // sorted weights
   const int32_t* cstart;
@@ -45,56 +58,45 @@ struct BrickArgs {
   double rc, rc2, sqrt_k;
   double hk[3];          // scaled grid spacing h sqrt(k) per axis
   float* out;
-  int64_t* useful;       // per brick: pairs inside the cutoff (with `examined`, optional)
-  int64_t* examined;     // per brick: queued sources x 16
+  int64_t* useful;       // per tile: pairs inside the cutoff (with `examined`, optional)
+  int64_t* examined;     // per tile: queued sources x 16
 };
 
-struct BrickNodes {
-  double x[4], y[2], z[2];   // node coordinates as the grid defines them: o + i h
-  uint32_t vmask;            // nodes inside the grid
+// One brick of a tile (uniform).  Its anchor is the centre of its whole
+// 4 x 2 x 2 box of nodes (also where the grid ends: nodes beyond it are never
+// stored, and classifying against the whole box is conservative for the
+// nodes that exist), so every brick has the same radius.
+struct Brick {
+  double y0, z0;         // its first node along y and z
+  double ay, az;         // anchor along y and z (x: the tile's)
+  uint32_t vmask;        // nodes inside the grid (bit i + 4 j + 8 k); 0: not evaluated
   int nvalid;
-  int64_t i0, j0, k0;        // first node of the brick
+  int64_t j0, k0;        // first node along y and z
 };
 
-__device__ __forceinline__ BrickNodes brick_nodes(const GridDesc& gd, int64_t b) {
-  BrickNodes bn;
-  const int64_t bx = b % gd.nb[0], by = (b / gd.nb[0]) % gd.nb[1], bz = b / (gd.nb[0] * gd.nb[1]);
-  bn.i0 = 4 * bx;
-  bn.j0 = 2 * by;
-  bn.k0 = 2 * bz;
-  for (int i = 0; i < 4; ++i) bn.x[i] = gd.o[0] + (double)(bn.i0 + i) * gd.h[0];
-  for (int j = 0; j < 2; ++j) {
-    bn.y[j] = gd.o[1] + (double)(bn.j0 + j) * gd.h[1];
-    bn.z[j] = gd.o[2] + (double)(bn.k0 + j) * gd.h[2];
-  }
-  bn.vmask = 0u;
-  bn.nvalid = 0;
-  for (int l = 0; l < kGroup; ++l) {
-    if (bn.i0 + (l & 3) < gd.n[0] && bn.j0 + ((l >> 2) & 1) < gd.n[1] && bn.k0 + (l >> 3) < gd.n[2]) {
-      bn.vmask |= 1u << l;
-      ++bn.nvalid;
-    }
-  }
-  return bn;
+// Radius of a box of nodes with sides (e0, e1, e2) around its centre: the
+// half diagonal, padded for the rounding of the centre and of the nodes.
+__device__ __forceinline__ double box_radius(double e0, double e1, double e2) {
+  return sqrt((e0 * e0 + e1 * e1) + e2 * e2) * (0.5 + 1e-14);
 }
 
 // Terms of `cnt` (<= 64) queued sources, one per lane, added to the lane's 16
-// node sums.  SHELL: each term only where the exact test puts the pair
-// inside the cutoff.  COUNT: add the pairs inside the cutoff to `use`.
+// node sums of one brick.  SHELL: each term only where the exact test puts
+// the pair inside the cutoff.  COUNT: add the pairs inside the cutoff to `use`.
 template <bool SHELL, bool COUNT>
-__device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes& bn, const uint32_t* q, int cnt,
-                                            float acc[kGroup], int64_t& use) {
+__device__ __forceinline__ void brick_batch(const TileArgs& a, const double (&x)[4], const Brick& bk,
+                                            const uint32_t* q, int cnt, float acc[kGroup], int64_t& use) {
   const int lane = threadIdx.x & 63;
   const bool valid = lane < cnt;
   // lanes without a source take the corner node with weight 0: every term 0
-  double4 s = make_double4(bn.x[0], bn.y[0], bn.z[0], 0.0);
+  double4 s = make_double4(x[0], bk.y0, bk.z0, 0.0);
   double wk = 0.0;
   if (valid) {
     const uint32_t k = q[lane];
     s = a.xs[k];
     wk = a.w[k];
   }
-  const double dx = (s.x - bn.x[0]) * a.sqrt_k, dy = (s.y - bn.y[0]) * a.sqrt_k, dz = (s.z - bn.z[0]) * a.sqrt_k;
+  const double dx = (s.x - x[0]) * a.sqrt_k, dy = (s.y - bk.y0) * a.sqrt_k, dz = (s.z - bk.z0) * a.sqrt_k;
   const double uq = fma(dx, dx, fma(dy, dy, dz * dz));
   // every exponent is formed in float64 and rounded once
   const float W = (float)wk * __builtin_amdgcn_exp2f(-(float)uq);
@@ -115,18 +117,20 @@ __device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes
       acc[i + 8] = __builtin_fmaf(A[i], Z, acc[i + 8]);
       acc[i + 12] = __builtin_fmaf(B, Z, acc[i + 12]);
     }
-    if (COUNT) use += (int64_t)cnt * bn.nvalid;
+    if (COUNT) use += (int64_t)cnt * bk.nvalid;
   } else {
     // the exact test, r^2 = (dx dx + dy dy) + dz dz with d = node - source
     double ex2[4], ey2[2], ez2[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const double e = bn.x[i] - s.x;
+      const double e = x[i] - s.x;
       ex2[i] = e * e;
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const double ey = bn.y[j] - s.y, ez = bn.z[j] - s.z;
+      // the node coordinates as the grid defines them: o + index h
+      const double ey = (a.gd.o[1] + (double)(bk.j0 + j) * a.gd.h[1]) - s.y;
+      const double ez = (a.gd.o[2] + (double)(bk.k0 + j) * a.gd.h[2]) - s.z;
       ey2[j] = ey * ey;
       ez2[j] = ez * ez;
     }
@@ -140,90 +144,18 @@ __device__ __forceinline__ void brick_batch(const BrickArgs& a, const BrickNodes
         const double r2 = (ex2[i] + ey2[jk & 1]) + ez2[jk >> 1];
         const bool in = valid && r2 <= a.rc2;
         acc[l] += in ? T[jk] : 0.0f;
-        if (COUNT) use += __popcll(ballot(in) & (((bn.vmask >> l) & 1u) ? ~0ull : 0ull));
+        if (COUNT) use += __popcll(ballot(in) & (((bk.vmask >> l) & 1u) ? ~0ull : 0ull));
       }
     }
   }
 }
 
-template <bool COUNT>
-__global__ __launch_bounds__(kBrickWaves * kWave, 5) void k_brick_sum_f32(BrickArgs a) {
-  // per wave: the two source queues and the cell prefix of the walk, later
-  // the cross-lane sums
-  __shared__ uint32_t lds_s[kBrickWaves][kWave * kRedPitch];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  uint32_t* const lds = lds_s[wave];
+// The 16 node sums of a brick added across the wave (lane L adds node L % 16
+// over the 16 lanes of part L / 16, then the four parts are added) and
+// stored with the node factor.
+__device__ __forceinline__ void brick_store(const TileArgs& a, const Brick& bk, int64_t i0, const float acc[kGroup],
+                                            float* red) {
   const int lane = threadIdx.x & 63;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kBrickWaves + wave;
-  if (g >= a.nb) return;
-  const int64_t b = a.ids ? a.ids[g] : g;
-  const BrickNodes bn = brick_nodes(a.gd, b);
-  int64_t use = 0, queued = 0;
-  float acc[kGroup];
-#pragma unroll
-  for (int l = 0; l < kGroup; ++l) acc[l] = 0.0f;
-  if (bn.nvalid > 0) {
-    // anchor (centre of the valid nodes' box) and radius, as the list builder
-    // takes them
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int l = 0; l < kGroup; ++l) {
-      if ((bn.vmask >> l) & 1u) {
-        const double t[3] = {bn.x[l & 3], bn.y[(l >> 2) & 1], bn.z[l >> 3]};
-        for (int d = 0; d < 3; ++d) {
-          lo[d] = fmin(lo[d], t[d]);
-          hi[d] = fmax(hi[d], t[d]);
-        }
-      }
-    }
-    const double ac[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
-    double rad = 0.0;
-    for (int l = 0; l < kGroup; ++l) {
-      if ((bn.vmask >> l) & 1u) {
-        const double ex = bn.x[l & 3] - ac[0], ey = bn.y[(l >> 2) & 1] - ac[1], ez = bn.z[l >> 3] - ac[2];
-        rad = fmax(rad, sqrt((ex * ex + ey * ey) + ez * ez));
-      }
-    }
-    const double r_in = a.rc * (1.0 - 1e-12) - rad;   // |s - a| <= r_in: inside for every node
-    const double r_out = a.rc * (1.0 + 1e-12) + rad;  // |s - a| >  r_out: inside for none
-    const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0;
-    const double r_out2 = r_out * r_out;
-    int cl[3], cn[3];
-    cell_cube(ac, r_out, a.lat, cl, cn);
-    uint32_t* qin = lds;
-    uint32_t* qsh = lds + 2 * kWave;
-    int32_t* cpre = reinterpret_cast<int32_t*>(lds + 4 * kWave);
-    int32_t* cst = reinterpret_cast<int32_t*>(lds + 5 * kWave);
-    uint8_t* cwhole = reinterpret_cast<uint8_t*>(lds + 6 * kWave);
-    int nin = 0, nsh = 0;
-    // take 64 queued sources from the front of a queue and move the rest down
-    auto drain = [&](uint32_t* qq, int& nq, auto shell) {
-      wave_sync_lds();
-      brick_batch<decltype(shell)::value, COUNT>(a, bn, qq, kWave, acc, use);
-      const uint32_t rest = lane + kWave < nq ? qq[kWave + lane] : 0u;
-      wave_sync_lds();
-      if (lane + kWave < nq) qq[lane] = rest;
-      nq -= kWave;
-      queued += kWave;
-      wave_sync_lds();
-    };
-    walk_candidates<false>(ac, r_in2, r_out2, cl, cn, a.xs, a.cstart, a.ccount, a.cmap, a.lat, cpre, cst, cwhole,
-                           [&](bool, uint32_t k, bool is_in, bool is_shell) {
-                             const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
-                             if (is_in) qin[nin + lanes_below(mi)] = k;
-                             if (is_shell) qsh[nsh + lanes_below(ms)] = k;
-                             nin += __popcll(mi);
-                             nsh += __popcll(ms);
-                             if (nin >= kWave) drain(qin, nin, std::false_type{});
-                             if (nsh >= kWave) drain(qsh, nsh, std::true_type{});
-                           });
-    wave_sync_lds();
-    if (nin > 0) brick_batch<false, COUNT>(a, bn, qin, nin, acc, use);
-    if (nsh > 0) brick_batch<true, COUNT>(a, bn, qsh, nsh, acc, use);
-    queued += nin + nsh;
-  }
-  // node sums across the wave: lane L adds node L % 16 over the 16 lanes of
-  // part L / 16, then the four parts are added
-  float* red = reinterpret_cast<float*>(lds);
   wave_sync_lds();
 #pragma unroll
   for (int l = 0; l < kGroup; ++l) red[lane * kRedPitch + l] = acc[l];
@@ -234,16 +166,211 @@ __global__ __launch_bounds__(kBrickWaves * kWave, 5) void k_brick_sum_f32(BrickA
   for (int t = 0; t < 16; ++t) v += red[(part * 16 + t) * kRedPitch + node];
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
-  if (lane < kGroup && ((bn.vmask >> lane) & 1u)) {
+  if (lane < kGroup && ((bk.vmask >> lane) & 1u)) {
     const int i = lane & 3, j = (lane >> 2) & 1, k = lane >> 3;
     const double hx = a.hk[0] * i, hy = a.hk[1] * j, hz = a.hk[2] * k;
     const double nf = exp2(-((hx * hx + hy * hy) + hz * hz));
-    a.out[(bn.i0 + i) + a.gd.n[0] * ((bn.j0 + j) + a.gd.n[1] * (bn.k0 + k))] = (float)((double)v * nf);
+    a.out[(i0 + i) + a.gd.n[0] * ((bk.j0 + j) + a.gd.n[1] * (bk.k0 + k))] = (float)((double)v * nf);
   }
+}
+
+template <bool COUNT>
+__global__ __launch_bounds__(kTileWaves * kWave, 4) void k_brick_sum_f32(TileArgs a) {
+  // per wave: two source queues per brick and the cell prefix of the walk,
+  // later (the same words) the cross-lane sums
+  constexpr int kQWords = 2 * kTileBricks * kQueue;
+  constexpr int kWaveWords = kQWords + 3 * kWave > kWave * kRedPitch ? kQWords + 3 * kWave : kWave * kRedPitch;
+  static_assert(kWaveWords >= kWave * kRedPitch && kWaveWords >= kQWords + 3 * kWave,
+                "a wave's LDS words hold its queues and walk prefix, and later its cross-lane sums");
+  __shared__ uint32_t lds_s[kTileWaves][kWaveWords];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t* const lds = lds_s[wave];
+  const int lane = threadIdx.x & 63;
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kTileWaves + wave;
+  if (g >= a.nt) return;
+  const GridDesc& gd = a.gd;
+  const int64_t t = a.tiles[g];
+  const uint32_t tmask = (uint32_t)a.masks[g];
+  const int64_t tx = t % a.nt0, ty = (t / a.nt0) % a.nt1, tz = t / (a.nt0 * a.nt1);
+  // the tile's nodes: 4 along x (shared by its bricks), 2 per brick along y and z
+  const int64_t i0 = 4 * tx, j0 = 2 * kTileY * ty, k0 = 2 * kTileZ * tz;
+  const int nx = (int)min<int64_t>(4, gd.n[0] - i0);
+  const int ny = (int)min<int64_t>(2 * kTileY, gd.n[1] - j0);
+  const int nz = (int)min<int64_t>(2 * kTileZ, gd.n[2] - k0);
+  double x[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x[i] = gd.o[0] + (double)(i0 + i) * gd.h[0];
+  const double ax = gd.o[0] + ((double)i0 + 1.5) * gd.h[0];
+  Brick bk[kTileBricks];
+#pragma unroll
+  for (int b = 0; b < kTileBricks; ++b) {
+    const int dyb = b % kTileY, dzb = b / kTileY;
+    Brick& r = bk[b];
+    r.j0 = j0 + 2 * dyb;
+    r.k0 = k0 + 2 * dzb;
+    r.y0 = gd.o[1] + (double)r.j0 * gd.h[1];
+    r.z0 = gd.o[2] + (double)r.k0 * gd.h[2];
+    r.ay = gd.o[1] + ((double)r.j0 + 0.5) * gd.h[1];
+    r.az = gd.o[2] + ((double)r.k0 + 0.5) * gd.h[2];
+    const int by = max(0, min(2, ny - 2 * dyb)), bz = max(0, min(2, nz - 2 * dzb));
+    r.nvalid = ((tmask >> b) & 1u) ? nx * by * bz : 0;
+    r.vmask = 0u;
+    if (r.nvalid > 0)
+      for (int k = 0; k < bz; ++k)
+        for (int j = 0; j < by; ++j) r.vmask |= ((1u << nx) - 1u) << (4 * j + 8 * k);
+  }
+  // every brick's radius (whole 4 x 2 x 2 box) and the tile's (its whole box)
+  const double rad = box_radius(3.0 * gd.h[0], gd.h[1], gd.h[2]);
+  const double r_in = a.rc * (1.0 - 1e-12) - rad, r_out = a.rc * (1.0 + 1e-12) + rad;
+  const double r_in2 = r_in > 0.0 ? r_in * r_in : -1.0, r_out2 = r_out * r_out;
+  const double ac[3] = {ax, gd.o[1] + ((double)j0 + (kTileY - 0.5)) * gd.h[1],
+                        gd.o[2] + ((double)k0 + (kTileZ - 0.5)) * gd.h[2]};
+  const double rad_t = box_radius(3.0 * gd.h[0], (2 * kTileY - 1) * gd.h[1], (2 * kTileZ - 1) * gd.h[2]);
+  const double rt_in = a.rc * (1.0 - 1e-12) - rad_t, rt_out = a.rc * (1.0 + 1e-12) + rad_t;
+  const double rt_in2 = rt_in > 0.0 ? rt_in * rt_in : -1.0, rt_out2 = rt_out * rt_out;
+
+  int64_t use = 0, queued = 0;
+  float acc[kTileBricks][kGroup];
+#pragma unroll
+  for (int b = 0; b < kTileBricks; ++b)
+#pragma unroll
+    for (int l = 0; l < kGroup; ++l) acc[b][l] = 0.0f;
+  int nin[kTileBricks] = {}, nsh[kTileBricks] = {};
+  uint32_t* const qbase = lds;
+  int32_t* cpre = reinterpret_cast<int32_t*>(lds + kQWords);
+  int32_t* cst = reinterpret_cast<int32_t*>(lds + kQWords + kWave);
+  uint8_t* cwhole = reinterpret_cast<uint8_t*>(lds + kQWords + 2 * kWave);
+  // take 64 queued sources from the front of a queue and move the rest down
+  auto drain = [&](uint32_t* qq, int& nq, const Brick& r, float (&ab)[kGroup], auto shell) {
+    wave_sync_lds();
+    brick_batch<decltype(shell)::value, COUNT>(a, x, r, qq, kWave, ab, use);
+    const uint32_t rest = lane + kWave < nq ? qq[kWave + lane] : 0u;
+    wave_sync_lds();
+    if (lane + kWave < nq) qq[lane] = rest;
+    nq -= kWave;
+    queued += kWave;
+    wave_sync_lds();
+  };
+  int cl[3], cn[3];
+  cell_cube(ac, rt_out, a.lat, cl, cn);
+  walk_candidates<false>(
+      ac, rt_in2, rt_out2, cl, cn, a.xs, a.cstart, a.ccount, a.cmap, a.lat, cpre, cst, cwhole,
+      [&](bool valid, uint32_t k, bool, bool, bool whole, const double4& s) {
+        const double ex = s.x - ax;
+        const double ex2 = ex * ex;
+#pragma unroll
+        for (int b = 0; b < kTileBricks; ++b) {
+          if (bk[b].nvalid == 0) continue;
+          const double ey = s.y - bk[b].ay, ez = s.z - bk[b].az;
+          const double d2 = (ex2 + ey * ey) + ez * ez;
+          const bool is_in = valid && (whole || d2 <= r_in2);
+          const bool is_sh = valid && !is_in && d2 <= r_out2;
+          const uint64_t mi = ballot(is_in), ms = ballot(is_sh);
+          uint32_t* qin = qbase + (2 * b) * kQueue;
+          uint32_t* qsh = qbase + (2 * b + 1) * kQueue;
+          if (is_in) qin[nin[b] + lanes_below(mi)] = k;
+          if (is_sh) qsh[nsh[b] + lanes_below(ms)] = k;
+          nin[b] += __popcll(mi);
+          nsh[b] += __popcll(ms);
+          if (nin[b] >= kWave) drain(qin, nin[b], bk[b], acc[b], std::false_type{});
+          if (nsh[b] >= kWave) drain(qsh, nsh[b], bk[b], acc[b], std::true_type{});
+        }
+      });
+  wave_sync_lds();
+#pragma unroll
+  for (int b = 0; b < kTileBricks; ++b) {
+    if (bk[b].nvalid == 0) continue;
+    if (nin[b] > 0) brick_batch<false, COUNT>(a, x, bk[b], qbase + (2 * b) * kQueue, nin[b], acc[b], use);
+    if (nsh[b] > 0) brick_batch<true, COUNT>(a, x, bk[b], qbase + (2 * b + 1) * kQueue, nsh[b], acc[b], use);
+    queued += nin[b] + nsh[b];
+  }
+  // the sums of every evaluated brick (the queues' LDS is free now)
+  float* red = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int b = 0; b < kTileBricks; ++b)
+    if (bk[b].nvalid > 0) brick_store(a, bk[b], i0, acc[b], red);
   if (COUNT && lane == 0) {
     a.useful[g] = use;
     a.examined[g] = queued * kGroup;
   }
+}
+
+// Tiles of the listed bricks: tmask[tile] |= bit of the brick.
+__global__ void k_tile_mark(const int64_t* __restrict__ ids, int64_t nact, GridDesc gd, int64_t nt0, int64_t nt1,
+                            unsigned long long* __restrict__ tmask) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nact) return;
+  const int64_t b = ids[e];
+  const int64_t bx = b % gd.nb[0], by = (b / gd.nb[0]) % gd.nb[1], bz = b / (gd.nb[0] * gd.nb[1]);
+  const int64_t t = bx + nt0 * (by / kTileY + nt1 * (bz / kTileZ));
+  atomicOr(tmask + t, 1ull << (by % kTileY + kTileY * (bz % kTileZ)));
+}
+
+// The tile masks of a brick marking (mark[b] != 0: brick b belongs), and
+// flag[t] = 1 for the tiles with a marked brick.
+__global__ void k_tiles_from_marks(const int64_t* __restrict__ mark, GridDesc gd, int64_t nt0, int64_t nt1, int64_t nt,
+                                   int64_t* __restrict__ tmask, int64_t* __restrict__ flag) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int64_t tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
+  int64_t m = 0;
+  for (int b = 0; b < kTileBricks; ++b) {
+    const int64_t by = kTileY * ty + b % kTileY, bz = kTileZ * tz + b / kTileY;
+    if (by < gd.nb[1] && bz < gd.nb[2] && mark[tx + gd.nb[0] * (by + gd.nb[1] * bz)]) m |= int64_t(1) << b;
+  }
+  tmask[t] = m;
+  flag[t] = m != 0 ? 1 : 0;
+}
+
+__global__ void k_fill_zero(int64_t* __restrict__ p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_nonzero(const int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = v[i] != 0 ? 1 : 0;
+}
+
+__global__ void k_tile_compact(const int64_t* __restrict__ tmask, const int64_t* __restrict__ pos, int64_t n,
+                               int64_t* __restrict__ tiles, int64_t* __restrict__ masks) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && tmask[i] != 0) {
+    tiles[pos[i]] = i;
+    masks[pos[i]] = tmask[i];
+  }
+}
+
+inline unsigned blocks_of(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kThreadsT)); }
+
+void tile_dims(const GridDesc& gd, int64_t* nt0, int64_t* nt1, int64_t* nt2) {
+  *nt0 = gd.nb[0];
+  *nt1 = ceil_div(gd.nb[1], kTileY);
+  *nt2 = ceil_div(gd.nb[2], kTileZ);
+}
+
+int64_t tile_count(const GridDesc& gd) {
+  int64_t nt0, nt1, nt2;
+  tile_dims(gd, &nt0, &nt1, &nt2);
+  return nt0 * nt1 * nt2;
+}
+
+// Scan of the tile flags and compaction of the marked tiles: ws holds tmask,
+// flag, pos, tiles, masks (NT each) and the scan's workspace; returns the
+// count (waits for it).
+int64_t compact_tiles(int64_t* ws, int64_t NT, hipStream_t s) {
+  int64_t* tmask = ws;
+  int64_t* flag = ws + NT;
+  int64_t* pos = ws + 2 * NT;
+  scan_exclusive_i64_ws(flag, pos, NT, ws + 5 * NT, s);
+  hipLaunchKernelGGL(k_tile_compact, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, tmask, pos, NT, ws + 3 * NT,
+                     ws + 4 * NT);
+  RBF_HIP(hipGetLastError());
+  int64_t last_pos = 0, last_flag = 0;
+  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (NT - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (NT - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  return last_pos + last_flag;
 }
 
 }  // namespace
@@ -260,13 +387,47 @@ bool brick_sum_applies(const Ctx& c, const rbf_grid& g) {
   return umax * umax + 2.0 * umax * hsum <= 64.0;
 }
 
-void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
-                   float* out, int64_t* useful, int64_t* examined, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  if (nact <= 0) return;
-  BrickArgs a;
-  a.gd = grid_desc(g);
-  a.ids = ids;
-  a.nb = nact;
+int64_t support_tiles_ws_elems(const rbf_grid& g) {
+  const GridDesc gd = grid_desc(g);
+  const int64_t NT = tile_count(gd);
+  return gd.nb[0] * gd.nb[1] * gd.nb[2] + 5 * NT + scan_ws_elems(NT);
+}
+
+int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_t** tiles, const int64_t** masks,
+                      hipStream_t s) {
+  const GridDesc gd = grid_desc(g);
+  int64_t nt0, nt1, nt2;
+  tile_dims(gd, &nt0, &nt1, &nt2);
+  const int64_t NT = nt0 * nt1 * nt2;
+  const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
+  int64_t* mark = ws;
+  int64_t* tw = ws + nbricks;
+  mark_support(c, gd, mark, nbricks, s);
+  hipLaunchKernelGGL(k_tiles_from_marks, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, mark, gd, nt0, nt1, NT, tw,
+                     tw + NT);
+  RBF_HIP(hipGetLastError());
+  const int64_t nt = compact_tiles(tw, NT, s);
+  *tiles = tw + 3 * NT;
+  *masks = tw + 4 * NT;
+  return nt;
+}
+
+void brick_sum_tiles(const Ctx& c, const rbf_grid& g, const int64_t* tiles, const int64_t* masks, int64_t nt,
+                     const double* w_sorted, float* out, int64_t* useful, int64_t* examined, hipStream_t s,
+                     hipEvent_t t0, hipEvent_t t1) {
+  if (useful) *useful = 0;
+  if (examined) *examined = 0;
+  if (nt <= 0) return;
+  const GridDesc gd = grid_desc(g);
+  int64_t nt0, nt1, nt2;
+  tile_dims(gd, &nt0, &nt1, &nt2);
+  TileArgs a;
+  a.gd = gd;
+  a.tiles = tiles;
+  a.masks = masks;
+  a.nt = nt;
+  a.nt0 = nt0;
+  a.nt1 = nt1;
   a.xs = c.xs;
   a.w = w_sorted;
   a.cstart = c.cell_start;
@@ -278,14 +439,47 @@ void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t 
   a.sqrt_k = c.sqrt_k;
   for (int d = 0; d < 3; ++d) a.hk[d] = g.h[d] * c.sqrt_k;
   a.out = out;
-  a.useful = useful;
-  a.examined = examined;
-  const int64_t nb = ceil_div(nact, kBrickWaves);
-  if (useful && examined)
-    hipExtLaunchKernelGGL(k_brick_sum_f32<true>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, t0, t1, 0, a);
-  else
-    hipExtLaunchKernelGGL(k_brick_sum_f32<false>, dim3((unsigned)nb), dim3(kBrickWaves * kWave), 0, s, t0, t1, 0, a);
+  a.useful = nullptr;
+  a.examined = nullptr;
+  const int64_t nb = ceil_div(nt, kTileWaves);
+  if (useful && examined) {
+    int64_t* cnt = talloc<int64_t>(2 * nt + 2);
+    a.useful = cnt;
+    a.examined = cnt + nt;
+    hipExtLaunchKernelGGL(k_brick_sum_f32<true>, dim3((unsigned)nb), dim3(kTileWaves * kWave), 0, s, t0, t1, 0, a);
+    RBF_HIP(hipGetLastError());
+    sum_i64(cnt, nt, cnt + 2 * nt, s);
+    sum_i64(cnt + nt, nt, cnt + 2 * nt + 1, s);
+    int64_t h[2] = {0, 0};
+    RBF_HIP(hipMemcpyAsync(h, cnt + 2 * nt, sizeof(h), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    temp_free(cnt);
+    *useful = h[0];
+    *examined = h[1];
+  } else {
+    hipExtLaunchKernelGGL(k_brick_sum_f32<false>, dim3((unsigned)nb), dim3(kTileWaves * kWave), 0, s, t0, t1, 0, a);
+    RBF_HIP(hipGetLastError());
+  }
+}
+
+void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t nact, const double* w_sorted,
+                   float* out, int64_t* useful, int64_t* examined, hipStream_t s) {
+  if (useful) *useful = 0;
+  if (examined) *examined = 0;
+  if (nact <= 0) return;
+  const GridDesc gd = grid_desc(g);
+  int64_t nt0, nt1, nt2;
+  tile_dims(gd, &nt0, &nt1, &nt2);
+  const int64_t NT = nt0 * nt1 * nt2;
+  int64_t* ws = talloc<int64_t>(5 * NT + scan_ws_elems(NT));
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, ws, NT);
+  hipLaunchKernelGGL(k_tile_mark, dim3(blocks_of(nact)), dim3(kThreadsT), 0, s, ids, nact, gd, nt0, nt1,
+                     reinterpret_cast<unsigned long long*>(ws));
+  hipLaunchKernelGGL(k_nonzero, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, ws, NT, ws + NT);
   RBF_HIP(hipGetLastError());
+  const int64_t nt = compact_tiles(ws, NT, s);
+  brick_sum_tiles(c, g, ws + 3 * NT, ws + 4 * NT, nt, w_sorted, out, useful, examined, s);
+  temp_free(ws);
 }
 
 }  // namespace rbf

@@ -583,16 +583,7 @@ void net_eval_grid_culled(const Ctx& c, const NetData& d, const double* w_sorted
     RBF_HIP(hipGetLastError());
     if (brick_sum_applies(c, g)) {
       // the bricks walk their candidate sources directly, as in the plain grid
-      int64_t* cnt = talloc<int64_t>(2 * nkeep + 2);
-      brick_sum_f32(c, g, kept, nkeep, w_sorted, out, cnt, cnt + nkeep, s);
-      sum_i64(cnt, nkeep, cnt + 2 * nkeep, s);
-      sum_i64(cnt + nkeep, nkeep, cnt + 2 * nkeep + 1, s);
-      int64_t h[2] = {0, 0};
-      RBF_HIP(hipMemcpyAsync(h, cnt + 2 * nkeep, sizeof(h), hipMemcpyDeviceToHost, s));
-      RBF_HIP(hipStreamSynchronize(s));
-      st->useful_pairs = h[0];
-      st->examined_pairs = h[1];
-      temp_free(cnt);
+      brick_sum_f32(c, g, kept, nkeep, w_sorted, out, &st->useful_pairs, &st->examined_pairs, s);
     } else {
       TargetSet ts;
       brick_targets(c, g, kept, nkeep, ts, s);

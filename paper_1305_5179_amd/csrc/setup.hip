@@ -633,7 +633,7 @@ __global__ __launch_bounds__(kThreads, LATTICE ? 1 : 8) void k_lists(const doubl
   int qn = 0;
   const int64_t cand = walk_candidates<MODE == kBound>(
       ac, r_in2, r_out2, cl, cn, xs, cstart, ccount, cmap, lat, cpre_s[wave], cst_s[wave], cwhole_s[wave],
-      [&](bool, uint32_t k, bool is_in, bool is_shell) {
+      [&](bool, uint32_t k, bool is_in, bool is_shell, bool, const double4&) {
         const uint64_t mi = ballot(is_in), ms = ballot(is_shell);
         if (WRITE && is_in) put_inner(o, n.n_in + lanes_below(mi), k);
         n.n_in += __popcll(mi);
@@ -1015,20 +1015,38 @@ void bounding_box(const double* X, int64_t m, double* box6, double* scratch, hip
   RBF_HIP(hipGetLastError());
 }
 
-void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+// Workspace of scan_exclusive_i64_ws for n entries: the tile sums and their
+// scan, two entries per tile at every level of the recursion.
+int64_t scan_ws_elems(int64_t n) {
+  int64_t total = 0;
+  while (n > 0) {
+    const int64_t nb = ceil_div(n, kScanTile);
+    total += 2 * nb;
+    if (nb <= 1) break;
+    n = nb;
+  }
+  return total;
+}
+
+void scan_exclusive_i64_ws(const int64_t* in, int64_t* out, int64_t n, int64_t* ws, hipStream_t s) {
   if (n <= 0) return;
-  int64_t nb = ceil_div(n, kScanTile);
-  int64_t* sums = talloc<int64_t>(nb);
-  int64_t* sums_scanned = talloc<int64_t>(nb);
+  const int64_t nb = ceil_div(n, kScanTile);
+  int64_t* sums = ws;
+  int64_t* sums_scanned = ws + nb;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kThreads), 0, s, in, out, n, sums);
   RBF_HIP(hipGetLastError());
   if (nb > 1) {
-    scan_exclusive_i64(sums, sums_scanned, nb, s);
+    scan_exclusive_i64_ws(sums, sums_scanned, nb, ws + 2 * nb, s);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kThreads), 0, s, out, n, sums_scanned);
     RBF_HIP(hipGetLastError());
   }
-  temp_free(sums);
-  temp_free(sums_scanned);
+}
+
+void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t* ws = talloc<int64_t>(scan_ws_elems(n));
+  scan_exclusive_i64_ws(in, out, n, ws, s);
+  temp_free(ws);
 }
 
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
@@ -1314,6 +1332,28 @@ GridDesc grid_desc(const rbf_grid& g) {
   return gd;
 }
 
+// mark[b] = 1 for the bricks with an occupied cell within the cutoff (plus a
+// node of slack), 0 for the others.
+void mark_support(const Ctx& c, const GridDesc& gd, int64_t* mark, int64_t nbricks, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
+  hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
+                     c.cutoff, gd, mark);
+  RBF_HIP(hipGetLastError());
+}
+
+// Marks the bricks with a centre in reach (mark, 0/1) and scans the marks
+// (pos); returns their count.  scan_ws: scan_ws_elems(nbricks) entries.
+static int64_t mark_support_bricks(const Ctx& c, const GridDesc& gd, int64_t nbricks, int64_t* mark, int64_t* pos,
+                                   int64_t* scan_ws, hipStream_t s) {
+  mark_support(c, gd, mark, nbricks, s);
+  scan_exclusive_i64_ws(mark, pos, nbricks, scan_ws, s);
+  int64_t last_pos = 0, last_mark = 0;
+  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipStreamSynchronize(s));
+  return last_pos + last_mark;
+}
+
 int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids_out, hipStream_t s) {
   const GridDesc gd = grid_desc(g);
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
@@ -1321,21 +1361,14 @@ int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids_out, hipSt
   if (!std::isfinite(c.cutoff)) return nbricks;
   int64_t* mark = talloc<int64_t>(nbricks);
   int64_t* pos = talloc<int64_t>(nbricks);
-  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, (int64_t)0, nbricks);
-  hipLaunchKernelGGL(k_mark_bricks, dim3(grid_for(c.n_cells)), dim3(kThreads), 0, s, c.cell_xyz, c.n_cells, c.lat,
-                     c.cutoff, gd, mark);
-  RBF_HIP(hipGetLastError());
-  scan_exclusive_i64(mark, pos, nbricks, s);
-  int64_t last_pos = 0, last_mark = 0;
-  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipStreamSynchronize(s));
-  const int64_t nact = last_pos + last_mark;
+  int64_t* ws = talloc<int64_t>(scan_ws_elems(nbricks));
+  const int64_t nact = mark_support_bricks(c, gd, nbricks, mark, pos, ws, s);
   int64_t* ids = talloc<int64_t>(nact);
   hipLaunchKernelGGL(k_compact, dim3(grid_for(nbricks)), dim3(kThreads), 0, s, mark, pos, nbricks, ids);
   RBF_HIP(hipGetLastError());
   temp_free(mark);
   temp_free(pos);
+  temp_free(ws);
   *ids_out = ids;
   return nact;
 }
