@@ -305,6 +305,24 @@ int rbf_eval_grid_culled(rbf_ctx* ctx, const double* c, const rbf_grid* grid, fl
 /* Sizes and pair counts of the context (host call, no device work). */
 int rbf_get_stats(const rbf_ctx* ctx, rbf_stats* stats);
 
+/* rbf_eval_grid in float32 for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation): it calls no hipMalloc/hipFree and no allocating library
+ * routine.  The same result as rbf_eval_grid(..., RBF_FP32, ...), bit for
+ * bit (the same kernels); its scratch memory (the marks of the bricks of
+ * 4 x 2 x 2 nodes with a centre in reach, and the list of the tiles of two
+ * bricks that hold them) is a fixed array of 48 MiB + 64 KiB in device memory
+ * that the library holds on every device it runs on until the process ends.
+ *   c: device 3n float64 weights; out: device float32, dims[0]*dims[1]*dims[2]
+ *   values, x fastest.
+ * Limits (RBF_EINVAL with a message beyond them): a context with a cutoff,
+ * a grid whose spacing is fine against sigma (the brick sums apply; else use
+ * rbf_eval_grid), at most 2^21 bricks (e.g. 256^3 nodes = 2^20 bricks)
+ * whose marks and tile list fit the array, the context's device current.  Every call on a device shares that device's
+ * array and the context's work vectors: calls that overlap on one device
+ * (two streams, two threads) race.  Synchronises with `stream`. */
+int rbf_eval_grid_noalloc(rbf_ctx* ctx, const double* c, const rbf_grid* grid, float* out, void* stream);
+
 /* Pairs one rbf_eval_grid over `grid` evaluates: useful = node-centre pairs
  * with r^2 <= cutoff^2 (decided in float64), examined = pairs the kernel
  * computes.  Synchronises with `stream`. */

@@ -580,6 +580,72 @@ int rbf_eval_grid(rbf_ctx* c, const double* cw, const rbf_grid* grid, void* out,
   });
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free float32 grid evaluation (rbf_eval_grid_noalloc).  Its only
+// scratch memory (the brick marks, their scan and the list of bricks with a
+// centre in reach) lives in `scratch`, a fixed array in device memory: each
+// device the library runs on holds its own copy until the process ends.  In
+// host code the array's name is not a device address; its address on a
+// device comes from hipGetSymbolAddress, looked up once per device with that
+// device current, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNoAllocMaxBricks = int64_t(1) << 21;           // bricks of 4 x 2 x 2 nodes
+constexpr int64_t kNoAllocScratch = 3 * kNoAllocMaxBricks + 8192;  // int64 entries: 48 MiB + 64 KiB
+static __device__ __align__(256) int64_t scratch[kNoAllocScratch];
+
+int64_t* scratch_address(int dev) {
+  static std::mutex mu;
+  static std::map<int, int64_t*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  int64_t* p = nullptr;
+  RBF_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+  if (!p) throw Error{RBF_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array"};
+  addr.emplace(dev, p);
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rbf_eval_grid_noalloc(rbf_ctx* c, const double* cw, const rbf_grid* grid, float* out, void* stream) {
+  if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");
+  int st = check_grid(c, grid);
+  if (st != RBF_OK) return st;
+  if (!is_device_ptr(cw) || !is_device_ptr(out)) return fail(c, RBF_EINVAL, "c and out must be device pointers");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return fail(c, RBF_EINVAL, "the context's device must be the current device");
+  if (!brick_sum_applies(*c, *grid))
+    return fail(c, RBF_EINVAL,
+                "rbf_eval_grid_noalloc sums float32 grids brick by brick: it needs a cutoff and a grid spacing "
+                "fine against sigma (rbf_eval_grid handles the other grids)");
+  const GridDesc gd = grid_desc(*grid);
+  const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
+  if (nbricks > kNoAllocMaxBricks || support_tiles_ws_elems(*grid) > kNoAllocScratch)
+    return fail(c, RBF_EINVAL,
+                "grid of " + std::to_string(nbricks) + " bricks of 4 x 2 x 2 nodes: rbf_eval_grid_noalloc holds at "
+                "most " + std::to_string(kNoAllocMaxBricks) + " (use rbf_eval_grid)");
+  return guarded(c, [&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    int64_t* ws = scratch_address(dev);
+    const int64_t total = grid->dims[0] * grid->dims[1] * grid->dims[2];
+    gather_to_sorted(cw, c->perm, c->m, c->vin, s);
+    fill_f32(out, 0.0f, total, s);
+    const int64_t *tiles = nullptr, *masks = nullptr;
+    const int64_t nt = support_tiles(*c, *grid, ws, &tiles, &masks, s);
+    brick_sum_tiles(*c, *grid, tiles, masks, nt, c->vin, out, nullptr, nullptr, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    return RBF_OK;
+  });
+}
+
 int rbf_count_grid_pairs(rbf_ctx* c, const rbf_grid* grid, int64_t* useful, int64_t* examined, void* stream) {
   TempStream temp_scope((hipStream_t)stream);
   if (!c) return fail(nullptr, RBF_EINVAL, "ctx is NULL");

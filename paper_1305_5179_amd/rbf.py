@@ -28,7 +28,7 @@ EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "
            "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error",
            "rbf_default_schwarz_opts", "rbf_schwarz_setup", "rbf_schwarz_apply", "rbf_schwarz_get_info",
            "rbf_schwarz_subdomains", "rbf_net_set", "rbf_net_get", "rbf_net_forward", "rbf_net_gradient",
-           "rbf_net_train", "rbf_eval_grid_culled", "rbf_arnoldi"]
+           "rbf_net_train", "rbf_eval_grid_culled", "rbf_arnoldi", "rbf_eval_grid_noalloc"]
 RBF_NET_PARAMS = 50177
 
 
@@ -107,6 +107,7 @@ def load_library() -> C.CDLL:
     lib.rbf_eval_points.argtypes = [vp, vp, vp, i64, vp, i32, vp]
     lib.rbf_density.argtypes = [vp, vp, i64, C.POINTER(DensityInfo), vp]
     lib.rbf_arnoldi.argtypes = [vp, vp, i32, i32, i32, vp, C.POINTER(dbl), C.POINTER(i32), vp]
+    lib.rbf_eval_grid_noalloc.argtypes = [vp, vp, C.POINTER(Grid), vp, vp]
     lib.rbf_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
     lib.rbf_profile_begin.argtypes = []
