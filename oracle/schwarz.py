@@ -29,14 +29,22 @@ subdomains, the overlap and the local matrices open; the readings here
     paper, and the shift is what keeps the local inverses bounded).
   * cap follows from the largest block: the largest p with
     3p + ceil(3p pct / 100) <= max_block.
+  * Small leaves merged (min_block > 0).  The leaves are taken in the
+    octree's depth-first order (children by the digit bx + 2 by + 4 bz of
+    their cell, the runs of a finest cell by index) and consecutive leaves
+    are joined into one core: the core being built is closed before the next
+    leaf when its block (3p centres plus their overlap) already reaches
+    min_block or when the next leaf would take it above cap points.  The
+    domain split then follows the density along the curve, as the paper's
+    subdomains of uneven size, without tiny blocks.
 """
 from __future__ import annotations
 
 
 import numpy as np
 
-__all__ = ["overlap_count", "core_cap", "octree_cores", "core_centres", "overlap", "subdomains", "local_matrix",
-           "schwarz_apply", "schwarz_matrix"]
+__all__ = ["overlap_count", "core_cap", "block_size", "octree_cores", "merge_leaves", "core_centres", "overlap",
+           "subdomains", "local_matrix", "schwarz_apply", "schwarz_matrix"]
 
 
 def _phi(r2, sigma):
@@ -59,6 +67,11 @@ def core_cap(max_block: int, pct: int) -> int:
     while p > 1 and 3 * p + overlap_count(3 * p, pct) > max_block:
         p -= 1
     return max(p, 1)
+
+
+def block_size(points: int, pct: int) -> int:
+    """Centres of a subdomain whose core holds `points` surface points."""
+    return 3 * points + overlap_count(3 * points, pct)
 
 
 def octree_cores(P: np.ndarray, cap: int) -> list[np.ndarray]:
@@ -91,6 +104,26 @@ def octree_cores(P: np.ndarray, cap: int) -> list[np.ndarray]:
     return leaves
 
 
+def merge_leaves(leaves: list[np.ndarray], cap: int, min_block: int, pct: int) -> list[np.ndarray]:
+    """Consecutive leaves (in the order octree_cores returns them) joined
+    into cores of at least min_block centres with their overlap where the
+    cap allows; min_block <= 0 keeps every leaf."""
+    if min_block <= 0:
+        return list(leaves)
+    out: list[np.ndarray] = []
+    cur: list[np.ndarray] = []
+    npts = 0
+    for leaf in leaves:
+        if cur and (block_size(npts, pct) >= min_block or npts + leaf.size > cap):
+            out.append(np.sort(np.concatenate(cur)))
+            cur, npts = [], 0
+        cur.append(leaf)
+        npts += leaf.size
+    if cur:
+        out.append(np.sort(np.concatenate(cur)))
+    return out
+
+
 def core_centres(points: np.ndarray, n: int) -> np.ndarray:
     """The three centres of each surface point of a core (rows i, N+i, 2N+i)."""
     points = np.asarray(points, dtype=np.int64)
@@ -109,13 +142,13 @@ def overlap(X: np.ndarray, core: np.ndarray, k: int) -> np.ndarray:
     return outside[order[:k]]
 
 
-def subdomains(points: np.ndarray, X: np.ndarray, max_block: int = 192, pct: int = 10):
+def subdomains(points: np.ndarray, X: np.ndarray, max_block: int = 192, pct: int = 10, min_block: int = 0):
     """[(core centres, overlap centres)] for the surface points `points`
     (N x 3) and the centres X (3N x 3, paper order)."""
     n = np.asarray(points).shape[0]
     cap = core_cap(max_block, pct)
     out = []
-    for leaf in octree_cores(points, cap):
+    for leaf in merge_leaves(octree_cores(points, cap), cap, min_block, pct):
         core = core_centres(leaf, n)
         out.append((core, overlap(X, core, overlap_count(core.size, pct))))
     return out

@@ -76,6 +76,82 @@ def test_octree_leaves_match_the_definition(cap):
             assert sorted(leaf.tolist()) in runs
 
 
+def _morton_full_depth(qcell, level):
+    """The depth-first position of a cell at `level`: its coordinates' bits
+    interleaved (x lowest), padded to the finest level."""
+    key = 0
+    for b in range(level):
+        bit = level - 1 - b
+        digit = ((qcell[0] >> bit) & 1) + 2 * ((qcell[1] >> bit) & 1) + 4 * ((qcell[2] >> bit) & 1)
+        key = key * 8 + digit
+    return key << (3 * (10 - level))
+
+
+@pytest.mark.parametrize("cap", [5, 20])
+def test_leaves_come_in_depth_first_order(cap):
+    """octree_cores returns its leaves in increasing Morton order of their
+    cells (x the lowest bit), the runs of one finest cell by index: the
+    order in which leaves are merged."""
+    P = _cloud(400, 3)
+    leaves = S.octree_cores(P, cap)
+    lo = P.min(0)
+    side = (P.max(0) - lo).max()
+    q = np.clip(np.floor((P - lo) / (side / 1024)), 0, 1023).astype(np.int64)
+    keys = []
+    for leaf in leaves:
+        # the leaf's level: the coarsest cell of its first point holding only leaf points
+        first = leaf[0]
+        for level in range(11):
+            sh = 10 - level
+            cell = [i for i in range(len(P)) if all((q[i, d] >> sh) == (q[first, d] >> sh) for d in range(3))]
+            if set(cell) <= set(leaf.tolist()) or level == 10:
+                break
+        keys.append((_morton_full_depth(q[first] >> (10 - level), level), int(leaf[0])))
+    assert keys == sorted(keys)
+
+
+def _merge_by_definition(leaves, cap, min_block, pct):
+    """Greedy runs of consecutive leaves, restated: a run grows while its
+    block is below min_block and the next leaf fits under the cap."""
+    runs, i = [], 0
+    while i < len(leaves):
+        j = i + 1
+        pts = leaves[i].size
+        while j < len(leaves) and 3 * pts + -(-(3 * pts * pct) // 100) < min_block and pts + leaves[j].size <= cap:
+            pts += leaves[j].size
+            j += 1
+        runs.append((i, j))
+        i = j
+    return runs
+
+
+@pytest.mark.parametrize("cap,min_block,pct", [(20, 64, 10), (20, 30, 0), (5, 200, 10), (50, 16, 25)])
+def test_merged_cores_are_greedy_runs_of_leaves(cap, min_block, pct):
+    P = _cloud(400, 3)
+    leaves = S.octree_cores(P, cap)
+    merged = S.merge_leaves(leaves, cap, min_block, pct)
+    runs = _merge_by_definition(leaves, cap, min_block, pct)
+    assert len(merged) == len(runs)
+    for core, (i, j) in zip(merged, runs):
+        assert np.array_equal(core, np.sort(np.concatenate(leaves[i:j])))
+        assert core.size <= cap
+    assert np.array_equal(np.sort(np.concatenate(merged)), np.arange(len(P)))
+    # fewer, larger cores than leaves whenever small leaves exist
+    small = [l for l in leaves if S.block_size(l.size, pct) < min_block]
+    if len(small) > 1:
+        assert len(merged) < len(leaves)
+
+
+def test_merge_off_keeps_the_leaves():
+    P = _cloud(400, 3)
+    leaves = S.octree_cores(P, 20)
+    merged = S.merge_leaves(leaves, 20, 0, 10)
+    assert len(merged) == len(leaves) and all(np.array_equal(a, b) for a, b in zip(merged, leaves))
+    X, _ = O.extended_centres(P, P, 0.01)
+    subs = S.subdomains(P, X, max_block=66, pct=10)
+    assert len(subs) == len(leaves)
+
+
 def test_overlap_is_the_k_nearest():
     rng = np.random.default_rng(5)
     X = rng.uniform(size=(90, 3))
