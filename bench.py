@@ -229,7 +229,8 @@ def main():
             ctx.matvec(x, y, prec=prec)
         torch.cuda.synchronize()
         phases[key] = 1e3 * (time.perf_counter() - t) / 5
-    schwarz = schwarz_measurement(rbf, ctx, torch, x)
+    schwarz = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_192)
+    schwarz1024 = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_1024)
     dens = ctx.density()
     density = {"q": dens.q, "h_max": dens.h_max, "h": dens.h, "h_from": "sqrt(2) h_max (eq. hmax)",
                "sigma_sep": dens.sigma_sep, "sigma_fill": dens.sigma_fill, "sigma": sigma,
@@ -277,6 +278,7 @@ def main():
                   "applications_per_step": applications},
         "grid_kernel_f32": evaluation,
         "schwarz": schwarz,
+        "schwarz1024": schwarz1024,
         "density": density,
         "fp64_kernel": {"launches": prof.launches[OP][F64],
                         "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
@@ -306,16 +308,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def schwarz_measurement(rbf, ctx, torch, x):
-    """The Schwarz preconditioner with its default options: setup time, and
-    the time of one apply (gather, local products, sums, scatter) from torch
-    events on the stream the library runs on.  The apply streams the float32
-    local inverses once: its algorithmic bytes are those plus the vector
-    traffic (members gathered, local results written and summed, result
-    written), against the 8 TB/s of HBM."""
+def schwarz_measurement(rbf, ctx, torch, x, opts):
+    """The Schwarz preconditioner with the given options: setup time (the
+    local inverses' own device time apart), and the time of one apply
+    (gather, local products, sums, scatter) from torch events on the stream
+    the library runs on.  The apply streams the float32 local inverses once:
+    its algorithmic bytes are those plus the vector traffic (members
+    gathered, local results written and summed, result written), against the
+    8 TB/s of HBM."""
     torch.cuda.synchronize()
     t = time.perf_counter()
-    info = ctx.schwarz_setup()
+    info = ctx.schwarz_setup(**opts)
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t)
     z = torch.empty_like(x)
@@ -330,9 +333,11 @@ def schwarz_measurement(rbf, ctx, torch, x):
     apply_ms = e0.elapsed_time(e1) / reps
     m = x.numel()
     alg_bytes = info.inverse_bytes + 8 * (3 * info.n_members + 4 * m)
-    return {"form": "additive", "max_block": 192, "overlap_pct": 10, "shift": 0.1,
-            "n_sub": info.n_sub, "n_members": info.n_members, "max_members": info.max_members,
-            "inverse_bytes": info.inverse_bytes, "retries": info.retries, "setup_ms": setup_ms,
+    return {"form": "additive", "options": opts, "overlap_pct": 10, "shift": 0.1,
+            "n_sub": info.n_sub, "n_members": info.n_members, "min_members": info.min_members,
+            "max_members": info.max_members, "inverse_bytes": info.inverse_bytes, "retries": info.retries,
+            "setup_ms": setup_ms, "factor_ms": info.factor_ms,
+            "apply_shape": {"threads": info.apply_threads, "workgroups": info.apply_blocks},
             "apply_ms": apply_ms,
             "apply_roofline": {"bound": "hbm", "achieved": alg_bytes / (apply_ms * 1e-3) / 1e9, "peak": 8000.0,
                                "unit": "GB/s", "frac": alg_bytes / (apply_ms * 1e-3) / 8e12,
@@ -403,12 +408,20 @@ def cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, n_samples, epochs):
             "sign_error_rate": float(wrong.sum()) / max(int(signed.sum()), 1)}
 
 
+# the Schwarz configurations: blocks up to 192 centres (every block inverted
+# in LDS; about 9,500 subdomains on the torus), and blocks of 64..1024
+# centres (small octree leaves merged; about 2,000 subdomains, the larger
+# blocks inverted in global memory), each with shift 0.1
+SCHWARZ_192 = dict(max_block=192)
+SCHWARZ_1024 = dict(max_block=1024, min_block=64)
+
 SOLVE_RUNS = (
-    # name, mode, basis, Schwarz preconditioner
-    ("ir_fp32", "ir", "fp32", False),
-    ("ir_fp32_basis64", "ir", "fp64", False),
-    ("ir_fp32_schwarz", "ir", "fp32", True),
-    ("plain_fp64", "plain", "fp64", False),
+    # name, mode, basis, Schwarz options (None: no preconditioner)
+    ("ir_fp32", "ir", "fp32", None),
+    ("ir_fp32_basis64", "ir", "fp64", None),
+    ("ir_fp32_schwarz", "ir", "fp32", SCHWARZ_192),
+    ("ir_fp32_schwarz1024", "ir", "fp32", SCHWARZ_1024),
+    ("plain_fp64", "plain", "fp64", None),
 )
 
 
@@ -427,13 +440,12 @@ def solve_comparison(rbf, torch, pts, nrm, cfg, g, iters):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ctx = rbf.Rbf(pts, nrm, cfg["eps"], cfg["sigma"], cfg["cutoff"])
-        if pre:
-            ctx.schwarz_setup()
+        sinfo = ctx.schwarz_setup(**pre) if pre is not None else None
         torch.cuda.synchronize()
         setup_ms = 1e3 * (time.perf_counter() - t0)
         m = rbf.RBF_SOLVE_IR_FP32 if mode == "ir" else rbf.RBF_SOLVE_PLAIN_FP64
         coef, info = ctx.solve(tol=1e-8, restart=cfg["restart"], max_iters=iters, mode=m,
-                               precond=rbf.RBF_PRECOND_SCHWARZ if pre else rbf.RBF_PRECOND_NONE,
+                               precond=rbf.RBF_PRECOND_SCHWARZ if pre is not None else rbf.RBF_PRECOND_NONE,
                                basis=rbf.RBF_FP32 if basis == "fp32" else rbf.RBF_FP64)
         t1 = time.perf_counter()
         prec = rbf.RBF_FP32 if mode == "ir" else rbf.RBF_FP64
@@ -446,7 +458,10 @@ def solve_comparison(rbf, torch, pts, nrm, cfg, g, iters):
             grids["abs_sum"] = ctx.eval_grid(torch.abs(coef), g.origin, g.h, g.dims, prec=rbf.RBF_FP64)
         grids[name] = out
         res[name] = {"operator": "float32" if mode == "ir" else "float64", "basis": basis,
-                     "precond": "schwarz" if pre else "none", "grid": "float32" if prec == rbf.RBF_FP32 else "float64",
+                     "precond": "none" if pre is None else
+                     {"schwarz": pre, "n_sub": sinfo.n_sub, "block_sizes": [sinfo.min_members, sinfo.max_members],
+                      "factor_ms": sinfo.factor_ms},
+                     "grid": "float32" if prec == rbf.RBF_FP32 else "float64",
                      "setup_ms": setup_ms, "grid_ms": grid_ms, "status": rbf.STATUS_NAMES[info.status],
                      "iters": info.iters, "rel_resid": info.rel_resid, "stall": min(info.history),
                      "solve_ms": info.history_ms[-1] if info.history_ms else 0.0,

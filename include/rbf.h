@@ -77,12 +77,18 @@ typedef struct {
 } rbf_solve_opts;
 
 typedef struct {
-    int max_block;     /* largest subdomain, core + overlap centres, 3..192 (default 192) */
+    int max_block;     /* largest subdomain, core + overlap centres, 3..1024 (default 192) */
     int overlap_pct;   /* overlap size in percent of the core, 0..100 (default 10) */
     int restricted;    /* 1: restricted additive Schwarz (core rows of each local solution);
                           0: additive (every row, summed) (default 0) */
-    int reserved;      /* must be 0 */
+    int min_block;     /* 0: every octree leaf is a core (default); > 0: consecutive leaves are
+                          joined while the block (core + overlap) is below min_block and the
+                          cap allows, 0..max_block */
     double shift;      /* added to the unit diagonal of every local block, >= 0 (default 0.1) */
+    int tune;          /* 1: time the apply kernel's launch shapes at setup and keep the
+                          fastest (default); 0: the fixed shape (256 threads, 4 workgroups
+                          per compute unit) */
+    int reserved;      /* must be 0 */
 } rbf_schwarz_opts;
 
 typedef struct {
@@ -92,6 +98,10 @@ typedef struct {
     int64_t inverse_bytes; /* device memory of the local inverses */
     int retries;           /* local blocks redone with a larger shift */
     double max_shift;      /* the largest shift a block ended with */
+    int64_t min_members;   /* the smallest subdomain */
+    int apply_threads;     /* launch shape of the apply: threads per workgroup (rows per task) */
+    int apply_blocks;      /* and workgroups of its persistent launch */
+    double factor_ms;      /* device time of the local inverses (all blocks, one launch) */
 } rbf_schwarz_info;
 
 typedef struct {
@@ -234,9 +244,17 @@ int rbf_arnoldi(rbf_ctx* ctx, const double* v0, int m, int op_prec, int basis, d
  *   core holds the three centres of each of its points.  The overlap adds
  *   the ceil(overlap_pct |core| / 100) centres outside the core nearest to it
  *   (squared float64 distance to the nearest core centre, ties by index).
+ *   With min_block > 0 the leaves, in the octree's depth-first order
+ *   (children by the digit bx + 2 by + 4 bz of their cell), are joined into
+ *   runs: the core being built is closed before the next leaf once its block
+ *   reaches min_block or when the leaf would take it above p points.
  *   Local matrices: the Gaussian of the subdomain without truncation plus
  *   shift * I, inverted in float64 (a block found indefinite is redone with
- *   ten times the shift, at most 8 times), kept in float32.
+ *   ten times the shift, at most 8 times), kept in float32.  All blocks are
+ *   inverted by one persistent launch, largest first.
+ *   Apply: one persistent launch takes strips of rows of the blocks
+ *   (largest first, cyclic over its workgroups); the additive form adds a
+ *   second launch that sums each centre's rows in subdomain order.
  * opts: NULL for defaults.  Replaces the context's previous preconditioner.
  * Synchronises with `stream`.  RBF_EBREAKDOWN when a block stays indefinite. */
 int rbf_default_schwarz_opts(rbf_schwarz_opts* opts);

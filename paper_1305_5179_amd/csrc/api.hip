@@ -759,11 +759,13 @@ int rbf_arnoldi(rbf_ctx* c, const double* v0, int m, int op_prec, int basis, dou
 
 int rbf_default_schwarz_opts(rbf_schwarz_opts* o) {
   if (!o) return fail(nullptr, RBF_EINVAL, "opts is NULL");
-  o->max_block = kSchwarzMaxBlock;
+  o->max_block = kSchwarzLdsBlock;
   o->overlap_pct = 10;
   o->restricted = 0;
-  o->reserved = 0;
+  o->min_block = 0;
   o->shift = 0.1;
+  o->tune = 1;
+  o->reserved = 0;
   return RBF_OK;
 }
 
@@ -774,7 +776,9 @@ int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream)
   rbf_default_schwarz_opts(&o);
   if (opts_in) o = *opts_in;
   if (o.max_block < 3 || o.max_block > kSchwarzMaxBlock)
-    return fail(c, RBF_EINVAL, "max_block must be in 3..192");
+    return fail(c, RBF_EINVAL, "max_block must be in 3..1024");
+  if (o.min_block < 0 || o.min_block > o.max_block) return fail(c, RBF_EINVAL, "min_block must be in 0..max_block");
+  if (o.tune != 0 && o.tune != 1) return fail(c, RBF_EINVAL, "tune must be 0 or 1");
   if (o.overlap_pct < 0 || o.overlap_pct > 100) return fail(c, RBF_EINVAL, "overlap_pct must be in 0..100");
   if (o.restricted != 0 && o.restricted != 1) return fail(c, RBF_EINVAL, "restricted must be 0 or 1");
   if (o.reserved != 0) return fail(c, RBF_EINVAL, "reserved must be 0");
@@ -785,7 +789,7 @@ int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream)
     hipStream_t s = (hipStream_t)stream;
     free_schwarz(c->schwarz);   // stream-ordered release: queued work on this stream finishes first
     c->schwarz = nullptr;
-    c->schwarz = schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.shift, s);
+    c->schwarz = schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, s);
     RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;
   });
@@ -812,12 +816,19 @@ int rbf_schwarz_get_info(const rbf_ctx* c, rbf_schwarz_info* out) {
   const SchwarzData& d = *c->schwarz;
   out->n_sub = d.nsub;
   out->n_members = d.nmem;
-  int64_t maxn = 0;
-  for (int64_t i = 0; i < d.nsub; ++i) maxn = std::max(maxn, d.h_mem_off[i + 1] - d.h_mem_off[i]);
+  int64_t maxn = 0, minn = d.nsub > 0 ? INT64_MAX : 0;
+  for (int64_t i = 0; i < d.nsub; ++i) {
+    maxn = std::max(maxn, d.h_mem_off[i + 1] - d.h_mem_off[i]);
+    minn = std::min(minn, d.h_mem_off[i + 1] - d.h_mem_off[i]);
+  }
   out->max_members = maxn;
+  out->min_members = minn;
   out->inverse_bytes = d.w_total * (int64_t)sizeof(float);
   out->retries = d.retries;
   out->max_shift = d.max_shift;
+  out->apply_threads = d.apply_threads;
+  out->apply_blocks = d.apply_blocks;
+  out->factor_ms = d.factor_ms;
   return RBF_OK;
 }
 

@@ -85,11 +85,18 @@ __host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt
 // The overlapping Schwarz preconditioner (schwarz.hip).  Subdomain i has
 // members mem[mem_off[i] .. mem_off[i+1]) (sorted positions), its ncore[i]
 // core centres first; its local inverse is W[woff[i] ..], float32, n x n.
-constexpr int kSchwarzMaxBlock = 192;   // a float64 packed triangle of this order fills the LDS of a CU
+constexpr int kSchwarzMaxBlock = 1024;   // largest subdomain (core + overlap centres)
+constexpr int kSchwarzLdsBlock = 192;    // a float64 packed triangle of this order fills the LDS of a CU
 struct SchwarzData {
   int64_t nsub = 0, nmem = 0, w_total = 0;
   int restricted = 0, max_block = 0, pct = 0, retries = 0;
-  double shift = 0, max_shift = 0;
+  double shift = 0, max_shift = 0, factor_ms = 0;
+  // the apply's persistent launch: tasks (subdomain, first row) of
+  // apply_threads rows each, largest first, taken cyclically by apply_blocks
+  // workgroups
+  int apply_threads = 256, apply_blocks = 0;
+  int64_t ntask = 0;
+  int2* tasks = nullptr;
   int64_t* mem_off = nullptr;
   int32_t* ncore = nullptr;
   uint32_t* mem = nullptr;
@@ -350,7 +357,8 @@ bool profiling();
 // schwarz.hip
 int schwarz_overlap_count(int ncore, int pct);
 int schwarz_core_cap(int max_block, int pct);
-SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, double shift, hipStream_t s);
+SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, int min_block, double shift,
+                           int tune, hipStream_t s);
 void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s,
                    const int* skip = nullptr);
 void free_schwarz(SchwarzData* d);

@@ -42,10 +42,15 @@ namespace {
 
 constexpr int kOvThreads = 256;
 constexpr int kCandCap = 2048;                 // candidate buffer of the overlap search
+static_assert(kCandCap >= kSchwarzMaxBlock + kOvThreads, "the best k and one round of candidates fit");
 constexpr int kFacThreads = 512;
-constexpr int kPacked = kSchwarzMaxBlock * (kSchwarzMaxBlock + 1) / 2;
-constexpr int kApplyThreads = 256;
-static_assert(kSchwarzMaxBlock <= kApplyThreads, "one lane per row of a block");
+constexpr int kPacked = kSchwarzLdsBlock * (kSchwarzLdsBlock + 1) / 2;
+constexpr int kPanel = 64;   // pivots per panel of the global-memory sweep
+constexpr int kSmallWords = kPacked + 4 * kSchwarzLdsBlock;
+constexpr int kBigWords = 3 * kSchwarzMaxBlock + 3 * kPanel * kPanel + kPanel;
+constexpr int kFacWords = kSmallWords > kBigWords ? kSmallWords : kBigWords;
+static_assert(kFacWords * 8 + 64 <= 160 * 1024, "the factor kernel's LDS fits a compute unit");
+static_assert(kFacThreads == 512, "the tile update maps 16 x 32 threads onto 64 x 64 entries");
 
 // ---------------------------------------------------------------------------
 // Bounding box of every core (one wave per subdomain).
@@ -217,24 +222,26 @@ __global__ __launch_bounds__(kOvThreads) void k_schwarz_overlap(OvArgs a) {
       const int64_t L2 = leaves[q];
       const int64_t b0 = a.core_off[L2];
       const int cnt = (int)(a.core_off[L2 + 1] - b0);
-      if (tid < cnt) {
-        const uint32_t j = a.core_mem[b0 + tid];
-        const double x = a.X[3 * (int64_t)j], y = a.X[3 * (int64_t)j + 1], z = a.X[3 * (int64_t)j + 2];
-        if (a.unbounded || box_dist2(x, y, z, mybox) <= margin) {
-          double best = INFINITY;
-          for (int p = 0; p < ncore; ++p) {
-            const double dx = x - cx[p], dy = y - cy[p], dz = z - cz[p];
-            best = fmin(best, (dx * dx + dy * dy) + dz * dz);
-          }
-          if (a.unbounded || best <= rho2) {
-            const int slot = atomicAdd(&s_nc, 1);
-            cd[slot] = best;
-            ci[slot] = j;
+      for (int c0 = 0; c0 < cnt; c0 += kOvThreads) {
+        if (c0 + tid < cnt) {
+          const uint32_t j = a.core_mem[b0 + c0 + tid];
+          const double x = a.X[3 * (int64_t)j], y = a.X[3 * (int64_t)j + 1], z = a.X[3 * (int64_t)j + 2];
+          if (a.unbounded || box_dist2(x, y, z, mybox) <= margin) {
+            double best = INFINITY;
+            for (int p = 0; p < ncore; ++p) {
+              const double dx = x - cx[p], dy = y - cy[p], dz = z - cz[p];
+              best = fmin(best, (dx * dx + dy * dy) + dz * dz);
+            }
+            if (a.unbounded || best <= rho2) {
+              const int slot = atomicAdd(&s_nc, 1);
+              cd[slot] = best;
+              ci[slot] = j;
+            }
           }
         }
+        __syncthreads();
+        if (s_nc > kCandCap - kOvThreads) merge();
       }
-      __syncthreads();
-      if (s_nc > kCandCap - kSchwarzMaxBlock) merge();
     }
   }
   merge();
@@ -261,6 +268,9 @@ struct FacArgs {
   int32_t* retries;
   int* failed;
   int* queue;
+  double* big;              // blocks above the LDS order: float64 work space per workgroup
+  int64_t big_ld;           // its leading dimension (the largest block)
+  int64_t big_stride;       // doubles per workgroup: big_ld^2 + 2 kPanel big_ld
 };
 
 __device__ __forceinline__ int packed(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -277,12 +287,180 @@ __device__ __forceinline__ void for_each_packed(int n, F&& f) {
   }
 }
 
+__device__ __forceinline__ double gauss_entry(const double* px, const double* py, const double* pz, int i, int j,
+                                              double shift, double two_s2) {
+  if (i == j) return 1.0 + shift;
+  const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
+  return exp(-((dx * dx + dy * dy) + dz * dz) / two_s2);
+}
+
+// Blocks up to kSchwarzLdsBlock: the packed triangle in LDS, one pivot at a
+// time.  Returns false when a pivot is not positive (the same decision in
+// every thread).  A holds the swept matrix, -A^{-1}, on success.
+__device__ bool sweep_lds(double* A, double* col, const double* px, const double* py, const double* pz, int n,
+                          double shift, double two_s2) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  for_each_packed(n, [&](int i, int j, int u) { A[u] = gauss_entry(px, py, pz, i, j, shift, two_s2); });
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double d = A[packed(k, k)];
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    for (int i = tid; i < n; i += kFacThreads) col[i] = i >= k ? A[packed(i, k)] : A[packed(k, i)];
+    __syncthreads();
+    const double inv = 1.0 / d;
+    for_each_packed(n, [&](int i, int j, int u) {
+      if (i != k && j != k)
+        A[u] = fma(-(col[i] * inv), col[j], A[u]);
+      else if (i == k && j == k)
+        A[u] = -inv;
+      else
+        A[u] = (i == k ? col[j] : col[i]) * inv;
+    });
+    __syncthreads();
+  }
+  return true;
+}
+
+// Larger blocks: the full n x n matrix G in global memory, swept kPanel
+// pivots at a time (the block form of the same sweep).  With the pivot block
+// D of the panel and Q its columns (= rows: the swept matrix stays
+// symmetric), one panel sweeps D in LDS to -D^{-1}, forms P = Q D^{-1}, then
+// updates every entry outside the panel, G_ij -= P_i . Q_j, and writes P into
+// the panel's rows and columns.  P and Q go to global memory first (the
+// tiles of the update overwrite the panel); the update runs in 64 x 64 tiles
+// from LDS, four rows by two columns per thread.
+__device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, double* lds, const double* px,
+                             const double* py, const double* pz, int n, double shift, double two_s2) {
+  const int tid = threadIdx.x;
+  double* D = lds;                        // kPanel x kPanel, row-major
+  double* PT = D + kPanel * kPanel;       // PT[l][r]: P of the rows of a tile, by panel column
+  double* QT = PT + kPanel * kPanel;      // QT[l][r]
+  double* colv = QT + kPanel * kPanel;    // kPanel
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    G[e] = gauss_entry(px, py, pz, i, j, shift, two_s2);
+  }
+  const int nt = (n + kPanel - 1) / kPanel;
+  for (int p = 0; p < nt; ++p) {
+    const int K = p * kPanel, kb = min(kPanel, n - K);
+    __syncthreads();
+    for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+      const int r = e / kPanel, c = e % kPanel;
+      D[e] = r < kb && c < kb ? G[(int64_t)(K + r) * n + K + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+      const double d = D[k * kPanel + k];
+      if (!(d > 0.0) || !isfinite(d)) return false;
+      if (tid < kb) colv[tid] = D[tid * kPanel + k];
+      __syncthreads();
+      const double inv = 1.0 / d;
+      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+        const int r = e / kPanel, c = e % kPanel;
+        if (r >= kb || c >= kb) continue;
+        if (r != k && c != k)
+          D[e] = fma(-(colv[r] * inv), colv[c], D[e]);
+        else if (r == k && c == k)
+          D[e] = -inv;
+        else
+          D[e] = (r == k ? colv[c] : colv[r]) * inv;
+      }
+      __syncthreads();
+    }
+    // Q (the panel's rows, read along them) and P = Q D^{-1} = -Q D, strip by strip
+    for (int s0 = 0; s0 < n; s0 += kPanel) {
+      const int rows = min(kPanel, n - s0);
+      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+        const int l = e / kPanel, r = e % kPanel;
+        QT[e] = l < kb && r < rows ? G[(int64_t)(K + l) * n + s0 + r] : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+        const int l = e / kPanel, r = e % kPanel;
+        if (l >= kb || r >= rows) continue;
+        double acc = 0.0;
+        for (int q = 0; q < kb; ++q) acc = fma(QT[q * kPanel + r], D[q * kPanel + l], acc);
+        Pg[(int64_t)l * ld + s0 + r] = -acc;
+        Qg[(int64_t)l * ld + s0 + r] = QT[e];
+      }
+      __syncthreads();
+    }
+    const int tr = tid >> 5, tc = tid & 31;   // 16 x 32 threads over a 64 x 64 tile
+    for (int ti = 0; ti < nt; ++ti) {
+      const int i0 = ti * kPanel, ri = min(kPanel, n - i0);
+      __syncthreads();
+      if (ti != p)
+        for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+          const int l = e / kPanel, r = e % kPanel;
+          PT[e] = l < kb && r < ri ? Pg[(int64_t)l * ld + i0 + r] : 0.0;
+        }
+      for (int tj = 0; tj < nt; ++tj) {
+        const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
+        __syncthreads();
+        if (ti != p && tj != p)
+          for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+            const int l = e / kPanel, r = e % kPanel;
+            QT[e] = l < kb && r < rj ? Qg[(int64_t)l * ld + j0 + r] : 0.0;
+          }
+        __syncthreads();
+        if (ti != p && tj != p) {
+          double acc[4][2];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int r = 4 * tr + q, cc = 2 * tc + c;
+              acc[q][c] = r < ri && cc < rj ? G[(int64_t)(i0 + r) * n + j0 + cc] : 0.0;
+            }
+          for (int l = 0; l < kb; ++l) {
+            double pv[4], qv[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pv[q] = PT[l * kPanel + 4 * tr + q];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) qv[c] = QT[l * kPanel + 2 * tc + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int c = 0; c < 2; ++c) acc[q][c] = fma(-pv[q], qv[c], acc[q][c]);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int r = 4 * tr + q, cc = 2 * tc + c;
+              if (r < ri && cc < rj) G[(int64_t)(i0 + r) * n + j0 + cc] = acc[q][c];
+            }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int r = 4 * tr + q, cc = 2 * tc + c;
+              if (r >= ri || cc >= rj) continue;
+              double v;
+              if (ti == p && tj == p)
+                v = D[r * kPanel + cc];
+              else if (ti == p)
+                v = Pg[(int64_t)r * ld + j0 + cc];   // row K + r: P of column j, panel column r
+              else
+                v = Pg[(int64_t)cc * ld + i0 + r];   // column K + cc: P of row i
+              G[(int64_t)(i0 + r) * n + j0 + cc] = v;
+            }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
-  __shared__ double A[kPacked];
-  __shared__ double px[kSchwarzMaxBlock], py[kSchwarzMaxBlock], pz[kSchwarzMaxBlock];
-  __shared__ double col[kSchwarzMaxBlock];
+  __shared__ double lds[kFacWords];
   __shared__ int s_task;
   const int tid = threadIdx.x;
+  double* const big = a.big ? a.big + (int64_t)blockIdx.x * a.big_stride : nullptr;
   for (;;) {
     __syncthreads();
     if (tid == 0) s_task = atomicAdd(a.queue, 1);
@@ -292,6 +470,13 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
     const int64_t sub = a.order[task];
     const int64_t off = a.mem_off[sub];
     const int n = (int)(a.mem_off[sub + 1] - off);
+    const bool in_lds = n <= kSchwarzLdsBlock;
+    // coordinates: after the packed triangle and its column (LDS form), at
+    // the front (global form, before the panel buffers)
+    double* px = in_lds ? lds + kPacked + kSchwarzLdsBlock : lds;
+    double* py = px + (in_lds ? kSchwarzLdsBlock : kSchwarzMaxBlock);
+    double* pz = py + (in_lds ? kSchwarzLdsBlock : kSchwarzMaxBlock);
+    __syncthreads();
     for (int p = tid; p < n; p += kFacThreads) {
       const double4 x = a.xs[a.mem[off + p]];
       px[p] = x.x;
@@ -302,52 +487,28 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
     int tries = 0;
     bool ok = false;
     for (;;) {
-      __syncthreads();
-      for_each_packed(n, [&](int i, int j, int u) {
-        double v;
-        if (i == j) {
-          v = 1.0 + shift;
-        } else {
-          const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
-          v = exp(-((dx * dx + dy * dy) + dz * dz) / a.two_s2);
-        }
-        A[u] = v;
-      });
-      __syncthreads();
-      bool bad = false;
-      for (int k = 0; k < n; ++k) {
-        const double d = A[packed(k, k)];
-        if (!(d > 0.0) || !isfinite(d)) {   // the same value for every thread
-          bad = true;
-          break;
-        }
-        for (int i = tid; i < n; i += kFacThreads) col[i] = i >= k ? A[packed(i, k)] : A[packed(k, i)];
-        __syncthreads();
-        const double inv = 1.0 / d;
-        for_each_packed(n, [&](int i, int j, int u) {
-          if (i != k && j != k)
-            A[u] = fma(-(col[i] * inv), col[j], A[u]);
-          else if (i == k && j == k)
-            A[u] = -inv;
-          else
-            A[u] = (i == k ? col[j] : col[i]) * inv;
-        });
-        __syncthreads();
-      }
-      if (!bad) {
+      const bool swept = in_lds ? sweep_lds(lds, lds + kPacked, px, py, pz, n, shift, a.two_s2)
+                                : sweep_global(big, big + a.big_ld * a.big_ld, big + a.big_ld * (a.big_ld + kPanel),
+                                               a.big_ld, pz + kSchwarzMaxBlock, px, py, pz, n, shift, a.two_s2);
+      if (swept) {
         ok = true;
         break;
       }
       if (++tries > a.max_retry) break;
       shift = shift > 0.0 ? 10.0 * shift : 1e-10;
     }
+    __syncthreads();
     // W = -(swept matrix), full n x n
     float* W = a.W + a.woff[sub];
-    for_each_packed(n, [&](int i, int j, int u) {
-      const float v = ok ? (float)(-A[u]) : 0.0f;
-      W[(int64_t)i * n + j] = v;
-      if (i != j) W[(int64_t)j * n + i] = v;
-    });
+    if (in_lds) {
+      for_each_packed(n, [&](int i, int j, int u) {
+        const float v = ok ? (float)(-lds[u]) : 0.0f;
+        W[(int64_t)i * n + j] = v;
+        if (i != j) W[(int64_t)j * n + i] = v;
+      });
+    } else {
+      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) W[e] = ok ? (float)(-big[e]) : 0.0f;
+    }
     if (tid == 0) {
       a.shift_used[sub] = shift;
       a.retries[sub] = tries;
@@ -359,39 +520,57 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
 // ---------------------------------------------------------------------------
 // Apply.
 // ---------------------------------------------------------------------------
-template <bool RESTRICTED>
-__global__ __launch_bounds__(kApplyThreads) void k_schwarz_local(const int64_t* __restrict__ mem_off,
-                                                                 const int32_t* __restrict__ ncore,
-                                                                 const uint32_t* __restrict__ mem,
-                                                                 const int64_t* __restrict__ woff,
-                                                                 const float* __restrict__ W,
-                                                                 const double* __restrict__ r,
-                                                                 double* __restrict__ out, const int* skip) {
-  if (skip && *skip) return;
+struct ApplyArgs {
+  const int2* tasks;        // (subdomain, first row), largest first
+  int64_t ntask;
+  const int64_t* mem_off;
+  const int32_t* ncore;
+  const uint32_t* mem;
+  const int64_t* woff;
+  const float* W;
+  const double* r;
+  double* out;              // restricted: z (sorted order); additive: the local solutions by member slot
+  const int* skip;
+};
+
+// One persistent launch: workgroup b takes tasks b, b + gridDim.x, ...; a
+// task gathers its block's vector into LDS and forms T rows of W r, a lane
+// per row (W is symmetric, so lane p reads column p of each row b:
+// consecutive lanes, consecutive addresses).  The restricted form scatters
+// the core rows (the cores partition the centres); the additive form stores
+// every row by member slot.
+template <bool RESTRICTED, int T>
+__global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
+  if (a.skip && *a.skip) return;
   __shared__ double rl[kSchwarzMaxBlock];
-  const int64_t sub = blockIdx.x;
-  const int64_t off = mem_off[sub];
-  const int n = (int)(mem_off[sub + 1] - off);
   const int tid = threadIdx.x;
-  if (tid < n) rl[tid] = r[mem[off + tid]];
-  __syncthreads();
-  const int rows = RESTRICTED ? ncore[sub] : n;
-  if (tid >= rows) return;
-  const float* w = W + woff[sub] + tid;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int b = 0;
-  for (; b + 4 <= n; b += 4) {
-    a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
-    a1 = fma((double)w[(int64_t)(b + 1) * n], rl[b + 1], a1);
-    a2 = fma((double)w[(int64_t)(b + 2) * n], rl[b + 2], a2);
-    a3 = fma((double)w[(int64_t)(b + 3) * n], rl[b + 3], a3);
+  for (int64_t t = blockIdx.x; t < a.ntask; t += gridDim.x) {
+    const int2 task = a.tasks[t];
+    const int64_t sub = task.x;
+    const int64_t off = a.mem_off[sub];
+    const int n = (int)(a.mem_off[sub + 1] - off);
+    __syncthreads();   // the previous task is done with rl
+    for (int p = tid; p < n; p += T) rl[p] = a.r[a.mem[off + p]];
+    __syncthreads();
+    const int rows = RESTRICTED ? a.ncore[sub] : n;
+    const int row = task.y + tid;
+    if (row >= rows) continue;
+    const float* w = a.W + a.woff[sub] + row;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = 0;
+    for (; b + 4 <= n; b += 4) {
+      a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
+      a1 = fma((double)w[(int64_t)(b + 1) * n], rl[b + 1], a1);
+      a2 = fma((double)w[(int64_t)(b + 2) * n], rl[b + 2], a2);
+      a3 = fma((double)w[(int64_t)(b + 3) * n], rl[b + 3], a3);
+    }
+    for (; b < n; ++b) a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
+    const double y = (a0 + a1) + (a2 + a3);
+    if (RESTRICTED)
+      a.out[a.mem[off + row]] = y;
+    else
+      a.out[off + row] = y;
   }
-  for (; b < n; ++b) a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
-  const double y = (a0 + a1) + (a2 + a3);
-  if (RESTRICTED)
-    out[mem[off + tid]] = y;
-  else
-    out[off + tid] = y;
 }
 
 __global__ void k_schwarz_sum(const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ_slot,
@@ -432,10 +611,101 @@ void free_schwarz(SchwarzData* d) {
   for (void* p : {(void*)d->mem_off, (void*)d->ncore, (void*)d->mem, (void*)d->woff, (void*)d->W, (void*)d->Y,
                   (void*)d->occ_off, (void*)d->occ_slot, (void*)d->z, (void*)d->t})
     dfree(p);
+  dfree(d->tasks);
   delete d;
 }
 
-SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, double shift, hipStream_t s) {
+namespace {
+
+// The tasks of the apply for strips of T rows: (subdomain, first row), by
+// decreasing work (rows x block size), ties by subdomain and row.
+std::vector<int2> apply_tasks(const SchwarzData& d, int T) {
+  std::vector<std::pair<int64_t, int2>> t;
+  for (int64_t i = 0; i < d.nsub; ++i) {
+    const int n = (int)(d.h_mem_off[i + 1] - d.h_mem_off[i]);
+    const int rows = d.restricted ? d.h_ncore[i] : n;
+    for (int r0 = 0; r0 < rows; r0 += T) t.push_back({(int64_t)n * std::min(T, rows - r0), make_int2((int)i, r0)});
+  }
+  std::stable_sort(t.begin(), t.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  std::vector<int2> out(t.size());
+  for (size_t k = 0; k < t.size(); ++k) out[k] = t[k].second;
+  return out;
+}
+
+void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, int64_t ntask, const double* r,
+                  double* out, hipStream_t s, const int* skip) {
+  const ApplyArgs aa{tasks, ntask, d.mem_off, d.ncore, d.mem, d.woff, d.W, r, out, skip};
+  const dim3 g((unsigned)std::max(blocks, 1));
+  if (d.restricted) {
+    if (T == 512)
+      hipLaunchKernelGGL((k_schwarz_local<true, 512>), g, dim3(512), 0, s, aa);
+    else
+      hipLaunchKernelGGL((k_schwarz_local<true, 256>), g, dim3(256), 0, s, aa);
+  } else {
+    if (T == 512)
+      hipLaunchKernelGGL((k_schwarz_local<false, 512>), g, dim3(512), 0, s, aa);
+    else
+      hipLaunchKernelGGL((k_schwarz_local<false, 256>), g, dim3(256), 0, s, aa);
+  }
+  RBF_HIP(hipGetLastError());
+}
+
+// The apply's launch shape: strips of 256 or 512 rows, taken by 2, 4 or 8
+// workgroups per compute unit or by one workgroup per task; each candidate
+// runs once untimed and three times timed on the work vector (the work and
+// the result do not depend on the values), and the fastest is kept.
+void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
+  struct Cand {
+    int T, blocks;
+  };
+  std::vector<Cand> cands;
+  for (int T : {256, 512})
+    for (int mult : {2, 4, 8, 0}) cands.push_back({T, mult});
+  hipEvent_t e0, e1;
+  RBF_HIP(hipEventCreate(&e0));
+  RBF_HIP(hipEventCreate(&e1));
+  double* out = d.restricted ? d.z : d.Y;
+  float best = INFINITY;
+  for (const Cand& c : cands) {
+    std::vector<int2> ht = apply_tasks(d, c.T);
+    int2* dt = upload(ht, s);
+    const int blocks = c.blocks > 0 ? std::min<int64_t>((int64_t)c.blocks * cus, (int64_t)ht.size()) : (int)ht.size();
+    launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
+    RBF_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < 3; ++k) launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
+    RBF_HIP(hipEventRecord(e1, s));
+    RBF_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    RBF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      dfree(d.tasks);
+      d.tasks = dt;
+      d.ntask = (int64_t)ht.size();
+      d.apply_threads = c.T;
+      d.apply_blocks = blocks;
+    } else {
+      dfree(dt);
+    }
+  }
+  RBF_HIP(hipEventDestroy(e0));
+  RBF_HIP(hipEventDestroy(e1));
+}
+
+// Depth-first (Morton) position of a cell at `level` of the 10-level
+// octree, padded to the finest level: the coordinates' bits interleaved,
+// x lowest.
+uint32_t morton_full_depth(const uint32_t q[3], int level) {
+  uint32_t key = 0;
+  for (int b = level - 1; b >= 0; --b)
+    key = (key << 3) | ((q[0] >> b) & 1u) | (((q[1] >> b) & 1u) << 1) | (((q[2] >> b) & 1u) << 2);
+  return key << (3 * (kCurveBits - level));
+}
+
+}  // namespace
+
+SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, int min_block, double shift,
+                           int tune, hipStream_t s) {
   const int64_t n = c.n, m = c.m;
   const int cap = schwarz_core_cap(max_block, pct);
   // 1. root cube of the surface points and their Hilbert order on it
@@ -489,7 +759,42 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     }
   };
   if (n > 0) visit(0, n, 0);
-  const int64_t nsub = (int64_t)leaves.size();
+
+  // the leaves in depth-first order (cell key of the first point at the
+  // leaf's level, then position: the runs of one finest cell in index order),
+  // then consecutive leaves joined while the block is below min_block and
+  // the cap allows
+  std::vector<double> hx = download(c.xpaper, 3 * n, s);
+  RBF_HIP(hipStreamSynchronize(s));
+  std::vector<std::pair<uint32_t, int64_t>> dfo(leaves.size());
+  for (size_t i = 0; i < leaves.size(); ++i) {
+    const uint32_t pt = hp[leaves[i].a];
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+      double v = std::floor((hx[3 * (size_t)pt + d] - L.origin[d]) / L.fine);
+      if (!(v >= 0.0)) v = 0.0;
+      if (v > (double)(kFineMax - 1)) v = (double)(kFineMax - 1);
+      q[d] = (uint32_t)v >> (kCurveBits - leaves[i].level);
+    }
+    dfo[i] = {morton_full_depth(q, leaves[i].level), leaves[i].a};
+  }
+  std::vector<int64_t> lorder(leaves.size());
+  for (size_t i = 0; i < leaves.size(); ++i) lorder[i] = (int64_t)i;
+  std::sort(lorder.begin(), lorder.end(), [&](int64_t x, int64_t y) { return dfo[x] < dfo[y]; });
+  auto block_of = [&](int64_t pts) { return 3 * pts + schwarz_overlap_count((int)(3 * pts), pct); };
+  std::vector<std::vector<int64_t>> groups;   // leaves of every core
+  int64_t npts = 0;
+  for (int64_t li : lorder) {
+    const int64_t sz = leaves[li].b - leaves[li].a;
+    const bool close = !groups.empty() && (min_block <= 0 || block_of(npts) >= min_block || npts + sz > cap);
+    if (groups.empty() || close) {
+      groups.emplace_back();
+      npts = 0;
+    }
+    groups.back().push_back(li);
+    npts += sz;
+  }
+  const int64_t nsub = (int64_t)groups.size();
 
   // 3. cores (paper indices: the points in increasing order, then their +, - offsets)
   std::vector<int64_t> core_off(nsub + 1, 0), ov_off(nsub + 1, 0);
@@ -498,7 +803,12 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   std::vector<double> rho(nsub);
   core_mem.reserve((size_t)m);
   for (int64_t i = 0; i < nsub; ++i) {
-    std::vector<uint32_t> pts(hp.begin() + leaves[i].a, hp.begin() + leaves[i].b);
+    std::vector<uint32_t> pts;
+    double r = 0.0;
+    for (int64_t li : groups[i]) {
+      pts.insert(pts.end(), hp.begin() + leaves[li].a, hp.begin() + leaves[li].b);
+      r = std::max(r, std::ldexp(side, -leaves[li].level));   // the side of the leaf's cell
+    }
     std::sort(pts.begin(), pts.end());
     for (int t = 0; t < 3; ++t)
       for (uint32_t p : pts) core_mem.push_back((uint32_t)(p + t * n));
@@ -506,7 +816,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     core_off[i + 1] = core_off[i] + nc;
     kcount[i] = (int32_t)std::min<int64_t>(schwarz_overlap_count(nc, pct), m - nc);
     ov_off[i + 1] = ov_off[i] + kcount[i];
-    rho[i] = std::ldexp(side, -leaves[i].level);   // the side of the leaf's cell
+    rho[i] = r;
   }
 
   // 4. overlaps on the device
@@ -609,16 +919,38 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     fill_u32(reinterpret_cast<uint32_t*>(d_flags), 0u, 2, s);
     int cus = 0;
     RBF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
-    const unsigned grid = (unsigned)std::min<int64_t>(nsub, std::max(cus, 1));
+    cus = std::max(cus, 1);
+    const unsigned grid = (unsigned)std::min<int64_t>(nsub, cus);
+    // blocks above the LDS order are swept in global memory: one work space
+    // (the block, and the P and Q of a panel) per workgroup
+    int64_t maxn = 0;
+    for (int64_t i = 0; i < nsub; ++i) maxn = std::max(maxn, d->h_mem_off[i + 1] - d->h_mem_off[i]);
+    double* big = nullptr;
+    int64_t big_stride = 0;
+    if (maxn > kSchwarzLdsBlock) {
+      big_stride = maxn * maxn + 2 * kPanel * maxn;
+      big = talloc<double>(big_stride * grid);
+    }
     FacArgs fa{c.xs, d->mem_off, d->mem, d_order, nsub, d->woff, 2.0 * c.sigma * c.sigma, shift, 8,
-               d->W, d_shift, d_retries, d_flags + 1, d_flags};
+               d->W, d_shift, d_retries, d_flags + 1, d_flags, big, maxn, big_stride};
+    hipEvent_t e0, e1;
+    RBF_HIP(hipEventCreate(&e0));
+    RBF_HIP(hipEventCreate(&e1));
+    RBF_HIP(hipEventRecord(e0, s));
     hipLaunchKernelGGL(k_schwarz_factor, dim3(grid), dim3(kFacThreads), 0, s, fa);
     RBF_HIP(hipGetLastError());
+    RBF_HIP(hipEventRecord(e1, s));
     std::vector<double> hs = download(d_shift, nsub, s);
     std::vector<int32_t> hr = download(d_retries, nsub, s);
     std::vector<int> hf = download(d_flags, 2, s);
     RBF_HIP(hipStreamSynchronize(s));
+    float fms = 0.f;
+    RBF_HIP(hipEventElapsedTime(&fms, e0, e1));
+    RBF_HIP(hipEventDestroy(e0));
+    RBF_HIP(hipEventDestroy(e1));
+    d->factor_ms = fms;
     for (void* p : {(void*)d_order, (void*)d_shift, (void*)d_retries, (void*)d_flags}) temp_free(p);
+    if (big) temp_free(big);
     d->max_shift = 0.0;
     d->retries = 0;
     for (int64_t i = 0; i < nsub; ++i) {
@@ -629,6 +961,17 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
       free_schwarz(d);
       throw Error{RBF_EBREAKDOWN, "a subdomain block stayed indefinite after the shift retries"};
     }
+    // 7. the apply's launch shape
+    if (tune) {
+      tune_apply(*d, cus, s);
+    } else {
+      std::vector<int2> ht = apply_tasks(*d, 256);
+      d->tasks = upload(ht, s);
+      d->ntask = (int64_t)ht.size();
+      d->apply_threads = 256;
+      d->apply_blocks = (int)std::min<int64_t>(4 * (int64_t)cus, d->ntask);
+      RBF_HIP(hipStreamSynchronize(s));
+    }
   }
   return d;
 }
@@ -636,16 +979,12 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
 // z = M^{-1} r (sorted order; z must not alias r; entries >= m untouched).
 void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s, const int* skip) {
   if (d.nsub == 0) return;
-  if (d.restricted) {
-    hipLaunchKernelGGL(k_schwarz_local<true>, dim3((unsigned)d.nsub), dim3(kApplyThreads), 0, s, d.mem_off, d.ncore,
-                       d.mem, d.woff, d.W, r, z, skip);
-  } else {
-    hipLaunchKernelGGL(k_schwarz_local<false>, dim3((unsigned)d.nsub), dim3(kApplyThreads), 0, s, d.mem_off, d.ncore,
-                       d.mem, d.woff, d.W, r, d.Y, skip);
+  launch_local(d, d.apply_threads, d.apply_blocks, d.tasks, d.ntask, r, d.restricted ? z : d.Y, s, skip);
+  if (!d.restricted) {
     hipLaunchKernelGGL(k_schwarz_sum, dim3((unsigned)ceil_div(c.m, 256)), dim3(256), 0, s, d.occ_off, d.occ_slot,
                        d.Y, c.m, z, skip);
+    RBF_HIP(hipGetLastError());
   }
-  RBF_HIP(hipGetLastError());
 }
 
 }  // namespace rbf

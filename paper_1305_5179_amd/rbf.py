@@ -39,12 +39,14 @@ class SolveOpts(C.Structure):
 
 class SchwarzOpts(C.Structure):
     _fields_ = [("max_block", C.c_int), ("overlap_pct", C.c_int), ("restricted", C.c_int),
-                ("reserved", C.c_int), ("shift", C.c_double)]
+                ("min_block", C.c_int), ("shift", C.c_double), ("tune", C.c_int), ("reserved", C.c_int)]
 
 
 class SchwarzInfo(C.Structure):
     _fields_ = [("n_sub", C.c_int64), ("n_members", C.c_int64), ("max_members", C.c_int64),
-                ("inverse_bytes", C.c_int64), ("retries", C.c_int), ("max_shift", C.c_double)]
+                ("inverse_bytes", C.c_int64), ("retries", C.c_int), ("max_shift", C.c_double),
+                ("min_members", C.c_int64), ("apply_threads", C.c_int), ("apply_blocks", C.c_int),
+                ("factor_ms", C.c_double)]
 
 
 class SolveInfo(C.Structure):

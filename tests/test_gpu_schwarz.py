@@ -76,6 +76,10 @@ OPTS = {
     "default": dict(),
     "restricted30": dict(restricted=1, overlap_pct=30),
     "small_blocks": dict(max_block=40, overlap_pct=20),
+    # blocks above the LDS order (swept in global memory), with and without
+    # the merge of small leaves; mixed sizes in one launch
+    "large_merged": dict(max_block=1024, min_block=64),
+    "mixed_restricted": dict(max_block=600, min_block=200, restricted=1),
 }
 
 
@@ -105,7 +109,7 @@ def built(torch, R):
 
 
 def _oracle_opts(optname):
-    d = dict(max_block=192, overlap_pct=10, restricted=0, shift=0.1)
+    d = dict(max_block=192, overlap_pct=10, restricted=0, shift=0.1, min_block=0)
     d.update(OPTS[optname])
     return d
 
@@ -119,7 +123,7 @@ def test_subdomains_are_the_oracles(built, name, optname):
     assert info.retries == 0 and info.n_sub == len(gpu)
     assert info.max_members <= oo["max_block"]
     cap = S.core_cap(oo["max_block"], oo["overlap_pct"])
-    leaves = S.octree_cores(c.points, cap)
+    leaves = S.merge_leaves(S.octree_cores(c.points, cap), cap, oo["min_block"], oo["overlap_pct"])
     n = len(c.points)
     cores = {int(np.min(S.core_centres(l, n))): np.sort(S.core_centres(l, n)) for l in leaves}
     g = _subs_key(gpu)
@@ -131,8 +135,9 @@ def test_subdomains_are_the_oracles(built, name, optname):
     assert np.array_equal(allc, np.arange(3 * n))
     # overlaps: all of them on small clouds, a seeded sample otherwise
     keys = sorted(cores)
-    if len(keys) > 60:
-        keys = list(np.random.default_rng(4).choice(keys, 60, replace=False))
+    nkeys = 60 if oo["max_block"] <= 192 else 16
+    if len(keys) > nkeys:
+        keys = list(np.random.default_rng(4).choice(keys, nkeys, replace=False))
     for k0 in keys:
         core = cores[k0]
         want = S.overlap(X, core, min(S.overlap_count(core.size, oo["overlap_pct"]), len(X) - core.size))
@@ -155,7 +160,7 @@ def _apply_bound(X, subs, sigma, shift, r, restricted):
 def test_apply_matches_the_oracle(torch, built, name, optname):
     c, ctx, info, X, sigma, cutoff = built(name, optname)
     oo = _oracle_opts(optname)
-    subs = S.subdomains(c.points, X, oo["max_block"], oo["overlap_pct"])
+    subs = S.subdomains(c.points, X, oo["max_block"], oo["overlap_pct"], oo["min_block"])
     r = np.random.default_rng(11).uniform(-1, 1, len(X))
     _say(f"[schwarz] apply {name} {optname}")
     z = host(ctx.schwarz_apply(dev(torch, r)))
@@ -264,9 +269,10 @@ def test_setup_rejects_bad_options(torch, R):
     c = w.sphere(50, 1)
     ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), 0.01, 0.05, math.inf)
     try:
-        for bad in (dict(max_block=2), dict(max_block=193), dict(overlap_pct=-1), dict(overlap_pct=101),
+        for bad in (dict(max_block=2), dict(max_block=1025), dict(overlap_pct=-1), dict(overlap_pct=101),
                     dict(restricted=2), dict(reserved=1), dict(shift=-1.0), dict(shift=float("nan")),
-                    dict(max_block=3, overlap_pct=10)):
+                    dict(max_block=3, overlap_pct=10), dict(min_block=-1), dict(max_block=100, min_block=101),
+                    dict(tune=2)):
             with pytest.raises(R.RbfError) as e:
                 ctx.schwarz_setup(**bad)
             assert e.value.status == R.RBF_EINVAL, bad
@@ -312,5 +318,118 @@ def test_restricted_solve_and_setup_twice(torch, R):
         torch.cuda.synchronize()
         assert res.status == R.RBF_OK, res
         assert np.linalg.norm(host(cw) - c_lu) <= 1e-5 * np.linalg.norm(c_lu)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("name", ["sphere2000", "clustered1500"])
+def test_large_blocks_are_used(built, name):
+    """The large configurations do put blocks above the LDS order (192) in
+    the launch, and one launch per cloud holds blocks of both kinds (the
+    LDS sweep and the global-memory sweep side by side)."""
+    c, ctx, info, X, sigma, cutoff = built(name, "large_merged")
+    gpu = ctx.schwarz_subdomains()
+    sizes = np.array([core.size + ov.size for core, ov in gpu])
+    _say(f"[schwarz] {name} large_merged: {len(gpu)} blocks, sizes {sizes.min()}..{sizes.max()}, "
+         f"factor {info.factor_ms:.2f} ms, apply {info.apply_threads} x {info.apply_blocks}")
+    assert sizes.max() > 192 and sizes.max() <= 1024
+    assert info.min_members == sizes.min() and info.max_members == sizes.max()
+    mixed = {"sphere2000": "mixed_restricted", "clustered1500": "large_merged"}[name]
+    c2, ctx2, info2, *_ = built(name, mixed)
+    sizes2 = np.array([core.size + ov.size for core, ov in ctx2.schwarz_subdomains()])
+    assert sizes2.max() > 192 and sizes2.min() <= 192
+
+
+def test_launch_shape_does_not_change_the_result(torch, R):
+    """Every row of W r is formed by one lane in a fixed order, so the tuned
+    and the fixed launch shapes give the same bits (additive and restricted)."""
+    make, eps, sigma, cutoff = CLOUDS["sphere2000"]
+    c = make()
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, cutoff)
+    try:
+        r = dev(torch, np.random.default_rng(21).uniform(-1, 1, 3 * len(c.points)))
+        for restricted in (0, 1):
+            out = []
+            for tune in (0, 1):
+                _say(f"[schwarz] sphere2000 max_block 700 restricted {restricted} tune {tune}")
+                info = ctx.schwarz_setup(max_block=700, restricted=restricted, tune=tune)
+                out.append(host(ctx.schwarz_apply(r)))
+                torch.cuda.synchronize()
+                if tune == 0:
+                    assert info.apply_threads == 256
+            assert np.array_equal(out[0], out[1])
+    finally:
+        ctx.close()
+
+
+def _k_nearest_outside(X, core, k):
+    """The k centres outside `core` nearest to it by the oracle's distance:
+    candidates from a k-d tree on the core (scipy), then the exact float64
+    (dx dx + dy dy) + dz dz to every core centre, ties by index."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(X[core])
+    d, _ = tree.query(X, k=1)
+    d[core] = np.inf
+    cand = np.argsort(d, kind="stable")[:k + 64]
+    dd = X[cand][:, None, :] - X[core][None, :, :]
+    exact = ((dd[..., 0] * dd[..., 0] + dd[..., 1] * dd[..., 1]) + dd[..., 2] * dd[..., 2]).min(axis=1)
+    order = np.lexsort((cand, exact))
+    return cand[order[:k]]
+
+
+def test_torus200k_2048_subdomains(torch, R):
+    """The torus workload split into about 2,000 subdomains of 64..1024
+    centres (blocks up to 1024, small octree leaves merged up to 64): cores
+    equal to the oracle's, overlaps of sampled cores the k nearest, and the
+    apply's rows of sampled cores against float64 local solves of every
+    subdomain holding them."""
+    cfg = w.TORUS_200K
+    c = w.torus(cfg["n"], cfg["seed"])
+    X, _ = o.extended_centres(c.points, c.normals, cfg["eps"])
+    n = len(c.points)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), cfg["eps"], cfg["sigma"], cfg["cutoff"])
+    try:
+        _say("[schwarz] torus200k max_block 1024 min_block 64: setup")
+        info = ctx.schwarz_setup(max_block=1024, min_block=64)
+        torch.cuda.synchronize()
+        gpu = ctx.schwarz_subdomains()
+        sizes = np.array([a.size + b.size for a, b in gpu])
+        _say(f"[schwarz] torus200k: {len(gpu)} subdomains, sizes {sizes.min()}..{sizes.max()} "
+             f"(median {int(np.median(sizes))}), factor {info.factor_ms:.1f} ms, retries {info.retries}, "
+             f"apply {info.apply_threads} x {info.apply_blocks}")
+        assert 1500 <= len(gpu) <= 2500 and sizes.max() <= 1024 and sizes.min() >= 64
+        cap = S.core_cap(1024, 10)
+        leaves = S.merge_leaves(S.octree_cores(c.points, cap), cap, 64, 10)
+        cores = {int(np.min(S.core_centres(l, n))): np.sort(S.core_centres(l, n)) for l in leaves}
+        g = _subs_key(gpu)
+        assert sorted(g) == sorted(cores)
+        for k0, core in cores.items():
+            assert np.array_equal(g[k0][0], core), k0
+        rng = np.random.default_rng(31)
+        for k0 in rng.choice(sorted(cores), 8, replace=False):
+            core = cores[int(k0)]
+            want = _k_nearest_outside(X, core, S.overlap_count(core.size, 10))
+            assert np.array_equal(g[int(k0)][1], want), k0
+        r = rng.uniform(-1, 1, len(X))
+        z = host(ctx.schwarz_apply(dev(torch, r)))
+        torch.cuda.synchronize()
+        members = [np.concatenate([a, b]) for a, b in gpu]
+        for i in rng.choice(len(gpu), 6, replace=False):
+            core = gpu[i][0]
+            want = np.zeros(core.size)
+            bound = np.zeros(core.size)
+            for h, mem in enumerate(members):
+                pos = np.nonzero(np.isin(mem, core))[0]
+                if pos.size == 0:
+                    continue
+                A = S.local_matrix(X, mem, cfg["sigma"], 0.1)
+                y = np.linalg.solve(A, r[mem])
+                b = np.abs(np.linalg.inv(A)) @ np.abs(r[mem])
+                idx = np.searchsorted(np.sort(core), mem[pos])
+                order = np.argsort(core)
+                want[order[idx]] += y[pos]
+                bound[order[idx]] += b[pos]
+            err = np.abs(z[core] - want)
+            assert np.all(err <= 4 * U32 * bound + 1e-12 * np.abs(want).max()), (i, err.max(), bound.max())
     finally:
         ctx.close()
