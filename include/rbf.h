@@ -74,6 +74,11 @@ typedef struct {
                           the operator's output: RBF_FP32 (default) or RBF_FP64.  Its dot products,
                           norms, updates and least squares are float64 either way.  The plain method
                           always stores float64 and ignores this field. */
+    int graph;         /* 1 (default): the Arnoldi steps of a full GMRES cycle (operator,
+                          preconditioner and orthogonalisation launches) are captured once into a
+                          HIP graph on the context and replayed for every full cycle; 0: launched
+                          one by one.  The same kernels in the same order: identical results.  Not
+                          used while launch profiling (rbf_profile_begin) is on. */
 } rbf_solve_opts;
 
 typedef struct {

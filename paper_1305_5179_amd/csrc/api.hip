@@ -88,11 +88,20 @@ bool is_device_ptr(const void* p) {
 }
 
 
+void drop_cycle_graph(Ctx* c) {
+  if (c->cycle_exec) (void)hipGraphExecDestroy(c->cycle_exec);
+  c->cycle_exec = nullptr;
+  c->cycle_key.clear();
+}
+
 void free_ctx(Ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   SyncedRelease synced;   // the device is idle: the blocks may go to any stream
+  drop_cycle_graph(c);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  c->capture_stream = nullptr;
   free_targets(c->centres);
   free_schwarz(c->schwarz);
   c->schwarz = nullptr;
@@ -215,6 +224,7 @@ int rbf_default_solve_opts(rbf_solve_opts* o) {
   o->mode = RBF_SOLVE_IR_FP32;
   o->precond = RBF_PRECOND_NONE;
   o->basis = RBF_FP32;
+  o->graph = 1;
   return RBF_OK;
 }
 
@@ -361,6 +371,7 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
   if (o.precond != RBF_PRECOND_NONE && o.precond != RBF_PRECOND_SCHWARZ)
     return fail(c, RBF_EINVAL, "unknown preconditioner");
   if (o.basis != RBF_FP32 && o.basis != RBF_FP64) return fail(c, RBF_EINVAL, "basis must be RBF_FP32 or RBF_FP64");
+  if (o.graph != 0 && o.graph != 1) return fail(c, RBF_EINVAL, "graph must be 0 or 1");
   if (o.precond == RBF_PRECOND_SCHWARZ && !c->schwarz)
     return fail(c, RBF_EINVAL, "no Schwarz preconditioner on this context (rbf_schwarz_setup)");
   if ((b && !is_device_ptr(b)) || (x0 && !is_device_ptr(x0)) || !is_device_ptr(cout))
@@ -449,27 +460,59 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
         const int steps = std::min<int64_t>(o.restart, (int64_t)o.max_iters - iters);
         const int* skip = gm_done_flag(c->state);
         const SchwarzData* pre = o.precond == RBF_PRECOND_SCHWARZ ? c->schwarz : nullptr;
-        for (int j = 0; j < steps; ++j) {
-          if (f32) {
-            const float* vj = reinterpret_cast<const float*>(c->V) + (int64_t)j * ldv;
-            float* w = reinterpret_cast<float*>(c->w);
-            if (pre) {
-              // right preconditioning: the basis is built on A M
-              to_f64(vj, c->vin, m, s);
-              schwarz_apply(*c, *pre, c->vin, pre->z, s, skip);
-              pairsum_f32(*c, c->centres, pre->z, true, w, s, skip);
+        // the Arnoldi steps of the cycle, on stream st (launches only: no
+        // allocation, copy or wait, so that they can be captured)
+        auto arnoldi_steps = [&](hipStream_t st, int count) {
+          for (int j = 0; j < count; ++j) {
+            if (f32) {
+              const float* vj = reinterpret_cast<const float*>(c->V) + (int64_t)j * ldv;
+              float* w = reinterpret_cast<float*>(c->w);
+              if (pre) {
+                // right preconditioning: the basis is built on A M
+                to_f64(vj, c->vin, m, st);
+                schwarz_apply(*c, *pre, c->vin, pre->z, st, skip);
+                pairsum_f32(*c, c->centres, pre->z, true, w, st, skip);
+              } else {
+                pairsum_f32(*c, c->centres, nullptr, true, w, st, skip, vj);
+              }
             } else {
-              pairsum_f32(*c, c->centres, nullptr, true, w, s, skip, vj);
+              const double* vj = c->V + (int64_t)j * ldv;
+              if (pre) {
+                schwarz_apply(*c, *pre, vj, pre->z, st, skip);
+                vj = pre->z;
+              }
+              apply_sorted(c, vj, c->w, prec, st, skip);
             }
-          } else {
-            const double* vj = c->V + (int64_t)j * ldv;
-            if (pre) {
-              schwarz_apply(*c, *pre, vj, pre->z, s, skip);
-              vj = pre->z;
-            }
-            apply_sorted(c, vj, c->w, prec, s, skip);
+            gm_step(c->V, ldv, c->w, f32, m, j, c->partial, c->state, st);
           }
-          gm_step(c->V, ldv, c->w, f32, m, j, c->partial, c->state, s);
+        };
+        if (o.graph && steps == o.restart && !profiling()) {
+          const std::vector<intptr_t> key = {o.restart, f32, prec, (intptr_t)pre, (intptr_t)c->V, (intptr_t)c->w,
+                                             (intptr_t)c->vin, (intptr_t)c->partial, (intptr_t)c->state,
+                                             (intptr_t)ldv, (intptr_t)m};
+          if (!c->cycle_exec || c->cycle_key != key) {
+            drop_cycle_graph(c);
+            if (!c->capture_stream) RBF_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            hipGraph_t g = nullptr;
+            RBF_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
+            try {
+              arnoldi_steps(c->capture_stream, steps);
+            } catch (...) {
+              (void)hipStreamEndCapture(c->capture_stream, &g);
+              if (g) (void)hipGraphDestroy(g);
+              throw;
+            }
+            RBF_HIP(hipStreamEndCapture(c->capture_stream, &g));
+            hipGraphExec_t ex = nullptr;
+            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            RBF_HIP(e);
+            c->cycle_exec = ex;
+            c->cycle_key = key;
+          }
+          RBF_HIP(hipGraphLaunch(c->cycle_exec, s));
+        } else {
+          arnoldi_steps(s, steps);
         }
         if (pre) {
           // c += M (V y)
@@ -787,6 +830,7 @@ int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream)
     return fail(c, RBF_EINVAL, "max_block too small for one point and its overlap");
   return guarded(c, [&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    drop_cycle_graph(c);        // it may hold the old preconditioner's launches
     free_schwarz(c->schwarz);   // stream-ordered release: queued work on this stream finishes first
     c->schwarz = nullptr;
     c->schwarz = schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, s);

@@ -201,6 +201,12 @@ struct Ctx {
   double* partial = nullptr;    // block partial sums
   int64_t partial_cap = 0;
   void* state = nullptr;        // device GMRES state
+  // The Arnoldi steps of one full GMRES cycle, captured (on a stream of the
+  // context's own) into a graph, with the buffers and options it was
+  // captured for.
+  hipGraphExec_t cycle_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::vector<intptr_t> cycle_key;
   std::vector<double> history;
   std::vector<double> history_ms;
   std::string err;

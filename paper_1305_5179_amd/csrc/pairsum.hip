@@ -564,12 +564,20 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   a.w32 = w32;
   const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
   ProfScope prof(RBF_FP32, ts.kind, ts.useful, ts.list_entries * kGroup, s);
-  if (w32)
-    hipExtLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
-                          prof.stop(), 0, a);
-  else
-    hipExtLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
-                          prof.stop(), 0, a);
+  // a timed launch carries its events in the dispatch; an untimed one is a
+  // plain launch (which a stream capture can record)
+  if (prof.start()) {
+    if (w32)
+      hipExtLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
+                            prof.stop(), 0, a);
+    else
+      hipExtLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
+                            prof.stop(), 0, a);
+  } else if (w32) {
+    hipLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
+  }
   RBF_HIP(hipGetLastError());
   prof.done();
 }
@@ -580,7 +588,10 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   PairArgs a = make_args(c, ts, w, out_f32, out, skip);
   const int64_t nb = ceil_div(ts.n_groups, kBlock / kWave);
   ProfScope prof(RBF_FP64, ts.kind, ts.useful, ts.list_entries * kGroup, s);
-  hipExtLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, prof.start(), prof.stop(), 0, a);
+  if (prof.start())
+    hipExtLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, prof.start(), prof.stop(), 0, a);
+  else
+    hipLaunchKernelGGL(k_pairsum_f64, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }

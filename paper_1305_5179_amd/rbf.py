@@ -34,7 +34,8 @@ RBF_NET_PARAMS = 50177
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_outer", C.c_int),
-                ("max_iters", C.c_int), ("mode", C.c_int), ("precond", C.c_int), ("basis", C.c_int)]
+                ("max_iters", C.c_int), ("mode", C.c_int), ("precond", C.c_int), ("basis", C.c_int),
+                ("graph", C.c_int)]
 
 
 class SchwarzOpts(C.Structure):

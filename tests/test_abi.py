@@ -43,9 +43,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_solve_options():
     o = rbf.default_opts()
-    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.precond, o.basis) == \
-        (1e-8, 30, 1000, 30000, 1, 0, rbf.RBF_FP32)
-    assert C.sizeof(rbf.SolveOpts) == 32
+    assert (o.tol, o.restart, o.max_outer, o.max_iters, o.mode, o.precond, o.basis, o.graph) == \
+        (1e-8, 30, 1000, 30000, 1, 0, rbf.RBF_FP32, 1)
+    assert C.sizeof(rbf.SolveOpts) == 40
     assert rbf.load_library().rbf_default_solve_opts(None) == rbf.RBF_EINVAL
 
 

@@ -259,3 +259,33 @@ def test_sphere_signs_match_the_geometry(torch, R):
              f"wrong {bad}")
         assert sel.sum() > 0.9 * band.sum()
         assert bad == 0
+
+
+# ---------------------------------------------------------------------------
+# Graph-captured GMRES cycles
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,basis,pre", [(1, 0, False), (1, 1, False), (0, 1, False), (1, 0, True), (0, 1, True)],
+                         ids=["refined-basis32", "refined-basis64", "plain", "refined-schwarz", "plain-schwarz"])
+def test_graph_replay_equals_eager_launches(torch, R, mode, basis, pre):
+    """A full cycle's Arnoldi steps captured into a graph and replayed every
+    cycle (eager work and host waits between the replays) give the same bits
+    as launching them one by one: the weights and every cycle's residual."""
+    c = w.torus(6000, seed=1, R=0.1732, r=0.0606)
+    ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), 0.005, 0.02, 0.08)
+    try:
+        if pre:
+            ctx.schwarz_setup(max_block=300, min_block=64)
+        out = {}
+        for graph in (0, 1, 1):
+            _say(f"[graph] mode {mode} basis {basis} schwarz {pre} graph {graph}")
+            cw, res = ctx.solve(tol=1e-12, restart=10, max_iters=95, mode=mode, basis=basis, graph=graph,
+                                precond=R.RBF_PRECOND_SCHWARZ if pre else R.RBF_PRECOND_NONE)
+            torch.cuda.synchronize()
+            out.setdefault(graph, []).append((host(cw), list(res.history), res.iters))
+        eager, g1, g2 = out[0][0], out[1][0], out[1][1]
+        assert eager[2] == 95 and len(eager[1]) >= 9      # nine full cycles replayed, then a partial one
+        for g in (g1, g2):
+            assert g[1] == eager[1] and g[2] == eager[2]
+            assert np.array_equal(g[0], eager[0])
+    finally:
+        ctx.close()
