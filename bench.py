@@ -11,6 +11,29 @@ value = useful kernel evaluations (pairs with r <= cutoff) of every operator
 application and of the grid, divided by the step time.  Inputs (points,
 normals) are resident in device memory before timing starts.
 
+Fields beside the step (all measured after the timed steps):
+  roofline      the float32 operator kernel's live launch time (HIP events in
+                its dispatches during the timed steps) against the pair peak,
+                with its HBM bytes from the committed counter summary;
+  phases, pairs setup / cycle / grid split, matvec times, pair counts;
+  schwarz, schwarz1024
+                the Schwarz preconditioner with blocks up to 192 and with
+                blocks of 64..1024: setup, local inverses, apply time and its
+                HBM fraction;
+  solve         the second half of the metric: setup -> solve -> grid to
+                relative residual 1e-8 (or 3,000 operator applications) for
+                the refinement (float32 and float64 Krylov basis), the same
+                with each Schwarz configuration, and the plain float64
+                method; residual/time histories, stall levels, and time to
+                the lowest residual all reach with the speed-up over plain;
+  signs         every pipeline's 256^3 grid against the plain method's on the
+                nodes with |f| > 1e-6 + 8 u32 sum_j |c_j phi_j| (and the
+                torus's signed distance);
+  cpu_baseline  the C cell-list oracle (float64, OpenMP) on one thread and on
+                every host thread: a sampled share of the operator's rows and
+                band points of the grid, scaled to the step, with the solve's
+                time extrapolated from its operator applications.
+
 Prints one JSON line.  --gpus above 1 is refused: this path runs on one GPU.
 """
 from __future__ import annotations
