@@ -47,7 +47,7 @@ constexpr int kFacThreads = 512;
 constexpr int kPacked = kSchwarzLdsBlock * (kSchwarzLdsBlock + 1) / 2;
 constexpr int kPanel = 64;   // pivots per panel of the global-memory sweep
 constexpr int kSmallWords = kPacked + 4 * kSchwarzLdsBlock;
-constexpr int kBigWords = 3 * kSchwarzMaxBlock + 3 * kPanel * kPanel + kPanel;
+constexpr int kBigWords = 3 * kSchwarzMaxBlock + 4 * kPanel * kPanel + kPanel;
 constexpr int kFacWords = kSmallWords > kBigWords ? kSmallWords : kBigWords;
 static_assert(kFacWords * 8 + 64 <= 160 * 1024, "the factor kernel's LDS fits a compute unit");
 static_assert(kFacThreads == 512, "the tile update maps 16 x 32 threads onto 64 x 64 entries");
@@ -322,33 +322,41 @@ __device__ bool sweep_lds(double* A, double* col, const double* px, const double
   return true;
 }
 
-// Larger blocks: the full n x n matrix G in global memory, swept kPanel
+// Larger blocks: the matrix G in global memory, of which only the lower
+// triangle (i >= j) is kept (the swept matrix stays symmetric), swept kPanel
 // pivots at a time (the block form of the same sweep).  With the pivot block
-// D of the panel and Q its columns (= rows: the swept matrix stays
-// symmetric), one panel sweeps D in LDS to -D^{-1}, forms P = Q D^{-1}, then
-// updates every entry outside the panel, G_ij -= P_i . Q_j, and writes P into
-// the panel's rows and columns.  P and Q go to global memory first (the
-// tiles of the update overwrite the panel); the update runs in 64 x 64 tiles
-// from LDS, four rows by two columns per thread.
+// D of the panel and Q its columns, one panel sweeps D in LDS to -D^{-1},
+// forms P = Q D^{-1}, then updates the lower entries outside the panel,
+// G_ij -= P_i . Q_j, and writes P into the panel's row (left of the
+// diagonal) and column (below it).  P and Q are written to global memory
+// first (the update overwrites what they were read from).  The update runs
+// over 64 x 64 tiles on or below the diagonal, 4 x 2 entries per thread from
+// LDS; the next tile's entries and Q rows are loaded into registers while
+// the current tile computes (two LDS buffers for Q).
 __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, double* lds, const double* px,
                              const double* py, const double* pz, int n, double shift, double two_s2) {
+  constexpr int kT = kPanel * kPanel;
+  constexpr int kSP = kPanel + 1;         // pitch of the strip buffer (rows read along G's rows)
   const int tid = threadIdx.x;
-  double* D = lds;                        // kPanel x kPanel, row-major
-  double* PT = D + kPanel * kPanel;       // PT[l][r]: P of the rows of a tile, by panel column
-  double* QT = PT + kPanel * kPanel;      // QT[l][r]
-  double* colv = QT + kPanel * kPanel;    // kPanel
+  double* D = lds;                        // kPanel x kPanel, row-major (symmetric)
+  double* PT = D + kT;                    // PT[l][r]: P of a tile's rows, by panel column
+  double* QB = PT + kT;                   // two buffers QB[b][l][r]: Q of a tile's columns
+  double* colv = QB + 2 * kT;             // kPanel
+  double* S = QB;                         // strip buffer S[l][r] (pitch kSP) over both Q buffers
+  static_assert(kSP * kPanel <= 2 * kT, "the strip buffer fits the two Q buffers");
   __syncthreads();
   for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
     const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-    G[e] = gauss_entry(px, py, pz, i, j, shift, two_s2);
+    if (i >= j) G[e] = gauss_entry(px, py, pz, i, j, shift, two_s2);
   }
   const int nt = (n + kPanel - 1) / kPanel;
+  const int tr = tid >> 5, tc = tid & 31;   // 16 x 32 threads over a 64 x 64 tile
   for (int p = 0; p < nt; ++p) {
     const int K = p * kPanel, kb = min(kPanel, n - K);
     __syncthreads();
-    for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+    for (int e = tid; e < kT; e += kFacThreads) {
       const int r = e / kPanel, c = e % kPanel;
-      D[e] = r < kb && c < kb ? G[(int64_t)(K + r) * n + K + c] : 0.0;
+      D[e] = r < kb && c < kb ? G[(int64_t)(K + max(r, c)) * n + K + min(r, c)] : 0.0;
     }
     __syncthreads();
     for (int k = 0; k < kb; ++k) {
@@ -357,7 +365,7 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       if (tid < kb) colv[tid] = D[tid * kPanel + k];
       __syncthreads();
       const double inv = 1.0 / d;
-      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+      for (int e = tid; e < kT; e += kFacThreads) {
         const int r = e / kPanel, c = e % kPanel;
         if (r >= kb || c >= kb) continue;
         if (r != k && c != k)
@@ -369,87 +377,121 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       }
       __syncthreads();
     }
-    // Q (the panel's rows, read along them) and P = Q D^{-1} = -Q D, strip by strip
+    // Q of every row outside the panel (left of it: along the panel's rows;
+    // below it: along the row itself) and P = Q D^{-1} = -Q D, strip by strip
     for (int s0 = 0; s0 < n; s0 += kPanel) {
+      if (s0 == K) continue;
       const int rows = min(kPanel, n - s0);
-      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
-        const int l = e / kPanel, r = e % kPanel;
-        QT[e] = l < kb && r < rows ? G[(int64_t)(K + l) * n + s0 + r] : 0.0;
+      for (int e = tid; e < kT; e += kFacThreads) {
+        if (s0 < K) {
+          const int l = e / kPanel, r = e % kPanel;
+          S[l * kSP + r] = l < kb && r < rows ? G[(int64_t)(K + l) * n + s0 + r] : 0.0;
+        } else {
+          const int r = e / kPanel, l = e % kPanel;
+          S[l * kSP + r] = l < kb && r < rows ? G[(int64_t)(s0 + r) * n + K + l] : 0.0;
+        }
       }
       __syncthreads();
-      for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
+      for (int e = tid; e < kT; e += kFacThreads) {
         const int l = e / kPanel, r = e % kPanel;
         if (l >= kb || r >= rows) continue;
+        // (a fixed trip count over the whole panel: the entries beyond kb
+        // are zero in both operands)
         double acc = 0.0;
-        for (int q = 0; q < kb; ++q) acc = fma(QT[q * kPanel + r], D[q * kPanel + l], acc);
+#pragma unroll 8
+        for (int q = 0; q < kPanel; ++q) acc = fma(S[q * kSP + r], D[q * kPanel + l], acc);
         Pg[(int64_t)l * ld + s0 + r] = -acc;
-        Qg[(int64_t)l * ld + s0 + r] = QT[e];
+        Qg[(int64_t)l * ld + s0 + r] = S[l * kSP + r];
       }
       __syncthreads();
     }
-    const int tr = tid >> 5, tc = tid & 31;   // 16 x 32 threads over a 64 x 64 tile
+    // the update of the lower tiles outside the panel's row and column
     for (int ti = 0; ti < nt; ++ti) {
+      if (ti == p) continue;
       const int i0 = ti * kPanel, ri = min(kPanel, n - i0);
+      const int nj = ti + 1;   // tiles tj = 0 .. ti, the panel's skipped
       __syncthreads();
-      if (ti != p)
-        for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
-          const int l = e / kPanel, r = e % kPanel;
-          PT[e] = l < kb && r < ri ? Pg[(int64_t)l * ld + i0 + r] : 0.0;
-        }
-      for (int tj = 0; tj < nt; ++tj) {
-        const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
-        __syncthreads();
-        if (ti != p && tj != p)
-          for (int e = tid; e < kPanel * kPanel; e += kFacThreads) {
-            const int l = e / kPanel, r = e % kPanel;
-            QT[e] = l < kb && r < rj ? Qg[(int64_t)l * ld + j0 + r] : 0.0;
-          }
-        __syncthreads();
-        if (ti != p && tj != p) {
-          double acc[4][2];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int r = 4 * tr + q, cc = 2 * tc + c;
-              acc[q][c] = r < ri && cc < rj ? G[(int64_t)(i0 + r) * n + j0 + cc] : 0.0;
-            }
-          for (int l = 0; l < kb; ++l) {
-            double pv[4], qv[2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) pv[q] = PT[l * kPanel + 4 * tr + q];
-#pragma unroll
-            for (int c = 0; c < 2; ++c) qv[c] = QT[l * kPanel + 2 * tc + c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-              for (int c = 0; c < 2; ++c) acc[q][c] = fma(-pv[q], qv[c], acc[q][c]);
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int r = 4 * tr + q, cc = 2 * tc + c;
-              if (r < ri && cc < rj) G[(int64_t)(i0 + r) * n + j0 + cc] = acc[q][c];
-            }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const int r = 4 * tr + q, cc = 2 * tc + c;
-              if (r >= ri || cc >= rj) continue;
-              double v;
-              if (ti == p && tj == p)
-                v = D[r * kPanel + cc];
-              else if (ti == p)
-                v = Pg[(int64_t)r * ld + j0 + cc];   // row K + r: P of column j, panel column r
-              else
-                v = Pg[(int64_t)cc * ld + i0 + r];   // column K + cc: P of row i
-              G[(int64_t)(i0 + r) * n + j0 + cc] = v;
-            }
-        }
+      for (int e = tid; e < kT; e += kFacThreads) {
+        const int l = e / kPanel, r = e % kPanel;
+        PT[e] = l < kb && r < ri ? Pg[(int64_t)l * ld + i0 + r] : 0.0;
       }
+      // tile tj: its 4 x 2 entries of this thread and its Q rows (8 per thread)
+      double g[4][2], gn[4][2], qn[kT / kFacThreads];
+      auto load_tile = [&](int tj, double (&gv)[4][2], double (&qv)[kT / kFacThreads]) {
+        const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int r = 4 * tr + q, cc = 2 * tc + c;
+            gv[q][c] = r < ri && cc < rj ? G[(int64_t)(i0 + r) * n + j0 + cc] : 0.0;
+          }
+#pragma unroll
+        for (int k = 0; k < kT / kFacThreads; ++k) {
+          const int e = tid + k * kFacThreads, l = e / kPanel, r = e % kPanel;
+          qv[k] = l < kb && r < rj ? Qg[(int64_t)l * ld + j0 + r] : 0.0;
+        }
+      };
+      auto next_tile = [&](int tj) { return tj + 1 == p ? tj + 2 : tj + 1; };
+      int tj = p == 0 ? 1 : 0;
+      if (tj >= nj) continue;
+      load_tile(tj, g, qn);
+#pragma unroll
+      for (int k = 0; k < kT / kFacThreads; ++k) QB[tid + k * kFacThreads] = qn[k];
+      __syncthreads();
+      for (int b = 0; tj < nj; b ^= 1) {
+        const int tn = next_tile(tj);
+        if (tn < nj) load_tile(tn, gn, qn);
+        const double* Q = QB + b * kT;
+        // (the rows of PT and Q beyond kb are zero: a fixed trip count)
+#pragma unroll 8
+        for (int l = 0; l < kPanel; ++l) {
+          double pv[4], qv[2];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) pv[q] = PT[l * kPanel + 4 * tr + q];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) qv[c] = Q[l * kPanel + 2 * tc + c];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) g[q][c] = fma(-pv[q], qv[c], g[q][c]);
+        }
+        const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int r = 4 * tr + q, cc = 2 * tc + c;
+            if (r < ri && cc < rj) G[(int64_t)(i0 + r) * n + j0 + cc] = g[q][c];
+          }
+        if (tn < nj) {
+#pragma unroll
+          for (int k = 0; k < kT / kFacThreads; ++k) QB[(b ^ 1) * kT + tid + k * kFacThreads] = qn[k];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) g[q][c] = gn[q][c];
+        }
+        __syncthreads();
+        tj = tn;
+      }
+    }
+    // the panel's row (left of the diagonal block), column (below it) and
+    // diagonal block
+    for (int64_t e = tid; e < (int64_t)kb * K; e += kFacThreads) {
+      const int r = (int)(e / K), j = (int)(e - (int64_t)r * K);
+      G[(int64_t)(K + r) * n + j] = Pg[(int64_t)r * ld + j];
+    }
+    // (by panel column, so that the reads are contiguous; the stores wait
+    // for nothing)
+    const int below = n - K - kb;
+    for (int64_t e = tid; e < (int64_t)below * kb; e += kFacThreads) {
+      const int c = (int)(e / below), i = K + kb + (int)(e % below);
+      G[(int64_t)i * n + K + c] = Pg[(int64_t)c * ld + i];
+    }
+    for (int e = tid; e < kT; e += kFacThreads) {
+      const int r = e / kPanel, c = e % kPanel;
+      if (r < kb && c <= r) G[(int64_t)(K + r) * n + K + c] = D[e];
     }
   }
   __syncthreads();
@@ -507,7 +549,15 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
         if (i != j) W[(int64_t)j * n + i] = v;
       });
     } else {
-      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) W[e] = ok ? (float)(-big[e]) : 0.0f;
+      // (the lower triangle holds the result: read along its rows, each
+      // entry stored at (i, j) and (j, i))
+      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j > i) continue;
+        const float v = ok ? (float)(-big[e]) : 0.0f;
+        W[e] = v;
+        W[(int64_t)j * n + i] = v;
+      }
     }
     if (tid == 0) {
       a.shift_used[sub] = shift;
