@@ -623,6 +623,36 @@ __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
   }
 }
 
+// Occurrences of the centres among the member slots (additive form): the
+// slots of centre j are occ_slot[occ_off[j] .. occ_off[j + 1]), increasing
+// (subdomain order).  Counted, scanned, filled in any order, then each
+// centre's few slots sorted by one thread.
+__global__ void k_occ_count(const uint32_t* __restrict__ mem, int64_t nmem, unsigned long long* __restrict__ cnt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nmem) atomicAdd(cnt + mem[e], 1ull);
+}
+__global__ void k_occ_fill(const uint32_t* __restrict__ mem, int64_t nmem, const int64_t* __restrict__ occ_off,
+                           unsigned long long* __restrict__ fill, int64_t* __restrict__ occ_slot) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nmem) return;
+  const uint32_t j = mem[e];
+  occ_slot[occ_off[j] + (int64_t)atomicAdd(fill + j, 1ull)] = e;
+}
+__global__ void k_occ_sort(const int64_t* __restrict__ occ_off, int64_t m, int64_t* __restrict__ occ_slot) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int64_t a = occ_off[j], b = occ_off[j + 1];
+  for (int64_t x = a + 1; x < b; ++x) {
+    const int64_t v = occ_slot[x];
+    int64_t y = x - 1;
+    while (y >= a && occ_slot[y] > v) {
+      occ_slot[y + 1] = occ_slot[y];
+      --y;
+    }
+    occ_slot[y + 1] = v;
+  }
+}
+
 __global__ void k_schwarz_sum(const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ_slot,
                               const double* __restrict__ Y, int64_t m, double* __restrict__ z, const int* skip) {
   if (skip && *skip) return;
@@ -702,7 +732,7 @@ void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, in
 
 // The apply's launch shape: strips of 256 or 512 rows, taken by 2, 4 or 8
 // workgroups per compute unit or by one workgroup per task; each candidate
-// runs once untimed and three times timed on the work vector (the work and
+// runs once untimed and twice timed on the work vector (the work and
 // the result do not depend on the values), and the fastest is kept.
 void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
   struct Cand {
@@ -722,7 +752,7 @@ void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
     const int blocks = c.blocks > 0 ? std::min<int64_t>((int64_t)c.blocks * cus, (int64_t)ht.size()) : (int)ht.size();
     launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
     RBF_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < 3; ++k) launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
+    for (int k = 0; k < 2; ++k) launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
     RBF_HIP(hipEventRecord(e1, s));
     RBF_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -874,7 +904,13 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   uint32_t* d_core_mem = upload(core_mem, s);
   int32_t* d_k = upload(kcount, s);
   int64_t* d_ov_off = upload(ov_off, s);
-  double* d_rho = upload(rho, s);
+  // the search radius: an eighth of the leaf side first (the overlap of a
+  // core is a thin shell around it, about 1/40 of the side of a full leaf at
+  // 10 %), then the side, then everything, for the cores still short of k
+  std::vector<double> rho8(rho);
+  for (double& r : rho8) r *= 0.125;
+  double* d_rho = upload(rho8, s);
+  double* d_rho_full = upload(rho, s);
   double* d_box = talloc<double>(6 * std::max<int64_t>(nsub, 1));
   uint32_t* d_ov = talloc<uint32_t>(std::max<int64_t>(ov_off[nsub], 1));
   int32_t* d_short = talloc<int32_t>(std::max<int64_t>(nsub, 1));
@@ -890,21 +926,27 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     std::vector<int32_t> again;
     for (int64_t i = 0; i < nsub; ++i)
       if (short_of[i]) again.push_back((int32_t)i);
-    if (!again.empty()) {
-      // too few centres within the leaf-sized radius: search them all
+    for (int pass = 0; pass < 2 && !again.empty(); ++pass) {
+      // too few centres within the radius: the leaf side, then every centre
       int32_t* d_list = upload(again, s);
       oa.list = d_list;
-      oa.unbounded = 1;
+      oa.rho = d_rho_full;
+      oa.unbounded = pass;
       hipLaunchKernelGGL(k_schwarz_overlap, dim3((unsigned)again.size()), dim3(kOvThreads), 0, s, oa);
       RBF_HIP(hipGetLastError());
+      short_of = download(d_short, nsub, s);
       RBF_HIP(hipStreamSynchronize(s));
       dfree(d_list);
+      std::vector<int32_t> still;
+      for (int32_t i : again)
+        if (short_of[i]) still.push_back(i);
+      again.swap(still);
     }
     ov = download(d_ov, ov_off[nsub], s);
     RBF_HIP(hipStreamSynchronize(s));
   }
-  for (void* p : {(void*)d_core_off, (void*)d_core_mem, (void*)d_k, (void*)d_ov_off, (void*)d_rho, (void*)d_box,
-                  (void*)d_ov, (void*)d_short})
+  for (void* p : {(void*)d_core_off, (void*)d_core_mem, (void*)d_k, (void*)d_ov_off, (void*)d_rho, (void*)d_rho_full,
+                  (void*)d_box, (void*)d_ov, (void*)d_short})
     dfree(p);
 
   // 5. members in sorted positions, layout of the inverses, occurrences
@@ -918,6 +960,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   d->pct = pct;
   d->h_mem_off.assign(nsub + 1, 0);
   d->h_ncore.resize(nsub);
+  d->h_mem_paper.reserve((size_t)(core_off[nsub] + ov_off[nsub]));
   std::vector<uint32_t> mem;
   std::vector<int64_t> woff(nsub, 0);
   std::vector<int32_t> order(nsub);
@@ -946,13 +989,22 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   d->W = dalloc<float>(std::max<int64_t>(wtotal, 1));
   d->w_total = wtotal;
   if (!restricted) {
-    std::vector<int64_t> occ_off(m + 1, 0), occ_slot(d->nmem);
-    for (int64_t e = 0; e < d->nmem; ++e) ++occ_off[mem[e] + 1];
-    for (int64_t j = 0; j < m; ++j) occ_off[j + 1] += occ_off[j];
-    std::vector<int64_t> fillp(occ_off.begin(), occ_off.end() - 1);
-    for (int64_t e = 0; e < d->nmem; ++e) occ_slot[fillp[mem[e]]++] = e;   // subdomain order
-    d->occ_off = upload(occ_off, s);
-    d->occ_slot = upload(occ_slot, s);
+    // counts (m + 1 entries, the last 0), their exclusive scan, the fill
+    int64_t* cnt = talloc<int64_t>(2 * (m + 1));
+    int64_t* fill = cnt + (m + 1);
+    fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 4 * (m + 1), s);
+    d->occ_off = dalloc<int64_t>(m + 1);
+    d->occ_slot = dalloc<int64_t>(std::max<int64_t>(d->nmem, 1));
+    const unsigned eb = (unsigned)ceil_div(std::max<int64_t>(d->nmem, 1), 256);
+    hipLaunchKernelGGL(k_occ_count, dim3(eb), dim3(256), 0, s, d->mem, d->nmem,
+                       reinterpret_cast<unsigned long long*>(cnt));
+    RBF_HIP(hipGetLastError());
+    scan_exclusive_i64(cnt, d->occ_off, m + 1, s);
+    hipLaunchKernelGGL(k_occ_fill, dim3(eb), dim3(256), 0, s, d->mem, d->nmem, d->occ_off,
+                       reinterpret_cast<unsigned long long*>(fill), d->occ_slot);
+    hipLaunchKernelGGL(k_occ_sort, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, d->occ_off, m, d->occ_slot);
+    RBF_HIP(hipGetLastError());
+    temp_free(cnt);
     d->Y = dalloc<double>(std::max<int64_t>(d->nmem, 1));
   }
   d->z = dalloc<double>(c.mpad);
