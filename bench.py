@@ -356,7 +356,8 @@ def schwarz_measurement(rbf, ctx, torch, x, opts):
     apply_ms = e0.elapsed_time(e1) / reps
     m = x.numel()
     alg_bytes = info.inverse_bytes + 8 * (3 * info.n_members + 4 * m)
-    return {"form": "additive", "options": opts, "overlap_pct": 10, "shift": 0.1,
+    return {"form": "additive", "options": opts, "overlap_pct": opts.get("overlap_pct", 10),
+            "shift": opts.get("shift", 0.3),
             "n_sub": info.n_sub, "n_members": info.n_members, "min_members": info.min_members,
             "max_members": info.max_members, "inverse_bytes": info.inverse_bytes, "retries": info.retries,
             "setup_ms": setup_ms, "factor_ms": info.factor_ms,
@@ -434,7 +435,8 @@ def cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, n_samples, epochs):
 # the Schwarz configurations: blocks up to 192 centres (every block inverted
 # in LDS; about 9,500 subdomains on the torus), and blocks of 64..1024
 # centres (small octree leaves merged; about 2,000 subdomains, the larger
-# blocks inverted in global memory), each with shift 0.1
+# blocks inverted in global memory), each with the library's default shift
+# (0.3) and overlap (10 %)
 SCHWARZ_192 = dict(max_block=192)
 SCHWARZ_1024 = dict(max_block=1024, min_block=64)
 

@@ -89,7 +89,7 @@ typedef struct {
     int min_block;     /* 0: every octree leaf is a core (default); > 0: consecutive leaves are
                           joined while the block (core + overlap) is below min_block and the
                           cap allows, 0..max_block */
-    double shift;      /* added to the unit diagonal of every local block, >= 0 (default 0.1) */
+    double shift;      /* added to the unit diagonal of every local block, >= 0 (default 0.3) */
     int tune;          /* 1: time the apply kernel's launch shapes at setup and keep the
                           fastest (default); 0: the fixed shape (256 threads, 4 workgroups
                           per compute unit) */

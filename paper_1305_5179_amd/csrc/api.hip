@@ -806,7 +806,7 @@ int rbf_default_schwarz_opts(rbf_schwarz_opts* o) {
   o->overlap_pct = 10;
   o->restricted = 0;
   o->min_block = 0;
-  o->shift = 0.1;
+  o->shift = 0.3;
   o->tune = 1;
   o->reserved = 0;
   return RBF_OK;

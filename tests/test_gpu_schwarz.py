@@ -109,7 +109,7 @@ def built(torch, R):
 
 
 def _oracle_opts(optname):
-    d = dict(max_block=192, overlap_pct=10, restricted=0, shift=0.1, min_block=0)
+    d = dict(max_block=192, overlap_pct=10, restricted=0, shift=0.3, min_block=0)
     d.update(OPTS[optname])
     return d
 
@@ -295,7 +295,7 @@ def test_one_point(torch, R):
         X, _ = o.extended_centres(P, N, 0.05)
         r = np.array([1.0, -2.0, 0.5])
         z = host(ctx.schwarz_apply(dev(torch, r)))
-        want = np.linalg.solve(S.local_matrix(X, np.arange(3), 0.1, 0.1), r)
+        want = np.linalg.solve(S.local_matrix(X, np.arange(3), 0.1, 0.3), r)
         assert np.allclose(z, want, rtol=1e-6, atol=0)
     finally:
         ctx.close()
@@ -422,7 +422,7 @@ def test_torus200k_2048_subdomains(torch, R):
                 pos = np.nonzero(np.isin(mem, core))[0]
                 if pos.size == 0:
                     continue
-                A = S.local_matrix(X, mem, cfg["sigma"], 0.1)
+                A = S.local_matrix(X, mem, cfg["sigma"], 0.3)
                 y = np.linalg.solve(A, r[mem])
                 b = np.abs(np.linalg.inv(A)) @ np.abs(r[mem])
                 idx = np.searchsorted(np.sort(core), mem[pos])
