@@ -50,7 +50,8 @@ constexpr int kSmallWords = kPacked + 4 * kSchwarzLdsBlock;
 constexpr int kBigWords = 3 * kSchwarzMaxBlock + 4 * kPanel * kPanel + kPanel;
 constexpr int kFacWords = kSmallWords > kBigWords ? kSmallWords : kBigWords;
 static_assert(kFacWords * 8 + 64 <= 160 * 1024, "the factor kernel's LDS fits a compute unit");
-static_assert(kFacThreads == 512, "the tile update maps 16 x 32 threads onto 64 x 64 entries");
+static_assert(kFacThreads == 512 && kPanel == 64,
+              "the eight waves of a workgroup own two 16 x 16 blocks each of a 64 x 64 tile");
 
 // ---------------------------------------------------------------------------
 // Bounding box of every core (one wave per subdomain).
@@ -275,6 +276,8 @@ struct FacArgs {
 
 __device__ __forceinline__ int packed(int i, int j) { return i * (i + 1) / 2 + j; }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 // The packed lower triangle is walked row by row: wave w takes the rows
 // i = w, w + 8, ..., its lanes the columns j = lane, lane + 64, ... <= i, so
 // that a wave touches consecutive LDS words and no thread keeps a table.
@@ -350,7 +353,7 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
     if (i >= j) G[e] = gauss_entry(px, py, pz, i, j, shift, two_s2);
   }
   const int nt = (n + kPanel - 1) / kPanel;
-  const int tr = tid >> 5, tc = tid & 31;   // 16 x 32 threads over a 64 x 64 tile
+  const int wave = tid >> 6, lane = tid & 63;
   for (int p = 0; p < nt; ++p) {
     const int K = p * kPanel, kb = min(kPanel, n - K);
     __syncthreads();
@@ -392,16 +395,29 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
         }
       }
       __syncthreads();
+      {
+        // -P = S^T D on the matrix cores: wave w, rows 16 bi.. of the strip,
+        // panel columns 16 bj.. and 16 (bj + 1).. (the entries beyond kb are
+        // zero in both operands)
+        const int bi = wave >> 1, bj = 2 * (wave & 1);
+        v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+#pragma unroll 4
+        for (int kk = 0; kk < kPanel / 4; ++kk) {
+          const int q = 4 * kk + (lane >> 4);
+          const double a = S[q * kSP + 16 * bi + (lane & 15)];
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, D[q * kPanel + 16 * bj + (lane & 15)], c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, D[q * kPanel + 16 * (bj + 1) + (lane & 15)], c1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * bi + (lane >> 4) + 4 * v, l0 = 16 * bj + (lane & 15), l1 = l0 + 16;
+          if (r < rows && l0 < kb) Pg[(int64_t)l0 * ld + s0 + r] = -c0[v];
+          if (r < rows && l1 < kb) Pg[(int64_t)l1 * ld + s0 + r] = -c1[v];
+        }
+      }
       for (int e = tid; e < kT; e += kFacThreads) {
         const int l = e / kPanel, r = e % kPanel;
-        if (l >= kb || r >= rows) continue;
-        // (a fixed trip count over the whole panel: the entries beyond kb
-        // are zero in both operands)
-        double acc = 0.0;
-#pragma unroll 8
-        for (int q = 0; q < kPanel; ++q) acc = fma(S[q * kSP + r], D[q * kPanel + l], acc);
-        Pg[(int64_t)l * ld + s0 + r] = -acc;
-        Qg[(int64_t)l * ld + s0 + r] = S[l * kSP + r];
+        if (l < kb && r < rows) Qg[(int64_t)l * ld + s0 + r] = S[l * kSP + r];
       }
       __syncthreads();
     }
@@ -415,17 +431,22 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
         const int l = e / kPanel, r = e % kPanel;
         PT[e] = l < kb && r < ri ? Pg[(int64_t)l * ld + i0 + r] : 0.0;
       }
-      // tile tj: its 4 x 2 entries of this thread and its Q rows (8 per thread)
-      double g[4][2], gn[4][2], qn[kT / kFacThreads];
-      auto load_tile = [&](int tj, double (&gv)[4][2], double (&qv)[kT / kFacThreads]) {
+      // tile tj on the matrix cores: wave w owns the 16 x 16 blocks (bi,
+      // bj) and (bi, bj + 1) of the tile, its accumulators in the result
+      // layout of v_mfma_f64_16x16x4f64 (lane l, value v: row l / 16 + 4 v,
+      // column l % 16 of the block); the next tile's entries and Q rows (8
+      // per thread) are loaded while the current one computes
+      const int bi = wave >> 1, bj = 2 * (wave & 1);
+      v4d g0, g1, gn0, gn1;
+      double qn[kT / kFacThreads];
+      auto load_tile = [&](int tj, v4d& x0, v4d& x1, double (&qv)[kT / kFacThreads]) {
         const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int r = 4 * tr + q, cc = 2 * tc + c;
-            gv[q][c] = r < ri && cc < rj ? G[(int64_t)(i0 + r) * n + j0 + cc] : 0.0;
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * bi + (lane >> 4) + 4 * v, c0 = 16 * bj + (lane & 15), c1 = c0 + 16;
+          x0[v] = r < ri && c0 < rj ? G[(int64_t)(i0 + r) * n + j0 + c0] : 0.0;
+          x1[v] = r < ri && c1 < rj ? G[(int64_t)(i0 + r) * n + j0 + c1] : 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < kT / kFacThreads; ++k) {
           const int e = tid + k * kFacThreads, l = e / kPanel, r = e % kPanel;
@@ -435,42 +456,34 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       auto next_tile = [&](int tj) { return tj + 1 == p ? tj + 2 : tj + 1; };
       int tj = p == 0 ? 1 : 0;
       if (tj >= nj) continue;
-      load_tile(tj, g, qn);
+      load_tile(tj, g0, g1, qn);
 #pragma unroll
       for (int k = 0; k < kT / kFacThreads; ++k) QB[tid + k * kFacThreads] = qn[k];
       __syncthreads();
       for (int b = 0; tj < nj; b ^= 1) {
         const int tn = next_tile(tj);
-        if (tn < nj) load_tile(tn, gn, qn);
+        if (tn < nj) load_tile(tn, gn0, gn1, qn);
+        // G_ij -= sum_l P_il Q_jl: A = -P (rows of the tile), B = Q^T
         const double* Q = QB + b * kT;
-        // (the rows of PT and Q beyond kb are zero: a fixed trip count)
-#pragma unroll 8
-        for (int l = 0; l < kPanel; ++l) {
-          double pv[4], qv[2];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) pv[q] = PT[l * kPanel + 4 * tr + q];
-#pragma unroll
-          for (int c = 0; c < 2; ++c) qv[c] = Q[l * kPanel + 2 * tc + c];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) g[q][c] = fma(-pv[q], qv[c], g[q][c]);
+#pragma unroll 4
+        for (int kk = 0; kk < kPanel / 4; ++kk) {
+          const int l = 4 * kk + (lane >> 4);
+          const double a = -PT[l * kPanel + 16 * bi + (lane & 15)];
+          g0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[l * kPanel + 16 * bj + (lane & 15)], g0, 0, 0, 0);
+          g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Q[l * kPanel + 16 * (bj + 1) + (lane & 15)], g1, 0, 0, 0);
         }
         const int j0 = tj * kPanel, rj = min(kPanel, n - j0);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int r = 4 * tr + q, cc = 2 * tc + c;
-            if (r < ri && cc < rj) G[(int64_t)(i0 + r) * n + j0 + cc] = g[q][c];
-          }
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * bi + (lane >> 4) + 4 * v, c0 = 16 * bj + (lane & 15), c1 = c0 + 16;
+          if (r < ri && c0 < rj) G[(int64_t)(i0 + r) * n + j0 + c0] = g0[v];
+          if (r < ri && c1 < rj) G[(int64_t)(i0 + r) * n + j0 + c1] = g1[v];
+        }
         if (tn < nj) {
 #pragma unroll
           for (int k = 0; k < kT / kFacThreads; ++k) QB[(b ^ 1) * kT + tid + k * kFacThreads] = qn[k];
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) g[q][c] = gn[q][c];
+          g0 = gn0;
+          g1 = gn1;
         }
         __syncthreads();
         tj = tn;
