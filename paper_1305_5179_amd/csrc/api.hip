@@ -802,7 +802,7 @@ int rbf_arnoldi(rbf_ctx* c, const double* v0, int m, int op_prec, int basis, dou
 
 int rbf_default_schwarz_opts(rbf_schwarz_opts* o) {
   if (!o) return fail(nullptr, RBF_EINVAL, "opts is NULL");
-  o->max_block = kSchwarzLdsBlock;
+  o->max_block = kSchwarzDefaultBlock;
   o->overlap_pct = 10;
   o->restricted = 0;
   o->min_block = 0;

@@ -86,7 +86,7 @@ __host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt
 // members mem[mem_off[i] .. mem_off[i+1]) (sorted positions), its ncore[i]
 // core centres first; its local inverse is W[woff[i] ..], float32, n x n.
 constexpr int kSchwarzMaxBlock = 1024;   // largest subdomain (core + overlap centres)
-constexpr int kSchwarzLdsBlock = 192;    // a float64 packed triangle of this order fills the LDS of a CU
+constexpr int kSchwarzDefaultBlock = 192;
 struct SchwarzData {
   int64_t nsub = 0, nmem = 0, w_total = 0;
   int restricted = 0, max_block = 0, pct = 0, retries = 0;

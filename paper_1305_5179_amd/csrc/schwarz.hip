@@ -11,25 +11,29 @@
 // of each of its points.  The points are sorted (stably) by the Hilbert
 // index of their finest cell; the cells of every level are then contiguous
 // ranges sharing a key prefix, and the host splits the ranges by key digits.
-// The overlap of a core is the k = ceil(pct |core| / 100) centres outside it
-// nearest to it (float64 squared distance to the nearest core centre, ties
-// by index), searched on the device one workgroup per subdomain.
+// Optionally, consecutive leaves of the octree's depth-first order are
+// joined up to a minimum block size.  The overlap of a core is the
+// k = ceil(pct |core| / 100) centres outside it nearest to it (float64
+// squared distance to the nearest core centre, ties by index), searched on
+// the device one workgroup per subdomain.
 //
 // Local inverses.  The untruncated Gaussian of a subdomain plus shift I is
-// assembled and inverted in float64 inside the LDS of one compute unit
-// (packed lower triangle, n <= 192: 148 KB) by symmetric Gauss-Jordan
-// sweeps: sweeping every pivot of a symmetric positive definite matrix
-// leaves -A^{-1}, and every pivot is a Schur complement, so a pivot <= 0
-// means the shift is too small and the subdomain is redone with ten times
-// the shift.  One persistent launch takes the subdomains from a queue,
-// largest first.  The inverses are kept in float32, full n x n.
+// assembled and inverted in float64 by symmetric Gauss-Jordan sweeps:
+// sweeping every pivot of a symmetric positive definite matrix leaves
+// -A^{-1}, and every pivot is a Schur complement, so a pivot <= 0 means the
+// shift is too small and the subdomain is redone with ten times the shift.
+// The sweep runs 64 pivots at a time on the block's lower triangle in a
+// global work space of its workgroup, its products on the FP64 matrix
+// cores.  One persistent launch takes the subdomains from a queue, largest
+// first.  The inverses are kept in float32, full n x n.
 //
-// Apply.  One workgroup per subdomain gathers the vector on its members into
-// LDS and forms W r, a lane per row (W is symmetric, so lane p reads column
-// p of each row b: consecutive lanes, consecutive addresses).  The
-// restricted form scatters the core rows (the cores partition the centres);
-// the additive form stores every row, and a second kernel sums, for every
-// centre, the rows of the subdomains that hold it, in subdomain order.
+// Apply.  One persistent launch takes strips of rows of the blocks; a task
+// gathers the vector on its block's members into LDS and forms its rows of
+// W r, a lane per row (W is symmetric, so lane p reads column p of each row
+// b: consecutive lanes, consecutive addresses).  The restricted form
+// scatters the core rows (the cores partition the centres); the additive
+// form stores every row, and a second kernel sums, for every centre, the
+// rows of the subdomains that hold it, in subdomain order.
 #include <algorithm>
 #include <functional>
 #include <vector>
@@ -44,11 +48,9 @@ constexpr int kOvThreads = 256;
 constexpr int kCandCap = 2048;                 // candidate buffer of the overlap search
 static_assert(kCandCap >= kSchwarzMaxBlock + kOvThreads, "the best k and one round of candidates fit");
 constexpr int kFacThreads = 512;
-constexpr int kPacked = kSchwarzLdsBlock * (kSchwarzLdsBlock + 1) / 2;
-constexpr int kPanel = 64;   // pivots per panel of the global-memory sweep
-constexpr int kSmallWords = kPacked + 4 * kSchwarzLdsBlock;
-constexpr int kBigWords = 3 * kSchwarzMaxBlock + 4 * kPanel * kPanel + kPanel;
-constexpr int kFacWords = kSmallWords > kBigWords ? kSmallWords : kBigWords;
+constexpr int kPanel = 64;   // pivots per panel of the sweep
+// LDS of the factor kernel: coordinates, pivot block, P of a tile, two Q buffers, a column
+constexpr int kFacWords = 3 * kSchwarzMaxBlock + 4 * kPanel * kPanel + 3 * kPanel;
 static_assert(kFacWords * 8 + 64 <= 160 * 1024, "the factor kernel's LDS fits a compute unit");
 static_assert(kFacThreads == 512 && kPanel == 64,
               "the eight waves of a workgroup own two 16 x 16 blocks each of a 64 x 64 tile");
@@ -269,24 +271,32 @@ struct FacArgs {
   int32_t* retries;
   int* failed;
   int* queue;
-  double* big;              // blocks above the LDS order: float64 work space per workgroup
+  double* big;              // float64 work space per workgroup
   int64_t big_ld;           // its leading dimension (the largest block)
   int64_t big_stride;       // doubles per workgroup: big_ld^2 + 2 kPanel big_ld
 };
 
-__device__ __forceinline__ int packed(int i, int j) { return i * (i + 1) / 2 + j; }
-
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// The packed lower triangle is walked row by row: wave w takes the rows
-// i = w, w + 8, ..., its lanes the columns j = lane, lane + 64, ... <= i, so
-// that a wave touches consecutive LDS words and no thread keeps a table.
-template <class F>
-__device__ __forceinline__ void for_each_packed(int n, F&& f) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < n; i += kFacThreads / 64) {
-    const int base = packed(i, 0);
-    for (int j = lane; j <= i; j += 64) f(i, j, base + j);
+// A row's replay of its panel's pivot steps (see sweep_global): lane j of
+// the row's 16 lanes holds entries j, j + 16, j + 32, j + 48 in sv, and
+// collects E of the steps it owns (k % 16 == j) in ev.
+__device__ __forceinline__ void replay_steps(double (&sv)[4], double (&ev)[4], int lane, const double* H,
+                                             const double* dd) {
+  const int j = lane & 15;
+  for (int k = 0; k < kPanel; ++k) {
+    const int ku = k >> 4;
+    const double own_v = ku == 0 ? sv[0] : ku == 1 ? sv[1] : ku == 2 ? sv[2] : sv[3];
+    const double c = __shfl(own_v, (lane & ~15) | (k & 15));
+    const double t = c * dd[k];
+    const bool own = j == (k & 15);
+    const double e = c * dd[kPanel + k];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double upd = fma(-t, H[k * kPanel + j + 16 * u], sv[u]);
+      sv[u] = own && u == ku ? t : upd;
+      ev[u] = own && u == ku ? e : ev[u];
+    }
   }
 }
 
@@ -297,56 +307,34 @@ __device__ __forceinline__ double gauss_entry(const double* px, const double* py
   return exp(-((dx * dx + dy * dy) + dz * dz) / two_s2);
 }
 
-// Blocks up to kSchwarzLdsBlock: the packed triangle in LDS, one pivot at a
-// time.  Returns false when a pivot is not positive (the same decision in
-// every thread).  A holds the swept matrix, -A^{-1}, on success.
-__device__ bool sweep_lds(double* A, double* col, const double* px, const double* py, const double* pz, int n,
-                          double shift, double two_s2) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  for_each_packed(n, [&](int i, int j, int u) { A[u] = gauss_entry(px, py, pz, i, j, shift, two_s2); });
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double d = A[packed(k, k)];
-    if (!(d > 0.0) || !isfinite(d)) return false;
-    for (int i = tid; i < n; i += kFacThreads) col[i] = i >= k ? A[packed(i, k)] : A[packed(k, i)];
-    __syncthreads();
-    const double inv = 1.0 / d;
-    for_each_packed(n, [&](int i, int j, int u) {
-      if (i != k && j != k)
-        A[u] = fma(-(col[i] * inv), col[j], A[u]);
-      else if (i == k && j == k)
-        A[u] = -inv;
-      else
-        A[u] = (i == k ? col[j] : col[i]) * inv;
-    });
-    __syncthreads();
-  }
-  return true;
-}
-
-// Larger blocks: the matrix G in global memory, of which only the lower
+// Every block: the matrix G in global memory, of which only the lower
 // triangle (i >= j) is kept (the swept matrix stays symmetric), swept kPanel
-// pivots at a time (the block form of the same sweep).  With the pivot block
-// D of the panel and Q its columns, one panel sweeps D in LDS to -D^{-1},
-// forms P = Q D^{-1}, then updates the lower entries outside the panel,
-// G_ij -= P_i . Q_j, and writes P into the panel's row (left of the
-// diagonal) and column (below it).  P and Q are written to global memory
-// first (the update overwrites what they were read from).  The update runs
-// over 64 x 64 tiles on or below the diagonal, 4 x 2 entries per thread from
-// LDS; the next tile's entries and Q rows are loaded into registers while
-// the current tile computes (two LDS buffers for Q).
+// pivots at a time with the arithmetic of the one-pivot sweep reordered:
+//   * the panel's pivot block D is swept in LDS pivot by pivot, recording
+//     at each step k its pivot d_k and its row H[k] as they were then;
+//   * every row outside the panel replays those steps on its own panel
+//     entries in registers (what the one-pivot sweep does to them), giving the row's
+//     final panel entries P and, from the entry c of column k at step k,
+//     E_k = c / sqrt(d_k);
+//   * the entries outside the panel, which the one-pivot sweep updates by
+//     -c_i c_j / d_k at each step, take the whole panel at once:
+//     G_ij -= E_i . E_j, over 64 x 64 tiles on or below the diagonal, on the
+//     FP64 matrix cores, the next tile's entries and E rows loaded while the
+//     current one computes;
+//   * P goes into the panel's row and column, the swept D into its diagonal
+//     block.
+// (Forming P = Q D^{-1} with the explicit inverse of the pivot block instead
+// loses accuracy when D is ill conditioned: small shifts.)
 __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, double* lds, const double* px,
                              const double* py, const double* pz, int n, double shift, double two_s2) {
   constexpr int kT = kPanel * kPanel;
-  constexpr int kSP = kPanel + 1;         // pitch of the strip buffer (rows read along G's rows)
   const int tid = threadIdx.x;
   double* D = lds;                        // kPanel x kPanel, row-major (symmetric)
-  double* PT = D + kT;                    // PT[l][r]: P of a tile's rows, by panel column
-  double* QB = PT + kT;                   // two buffers QB[b][l][r]: Q of a tile's columns
+  double* PT = D + kT;                    // PT[l][r]: E of a tile's rows, by panel column
+  double* QB = PT + kT;                   // two buffers QB[b][l][r]: E of a tile's columns
   double* colv = QB + 2 * kT;             // kPanel
-  double* S = QB;                         // strip buffer S[l][r] (pitch kSP) over both Q buffers
-  static_assert(kSP * kPanel <= 2 * kT, "the strip buffer fits the two Q buffers");
+  double* dd = colv + kPanel;             // 1 / d_k, then 1 / sqrt(d_k), of the panel's pivots
+  double* H = PT;                         // H[k][m]: row k of the pivot block when pivot k is swept
   __syncthreads();
   for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
     const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
@@ -360,14 +348,24 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
     for (int e = tid; e < kT; e += kFacThreads) {
       const int r = e / kPanel, c = e % kPanel;
       D[e] = r < kb && c < kb ? G[(int64_t)(K + max(r, c)) * n + K + min(r, c)] : 0.0;
+      H[e] = 0.0;   // (steps beyond kb stay zero: no-ops in the replay)
     }
+    if (tid < 2 * kPanel) dd[tid] = 0.0;
     __syncthreads();
     for (int k = 0; k < kb; ++k) {
       const double d = D[k * kPanel + k];
       if (!(d > 0.0) || !isfinite(d)) return false;
-      if (tid < kb) colv[tid] = D[tid * kPanel + k];
-      __syncthreads();
+      if (tid < kPanel) {
+        const double v = tid < kb ? D[tid * kPanel + k] : 0.0;
+        colv[tid] = v;
+        H[k * kPanel + tid] = v;
+      }
       const double inv = 1.0 / d;
+      if (tid == 0) {
+        dd[k] = inv;
+        dd[kPanel + k] = 1.0 / sqrt(d);
+      }
+      __syncthreads();
       for (int e = tid; e < kT; e += kFacThreads) {
         const int r = e / kPanel, c = e % kPanel;
         if (r >= kb || c >= kb) continue;
@@ -380,46 +378,41 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       }
       __syncthreads();
     }
-    // Q of every row outside the panel (left of it: along the panel's rows;
-    // below it: along the row itself) and P = Q D^{-1} = -Q D, strip by strip
-    for (int s0 = 0; s0 < n; s0 += kPanel) {
-      if (s0 == K) continue;
-      const int rows = min(kPanel, n - s0);
-      for (int e = tid; e < kT; e += kFacThreads) {
-        if (s0 < K) {
-          const int l = e / kPanel, r = e % kPanel;
-          S[l * kSP + r] = l < kb && r < rows ? G[(int64_t)(K + l) * n + s0 + r] : 0.0;
-        } else {
-          const int r = e / kPanel, l = e % kPanel;
-          S[l * kSP + r] = l < kb && r < rows ? G[(int64_t)(s0 + r) * n + K + l] : 0.0;
-        }
-      }
-      __syncthreads();
-      {
-        // -P = S^T D on the matrix cores: wave w, rows 16 bi.. of the strip,
-        // panel columns 16 bj.. and 16 (bj + 1).. (the entries beyond kb are
-        // zero in both operands)
-        const int bi = wave >> 1, bj = 2 * (wave & 1);
-        v4d c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
-#pragma unroll 4
-        for (int kk = 0; kk < kPanel / 4; ++kk) {
-          const int q = 4 * kk + (lane >> 4);
-          const double a = S[q * kSP + 16 * bi + (lane & 15)];
-          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, D[q * kPanel + 16 * bj + (lane & 15)], c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, D[q * kPanel + 16 * (bj + 1) + (lane & 15)], c1, 0, 0, 0);
-        }
+    // every row outside the panel, one per 16-lane row of a wave (each lane
+    // holding 4 of its panel entries, m = lane % 16 + 16 t; left of the
+    // panel they are read along the panel's rows, below it along the row
+    // itself), replays the panel's pivot steps exactly as the one-pivot
+    // sweep would apply them to it: at step k the entry c of column k is
+    // the pivot column's, every other panel entry m takes
+    // -(c / d_k) H[k][m], and the entry k becomes c / d_k.  E = c / sqrt(d_k)
+    // of every step is the row's factor of the trailing update; the final
+    // entries are P.  Every step runs (the steps beyond kb have zero H rows
+    // and pivot factors and change nothing).
+    {
+      const int j = lane & 15;
+      for (int base = 0; base < n; base += kFacThreads / 16) {
+        const int i = base + (tid >> 4);
+        if (i < n && (i < K || i >= K + kb)) {   // (the same for the 16 lanes of the row)
+          double sv[4], ev[4] = {0.0, 0.0, 0.0, 0.0};
+          const double* src = i < K ? G + (int64_t)K * n + i : G + (int64_t)i * n + K;
+          const int64_t step = i < K ? n : 1;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * bi + (lane >> 4) + 4 * v, l0 = 16 * bj + (lane & 15), l1 = l0 + 16;
-          if (r < rows && l0 < kb) Pg[(int64_t)l0 * ld + s0 + r] = -c0[v];
-          if (r < rows && l1 < kb) Pg[(int64_t)l1 * ld + s0 + r] = -c1[v];
+          for (int t = 0; t < 4; ++t) {
+            const int M = j + 16 * t;
+            sv[t] = M < kb ? src[M * step] : 0.0;
+          }
+          replay_steps(sv, ev, lane, H, dd);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int M = j + 16 * t;
+            if (M < kb) {
+              Pg[(int64_t)M * ld + i] = sv[t];
+              Qg[(int64_t)M * ld + i] = ev[t];
+            }
+          }
         }
+        __syncthreads();
       }
-      for (int e = tid; e < kT; e += kFacThreads) {
-        const int l = e / kPanel, r = e % kPanel;
-        if (l < kb && r < rows) Qg[(int64_t)l * ld + s0 + r] = S[l * kSP + r];
-      }
-      __syncthreads();
     }
     // the update of the lower tiles outside the panel's row and column
     for (int ti = 0; ti < nt; ++ti) {
@@ -429,12 +422,12 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       __syncthreads();
       for (int e = tid; e < kT; e += kFacThreads) {
         const int l = e / kPanel, r = e % kPanel;
-        PT[e] = l < kb && r < ri ? Pg[(int64_t)l * ld + i0 + r] : 0.0;
+        PT[e] = l < kb && r < ri ? Qg[(int64_t)l * ld + i0 + r] : 0.0;
       }
       // tile tj on the matrix cores: wave w owns the 16 x 16 blocks (bi,
       // bj) and (bi, bj + 1) of the tile, its accumulators in the result
       // layout of v_mfma_f64_16x16x4f64 (lane l, value v: row l / 16 + 4 v,
-      // column l % 16 of the block); the next tile's entries and Q rows (8
+      // column l % 16 of the block); the next tile's entries and E rows (8
       // per thread) are loaded while the current one computes
       const int bi = wave >> 1, bj = 2 * (wave & 1);
       v4d g0, g1, gn0, gn1;
@@ -463,7 +456,7 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
       for (int b = 0; tj < nj; b ^= 1) {
         const int tn = next_tile(tj);
         if (tn < nj) load_tile(tn, gn0, gn1, qn);
-        // G_ij -= sum_l P_il Q_jl: A = -P (rows of the tile), B = Q^T
+        // G_ij -= sum_l E_il E_jl: A = -E (rows of the tile), B = E^T
         const double* Q = QB + b * kT;
 #pragma unroll 4
         for (int kk = 0; kk < kPanel / 4; ++kk) {
@@ -515,7 +508,7 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
   __shared__ double lds[kFacWords];
   __shared__ int s_task;
   const int tid = threadIdx.x;
-  double* const big = a.big ? a.big + (int64_t)blockIdx.x * a.big_stride : nullptr;
+  double* const big = a.big + (int64_t)blockIdx.x * a.big_stride;
   for (;;) {
     __syncthreads();
     if (tid == 0) s_task = atomicAdd(a.queue, 1);
@@ -525,12 +518,10 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
     const int64_t sub = a.order[task];
     const int64_t off = a.mem_off[sub];
     const int n = (int)(a.mem_off[sub + 1] - off);
-    const bool in_lds = n <= kSchwarzLdsBlock;
-    // coordinates: after the packed triangle and its column (LDS form), at
-    // the front (global form, before the panel buffers)
-    double* px = in_lds ? lds + kPacked + kSchwarzLdsBlock : lds;
-    double* py = px + (in_lds ? kSchwarzLdsBlock : kSchwarzMaxBlock);
-    double* pz = py + (in_lds ? kSchwarzLdsBlock : kSchwarzMaxBlock);
+    // coordinates at the front of the LDS, before the panel buffers
+    double* px = lds;
+    double* py = px + kSchwarzMaxBlock;
+    double* pz = py + kSchwarzMaxBlock;
     __syncthreads();
     for (int p = tid; p < n; p += kFacThreads) {
       const double4 x = a.xs[a.mem[off + p]];
@@ -542,10 +533,8 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
     int tries = 0;
     bool ok = false;
     for (;;) {
-      const bool swept = in_lds ? sweep_lds(lds, lds + kPacked, px, py, pz, n, shift, a.two_s2)
-                                : sweep_global(big, big + a.big_ld * a.big_ld, big + a.big_ld * (a.big_ld + kPanel),
-                                               a.big_ld, pz + kSchwarzMaxBlock, px, py, pz, n, shift, a.two_s2);
-      if (swept) {
+      if (sweep_global(big, big + a.big_ld * a.big_ld, big + a.big_ld * (a.big_ld + kPanel), a.big_ld,
+                       pz + kSchwarzMaxBlock, px, py, pz, n, shift, a.two_s2)) {
         ok = true;
         break;
       }
@@ -553,24 +542,15 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
       shift = shift > 0.0 ? 10.0 * shift : 1e-10;
     }
     __syncthreads();
-    // W = -(swept matrix), full n x n
+    // W = -(swept matrix), full n x n; the lower triangle holds the result:
+    // read along its rows, each entry stored at (i, j) and (j, i)
     float* W = a.W + a.woff[sub];
-    if (in_lds) {
-      for_each_packed(n, [&](int i, int j, int u) {
-        const float v = ok ? (float)(-lds[u]) : 0.0f;
-        W[(int64_t)i * n + j] = v;
-        if (i != j) W[(int64_t)j * n + i] = v;
-      });
-    } else {
-      // (the lower triangle holds the result: read along its rows, each
-      // entry stored at (i, j) and (j, i))
-      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
-        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-        if (j > i) continue;
-        const float v = ok ? (float)(-big[e]) : 0.0f;
-        W[e] = v;
-        W[(int64_t)j * n + i] = v;
-      }
+    for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
+      const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+      if (j > i) continue;
+      const float v = ok ? (float)(-big[e]) : 0.0f;
+      W[e] = v;
+      W[(int64_t)j * n + i] = v;
     }
     if (tid == 0) {
       a.shift_used[sub] = shift;
@@ -1036,16 +1016,12 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     RBF_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device));
     cus = std::max(cus, 1);
     const unsigned grid = (unsigned)std::min<int64_t>(nsub, cus);
-    // blocks above the LDS order are swept in global memory: one work space
-    // (the block, and the P and Q of a panel) per workgroup
+    // the blocks are swept in global memory: one work space (the block, and
+    // the P and Q of a panel) per workgroup
     int64_t maxn = 0;
     for (int64_t i = 0; i < nsub; ++i) maxn = std::max(maxn, d->h_mem_off[i + 1] - d->h_mem_off[i]);
-    double* big = nullptr;
-    int64_t big_stride = 0;
-    if (maxn > kSchwarzLdsBlock) {
-      big_stride = maxn * maxn + 2 * kPanel * maxn;
-      big = talloc<double>(big_stride * grid);
-    }
+    const int64_t big_stride = maxn * maxn + 2 * kPanel * maxn;
+    double* big = talloc<double>(big_stride * grid);
     FacArgs fa{c.xs, d->mem_off, d->mem, d_order, nsub, d->woff, 2.0 * c.sigma * c.sigma, shift, 8,
                d->W, d_shift, d_retries, d_flags + 1, d_flags, big, maxn, big_stride};
     hipEvent_t e0, e1;
@@ -1065,7 +1041,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     RBF_HIP(hipEventDestroy(e1));
     d->factor_ms = fms;
     for (void* p : {(void*)d_order, (void*)d_shift, (void*)d_retries, (void*)d_flags}) temp_free(p);
-    if (big) temp_free(big);
+    temp_free(big);
     d->max_shift = 0.0;
     d->retries = 0;
     for (int64_t i = 0; i < nsub; ++i) {
