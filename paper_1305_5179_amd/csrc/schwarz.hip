@@ -278,24 +278,35 @@ struct FacArgs {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// A row's replay of its panel's pivot steps (see sweep_global): lane j of
-// the row's 16 lanes holds entries j, j + 16, j + 32, j + 48 in sv, and
-// collects E of the steps it owns (k % 16 == j) in ev.
-__device__ __forceinline__ void replay_steps(double (&sv)[4], double (&ev)[4], int lane, const double* H,
+// The replay of a panel's pivot steps (see sweep_global) on R rows at
+// once: lane j of a row's 16 lanes holds its entries j, j + 16, j + 32,
+// j + 48 in sv[r], and collects E of the steps it owns (k % 16 == j) in
+// ev[r]; the rows' chains of dependent steps interleave, and share the
+// step table's loads.
+template <int R>
+__device__ __forceinline__ void replay_steps(double (&sv)[R][4], double (&ev)[R][4], int lane, const double* H,
                                              const double* dd) {
   const int j = lane & 15;
   for (int k = 0; k < kPanel; ++k) {
     const int ku = k >> 4;
-    const double own_v = ku == 0 ? sv[0] : ku == 1 ? sv[1] : ku == 2 ? sv[2] : sv[3];
-    const double c = __shfl(own_v, (lane & ~15) | (k & 15));
-    const double t = c * dd[k];
+    const int src = (lane & ~15) | (k & 15);
     const bool own = j == (k & 15);
-    const double e = c * dd[kPanel + k];
+    const double dk = dd[k], rk = dd[kPanel + k];
+    double h[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double upd = fma(-t, H[k * kPanel + j + 16 * u], sv[u]);
-      sv[u] = own && u == ku ? t : upd;
-      ev[u] = own && u == ku ? e : ev[u];
+    for (int u = 0; u < 4; ++u) h[u] = H[k * kPanel + j + 16 * u];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double own_v = ku == 0 ? sv[r][0] : ku == 1 ? sv[r][1] : ku == 2 ? sv[r][2] : sv[r][3];
+      const double c = __shfl(own_v, src);
+      const double t = c * dk;
+      const double e = c * rk;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double upd = fma(-t, h[u], sv[r][u]);
+        sv[r][u] = own && u == ku ? t : upd;
+        ev[r][u] = own && u == ku ? e : ev[r][u];
+      }
     }
   }
 }
@@ -305,6 +316,53 @@ __device__ __forceinline__ double gauss_entry(const double* px, const double* py
   if (i == j) return 1.0 + shift;
   const double dx = px[i] - px[j], dy = py[i] - py[j], dz = pz[i] - pz[j];
   return exp(-((dx * dx + dy * dy) + dz * dz) / two_s2);
+}
+
+// Every row outside the panel [K, K + kb): its panel entries (left of the
+// panel read along the panel's rows, below it along the row itself) replay
+// the panel's pivot steps; the final entries go to Pg, the factors E of the
+// trailing update to Qg (both by panel column, leading dimension ld).
+template <int R>
+__device__ __forceinline__ void replay_rows(const double* G, double* Pg, double* Qg, int64_t ld, const double* H,
+                                            const double* dd, int n, int K, int kb) {
+  const int tid = threadIdx.x, lane = tid & 63, j = lane & 15;
+  for (int i0 = (tid >> 4) * R; i0 < n; i0 += (kFacThreads / 16) * R) {
+    // (rows in the panel or past the end ride along with zeros and are not
+    // stored; a group with none to do skips the steps; the same for the 16
+    // lanes of a row)
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) any |= i0 + r < n && (i0 + r < K || i0 + r >= K + kb);
+    if (!any) continue;
+    double sv[R][4], ev[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + r;
+      const bool row_ok = i < n && (i < K || i >= K + kb);
+      const double* src = i < K ? G + (int64_t)K * n + i : G + (int64_t)i * n + K;
+      const int64_t step = i < K ? n : 1;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int M = j + 16 * t;
+        sv[r][t] = row_ok && M < kb ? src[M * step] : 0.0;
+        ev[r][t] = 0.0;
+      }
+    }
+    replay_steps<R>(sv, ev, lane, H, dd);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = i0 + r;
+      if (!(i < n && (i < K || i >= K + kb))) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int M = j + 16 * t;
+        if (M < kb) {
+          Pg[(int64_t)M * ld + i] = sv[r][t];
+          Qg[(int64_t)M * ld + i] = ev[r][t];
+        }
+      }
+    }
+  }
 }
 
 // Every block: the matrix G in global memory, of which only the lower
@@ -388,32 +446,13 @@ __device__ bool sweep_global(double* G, double* Pg, double* Qg, int64_t ld, doub
     // of every step is the row's factor of the trailing update; the final
     // entries are P.  Every step runs (the steps beyond kb have zero H rows
     // and pivot factors and change nothing).
-    {
-      const int j = lane & 15;
-      for (int base = 0; base < n; base += kFacThreads / 16) {
-        const int i = base + (tid >> 4);
-        if (i < n && (i < K || i >= K + kb)) {   // (the same for the 16 lanes of the row)
-          double sv[4], ev[4] = {0.0, 0.0, 0.0, 0.0};
-          const double* src = i < K ? G + (int64_t)K * n + i : G + (int64_t)i * n + K;
-          const int64_t step = i < K ? n : 1;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int M = j + 16 * t;
-            sv[t] = M < kb ? src[M * step] : 0.0;
-          }
-          replay_steps(sv, ev, lane, H, dd);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int M = j + 16 * t;
-            if (M < kb) {
-              Pg[(int64_t)M * ld + i] = sv[t];
-              Qg[(int64_t)M * ld + i] = ev[t];
-            }
-          }
-        }
-        __syncthreads();
-      }
-    }
+    // (four rows per 16 lanes for large blocks, whose rows are many; one for
+    // small blocks, where more rows per lane would be mostly padding)
+    if (n > 4 * (kFacThreads / 16))
+      replay_rows<4>(G, Pg, Qg, ld, H, dd, n, K, kb);
+    else
+      replay_rows<1>(G, Pg, Qg, ld, H, dd, n, K, kb);
+    __syncthreads();
     // the update of the lower tiles outside the panel's row and column
     for (int ti = 0; ti < nt; ++ti) {
       if (ti == p) continue;
