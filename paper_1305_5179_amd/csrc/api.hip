@@ -468,10 +468,11 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
               const float* vj = reinterpret_cast<const float*>(c->V) + (int64_t)j * ldv;
               float* w = reinterpret_cast<float*>(c->w);
               if (pre) {
-                // right preconditioning: the basis is built on A M
-                to_f64(vj, c->vin, m, st);
-                schwarz_apply(*c, *pre, c->vin, pre->z, st, skip);
-                pairsum_f32(*c, c->centres, pre->z, true, w, st, skip);
+                // right preconditioning: the basis is built on A M (M applied
+                // to the float32 basis vector, its result rounded to float32
+                // for the float32 operator)
+                schwarz_apply_f32(*c, *pre, vj, pre->z32, st, skip);
+                pairsum_f32(*c, c->centres, nullptr, true, w, st, skip, pre->z32);
               } else {
                 pairsum_f32(*c, c->centres, nullptr, true, w, st, skip, vj);
               }

@@ -107,6 +107,7 @@ struct SchwarzData {
   int64_t* occ_slot = nullptr;
   double* z = nullptr;          // work vectors of the preconditioned solve (length mpad)
   double* t = nullptr;
+  float* z32 = nullptr;         // the preconditioned vector for the float32 operator (length mpad)
   std::vector<int64_t> h_mem_off;
   std::vector<int32_t> h_ncore;
   std::vector<uint32_t> h_mem_paper;   // members as paper indices
@@ -367,6 +368,8 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
                            int tune, hipStream_t s);
 void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s,
                    const int* skip = nullptr);
+void schwarz_apply_f32(const Ctx& c, const SchwarzData& d, const float* r, float* z, hipStream_t s,
+                       const int* skip = nullptr);
 void free_schwarz(SchwarzData* d);
 
 // mlp.hip

@@ -610,8 +610,9 @@ struct ApplyArgs {
   const uint32_t* mem;
   const int64_t* woff;
   const float* W;
-  const double* r;
-  double* out;              // restricted: z (sorted order); additive: the local solutions by member slot
+  const void* r;            // float64, or float32 with F32
+  void* out;                // restricted: z (sorted order; float32 with F32); additive: the local solutions
+                            // by member slot (float64)
   const int* skip;
 };
 
@@ -621,7 +622,7 @@ struct ApplyArgs {
 // consecutive lanes, consecutive addresses).  The restricted form scatters
 // the core rows (the cores partition the centres); the additive form stores
 // every row by member slot.
-template <bool RESTRICTED, int T>
+template <bool RESTRICTED, int T, bool F32>
 __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ double rl[kSchwarzMaxBlock];
@@ -632,7 +633,9 @@ __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
     const int64_t off = a.mem_off[sub];
     const int n = (int)(a.mem_off[sub + 1] - off);
     __syncthreads();   // the previous task is done with rl
-    for (int p = tid; p < n; p += T) rl[p] = a.r[a.mem[off + p]];
+    for (int p = tid; p < n; p += T)
+      rl[p] = F32 ? (double)static_cast<const float*>(a.r)[a.mem[off + p]]
+                  : static_cast<const double*>(a.r)[a.mem[off + p]];
     __syncthreads();
     const int rows = RESTRICTED ? a.ncore[sub] : n;
     const int row = task.y + tid;
@@ -648,10 +651,12 @@ __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
     }
     for (; b < n; ++b) a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
     const double y = (a0 + a1) + (a2 + a3);
-    if (RESTRICTED)
-      a.out[a.mem[off + row]] = y;
+    if (RESTRICTED && F32)
+      static_cast<float*>(a.out)[a.mem[off + row]] = (float)y;
+    else if (RESTRICTED)
+      static_cast<double*>(a.out)[a.mem[off + row]] = y;
     else
-      a.out[off + row] = y;
+      static_cast<double*>(a.out)[off + row] = y;
   }
 }
 
@@ -685,14 +690,15 @@ __global__ void k_occ_sort(const int64_t* __restrict__ occ_off, int64_t m, int64
   }
 }
 
+template <class TO>
 __global__ void k_schwarz_sum(const int64_t* __restrict__ occ_off, const int64_t* __restrict__ occ_slot,
-                              const double* __restrict__ Y, int64_t m, double* __restrict__ z, const int* skip) {
+                              const double* __restrict__ Y, int64_t m, TO* __restrict__ z, const int* skip) {
   if (skip && *skip) return;
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= m) return;
   double s = 0.0;
   for (int64_t e = occ_off[j]; e < occ_off[j + 1]; ++e) s += Y[occ_slot[e]];
-  z[j] = s;
+  z[j] = (TO)s;
 }
 
 template <class T>
@@ -721,7 +727,7 @@ int schwarz_core_cap(int max_block, int pct) {
 void free_schwarz(SchwarzData* d) {
   if (!d) return;
   for (void* p : {(void*)d->mem_off, (void*)d->ncore, (void*)d->mem, (void*)d->woff, (void*)d->W, (void*)d->Y,
-                  (void*)d->occ_off, (void*)d->occ_slot, (void*)d->z, (void*)d->t})
+                  (void*)d->occ_off, (void*)d->occ_slot, (void*)d->z, (void*)d->t, (void*)d->z32})
     dfree(p);
   dfree(d->tasks);
   delete d;
@@ -744,22 +750,31 @@ std::vector<int2> apply_tasks(const SchwarzData& d, int T) {
   return out;
 }
 
-void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, int64_t ntask, const double* r,
-                  double* out, hipStream_t s, const int* skip) {
-  const ApplyArgs aa{tasks, ntask, d.mem_off, d.ncore, d.mem, d.woff, d.W, r, out, skip};
-  const dim3 g((unsigned)std::max(blocks, 1));
+template <bool F32>
+void launch_local_t(const SchwarzData& d, int T, const dim3& g, const ApplyArgs& aa, hipStream_t s) {
   if (d.restricted) {
     if (T == 512)
-      hipLaunchKernelGGL((k_schwarz_local<true, 512>), g, dim3(512), 0, s, aa);
+      hipLaunchKernelGGL((k_schwarz_local<true, 512, F32>), g, dim3(512), 0, s, aa);
     else
-      hipLaunchKernelGGL((k_schwarz_local<true, 256>), g, dim3(256), 0, s, aa);
+      hipLaunchKernelGGL((k_schwarz_local<true, 256, F32>), g, dim3(256), 0, s, aa);
   } else {
     if (T == 512)
-      hipLaunchKernelGGL((k_schwarz_local<false, 512>), g, dim3(512), 0, s, aa);
+      hipLaunchKernelGGL((k_schwarz_local<false, 512, F32>), g, dim3(512), 0, s, aa);
     else
-      hipLaunchKernelGGL((k_schwarz_local<false, 256>), g, dim3(256), 0, s, aa);
+      hipLaunchKernelGGL((k_schwarz_local<false, 256, F32>), g, dim3(256), 0, s, aa);
   }
   RBF_HIP(hipGetLastError());
+}
+
+// f32: r is float32, and the restricted form writes out in float32.
+void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, int64_t ntask, const void* r,
+                  void* out, hipStream_t s, const int* skip, bool f32 = false) {
+  const ApplyArgs aa{tasks, ntask, d.mem_off, d.ncore, d.mem, d.woff, d.W, r, out, skip};
+  const dim3 g((unsigned)std::max(blocks, 1));
+  if (f32)
+    launch_local_t<true>(d, T, g, aa, s);
+  else
+    launch_local_t<false>(d, T, g, aa, s);
 }
 
 // The apply's launch shape: strips of 256 or 512 rows, taken by 2, 4 or 8
@@ -1041,8 +1056,10 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   }
   d->z = dalloc<double>(c.mpad);
   d->t = dalloc<double>(c.mpad);
+  d->z32 = dalloc<float>(c.mpad);
   fill_f64(d->z, 0.0, c.mpad, s);
   fill_f64(d->t, 0.0, c.mpad, s);
+  fill_u32(reinterpret_cast<uint32_t*>(d->z32), 0u, c.mpad, s);
 
   // 6. local inverses
   if (nsub > 0) {
@@ -1109,10 +1126,25 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
 // z = M^{-1} r (sorted order; z must not alias r; entries >= m untouched).
 void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s, const int* skip) {
   if (d.nsub == 0) return;
-  launch_local(d, d.apply_threads, d.apply_blocks, d.tasks, d.ntask, r, d.restricted ? z : d.Y, s, skip);
+  launch_local(d, d.apply_threads, d.apply_blocks, d.tasks, d.ntask, r, d.restricted ? (void*)z : (void*)d.Y, s, skip);
   if (!d.restricted) {
-    hipLaunchKernelGGL(k_schwarz_sum, dim3((unsigned)ceil_div(c.m, 256)), dim3(256), 0, s, d.occ_off, d.occ_slot,
-                       d.Y, c.m, z, skip);
+    hipLaunchKernelGGL(k_schwarz_sum<double>, dim3((unsigned)ceil_div(c.m, 256)), dim3(256), 0, s, d.occ_off,
+                       d.occ_slot, d.Y, c.m, z, skip);
+    RBF_HIP(hipGetLastError());
+  }
+}
+
+// The same from a float32 vector to a float32 result: the float64 products
+// and sums of schwarz_apply, the input widened and the result rounded once
+// (what the float32 operator does to a float64 input).
+void schwarz_apply_f32(const Ctx& c, const SchwarzData& d, const float* r, float* z, hipStream_t s,
+                       const int* skip) {
+  if (d.nsub == 0) return;
+  launch_local(d, d.apply_threads, d.apply_blocks, d.tasks, d.ntask, r, d.restricted ? (void*)z : (void*)d.Y, s, skip,
+               true);
+  if (!d.restricted) {
+    hipLaunchKernelGGL(k_schwarz_sum<float>, dim3((unsigned)ceil_div(c.m, 256)), dim3(256), 0, s, d.occ_off,
+                       d.occ_slot, d.Y, c.m, z, skip);
     RBF_HIP(hipGetLastError());
   }
 }
