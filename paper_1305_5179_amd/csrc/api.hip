@@ -487,11 +487,22 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
             gm_step(c->V, ldv, c->w, f32, m, j, c->partial, c->state, st);
           }
         };
-        if (o.graph && steps == o.restart && !profiling()) {
-          const std::vector<intptr_t> key = {o.restart, f32, prec, (intptr_t)pre, (intptr_t)c->V, (intptr_t)c->w,
-                                             (intptr_t)c->vin, (intptr_t)c->partial, (intptr_t)c->state,
-                                             (intptr_t)ldv, (intptr_t)m};
-          if (!c->cycle_exec || c->cycle_key != key) {
+        // Full cycles replay a captured graph of these launches.  Capturing
+        // and instantiating takes the host about a millisecond, so a cycle
+        // without a graph is launched directly, and the graph is captured
+        // afterwards (while the device runs that cycle) only when another
+        // full cycle may follow.
+        const bool use_graph = o.graph && steps == o.restart && !profiling();
+        std::vector<intptr_t> key;
+        if (use_graph)
+          key = {o.restart, f32, prec, (intptr_t)pre, (intptr_t)c->V, (intptr_t)c->w, (intptr_t)c->vin,
+                 (intptr_t)c->partial, (intptr_t)c->state, (intptr_t)ldv, (intptr_t)m};
+        if (use_graph && c->cycle_exec && c->cycle_key == key) {
+          RBF_HIP(hipGraphLaunch(c->cycle_exec, s));
+        } else {
+          arnoldi_steps(s, steps);
+          const bool later_full = outer + 1 < o.max_outer && (int64_t)o.max_iters - iters - steps >= o.restart;
+          if (use_graph && later_full) {
             drop_cycle_graph(c);
             if (!c->capture_stream) RBF_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
             hipGraph_t g = nullptr;
@@ -511,9 +522,6 @@ int rbf_solve(rbf_ctx* c, const double* b, const double* x0, double* cout, const
             c->cycle_exec = ex;
             c->cycle_key = key;
           }
-          RBF_HIP(hipGraphLaunch(c->cycle_exec, s));
-        } else {
-          arnoldi_steps(s, steps);
         }
         if (pre) {
           // c += M (V y)
