@@ -30,9 +30,14 @@ Fields beside the step (all measured after the timed steps):
                 nodes with |f| > 1e-6 + 8 u32 sum_j |c_j phi_j| (and the
                 torus's signed distance);
   cpu_baseline  the C cell-list oracle (float64, OpenMP) on one thread and on
-                every host thread: a sampled share of the operator's rows and
-                band points of the grid, scaled to the step, with the solve's
-                time extrapolated from its operator applications.
+                every host thread: the operator's rows (all of them, and a
+                sample on one thread), band points of the grid, one GMRES(30)
+                cycle of the oracle, and the solve's time extrapolated from
+                that cycle.
+  roofline.measured_rates
+                the device's vector-ALU issue rates (FMA, v_exp_f32 and their
+                mixes) from register-resident loops: the evidence for the pair
+                peak's cost model.
 
 Prints one JSON line.  --gpus above 1 is refused: this path runs on one GPU.
 """
@@ -111,22 +116,41 @@ def parse():
     return ap.parse_args()
 
 
+def measured_rates(rbf):
+    """The device's vector-ALU issue rates (rbf_measure_rates): VOP2 FMA, its
+    DPP row-broadcast form, v_exp_f32 and their mixes, and the float32 pair
+    kernel's own chunk bodies on register operands.  The clock is the one the
+    VOP2 FMA rate implies at 32 lanes per SIMD per cycle; body_pairs_per_s is
+    the bodies' rate weighted by the operator's share of inner and masked
+    examined pairs (filled in by the caller)."""
+    r = rbf.measure_rates()
+    simds = r.compute_units * 4
+    return {
+        "fma_vop2_per_s": r.fma_per_s, "fma_dpp_per_s": r.dpp_fma_per_s, "exp_per_s": r.exp_per_s,
+        "exp_3fma_chains_per_s": r.exp_3fma_per_s, "exp_7fma_chains_per_s": r.exp_7fma_per_s,
+        "inner_body_pair_steps_per_s": r.inner_pair_steps_per_s,
+        "masked_body_pair_steps_per_s": r.masked_pair_steps_per_s,
+        "clock_ghz_if_32_lanes": r.fma_per_s / (simds * 32) / 1e9,
+    }
+
+
 def cpu_baseline(cloud, eps, sigma, cutoff, row_frac, eval_points, solve_apps):
     """The C cell-list oracle (float64, oracle/cellsum.c) on the host: one
     operator application over every row on all threads, the same on one
     thread over a seeded sample of the rows, and the interpolant at points of
     the support band (a cloud point plus a uniform offset in the cutoff ball,
-    seeded) on all threads and on one.  The solve is not run on the host (its
-    thousands of applications would take hours): its time is extrapolated as
-    the all-thread application time x the applications the plain float64
-    method needed to reach the common residual."""
+    seeded) on all threads and on one, and one GMRES(30) cycle of the oracle
+    (oracle GMRES, the C operator on all threads).  The solve to the common
+    residual is not run on the host (its thousands of applications would take
+    about half an hour): its time is extrapolated as the measured cycle time x
+    the cycles the plain float64 method needed to reach that residual."""
     import numpy as np
 
     from oracle import cells
     from oracle import rbf_oracle as o
     from paper_1305_5179_amd import workloads as w
 
-    X, _ = o.extended_centres(cloud.points, cloud.normals, eps)
+    X, b = o.extended_centres(cloud.points, cloud.normals, eps)
     t0 = time.perf_counter()
     L = cells.CellOracle(X, cutoff)
     build_s = time.perf_counter() - t0
@@ -155,16 +179,25 @@ def cpu_baseline(cloud, eps, sigma, cutoff, row_frac, eval_points, solve_apps):
         dt = time.perf_counter() - t0
         res[key] = {"threads": thr, "points": npts, "s": dt, "useful": L.useful, "examined": L.examined,
                     "useful_per_s": L.useful / dt}
+    # one restart cycle of the oracle's GMRES(30) on the C operator (all threads)
+    t0 = time.perf_counter()
+    g = o.gmres(lambda v: L.matvec_rows(v, sigma, threads=nthr), b, restart=30, max_iters=30, tol=1e-8)
+    dt = time.perf_counter() - t0
+    res["gmres_cycle_all"] = {"threads": nthr, "restart": 30, "iters": int(g.iters), "s": dt,
+                              "rel_resid": float(g.rel_resid)}
     L.close()
     out = {"value": res["matvec_all"]["useful_per_s"], "unit": "evals/s", "cores": nthr, "kind": "oracle",
            "sample": (f"C cell-list float64 oracle: one full operator application ({X.shape[0]} rows) on {nthr} "
                       f"threads; {rows.size} sampled rows on 1 thread; the interpolant at {eval_points} band "
-                      f"points on {nthr} threads and {eval_points // 10} on 1"),
+                      f"points on {nthr} threads and {eval_points // 10} on 1; one GMRES(30) cycle of the "
+                      f"oracle on the operator on {nthr} threads"),
            "host_cpus": os.cpu_count(), "cell_list_s": build_s, **res}
     if solve_apps:
-        out["solve_extrapolated_s"] = res["matvec_all"]["s"] * solve_apps
-        out["solve_extrapolated_note"] = (f"{solve_apps} float64 operator applications (the plain method's count to "
-                                          f"the common residual) x the all-thread application time")
+        cycles = solve_apps / 31
+        out["solve_extrapolated_s"] = res["gmres_cycle_all"]["s"] * cycles
+        out["solve_extrapolated_note"] = (f"{cycles:.0f} GMRES(30) cycles (the plain float64 method's count to the "
+                                          f"common residual, {solve_apps} operator applications) x the measured "
+                                          f"all-thread cycle time of the oracle")
     return out
 
 
@@ -281,7 +314,16 @@ def main():
         "useful_pairs_per_launch": prof.useful_pairs[OP][F32] / max(f32_launch, 1),
         "examined_per_useful": prof.examined_pairs[OP][F32] / max(prof.useful_pairs[OP][F32], 1),
         "examined_rate": prof.examined_pairs[OP][F32] / (f32_ms * 1e-3) / 1e9,
+        "measured_rates": measured_rates(rbf),
     }
+    # the chunk bodies' rate for this operator's mix of inner and masked
+    # examined pairs, and the kernel's examined-pair rate against it
+    mr = roofline["measured_rates"]
+    fin = st.inner_entries / max(st.list_entries, 1)
+    body = 1.0 / (fin / mr["inner_body_pair_steps_per_s"] + (1 - fin) / mr["masked_body_pair_steps_per_s"])
+    mr["inner_share_of_examined"] = fin
+    mr["body_pairs_per_s"] = body
+    mr["kernel_examined_rate_over_body"] = roofline["examined_rate"] * 1e9 / body
     ev_ms = prof.kernel_ms[EV][F32]
     # (the grid's launches count no pairs themselves: the pair count of the
     # grid, from the list builder, times the launches)

@@ -138,6 +138,8 @@ typedef struct {
     int64_t n_cells;         /* occupied cells of the neighbour lattice */
     double cell_size;        /* side of a lattice cell */
     double sigma, cutoff, eps;
+    int64_t inner_entries;   /* list entries in the groups' leading inner chunks (every pair inside
+                                the cutoff: the pair kernels apply no test there) */
 } rbf_stats;
 
 /* Fill `opts` with the defaults listed in rbf_solve_opts. */
@@ -371,6 +373,29 @@ typedef struct {
 
 int rbf_profile_begin(void);
 int rbf_profile_end(rbf_profile* out);
+
+/* Issue rates of the current device's vector ALU, measured by
+ * register-resident loops that fill every wave slot (eight waves per SIMD),
+ * as evidence for the float32 pair kernel's roofline (measurement, not part
+ * of the method): float32 FMAs (VOP2, unpacked; eight independent chains per
+ * lane), the same FMA in its DPP row-broadcast form, v_exp_f32, chains of one
+ * v_exp_f32 with three or seven FMAs, and the float32 pair kernel's own
+ * 16-step chunk bodies (inner and masked) on register operands, without the
+ * kernel's list reads, gathers and per-chunk set-up.  Runs seven short
+ * kernels (milliseconds each) on `stream` and synchronises with it;
+ * allocates a 2 MB output from the library's cache. */
+typedef struct {
+    int compute_units;
+    double fma_per_s;                /* lane FMAs per second (VOP2) */
+    double exp_per_s;                /* lane exponentials per second */
+    double exp_3fma_per_s;           /* lane (exp + 3 FMA) chains per second */
+    double exp_7fma_per_s;           /* lane (exp + 7 FMA) chains per second */
+    double dpp_fma_per_s;            /* lane FMAs per second, DPP row-broadcast form */
+    double inner_pair_steps_per_s;   /* pair steps per second of the inner chunk body */
+    double masked_pair_steps_per_s;  /* pair steps per second of the masked chunk body */
+} rbf_rates;
+
+int rbf_measure_rates(rbf_rates* out, void* stream);
 
 /* Release every resource of the context (NULL is ignored).  Waits for work
  * enqueued by the context. */

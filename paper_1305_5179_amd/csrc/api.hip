@@ -1018,6 +1018,7 @@ int rbf_get_stats(const rbf_ctx* c, rbf_stats* st) {
   st->sigma = c->sigma;
   st->cutoff = c->cutoff;
   st->eps = c->eps;
+  st->inner_entries = c->centres.inner_entries;
   return RBF_OK;
 }
 
@@ -1027,6 +1028,15 @@ int rbf_profile_begin(void) {
 
 int rbf_profile_end(rbf_profile* out) {
   return guarded(nullptr, [&]() -> int { return profile_end(out); });
+}
+
+int rbf_measure_rates(rbf_rates* out, void* stream) {
+  TempStream temp_scope((hipStream_t)stream);
+  if (!out) return fail(nullptr, RBF_EINVAL, "out is NULL");
+  return guarded(nullptr, [&]() -> int {
+    measure_rates(out, (hipStream_t)stream);
+    return RBF_OK;
+  });
 }
 
 void rbf_destroy(rbf_ctx* c) {

@@ -142,6 +142,7 @@ struct TargetSet {
   uint16_t* mask = nullptr; // per-entry target masks of the non-inner chunks (mask_slot)
   int64_t list_entries = 0;
   int64_t useful = 0;       // pairs with r^2 <= cutoff^2 (float64 decision)
+  int64_t inner_entries = 0; // list entries in the groups' leading inner chunks (no cutoff test)
   bool dense = false;       // no cutoff: every group's list is 0..M-1 (implicit)
   bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
   int kind = 0;             // 0: the centres (operator), 1: evaluation targets
@@ -360,6 +361,11 @@ struct ProfScope {
 int profile_begin();
 int profile_end(rbf_profile* out);
 bool profiling();
+// Issue rates of the vector ALU on the current device (rbf_measure_rates).
+void measure_rates(rbf_rates* r, hipStream_t s);
+// The float32 pair kernel's chunk bodies on register operands (pairsum.hip):
+// blocks x 256 lanes x iters x 16 pair steps.
+void launch_step_rate(bool masked, float* out, int blocks, int iters, hipStream_t s);
 
 // schwarz.hip
 int schwarz_overlap_count(int ncore, int pct);

@@ -529,6 +529,30 @@ __global__ __launch_bounds__(kBlock, 6) void k_pairsum_f64(PairArgs a) {
     direct_group_f64(a, gi, g, wave, lane, sh);
 }
 
+// Register-resident rate of the float32 pair steps (rbf_measure_rates): the
+// kernel's own 16-step chunk bodies, inner and masked, on operands held in
+// registers (no list, gather or set-up), one accumulator per lane as in the
+// kernel.  Lane masks alternate bits.
+template <bool MASKED>
+__global__ __launch_bounds__(256) void k_step_rate(float* __restrict__ out, int iters) {
+  const int lane = threadIdx.x & 63;
+  const Tgt t{0.01f * (float)(lane & 15), 0.02f, -0.01f};
+  Src s{0.1f, 0.05f * (float)((lane >> 4) + 1), 0.02f, 0.5f};
+  StepMasks mk;
+#pragma unroll
+  for (int k = 0; k < kGroup; ++k) mk.m[k] = 0x5555555555555555ull << (k & 1);
+  float acc = 0.0f;
+  for (int it = 0; it < iters; ++it) {
+    // opaque to the compiler: the chunk body is not hoisted out of the loop
+    asm volatile("" : "+v"(s.x), "+v"(s.y), "+v"(s.z), "+v"(s.w));
+    if constexpr (MASKED)
+      expanded_masked_chunk(acc, t, s, mk);
+    else
+      expanded_inner_chunk(acc, t, s);
+  }
+  out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
 PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out,
                    const int* skip) {
   PairArgs a;
@@ -580,6 +604,14 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   }
   RBF_HIP(hipGetLastError());
   prof.done();
+}
+
+void launch_step_rate(bool masked, float* out, int blocks, int iters, hipStream_t s) {
+  if (masked)
+    hipLaunchKernelGGL(k_step_rate<true>, dim3(blocks), dim3(256), 0, s, out, iters);
+  else
+    hipLaunchKernelGGL(k_step_rate<false>, dim3(blocks), dim3(256), 0, s, out, iters);
+  RBF_HIP(hipGetLastError());
 }
 
 void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f32, void* out, hipStream_t s,

@@ -732,6 +732,10 @@ __global__ void k_list_lengths(const GroupInfo* __restrict__ groups, int64_t G, 
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g < G) len[g] = (int64_t)groups[g].n_chunks * kChunk;
 }
+__global__ void k_inner_lengths(const GroupInfo* __restrict__ groups, int64_t G, int64_t* __restrict__ len) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g < G) len[g] = (int64_t)groups[g].n_inner * kChunk;
+}
 // Dense sets: every group sees all m centres (padded to whole chunks).
 __global__ void k_dense_groups(const double4* __restrict__ tpts, int64_t G, int64_t m, GroupInfo* __restrict__ groups) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1217,6 +1221,7 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     ts.list = nullptr;
     ts.mask = nullptr;
     ts.list_entries = G * round_up(c.m, kChunk);
+    ts.inner_entries = ts.list_entries;
     ts.useful = ts.n_targets * c.m;
   } else {
     int64_t* bnd = talloc<int64_t>(G);
@@ -1284,6 +1289,11 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
                        slist, smask, (uint32_t)c.m, ts.list, ts.mask);
     RBF_HIP(hipGetLastError());
     temp_free(slist); temp_free(smask); temp_free(bnd); temp_free(soff); temp_free(cin); temp_free(cout);
+    // entries of the inner chunks (the pair kernels' unmasked loop), for the statistics
+    hipLaunchKernelGGL(k_inner_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
+    RBF_HIP(hipGetLastError());
+    sum_i64(len, G, tmp, s);
+    RBF_HIP(hipMemcpyAsync(&ts.inner_entries, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     temp_free(use); temp_free(vm); temp_free(len); temp_free(off);
   }
   RBF_HIP(hipStreamSynchronize(s));

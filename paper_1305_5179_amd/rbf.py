@@ -28,7 +28,8 @@ EXPORTS = ["rbf_default_solve_opts", "rbf_setup", "rbf_centres", "rbf_matvec", "
            "rbf_profile_begin", "rbf_profile_end", "rbf_destroy", "rbf_last_error",
            "rbf_default_schwarz_opts", "rbf_schwarz_setup", "rbf_schwarz_apply", "rbf_schwarz_get_info",
            "rbf_schwarz_subdomains", "rbf_net_set", "rbf_net_get", "rbf_net_forward", "rbf_net_gradient",
-           "rbf_net_train", "rbf_eval_grid_culled", "rbf_arnoldi", "rbf_eval_grid_noalloc"]
+           "rbf_net_train", "rbf_eval_grid_culled", "rbf_arnoldi", "rbf_eval_grid_noalloc",
+           "rbf_measure_rates"]
 RBF_NET_PARAMS = 50177
 
 
@@ -69,13 +70,19 @@ class Stats(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_centres", C.c_int64), ("n_groups", C.c_int64),
                 ("list_entries", C.c_int64), ("useful_pairs", C.c_int64), ("examined_pairs", C.c_int64),
                 ("n_cells", C.c_int64), ("cell_size", C.c_double), ("sigma", C.c_double),
-                ("cutoff", C.c_double), ("eps", C.c_double)]
+                ("cutoff", C.c_double), ("eps", C.c_double), ("inner_entries", C.c_int64)]
 
 
 class Profile(C.Structure):
     """Arrays indexed [kind][prec]: kind 0 = operator, 1 = evaluation."""
     _fields_ = [("launches", (C.c_int64 * 2) * 2), ("kernel_ms", (C.c_double * 2) * 2),
                 ("useful_pairs", (C.c_int64 * 2) * 2), ("examined_pairs", (C.c_int64 * 2) * 2)]
+
+
+class Rates(C.Structure):
+    _fields_ = [("compute_units", C.c_int), ("fma_per_s", C.c_double), ("exp_per_s", C.c_double),
+                ("exp_3fma_per_s", C.c_double), ("exp_7fma_per_s", C.c_double), ("dpp_fma_per_s", C.c_double),
+                ("inner_pair_steps_per_s", C.c_double), ("masked_pair_steps_per_s", C.c_double)]
 
 
 class CullStats(C.Structure):
@@ -115,6 +122,7 @@ def load_library() -> C.CDLL:
     lib.rbf_count_grid_pairs.argtypes = [vp, C.POINTER(Grid), C.POINTER(i64), C.POINTER(i64), vp]
     lib.rbf_profile_begin.argtypes = []
     lib.rbf_profile_end.argtypes = [C.POINTER(Profile)]
+    lib.rbf_measure_rates.argtypes = [C.POINTER(Rates), vp]
     lib.rbf_default_schwarz_opts.argtypes = [C.POINTER(SchwarzOpts)]
     lib.rbf_schwarz_setup.argtypes = [vp, C.POINTER(SchwarzOpts), vp]
     lib.rbf_schwarz_apply.argtypes = [vp, vp, vp, vp]
@@ -149,6 +157,16 @@ def profile_end() -> Profile:
     if st != RBF_OK:
         raise RbfError(st, load_library().rbf_last_error(None).decode())
     return p
+
+
+def measure_rates() -> Rates:
+    """Issue rates of the device's vector ALU (rbf_measure_rates), on the
+    current stream."""
+    r = Rates()
+    st = load_library().rbf_measure_rates(C.byref(r), _stream())
+    if st != RBF_OK:
+        raise RbfError(st, load_library().rbf_last_error(None).decode())
+    return r
 
 
 def default_opts(**kw) -> SolveOpts:

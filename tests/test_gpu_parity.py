@@ -578,3 +578,25 @@ def test_density_matches_oracle_on_a_patch(case):
     assert d.h == math.sqrt(2.0) * o.h_max(c.points)
     assert d.sigma_sep == 2.0 * q
     assert d.sigma_fill == math.sqrt(2.0) * (math.sqrt(2.0) * o.h_max(c.points))
+
+
+def test_measured_alu_rates_are_physical(torch, R):
+    """The issue-rate probe behind the pair roofline, against the chip's unit
+    counts: VOP2 float32 FMAs at most 32 lanes per SIMD per cycle at 2.5 GHz
+    (the published float32 vector rate) and at least 16 lanes at 1 GHz; the
+    DPP form, an exponential and the mixes no faster than the VOP2 FMA; the
+    pair kernel's chunk bodies no faster than one exponential per pair step
+    and the masked body (one more instruction per step) no faster than the
+    inner one."""
+    r = R.measure_rates()
+    simds = r.compute_units * 4
+    _say(f"[rates] CUs {r.compute_units} fma {r.fma_per_s:.3e}/s dpp fma {r.dpp_fma_per_s:.3e}/s "
+         f"exp {r.exp_per_s:.3e}/s exp+3fma {r.exp_3fma_per_s:.3e}/s exp+7fma {r.exp_7fma_per_s:.3e}/s "
+         f"inner steps {r.inner_pair_steps_per_s:.3e}/s masked steps {r.masked_pair_steps_per_s:.3e}/s")
+    assert r.compute_units > 0
+    assert simds * 16 * 1.0e9 <= r.fma_per_s <= simds * 32 * 2.5e9
+    assert 0 < r.dpp_fma_per_s <= r.fma_per_s * 1.05
+    assert 0 < r.exp_per_s <= r.fma_per_s * 1.05
+    assert 0 < r.exp_7fma_per_s < r.exp_3fma_per_s < r.exp_per_s
+    assert 0 < r.masked_pair_steps_per_s <= r.inner_pair_steps_per_s * 1.05
+    assert r.inner_pair_steps_per_s <= r.exp_per_s * 1.05
