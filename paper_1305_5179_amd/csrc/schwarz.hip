@@ -45,8 +45,18 @@ namespace rbf {
 namespace {
 
 constexpr int kOvThreads = 256;
-constexpr int kCandCap = 2048;                 // candidate buffer of the overlap search
-static_assert(kCandCap >= kSchwarzMaxBlock + kOvThreads, "the best k and one round of candidates fit");
+// The overlap search's LDS is sized for blocks of up to MAXB centres (cores
+// and overlaps): 256 for the usual block sizes (several workgroups per
+// compute unit), kSchwarzMaxBlock otherwise.  Its candidate buffer holds the
+// best k and at least one round of candidates.
+constexpr int kOvSmall = 256;
+template <int MAXB>
+constexpr int ov_cand_cap() {
+  return MAXB <= kOvSmall ? 4 * MAXB : 2 * MAXB;
+}
+static_assert(ov_cand_cap<kOvSmall>() >= kOvSmall + kOvThreads, "the best k and one round of candidates fit");
+static_assert(ov_cand_cap<kSchwarzMaxBlock>() >= kSchwarzMaxBlock + kOvThreads,
+              "the best k and one round of candidates fit");
 constexpr int kFacThreads = 512;
 constexpr int kPanel = 64;   // pivots per panel of the sweep
 // LDS of the factor kernel: coordinates, pivot block, P of a tile, two Q buffers, a column
@@ -124,12 +134,14 @@ struct OvArgs {
 // front, the best k found so far; when it fills, k rounds of a block-wide
 // lexicographic argmin keep the best k.  The selection depends only on the
 // (distance, index) pairs, not on the order in which candidates arrive.
+template <int MAXB>
 __global__ __launch_bounds__(kOvThreads) void k_schwarz_overlap(OvArgs a) {
-  __shared__ double cx[kSchwarzMaxBlock], cy[kSchwarzMaxBlock], cz[kSchwarzMaxBlock];
+  constexpr int kCandCap = ov_cand_cap<MAXB>();
+  __shared__ double cx[MAXB], cy[MAXB], cz[MAXB];
   __shared__ double cd[kCandCap];
   __shared__ uint32_t ci[kCandCap];
-  __shared__ double bd[kSchwarzMaxBlock];
-  __shared__ uint32_t bi[kSchwarzMaxBlock];
+  __shared__ double bd[MAXB];
+  __shared__ uint32_t bi[MAXB];
   __shared__ int32_t leaves[kOvThreads];
   __shared__ double wd[kOvThreads / 64];
   __shared__ uint32_t wi[kOvThreads / 64];
@@ -778,55 +790,102 @@ void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, in
 }
 
 // The apply's launch shape: strips of 256 or 512 rows, taken by 2, 4 or 8
-// workgroups per compute unit or by one workgroup per task; each candidate
-// runs once untimed and twice timed on the work vector (the work and
-// the result do not depend on the values), and the fastest is kept.
+// workgroups per compute unit or by one workgroup per task.  The two task
+// lists are built and uploaded once; after one untimed apply every candidate
+// runs once between its own pair of events, all back to back (the work and
+// the result do not depend on the values), and the host waits once; the
+// fastest is kept.
 void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
   struct Cand {
-    int T, blocks;
+    int T, mult, blocks;
+    hipEvent_t e0, e1;
   };
+  const int Ts[2] = {256, 512};
+  int2* dt[2];
+  int64_t nt[2];
+  for (int k = 0; k < 2; ++k) {
+    std::vector<int2> ht = apply_tasks(d, Ts[k]);
+    dt[k] = upload(ht, s);
+    nt[k] = (int64_t)ht.size();
+  }
   std::vector<Cand> cands;
-  for (int T : {256, 512})
-    for (int mult : {2, 4, 8, 0}) cands.push_back({T, mult});
-  hipEvent_t e0, e1;
-  RBF_HIP(hipEventCreate(&e0));
-  RBF_HIP(hipEventCreate(&e1));
+  for (int k = 0; k < 2; ++k)
+    for (int mult : {2, 4, 8, 0}) {
+      Cand c{Ts[k], mult, 0, nullptr, nullptr};
+      c.blocks = mult > 0 ? (int)std::min<int64_t>((int64_t)mult * cus, nt[k]) : (int)nt[k];
+      cands.push_back(c);
+    }
   double* out = d.restricted ? d.z : d.Y;
+  launch_local(d, cands[0].T, cands[0].blocks, dt[0], nt[0], d.t, out, s, nullptr);   // warm-up
+  for (Cand& c : cands) {
+    const int k = c.T == Ts[0] ? 0 : 1;
+    RBF_HIP(hipEventCreate(&c.e0));
+    RBF_HIP(hipEventCreate(&c.e1));
+    RBF_HIP(hipEventRecord(c.e0, s));
+    launch_local(d, c.T, c.blocks, dt[k], nt[k], d.t, out, s, nullptr);
+    RBF_HIP(hipEventRecord(c.e1, s));
+  }
+  RBF_HIP(hipEventSynchronize(cands.back().e1));
   float best = INFINITY;
-  for (const Cand& c : cands) {
-    std::vector<int2> ht = apply_tasks(d, c.T);
-    int2* dt = upload(ht, s);
-    const int blocks = c.blocks > 0 ? std::min<int64_t>((int64_t)c.blocks * cus, (int64_t)ht.size()) : (int)ht.size();
-    launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
-    RBF_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < 2; ++k) launch_local(d, c.T, blocks, dt, (int64_t)ht.size(), d.t, out, s, nullptr);
-    RBF_HIP(hipEventRecord(e1, s));
-    RBF_HIP(hipEventSynchronize(e1));
+  int pick = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
     float ms = 0.f;
-    RBF_HIP(hipEventElapsedTime(&ms, e0, e1));
+    RBF_HIP(hipEventElapsedTime(&ms, cands[i].e0, cands[i].e1));
     if (ms < best) {
       best = ms;
-      dfree(d.tasks);
-      d.tasks = dt;
-      d.ntask = (int64_t)ht.size();
-      d.apply_threads = c.T;
-      d.apply_blocks = blocks;
-    } else {
-      dfree(dt);
+      pick = (int)i;
     }
+    RBF_HIP(hipEventDestroy(cands[i].e0));
+    RBF_HIP(hipEventDestroy(cands[i].e1));
   }
-  RBF_HIP(hipEventDestroy(e0));
-  RBF_HIP(hipEventDestroy(e1));
+  const int k = cands[pick].T == Ts[0] ? 0 : 1;
+  dfree(d.tasks);
+  d.tasks = dt[k];
+  d.ntask = nt[k];
+  dfree(dt[1 - k]);
+  d.apply_threads = cands[pick].T;
+  d.apply_blocks = cands[pick].blocks;
 }
 
 // Depth-first (Morton) position of a cell at `level` of the 10-level
 // octree, padded to the finest level: the coordinates' bits interleaved,
 // x lowest.
-uint32_t morton_full_depth(const uint32_t q[3], int level) {
+__host__ __device__ inline uint32_t morton_full_depth(const uint32_t q[3], int level) {
   uint32_t key = 0;
   for (int b = level - 1; b >= 0; --b)
     key = (key << 3) | ((q[0] >> b) & 1u) | (((q[1] >> b) & 1u) << 1) | (((q[2] >> b) & 1u) << 2);
   return key << (3 * (kCurveBits - level));
+}
+
+// Depth-first key of every octree leaf: the cell, at the leaf's level, of
+// the leaf's first point (fine-cell index of each coordinate, clamped to the
+// lattice, shifted to the level).
+__global__ void k_leaf_keys(const double* __restrict__ xp, const uint32_t* __restrict__ first_pt,
+                            const int32_t* __restrict__ level, int64_t nleaf, Lattice L, uint32_t* __restrict__ key) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nleaf) return;
+  const uint32_t pt = first_pt[i];
+  const int lev = level[i];
+  uint32_t q[3];
+  for (int d = 0; d < 3; ++d) {
+    double v = floor((xp[3 * (int64_t)pt + d] - L.origin[d]) / L.fine);
+    if (!(v >= 0.0)) v = 0.0;
+    if (v > (double)(kFineMax - 1)) v = (double)(kFineMax - 1);
+    q[d] = (uint32_t)v >> (kCurveBits - lev);
+  }
+  key[i] = morton_full_depth(q, lev);
+}
+
+// Members in sorted positions: mem[e] = the sorted position of paper index
+// mem_paper[e] (inv = the inverse of the sorting permutation).
+__global__ void k_sorted_inverse(const uint32_t* __restrict__ perm, int64_t m, uint32_t* __restrict__ inv) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < m) inv[perm[k]] = (uint32_t)k;
+}
+__global__ void k_members_sorted(const uint32_t* __restrict__ mem_paper, int64_t nmem,
+                                 const uint32_t* __restrict__ inv, uint32_t* __restrict__ mem) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < nmem) mem[e] = inv[mem_paper[e]];
 }
 
 }  // namespace
@@ -859,7 +918,6 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   uint32_t* skeys = talloc<uint32_t>(n);
   sort_points(c.xpaper, n, L, sperm, skeys, s);
   std::vector<uint32_t> hk = download(skeys, n, s), hp = download(sperm, n, s);
-  std::vector<uint32_t> perm = download(c.perm, m, s);
   RBF_HIP(hipStreamSynchronize(s));
   temp_free(sperm);
   temp_free(skeys);
@@ -891,20 +949,27 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   // leaf's level, then position: the runs of one finest cell in index order),
   // then consecutive leaves joined while the block is below min_block and
   // the cap allows
-  std::vector<double> hx = download(c.xpaper, 3 * n, s);
-  RBF_HIP(hipStreamSynchronize(s));
-  std::vector<std::pair<uint32_t, int64_t>> dfo(leaves.size());
-  for (size_t i = 0; i < leaves.size(); ++i) {
-    const uint32_t pt = hp[leaves[i].a];
-    uint32_t q[3];
-    for (int d = 0; d < 3; ++d) {
-      double v = std::floor((hx[3 * (size_t)pt + d] - L.origin[d]) / L.fine);
-      if (!(v >= 0.0)) v = 0.0;
-      if (v > (double)(kFineMax - 1)) v = (double)(kFineMax - 1);
-      q[d] = (uint32_t)v >> (kCurveBits - leaves[i].level);
-    }
-    dfo[i] = {morton_full_depth(q, leaves[i].level), leaves[i].a};
+  const int64_t nleaf = (int64_t)leaves.size();
+  std::vector<uint32_t> lfirst(nleaf);
+  std::vector<int32_t> llevel(nleaf);
+  for (int64_t i = 0; i < nleaf; ++i) {
+    lfirst[i] = hp[leaves[i].a];
+    llevel[i] = leaves[i].level;
   }
+  std::vector<uint32_t> lkey;
+  if (nleaf > 0) {
+    uint32_t* d_first = upload(lfirst, s);
+    int32_t* d_level = upload(llevel, s);
+    uint32_t* d_key = dalloc<uint32_t>(nleaf);
+    hipLaunchKernelGGL(k_leaf_keys, dim3((unsigned)ceil_div(nleaf, 256)), dim3(256), 0, s, c.xpaper, d_first, d_level,
+                       nleaf, L, d_key);
+    RBF_HIP(hipGetLastError());
+    lkey = download(d_key, nleaf, s);
+    RBF_HIP(hipStreamSynchronize(s));
+    for (void* p : {(void*)d_first, (void*)d_level, (void*)d_key}) dfree(p);
+  }
+  std::vector<std::pair<uint32_t, int64_t>> dfo(nleaf);
+  for (int64_t i = 0; i < nleaf; ++i) dfo[i] = {lkey[i], leaves[i].a};
   std::vector<int64_t> lorder(leaves.size());
   for (size_t i = 0; i < leaves.size(); ++i) lorder[i] = (int64_t)i;
   std::sort(lorder.begin(), lorder.end(), [&](int64_t x, int64_t y) { return dfo[x] < dfo[y]; });
@@ -929,17 +994,29 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   std::vector<int32_t> kcount(nsub);
   std::vector<double> rho(nsub);
   core_mem.reserve((size_t)m);
+  // every point's core, then the points of every core in increasing index
+  // order by one pass over the indices (a counting sort by core)
+  std::vector<int32_t> core_of(n);
+  std::vector<int64_t> pt_off(nsub + 1, 0);
   for (int64_t i = 0; i < nsub; ++i) {
-    std::vector<uint32_t> pts;
-    double r = 0.0;
+    int64_t cnt = 0;
     for (int64_t li : groups[i]) {
-      pts.insert(pts.end(), hp.begin() + leaves[li].a, hp.begin() + leaves[li].b);
-      r = std::max(r, std::ldexp(side, -leaves[li].level));   // the side of the leaf's cell
+      for (int64_t q = leaves[li].a; q < leaves[li].b; ++q) core_of[hp[q]] = (int32_t)i;
+      cnt += leaves[li].b - leaves[li].a;
     }
-    std::sort(pts.begin(), pts.end());
+    pt_off[i + 1] = pt_off[i] + cnt;
+  }
+  std::vector<uint32_t> pt_sorted(n);
+  {
+    std::vector<int64_t> at(pt_off.begin(), pt_off.end() - 1);
+    for (int64_t p = 0; p < n; ++p) pt_sorted[at[core_of[p]]++] = (uint32_t)p;
+  }
+  for (int64_t i = 0; i < nsub; ++i) {
+    double r = 0.0;
+    for (int64_t li : groups[i]) r = std::max(r, std::ldexp(side, -leaves[li].level));   // the side of the leaf's cell
     for (int t = 0; t < 3; ++t)
-      for (uint32_t p : pts) core_mem.push_back((uint32_t)(p + t * n));
-    const int nc = (int)(3 * pts.size());
+      for (int64_t q = pt_off[i]; q < pt_off[i + 1]; ++q) core_mem.push_back((uint32_t)(pt_sorted[q] + t * n));
+    const int nc = (int)(3 * (pt_off[i + 1] - pt_off[i]));
     core_off[i + 1] = core_off[i] + nc;
     kcount[i] = (int32_t)std::min<int64_t>(schwarz_overlap_count(nc, pct), m - nc);
     ov_off[i + 1] = ov_off[i] + kcount[i];
@@ -966,7 +1043,13 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     hipLaunchKernelGGL(k_schwarz_box, dim3((unsigned)nsub), dim3(64), 0, s, c.xpaper, d_core_off, d_core_mem, d_box);
     RBF_HIP(hipGetLastError());
     OvArgs oa{c.xpaper, nsub, d_core_off, d_core_mem, d_box, d_k, d_ov_off, d_rho, nullptr, 0, d_ov, d_short};
-    hipLaunchKernelGGL(k_schwarz_overlap, dim3((unsigned)nsub), dim3(kOvThreads), 0, s, oa);
+    auto overlap = [&](unsigned blocks) {
+      if (max_block <= kOvSmall)
+        hipLaunchKernelGGL(k_schwarz_overlap<kOvSmall>, dim3(blocks), dim3(kOvThreads), 0, s, oa);
+      else
+        hipLaunchKernelGGL(k_schwarz_overlap<kSchwarzMaxBlock>, dim3(blocks), dim3(kOvThreads), 0, s, oa);
+    };
+    overlap((unsigned)nsub);
     RBF_HIP(hipGetLastError());
     std::vector<int32_t> short_of = download(d_short, nsub, s);
     RBF_HIP(hipStreamSynchronize(s));
@@ -979,7 +1062,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
       oa.list = d_list;
       oa.rho = d_rho_full;
       oa.unbounded = pass;
-      hipLaunchKernelGGL(k_schwarz_overlap, dim3((unsigned)again.size()), dim3(kOvThreads), 0, s, oa);
+      overlap((unsigned)again.size());
       RBF_HIP(hipGetLastError());
       short_of = download(d_short, nsub, s);
       RBF_HIP(hipStreamSynchronize(s));
@@ -997,8 +1080,6 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     dfree(p);
 
   // 5. members in sorted positions, layout of the inverses, occurrences
-  std::vector<uint32_t> inv(m);
-  for (int64_t q = 0; q < m; ++q) inv[perm[q]] = (uint32_t)q;
   SchwarzData* d = new SchwarzData();
   d->nsub = nsub;
   d->restricted = restricted;
@@ -1008,7 +1089,6 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   d->h_mem_off.assign(nsub + 1, 0);
   d->h_ncore.resize(nsub);
   d->h_mem_paper.reserve((size_t)(core_off[nsub] + ov_off[nsub]));
-  std::vector<uint32_t> mem;
   std::vector<int64_t> woff(nsub, 0);
   std::vector<int32_t> order(nsub);
   int64_t wtotal = 0;
@@ -1024,14 +1104,22 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     order[i] = (int32_t)i;
   }
   d->nmem = d->h_mem_off[nsub];
-  mem.resize(d->nmem);
-  for (int64_t e = 0; e < d->nmem; ++e) mem[e] = inv[d->h_mem_paper[e]];
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
     return d->h_mem_off[x + 1] - d->h_mem_off[x] > d->h_mem_off[y + 1] - d->h_mem_off[y];
   });
   d->mem_off = upload(d->h_mem_off, s);
   d->ncore = upload(d->h_ncore, s);
-  d->mem = upload(mem, s);
+  d->mem = dalloc<uint32_t>(std::max<int64_t>(d->nmem, 1));
+  if (d->nmem > 0) {
+    uint32_t* d_paper = upload(d->h_mem_paper, s);
+    uint32_t* d_inv = talloc<uint32_t>(m);
+    hipLaunchKernelGGL(k_sorted_inverse, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, c.perm, m, d_inv);
+    hipLaunchKernelGGL(k_members_sorted, dim3((unsigned)ceil_div(d->nmem, 256)), dim3(256), 0, s, d_paper, d->nmem,
+                       d_inv, d->mem);
+    RBF_HIP(hipGetLastError());
+    temp_free(d_inv);
+    dfree(d_paper);
+  }
   d->woff = upload(woff, s);
   d->W = dalloc<float>(std::max<int64_t>(wtotal, 1));
   d->w_total = wtotal;
