@@ -2,11 +2,16 @@
 // interpolation system is solved by GMRES; the paper relies on PETSc's
 // KSPSolve).  One Arnoldi step after the operator has produced w = A v_j:
 //   pass 1  h1 = V^T w                       (block partial dot products)
-//   pass 2  w <- w - V h1,  h2 = V^T w       (one sweep: update, then dots)
-//   pass 3  w <- w - V h2,  |w|^2            (classical Gram-Schmidt applied
+//   pass 2  w <- w - V h1,  h2 = V^T w,      (one sweep: update, then dots;
+//           |w|^2                             classical Gram-Schmidt applied
 //                                             twice, "twice is enough")
-//   finish  H(:,j) = h1 + h2, H(j+1,j) = |w|, Givens rotations, |g_{j+1}|,
-//           and v_{j+1} = w / |w| (one launch)
+//   pass 3  beta = |w - V h2| = sqrt(|w|^2 - |h2|^2), H(:,j) = h1 + h2,
+//           H(j+1,j) = beta, Givens rotations, |g_{j+1}|, and
+//           v_{j+1} = (w - V h2) / beta in one sweep
+// (the second pass's coefficients h2 are of the order of the basis' rounding
+// times |w|, so the norm of the corrected vector follows from |w|^2 - |h2|^2
+// to float64 precision unless the step is at a breakdown, which ends the
+// cycle anyway; every block forms beta from the same folded values).
 // Every kernel of a step first reads the device flag `done`, set when the
 // residual estimate |g_{j+1}| reaches the tolerance (or on breakdown), so the
 // host can enqueue a whole cycle without waiting on it.
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dots(const T* __restrict__ V, i
   block_store(s, ncols, partial);
 }
 
-// pass 2: w <- w - V h1 ; partial = V^T w
+// pass 2: w <- w - V h1 ; partial = V^T w, and |w|^2 as column ncols
 template <class T>
 __global__ __launch_bounds__(kVecThreads) void k_update_dots(const T* __restrict__ V, int64_t ldv, int ncols,
                                                              T* __restrict__ w, int64_t n,
@@ -151,6 +156,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots(const T* __restrict
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
   double wr[kRowsPerThread];
+  double nrm = 0.0;
   for (int q = 0; q < kRowsPerThread; ++q) {
     const int64_t r = base + (int64_t)q * kVecThreads;
     if (r < n) {
@@ -159,13 +165,15 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots(const T* __restrict
       const T vt = (T)v;
       w[r] = vt;
       wr[q] = (double)vt;
+      nrm = fma(wr[q], wr[q], nrm);
     } else {
       wr[q] = 0.0;
     }
   }
   __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
   block_dots(V, ldv, ncols, wr, base, n, s);
-  block_store(s, ncols, partial);
+  wave_partial(nrm, ncols, s);
+  block_store(s, ncols + 1, partial);
 }
 
 // pass 2 with the basis values of the thread's rows kept in registers
@@ -206,6 +214,9 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots_reg(const float* __
       wr[q] = 0.0;
     }
   }
+  double nrm = 0.0;
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) nrm = fma(wr[q], wr[q], nrm);
   __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -223,34 +234,8 @@ __global__ __launch_bounds__(kVecThreads) void k_update_dots_reg(const float* __
         if (b * kColPad + c < ncols) s[wave][b * kColPad + c] = a[c];
     }
   }
-  block_store(s, ncols, partial);
-}
-
-// pass 3: w <- w - V h2 ; partial = |w|^2
-template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_update_norm(const T* __restrict__ V, int64_t ldv, int ncols,
-                                                             T* __restrict__ w, int64_t n,
-                                                             const GmState* __restrict__ st,
-                                                             double* __restrict__ partial) {
-  if (st->done) return;
-  __shared__ double h[kMaxRestart + 1];
-  for (int i = threadIdx.x; i < ncols; i += kVecThreads) h[i] = st->h2[i];
-  __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
-  double a = 0.0;
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int64_t r = base + (int64_t)q * kVecThreads;
-    if (r < n) {
-      double v = (double)w[r];
-      for (int i = 0; i < ncols; ++i) v = fma(-h[i], (double)V[(int64_t)i * ldv + r], v);
-      const T vt = (T)v;
-      w[r] = vt;
-      a = fma((double)vt, (double)vt, a);
-    }
-  }
-  __shared__ double s[kVecThreads / 64][kMaxRestart + 1];
-  wave_partial(a, 0, s);
-  block_store(s, 1, partial);
+  wave_partial(nrm, ncols, s);
+  block_store(s, ncols + 1, partial);
 }
 
 // Sum of the block partials of one column by a whole block: thread t adds
@@ -337,27 +322,37 @@ __device__ void finish_step(double beta, int j, GmState* __restrict__ st) {
   for (int i = t; i <= j + 1; i += kVecThreads) Hc[i] = hc[i];
 }
 
-// End of step j: v_{j+1} = w / |w|, with the step's bookkeeping.  Every
-// block folds the norm partials itself (in the same fixed order, so all get
-// the same |w| to the bit); block 0 also runs finish_step.  A block that
-// already sees the stop flag block 0 may set skips the scaling: the column
-// past the last step of a cycle is never read.
-constexpr int kScaleRows = 4;   // elements per thread
+// pass 3 and the end of step j: beta = |w - V h2| from |w|^2 - |h2|^2 (the
+// folded column ncols of pass 2 and h2), v_{j+1} = (w - V h2) / beta formed
+// in float64 and rounded to T once; block 0 also runs finish_step.  Every
+// block forms beta from the same folded values in the same order (the same
+// bits).  A block that already sees the stop flag block 0 may set skips the
+// sweep: the column past the last step of a cycle is never read.
 template <class T>
-__global__ __launch_bounds__(kVecThreads) void k_finish_scale(const double* __restrict__ partial, int nb, int j,
-                                                              GmState* __restrict__ st, const T* __restrict__ w,
-                                                              int64_t n, T* __restrict__ out) {
+__global__ __launch_bounds__(kVecThreads) void k_update_scale(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                              const T* __restrict__ w, int64_t n, int j,
+                                                              GmState* __restrict__ st, T* __restrict__ out) {
   if (st->done) return;
-  const double beta = sqrt(block_fold(partial, nb, 0));
+  __shared__ double h[kMaxRestart + 1];
+  for (int i = threadIdx.x; i < ncols; i += kVecThreads) h[i] = st->h2[i];
+  __syncthreads();
+  double hh = 0.0;
+  for (int i = 0; i < ncols; ++i) hh = fma(h[i], h[i], hh);
+  const double beta = sqrt(fmax(st->h2[ncols] - hh, 0.0));
   if (blockIdx.x == 0) finish_step(beta, j, st);
   const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const int64_t base = (int64_t)blockIdx.x * (kVecThreads * kScaleRows) + threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < kScaleRows; ++q) {
-    const int64_t i = base + (int64_t)q * kVecThreads;
-    if (i < n) out[i] = (T)((double)w[i] * inv);
+  const int64_t base = (int64_t)blockIdx.x * kRowsPerBlock + threadIdx.x;
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int64_t r = base + (int64_t)q * kVecThreads;
+    if (r < n) {
+      double v = (double)w[r];
+      for (int i = 0; i < ncols; ++i) v = fma(-h[i], (double)V[(int64_t)i * ldv + r], v);
+      out[r] = (T)(v * inv);
+    }
   }
 }
+
+constexpr int kScaleRows = 4;   // elements per thread of the start's scaling
 
 // r = b - y and |r|^2 partials (y may be null: r = b)
 __global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restrict__ b, const double* __restrict__ y,
@@ -551,10 +546,9 @@ static void gm_step_t(T* V, int64_t ldv, T* w, int64_t n, int j, double* partial
   } else {
     hipLaunchKernelGGL(k_update_dots<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
   }
-  hipLaunchKernelGGL(k_reduce_h2, dim3(ncols), dim3(kVecThreads), 0, s, partial, (int)nb, st);
-  hipLaunchKernelGGL(k_update_norm<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, st, partial);
-  const unsigned sb = (unsigned)std::max<int64_t>(1, ceil_div(n, (int64_t)kVecThreads * kScaleRows));
-  hipLaunchKernelGGL(k_finish_scale<T>, dim3(sb), dim3(kVecThreads), 0, s, partial, (int)nb, j, st, w, n,
+  // (ncols + 1 columns: h2 and |w|^2)
+  hipLaunchKernelGGL(k_reduce_h2, dim3(ncols + 1), dim3(kVecThreads), 0, s, partial, (int)nb, st);
+  hipLaunchKernelGGL(k_update_scale<T>, dim3(nb), dim3(kVecThreads), 0, s, V, ldv, ncols, w, n, j, st,
                      V + (int64_t)(j + 1) * ldv);
   RBF_HIP(hipGetLastError());
 }
