@@ -295,31 +295,69 @@ __global__ __launch_bounds__(kTileWaves * kWave, 4) void k_brick_sum_f32(TileArg
   }
 }
 
-// Tiles of the listed bricks: tmask[tile] |= bit of the brick.
-__global__ void k_tile_mark(const int64_t* __restrict__ ids, int64_t nact, GridDesc gd, int64_t nt0, int64_t nt1,
+// Launch order of the tiles.  The tiles are listed block by block, blocks of
+// 16 x 16 x 16 tiles in raster order and the tiles of a block in raster
+// order, so that the waves resident on one XCD at a time (about 512, about
+// the support tiles of one block near a surface) cover a compact part of the
+// grid and share the sources they gather in that XCD's L2 (in plain raster
+// order they cover a thin slab).  A slot is a position in that order over
+// the grid's tiles padded to whole blocks.
+constexpr int kSlotBlock = 16;
+struct SlotSpace {
+  int64_t nt0, nt1, nt2;   // tiles per axis
+  int64_t b0, b1;          // blocks along x and y
+  int64_t n;               // slots (whole blocks)
+};
+SlotSpace slot_space(int64_t nt0, int64_t nt1, int64_t nt2) {
+  SlotSpace S;
+  S.nt0 = nt0;
+  S.nt1 = nt1;
+  S.nt2 = nt2;
+  S.b0 = ceil_div(nt0, (int64_t)kSlotBlock);
+  S.b1 = ceil_div(nt1, (int64_t)kSlotBlock);
+  S.n = S.b0 * S.b1 * ceil_div(nt2, (int64_t)kSlotBlock) * (kSlotBlock * kSlotBlock * kSlotBlock);
+  return S;
+}
+__device__ __forceinline__ int64_t tile_slot(const SlotSpace& S, int64_t tx, int64_t ty, int64_t tz) {
+  constexpr int B = kSlotBlock;
+  const int64_t blk = tx / B + S.b0 * (ty / B + S.b1 * (tz / B));
+  return blk * (B * B * B) + tx % B + B * (ty % B + B * (tz % B));
+}
+// The tile of slot p; false for the padding slots.
+__device__ __forceinline__ bool slot_tile(const SlotSpace& S, int64_t p, int64_t& tx, int64_t& ty, int64_t& tz) {
+  constexpr int B = kSlotBlock;
+  const int64_t blk = p / (B * B * B), w = p % (B * B * B);
+  tx = B * (blk % S.b0) + w % B;
+  ty = B * ((blk / S.b0) % S.b1) + (w / B) % B;
+  tz = B * (blk / (S.b0 * S.b1)) + w / (B * B);
+  return tx < S.nt0 && ty < S.nt1 && tz < S.nt2;
+}
+
+// Tiles of the listed bricks: tmask[slot of the tile] |= bit of the brick.
+__global__ void k_tile_mark(const int64_t* __restrict__ ids, int64_t nact, GridDesc gd, SlotSpace S,
                             unsigned long long* __restrict__ tmask) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= nact) return;
   const int64_t b = ids[e];
   const int64_t bx = b % gd.nb[0], by = (b / gd.nb[0]) % gd.nb[1], bz = b / (gd.nb[0] * gd.nb[1]);
-  const int64_t t = bx + nt0 * (by / kTileY + nt1 * (bz / kTileZ));
-  atomicOr(tmask + t, 1ull << (by % kTileY + kTileY * (bz % kTileZ)));
+  atomicOr(tmask + tile_slot(S, bx, by / kTileY, bz / kTileZ), 1ull << (by % kTileY + kTileY * (bz % kTileZ)));
 }
 
-// The tile masks of a brick marking (mark[b] != 0: brick b belongs), and
-// flag[t] = 1 for the tiles with a marked brick.
-__global__ void k_tiles_from_marks(const int64_t* __restrict__ mark, GridDesc gd, int64_t nt0, int64_t nt1, int64_t nt,
+// The tile masks of a brick marking (mark[b] != 0: brick b belongs), by
+// slot, and flag[p] = 1 for the slots of tiles with a marked brick.
+__global__ void k_tiles_from_marks(const int64_t* __restrict__ mark, GridDesc gd, SlotSpace S,
                                    int64_t* __restrict__ tmask, int64_t* __restrict__ flag) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= nt) return;
-  const int64_t tx = t % nt0, ty = (t / nt0) % nt1, tz = t / (nt0 * nt1);
-  int64_t m = 0;
-  for (int b = 0; b < kTileBricks; ++b) {
-    const int64_t by = kTileY * ty + b % kTileY, bz = kTileZ * tz + b / kTileY;
-    if (by < gd.nb[1] && bz < gd.nb[2] && mark[tx + gd.nb[0] * (by + gd.nb[1] * bz)]) m |= int64_t(1) << b;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= S.n) return;
+  int64_t tx, ty, tz, m = 0;
+  if (slot_tile(S, p, tx, ty, tz)) {
+    for (int b = 0; b < kTileBricks; ++b) {
+      const int64_t by = kTileY * ty + b % kTileY, bz = kTileZ * tz + b / kTileY;
+      if (by < gd.nb[1] && bz < gd.nb[2] && mark[tx + gd.nb[0] * (by + gd.nb[1] * bz)]) m |= int64_t(1) << b;
+    }
   }
-  tmask[t] = m;
-  flag[t] = m != 0 ? 1 : 0;
+  tmask[p] = m;
+  flag[p] = m != 0 ? 1 : 0;
 }
 
 __global__ void k_fill_zero(int64_t* __restrict__ p, int64_t n) {
@@ -332,13 +370,16 @@ __global__ void k_nonzero(const int64_t* __restrict__ v, int64_t n, int64_t* __r
   if (i < n) flag[i] = v[i] != 0 ? 1 : 0;
 }
 
-__global__ void k_tile_compact(const int64_t* __restrict__ tmask, const int64_t* __restrict__ pos, int64_t n,
+// The marked slots in slot order: tiles[] their tiles' raster indices
+// (tx + nt0 (ty + nt1 tz)), masks[] their brick masks.
+__global__ void k_tile_compact(const int64_t* __restrict__ tmask, const int64_t* __restrict__ pos, SlotSpace S,
                                int64_t* __restrict__ tiles, int64_t* __restrict__ masks) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n && tmask[i] != 0) {
-    tiles[pos[i]] = i;
-    masks[pos[i]] = tmask[i];
-  }
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= S.n || tmask[p] == 0) return;
+  int64_t tx, ty, tz;
+  slot_tile(S, p, tx, ty, tz);
+  tiles[pos[p]] = tx + S.nt0 * (ty + S.nt1 * tz);
+  masks[pos[p]] = tmask[p];
 }
 
 inline unsigned blocks_of(int64_t n) { return (unsigned)std::max<int64_t>(1, ceil_div(n, kThreadsT)); }
@@ -349,26 +390,33 @@ void tile_dims(const GridDesc& gd, int64_t* nt0, int64_t* nt1, int64_t* nt2) {
   *nt2 = ceil_div(gd.nb[2], kTileZ);
 }
 
-int64_t tile_count(const GridDesc& gd) {
+SlotSpace grid_slots(const GridDesc& gd) {
   int64_t nt0, nt1, nt2;
   tile_dims(gd, &nt0, &nt1, &nt2);
-  return nt0 * nt1 * nt2;
+  return slot_space(nt0, nt1, nt2);
 }
 
-// Scan of the tile flags and compaction of the marked tiles: ws holds tmask,
-// flag, pos, tiles, masks (NT each) and the scan's workspace; returns the
-// count (waits for it).
-int64_t compact_tiles(int64_t* ws, int64_t NT, hipStream_t s) {
+// Workspace of the tile compaction: tmask, flag and pos by slot (S.n each),
+// tiles and masks (one per tile), and the scan's workspace.
+int64_t compact_ws_elems(const SlotSpace& S) {
+  return 3 * S.n + 2 * S.nt0 * S.nt1 * S.nt2 + scan_ws_elems(S.n);
+}
+int64_t* compact_tiles_out(int64_t* ws, const SlotSpace& S) { return ws + 3 * S.n; }
+int64_t* compact_masks_out(int64_t* ws, const SlotSpace& S) { return ws + 3 * S.n + S.nt0 * S.nt1 * S.nt2; }
+
+// Scan of the slot flags and compaction of the marked tiles in slot order;
+// returns the count (waits for it).
+int64_t compact_tiles(int64_t* ws, const SlotSpace& S, hipStream_t s) {
   int64_t* tmask = ws;
-  int64_t* flag = ws + NT;
-  int64_t* pos = ws + 2 * NT;
-  scan_exclusive_i64_ws(flag, pos, NT, ws + 5 * NT, s);
-  hipLaunchKernelGGL(k_tile_compact, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, tmask, pos, NT, ws + 3 * NT,
-                     ws + 4 * NT);
+  int64_t* flag = ws + S.n;
+  int64_t* pos = ws + 2 * S.n;
+  scan_exclusive_i64_ws(flag, pos, S.n, ws + 3 * S.n + 2 * S.nt0 * S.nt1 * S.nt2, s);
+  hipLaunchKernelGGL(k_tile_compact, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, tmask, pos, S,
+                     compact_tiles_out(ws, S), compact_masks_out(ws, S));
   RBF_HIP(hipGetLastError());
   int64_t last_pos = 0, last_flag = 0;
-  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (NT - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (NT - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
   return last_pos + last_flag;
 }
@@ -389,26 +437,22 @@ bool brick_sum_applies(const Ctx& c, const rbf_grid& g) {
 
 int64_t support_tiles_ws_elems(const rbf_grid& g) {
   const GridDesc gd = grid_desc(g);
-  const int64_t NT = tile_count(gd);
-  return gd.nb[0] * gd.nb[1] * gd.nb[2] + 5 * NT + scan_ws_elems(NT);
+  return gd.nb[0] * gd.nb[1] * gd.nb[2] + compact_ws_elems(grid_slots(gd));
 }
 
 int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_t** tiles, const int64_t** masks,
                       hipStream_t s) {
   const GridDesc gd = grid_desc(g);
-  int64_t nt0, nt1, nt2;
-  tile_dims(gd, &nt0, &nt1, &nt2);
-  const int64_t NT = nt0 * nt1 * nt2;
+  const SlotSpace S = grid_slots(gd);
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
   int64_t* mark = ws;
   int64_t* tw = ws + nbricks;
   mark_support(c, gd, mark, nbricks, s);
-  hipLaunchKernelGGL(k_tiles_from_marks, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, mark, gd, nt0, nt1, NT, tw,
-                     tw + NT);
+  hipLaunchKernelGGL(k_tiles_from_marks, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, mark, gd, S, tw, tw + S.n);
   RBF_HIP(hipGetLastError());
-  const int64_t nt = compact_tiles(tw, NT, s);
-  *tiles = tw + 3 * NT;
-  *masks = tw + 4 * NT;
+  const int64_t nt = compact_tiles(tw, S, s);
+  *tiles = compact_tiles_out(tw, S);
+  *masks = compact_masks_out(tw, S);
   return nt;
 }
 
@@ -468,17 +512,15 @@ void brick_sum_f32(const Ctx& c, const rbf_grid& g, const int64_t* ids, int64_t 
   if (examined) *examined = 0;
   if (nact <= 0) return;
   const GridDesc gd = grid_desc(g);
-  int64_t nt0, nt1, nt2;
-  tile_dims(gd, &nt0, &nt1, &nt2);
-  const int64_t NT = nt0 * nt1 * nt2;
-  int64_t* ws = talloc<int64_t>(5 * NT + scan_ws_elems(NT));
-  hipLaunchKernelGGL(k_fill_zero, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, ws, NT);
-  hipLaunchKernelGGL(k_tile_mark, dim3(blocks_of(nact)), dim3(kThreadsT), 0, s, ids, nact, gd, nt0, nt1,
+  const SlotSpace S = grid_slots(gd);
+  int64_t* ws = talloc<int64_t>(compact_ws_elems(S));
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, ws, S.n);
+  hipLaunchKernelGGL(k_tile_mark, dim3(blocks_of(nact)), dim3(kThreadsT), 0, s, ids, nact, gd, S,
                      reinterpret_cast<unsigned long long*>(ws));
-  hipLaunchKernelGGL(k_nonzero, dim3(blocks_of(NT)), dim3(kThreadsT), 0, s, ws, NT, ws + NT);
+  hipLaunchKernelGGL(k_nonzero, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, ws, S.n, ws + S.n);
   RBF_HIP(hipGetLastError());
-  const int64_t nt = compact_tiles(ws, NT, s);
-  brick_sum_tiles(c, g, ws + 3 * NT, ws + 4 * NT, nt, w_sorted, out, useful, examined, s);
+  const int64_t nt = compact_tiles(ws, S, s);
+  brick_sum_tiles(c, g, compact_tiles_out(ws, S), compact_masks_out(ws, S), nt, w_sorted, out, useful, examined, s);
   temp_free(ws);
 }
 
