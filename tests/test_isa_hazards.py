@@ -1,4 +1,5 @@
-"""Static checks on the gfx950 assembly of the float32 pair-sum kernel.
+"""Static checks on the gfx950 assembly of the float32 pair-sum kernel and
+of the issue-rate probes that reuse its steps.
 
 Parts of the kernel's pair loop are inline assembly (DPP row_newbcast FMAs,
 and whole pipelined chunks), which the compiler's hazard recognizer does not
@@ -8,7 +9,7 @@ the instruction order or by s_nop wait states:
     needs two wait states after that write;
   * a (non-transcendental) VALU reading the result of a transcendental
     (v_exp_f32 and the like) needs one wait state on gfx950.
-This test compiles the kernel and checks every instruction of it against
+This test compiles the kernels and checks every instruction of them against
 the instructions that can precede it, following branches into labels."""
 import os
 import re
@@ -31,19 +32,20 @@ def _hipcc():
     return None
 
 
-@pytest.fixture(scope="module")
-def f32_asm(tmp_path_factory):
+def _kernel_bodies(tmp_path_factory, src, prefix):
+    """Instructions (labels kept) of every kernel of `src` whose symbol
+    starts with `prefix`, from the device assembly of this build's flags."""
     hipcc = _hipcc()
     if hipcc is None:
         pytest.skip("hipcc not available")
     from paper_1305_5179_amd.build import HIPFLAGS
-    out = tmp_path_factory.mktemp("isa") / "pairsum.s"
+    out = tmp_path_factory.mktemp("isa") / (os.path.basename(src) + ".s")
     flags = [f for f in HIPFLAGS if f not in ("-fPIC",)]
-    subprocess.run([hipcc, *flags, "--cuda-device-only", "-S", SRC, "-o", str(out)], check=True,
+    subprocess.run([hipcc, *flags, "--cuda-device-only", "-S", src, "-o", str(out)], check=True,
                    capture_output=True)
     text = out.read_text()
     bodies = []
-    for m in re.finditer(r"^(" + KERNEL + r"\w*):", text, re.M):
+    for m in re.finditer(r"^(" + prefix + r"\w*):", text, re.M):
         end = text.index(".Lfunc_end", m.end())
         lines = []
         for raw in text[m.end():end].splitlines()[1:]:
@@ -52,6 +54,12 @@ def f32_asm(tmp_path_factory):
                 continue
             lines.append(l)
         bodies.append((m.group(1), lines))
+    return bodies
+
+
+@pytest.fixture(scope="module")
+def f32_asm(tmp_path_factory):
+    bodies = _kernel_bodies(tmp_path_factory, SRC, KERNEL)
     assert len(bodies) == 2, [b[0] for b in bodies]
     return bodies
 
@@ -148,7 +156,23 @@ def test_no_dpp_or_transcendental_forwarding_hazard(f32_asm):
         _check_kernel(name, lines)
 
 
-def _check_kernel(name, lines):
+def test_rate_probes_have_no_hazard(tmp_path_factory):
+    """The register-resident rate kernels of rbf_measure_rates: the pair
+    kernel's own chunk bodies (pairsum.hip) and the DPP FMA and
+    exponential-mix loops (profile.hip)."""
+    steps = _kernel_bodies(tmp_path_factory, SRC, "_ZN3rbf12_GLOBAL__N_111k_step_rate")
+    assert len(steps) == 2, [b[0] for b in steps]
+    for name, lines in steps:
+        _check_kernel(name, lines, min_fmac_dpp=48, min_dpp=64)
+    rates = _kernel_bodies(tmp_path_factory, os.path.join(os.path.dirname(SRC), "profile.hip"),
+                           "_ZN3rbf12_GLOBAL__N_17k_rates")
+    assert len(rates) == 5, [b[0] for b in rates]
+    for name, lines in rates:
+        _check_kernel(name, lines, min_fmac_dpp=0, min_dpp=0)
+    assert any(l.startswith("v_fmac_f32_dpp") for _, lines in rates for l in lines)
+
+
+def _check_kernel(name, lines, min_fmac_dpp=64, min_dpp=128):
     _predecessors.cache = _predecessors(lines)
     n_dpp = n_fmac_dpp = 0
     problems = []
@@ -168,9 +192,9 @@ def _check_kernel(name, lines):
             for p, w in _violations(lines, i, _reads(l), 1, lambda x: _parse(x)[0].startswith(TRANS)):
                 problems.append(f"transcendental result read after {w} wait states: '{p}' -> '{l}'")
     assert not problems, name + "\n" + "\n".join(problems[:20])
-    # the pair loops of both forms are present
-    assert n_fmac_dpp >= 64, (name, n_fmac_dpp)
-    assert n_dpp >= 128, (name, n_dpp)
+    # the pair loops (of both forms, in the pair kernel) are present
+    assert n_fmac_dpp >= min_fmac_dpp, (name, n_fmac_dpp)
+    assert n_dpp >= min_dpp, (name, n_dpp)
 
 
 def test_checker_sees_planted_hazards():
