@@ -58,6 +58,9 @@ struct PairArgs {
   const int* skip;
 };
 
+// Word 3 of a raw buffer descriptor on gfx9 (32-bit data format, no swizzle).
+constexpr int kBufferDword3 = 0x00020000;
+
 template <int K>
 __device__ __forceinline__ float bcast(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + K, 0xf, 0xf, true));
@@ -232,33 +235,75 @@ __device__ __forceinline__ double weight(const PairArgs& a, uint32_t i) {
     return a.w[i];
 }
 
-template <bool W32, class Inner, class Masked>
+// A source (scaled coordinates) and its weight.  BUF: by buffer loads at
+// 32-bit byte offsets from descriptors of the two arrays (one shift per
+// offset instead of 64-bit address arithmetic; the host takes this path
+// when the arrays span less than 4 GiB); else by flat 64-bit addresses.
+template <bool W32, bool BUF>
+struct SourceLoader {
+  __amdgpu_buffer_rsrc_t xk, w;
+  const PairArgs* a;
+  __device__ __forceinline__ explicit SourceLoader(const PairArgs& args) : a(&args) {
+    if constexpr (BUF) {
+      const int n = (int)(uint32_t)((args.m + 1) * (int64_t)sizeof(double4));
+      xk = __builtin_amdgcn_make_buffer_rsrc((void*)args.xk, 0, n, kBufferDword3);
+      const void* wp = W32 ? (const void*)args.w32 : (const void*)args.w;
+      const int nw = (int)(uint32_t)((args.m + 1) * (int64_t)(W32 ? sizeof(float) : sizeof(double)));
+      w = __builtin_amdgcn_make_buffer_rsrc((void*)wp, 0, nw, kBufferDword3);
+    }
+  }
+  __device__ __forceinline__ void operator()(uint32_t i, double4& s, double& wt) const {
+    if constexpr (BUF) {
+      const uint32_t off = i * (uint32_t)sizeof(double4);
+      const auto xy = __builtin_amdgcn_raw_buffer_load_b128(xk, off, 0, 0);
+      const auto z = __builtin_amdgcn_raw_buffer_load_b64(xk, off + 16u, 0, 0);
+      s.x = __builtin_bit_cast(double, ((uint64_t)xy[1] << 32) | xy[0]);
+      s.y = __builtin_bit_cast(double, ((uint64_t)xy[3] << 32) | xy[2]);
+      s.z = __builtin_bit_cast(double, ((uint64_t)z[1] << 32) | z[0]);
+      s.w = 0.0;
+      if constexpr (W32)
+        wt = (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(w, i * 4u, 0, 0));
+      else
+      {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(w, i * 8u, 0, 0);
+        wt = __builtin_bit_cast(double, ((uint64_t)v[1] << 32) | v[0]);
+      }
+    } else {
+      s = a->xk[i];
+      wt = weight<W32>(*a, i);
+    }
+  }
+};
+
+template <bool W32, bool BUF, class Inner, class Masked>
 __device__ __forceinline__ void chunk_loop(const PairArgs& a, const GroupInfo& gi, int lane, Inner&& inner,
                                            Masked&& masked) {
+  const SourceLoader<W32, BUF> load(a);
   const int nch = gi.n_chunks, nin = gi.n_inner;
   const uint32_t i0 = list_entry(a, gi, 0, lane);
   uint32_t i1 = list_entry(a, gi, 1, lane);
-  double4 sA = a.xk[i0];
-  double wA = weight<W32>(a, i0);
+  double4 sA;
+  double wA;
+  load(i0, sA, wA);
   int c = 0;
   for (; c < nin; c += 2) {
-    const double4 sB = a.xk[i1];
-    const double wB = weight<W32>(a, i1);
+    double4 sB;
+    double wB;
+    load(i1, sB, wB);
     const uint32_t i2 = list_entry(a, gi, c + 2, lane);
     inner(c, sA, wA);
-    sA = a.xk[i2];
-    wA = weight<W32>(a, i2);
+    load(i2, sA, wA);
     i1 = list_entry(a, gi, c + 3, lane);
     inner(c + 1, sB, wB);
   }
   for (; c < nch; c += 2) {
-    const double4 sB = a.xk[i1];
-    const double wB = weight<W32>(a, i1);
+    double4 sB;
+    double wB;
+    load(i1, sB, wB);
     const uint32_t i2 = list_entry(a, gi, c + 2, lane);
     masked(c, sA, wA);
     if (c + 1 >= nch) break;
-    sA = a.xk[i2];
-    wA = weight<W32>(a, i2);
+    load(i2, sA, wA);
     i1 = list_entry(a, gi, c + 3, lane);
     masked(c + 1, sB, wB);
   }
@@ -281,7 +326,7 @@ __device__ __forceinline__ void direct_chunk(float& acc, const Tgt& t, const dou
   }
 }
 
-template <bool W32>
+template <bool W32, bool BUF>
 __device__ __forceinline__ void direct_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
   const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
@@ -291,7 +336,7 @@ __device__ __forceinline__ void direct_group(const PairArgs& a, const GroupInfo&
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
   const uint64_t* masks = a.mask + (gi.off >> 2);
   float acc = 0.0f;
-  chunk_loop<W32>(
+  chunk_loop<W32, BUF>(
       a, gi, lane,
       [&](int, const double4& sk, double wk) { direct_chunk<false>(acc, t, sk, wk, akx, aky, akz, nullptr); },
       [&](int c, const double4& sk, double wk) {
@@ -317,7 +362,7 @@ __device__ __forceinline__ Src expanded_source(const double4& sk, double wk, dou
   return s;
 }
 
-template <bool W32>
+template <bool W32, bool BUF>
 __device__ __forceinline__ void expanded_group(const PairArgs& a, const GroupInfo& gi, int64_t g, int lane) {
   const int row = lane >> 4, tl = lane & 15;
   const int64_t tid = g * kGroup + tl;
@@ -329,7 +374,7 @@ __device__ __forceinline__ void expanded_group(const PairArgs& a, const GroupInf
   const double akx = gi.ax * a.sqrt_k, aky = gi.ay * a.sqrt_k, akz = gi.az * a.sqrt_k;
   const uint64_t* masks = a.mask + (gi.off >> 2);
   float acc = 0.0f;
-  chunk_loop<W32>(
+  chunk_loop<W32, BUF>(
       a, gi, lane,
       [&](int, const double4& sk, double wk) {
         expanded_inner_chunk(acc, t, expanded_source(sk, wk, akx, aky, akz));
@@ -368,7 +413,7 @@ __device__ __forceinline__ GroupInfo load_group(const GroupInfo* gp) {
 // tail.
 constexpr int kPairWaves = 4;
 
-template <bool W32>
+template <bool W32, bool BUF>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -378,9 +423,9 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) 
   if (a.skip && *a.skip) return;
   const GroupInfo gi = load_group(a.groups + g);
   if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
-    expanded_group<W32>(a, gi, g, lane);
+    expanded_group<W32, BUF>(a, gi, g, lane);
   else
-    direct_group<W32>(a, gi, g, lane);
+    direct_group<W32, BUF>(a, gi, g, lane);
 }
 
 // ---- float64 ---------------------------------------------------------------
@@ -588,20 +633,17 @@ void pairsum_f32(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
   a.w32 = w32;
   const int64_t nb = ceil_div(ts.n_groups, kPairWaves);
   ProfScope prof(RBF_FP32, ts.kind, ts.useful, ts.list_entries * kGroup, s);
+  // buffer loads when the sources (32 B each) span less than 4 GiB
+  const bool buf = (c.m + 1) * (int64_t)sizeof(double4) < ((int64_t)1 << 32);
+  auto kernel = w32 ? (buf ? k_pairsum_f32<true, true> : k_pairsum_f32<true, false>)
+                    : (buf ? k_pairsum_f32<false, true> : k_pairsum_f32<false, false>);
   // a timed launch carries its events in the dispatch; an untimed one is a
   // plain launch (which a stream capture can record)
-  if (prof.start()) {
-    if (w32)
-      hipExtLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
-                            prof.stop(), 0, a);
-    else
-      hipExtLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(),
-                            prof.stop(), 0, a);
-  } else if (w32) {
-    hipLaunchKernelGGL(k_pairsum_f32<true>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(k_pairsum_f32<false>, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
-  }
+  if (prof.start())
+    hipExtLaunchKernelGGL(kernel, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, prof.start(), prof.stop(), 0,
+                          a);
+  else
+    hipLaunchKernelGGL(kernel, dim3((unsigned)nb), dim3(kPairWaves * kWave), 0, s, a);
   RBF_HIP(hipGetLastError());
   prof.done();
 }
