@@ -19,7 +19,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "paper_1305_5179_amd", "csrc", "pairsum.hip")
-# every instantiation of the kernel (float64 or float32 weights)
+# every instantiation of the kernel
 KERNEL = "_ZN3rbf12_GLOBAL__N_113k_pairsum_f32"
 TRANS = ("v_exp_f32", "v_log_f32", "v_rcp_f32", "v_rsq_f32", "v_sqrt_f32", "v_sin_f32", "v_cos_f32",
          "v_rcp_f64", "v_rsq_f64", "v_sqrt_f64", "v_rcp_iflag_f32")
@@ -60,7 +60,8 @@ def _kernel_bodies(tmp_path_factory, src, prefix):
 @pytest.fixture(scope="module")
 def f32_asm(tmp_path_factory):
     bodies = _kernel_bodies(tmp_path_factory, SRC, KERNEL)
-    assert len(bodies) == 2, [b[0] for b in bodies]
+    # float32 or float64 weights, buffer or flat loads
+    assert len(bodies) == 4, [b[0] for b in bodies]
     return bodies
 
 
