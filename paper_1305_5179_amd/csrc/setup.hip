@@ -587,7 +587,8 @@ __global__ __launch_bounds__(kThreads, LATTICE ? 1 : 8) void k_lists(const doubl
   __shared__ uint8_t cwhole_s[kThreads / kWave][kWave];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+  // neighbouring groups (which share candidate sources) on one XCD's L2
+  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (g >= G) return;
   uint32_t* q = qbuf[wave];
   const double4* tg = tpts + g * kGroup;
