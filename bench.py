@@ -16,14 +16,16 @@ Fields beside the step (all measured after the timed steps):
                 its dispatches during the timed steps) against the pair peak,
                 with its HBM bytes from the committed counter summary;
   phases, pairs setup / cycle / grid split, matvec times, pair counts;
-  schwarz, schwarz1024
+  schwarz, schwarz1024, schwarz_half, schwarz1024_half
                 the Schwarz preconditioner with blocks up to 192 and with
-                blocks of 64..1024: setup, local inverses, apply time and its
-                HBM fraction;
+                blocks of 64..1024, its local inverses in float32 and in
+                float16: setup, local inverses, apply time and its HBM
+                fraction;
   solve         the second half of the metric: setup -> solve -> grid to
                 relative residual 1e-8 (or 3,000 operator applications) for
                 the refinement (float32 and float64 Krylov basis), the same
-                with each Schwarz configuration, and the plain float64
+                with each Schwarz configuration (float32 and float16 local
+                inverses), and the plain float64
                 method; residual/time histories, stall levels, and time to
                 the lowest residual all reach with the speed-up over plain;
   signs         every pipeline's 256^3 grid against the plain method's on the
@@ -287,6 +289,8 @@ def main():
         phases[key] = 1e3 * (time.perf_counter() - t) / 5
     schwarz = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_192)
     schwarz1024 = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_1024)
+    schwarz_half = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_192_HALF)
+    schwarz1024_half = schwarz_measurement(rbf, ctx, torch, x, SCHWARZ_1024_HALF)
     dens = ctx.density()
     density = {"q": dens.q, "h_max": dens.h_max, "h": dens.h, "h_from": "sqrt(2) h_max (eq. hmax)",
                "sigma_sep": dens.sigma_sep, "sigma_fill": dens.sigma_fill, "sigma": sigma,
@@ -344,6 +348,8 @@ def main():
         "grid_kernel_f32": evaluation,
         "schwarz": schwarz,
         "schwarz1024": schwarz1024,
+        "schwarz_half": schwarz_half,
+        "schwarz1024_half": schwarz1024_half,
         "density": density,
         "fp64_kernel": {"launches": prof.launches[OP][F64],
                         "avg_launch_ms": prof.kernel_ms[OP][F64] / max(prof.launches[OP][F64], 1),
@@ -377,7 +383,8 @@ def schwarz_measurement(rbf, ctx, torch, x, opts):
     """The Schwarz preconditioner with the given options: setup time (the
     local inverses' own device time apart), and the time of one apply
     (gather, local products, sums, scatter) from torch events on the stream
-    the library runs on.  The apply streams the float32 local inverses once:
+    the library runs on.  The apply streams the local inverses (float32 or
+    float16) once:
     its algorithmic bytes are those plus the vector traffic (members
     gathered, local results written and summed, result written), against the
     8 TB/s of HBM."""
@@ -481,6 +488,9 @@ def cull_measurement(rbf, torch, pts, nrm, cloud, cfg, g, n_samples, epochs):
 # (0.3) and overlap (10 %)
 SCHWARZ_192 = dict(max_block=192)
 SCHWARZ_1024 = dict(max_block=1024, min_block=64)
+# the same with the local inverses stored in float16
+SCHWARZ_192_HALF = dict(max_block=192, half=1)
+SCHWARZ_1024_HALF = dict(max_block=1024, min_block=64, half=1)
 
 SOLVE_RUNS = (
     # name, mode, basis, Schwarz options (None: no preconditioner)
@@ -488,6 +498,8 @@ SOLVE_RUNS = (
     ("ir_fp32_basis64", "ir", "fp64", None),
     ("ir_fp32_schwarz", "ir", "fp32", SCHWARZ_192),
     ("ir_fp32_schwarz1024", "ir", "fp32", SCHWARZ_1024),
+    ("ir_fp32_schwarz_half", "ir", "fp32", SCHWARZ_192_HALF),
+    ("ir_fp32_schwarz1024_half", "ir", "fp32", SCHWARZ_1024_HALF),
     ("plain_fp64", "plain", "fp64", None),
 )
 

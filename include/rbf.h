@@ -93,7 +93,11 @@ typedef struct {
     int tune;          /* 1: time the apply kernel's launch shapes at setup and keep the
                           fastest (default); 0: the fixed shape (256 threads, 4 workgroups
                           per compute unit) */
-    int reserved;      /* must be 0 */
+    int half;          /* 1: the local inverses stored in float16 (half the apply's bytes; each
+                          entry then carries a relative rounding of at most 2^-11, and the
+                          apply's products and sums are float32; this changes the
+                          preconditioner, not the solution: the solver's residual stays the
+                          float64 one); 0: float32 entries, float64 sums (default) */
 } rbf_schwarz_opts;
 
 typedef struct {
@@ -104,7 +108,8 @@ typedef struct {
     int retries;           /* local blocks redone with a larger shift */
     double max_shift;      /* the largest shift a block ended with */
     int64_t min_members;   /* the smallest subdomain */
-    int apply_threads;     /* launch shape of the apply: threads per workgroup (rows per task) */
+    int apply_threads;     /* launch shape of the apply: threads per workgroup (rows per task:
+                              one per thread, two with half) */
     int apply_blocks;      /* and workgroups of its persistent launch */
     double factor_ms;      /* device time of the local inverses (all blocks, one launch) */
 } rbf_schwarz_info;

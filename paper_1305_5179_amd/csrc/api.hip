@@ -817,7 +817,7 @@ int rbf_default_schwarz_opts(rbf_schwarz_opts* o) {
   o->min_block = 0;
   o->shift = 0.3;
   o->tune = 1;
-  o->reserved = 0;
+  o->half = 0;
   return RBF_OK;
 }
 
@@ -833,7 +833,7 @@ int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream)
   if (o.tune != 0 && o.tune != 1) return fail(c, RBF_EINVAL, "tune must be 0 or 1");
   if (o.overlap_pct < 0 || o.overlap_pct > 100) return fail(c, RBF_EINVAL, "overlap_pct must be in 0..100");
   if (o.restricted != 0 && o.restricted != 1) return fail(c, RBF_EINVAL, "restricted must be 0 or 1");
-  if (o.reserved != 0) return fail(c, RBF_EINVAL, "reserved must be 0");
+  if (o.half != 0 && o.half != 1) return fail(c, RBF_EINVAL, "half must be 0 or 1");
   if (!(o.shift >= 0.0) || !std::isfinite(o.shift)) return fail(c, RBF_EINVAL, "shift must be finite and >= 0");
   if (3 + schwarz_overlap_count(3, o.overlap_pct) > o.max_block)
     return fail(c, RBF_EINVAL, "max_block too small for one point and its overlap");
@@ -842,7 +842,8 @@ int rbf_schwarz_setup(rbf_ctx* c, const rbf_schwarz_opts* opts_in, void* stream)
     drop_cycle_graph(c);        // it may hold the old preconditioner's launches
     free_schwarz(c->schwarz);   // stream-ordered release: queued work on this stream finishes first
     c->schwarz = nullptr;
-    c->schwarz = schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, s);
+    c->schwarz =
+        schwarz_setup(*c, o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, o.half != 0, s);
     RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;
   });
@@ -876,7 +877,7 @@ int rbf_schwarz_get_info(const rbf_ctx* c, rbf_schwarz_info* out) {
   }
   out->max_members = maxn;
   out->min_members = minn;
-  out->inverse_bytes = d.w_total * (int64_t)sizeof(float);
+  out->inverse_bytes = d.w_total * (int64_t)(d.half ? sizeof(_Float16) : sizeof(float));
   out->retries = d.retries;
   out->max_shift = d.max_shift;
   out->apply_threads = d.apply_threads;

@@ -84,16 +84,19 @@ __host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt
 
 // The overlapping Schwarz preconditioner (schwarz.hip).  Subdomain i has
 // members mem[mem_off[i] .. mem_off[i+1]) (sorted positions), its ncore[i]
-// core centres first; its local inverse is W[woff[i] ..], float32, n x n.
+// core centres first; its local inverse is W[woff[i] ..], float32, n x n, or
+// with `half` W16[woff[i] ..], float16, n rows of ld = n rounded up to even
+// entries (the pad entry of odd n unused).
 constexpr int kSchwarzMaxBlock = 1024;   // largest subdomain (core + overlap centres)
 constexpr int kSchwarzDefaultBlock = 192;
 struct SchwarzData {
   int64_t nsub = 0, nmem = 0, w_total = 0;
   int restricted = 0, max_block = 0, pct = 0, retries = 0;
+  bool half = false;
   double shift = 0, max_shift = 0, factor_ms = 0;
   // the apply's persistent launch: tasks (subdomain, first row) of
-  // apply_threads rows each, largest first, taken cyclically by apply_blocks
-  // workgroups
+  // apply_threads rows each (twice as many with `half`), largest first, taken
+  // cyclically by apply_blocks workgroups
   int apply_threads = 256, apply_blocks = 0;
   int64_t ntask = 0;
   int2* tasks = nullptr;
@@ -102,6 +105,7 @@ struct SchwarzData {
   uint32_t* mem = nullptr;
   int64_t* woff = nullptr;
   float* W = nullptr;
+  _Float16* W16 = nullptr;
   double* Y = nullptr;          // additive form: the local solutions, by member slot
   int64_t* occ_off = nullptr;   // additive form: the member slots of every centre
   int64_t* occ_slot = nullptr;
@@ -371,7 +375,7 @@ void launch_step_rate(bool masked, float* out, int blocks, int iters, hipStream_
 int schwarz_overlap_count(int ncore, int pct);
 int schwarz_core_cap(int max_block, int pct);
 SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, int min_block, double shift,
-                           int tune, hipStream_t s);
+                           int tune, bool half, hipStream_t s);
 void schwarz_apply(const Ctx& c, const SchwarzData& d, const double* r, double* z, hipStream_t s,
                    const int* skip = nullptr);
 void schwarz_apply_f32(const Ctx& c, const SchwarzData& d, const float* r, float* z, hipStream_t s,

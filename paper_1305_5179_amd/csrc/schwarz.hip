@@ -278,7 +278,8 @@ struct FacArgs {
   double two_s2;            // 2 sigma^2
   double shift;
   int max_retry;
-  float* W;
+  float* W;                 // float32 inverses, or null
+  _Float16* W16;            // float16 inverses (rows of even length), or null
   double* shift_used;
   int32_t* retries;
   int* failed;
@@ -595,13 +596,25 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
     __syncthreads();
     // W = -(swept matrix), full n x n; the lower triangle holds the result:
     // read along its rows, each entry stored at (i, j) and (j, i)
-    float* W = a.W + a.woff[sub];
-    for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
-      const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-      if (j > i) continue;
-      const float v = ok ? (float)(-big[e]) : 0.0f;
-      W[e] = v;
-      W[(int64_t)j * n + i] = v;
+    if (a.W16) {
+      _Float16* W = a.W16 + a.woff[sub];
+      const int ld = (n + 1) & ~1;
+      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j > i) continue;
+        const _Float16 v = ok ? (_Float16)(float)(-big[e]) : (_Float16)0.0f;
+        W[(int64_t)i * ld + j] = v;
+        W[(int64_t)j * ld + i] = v;
+      }
+    } else {
+      float* W = a.W + a.woff[sub];
+      for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j > i) continue;
+        const float v = ok ? (float)(-big[e]) : 0.0f;
+        W[e] = v;
+        W[(int64_t)j * n + i] = v;
+      }
     }
     if (tid == 0) {
       a.shift_used[sub] = shift;
@@ -621,7 +634,8 @@ struct ApplyArgs {
   const int32_t* ncore;
   const uint32_t* mem;
   const int64_t* woff;
-  const float* W;
+  const float* W;           // float32 inverses (n x n), or
+  const _Float16* W16;      // float16 inverses (n rows of even length)
   const void* r;            // float64, or float32 with F32
   void* out;                // restricted: z (sorted order; float32 with F32); additive: the local solutions
                             // by member slot (float64)
@@ -634,10 +648,11 @@ struct ApplyArgs {
 // consecutive lanes, consecutive addresses).  The restricted form scatters
 // the core rows (the cores partition the centres); the additive form stores
 // every row by member slot.
-template <bool RESTRICTED, int T, bool F32>
+template <bool RESTRICTED, int T, bool F32, bool HALF>
 __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
   if (a.skip && *a.skip) return;
   __shared__ double rl[kSchwarzMaxBlock];
+  float* rlf = reinterpret_cast<float*>(rl);   // the float32 copy of the HALF form
   const int tid = threadIdx.x;
   for (int64_t t = blockIdx.x; t < a.ntask; t += gridDim.x) {
     const int2 task = a.tasks[t];
@@ -645,30 +660,75 @@ __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
     const int64_t off = a.mem_off[sub];
     const int n = (int)(a.mem_off[sub + 1] - off);
     __syncthreads();   // the previous task is done with rl
-    for (int p = tid; p < n; p += T)
-      rl[p] = F32 ? (double)static_cast<const float*>(a.r)[a.mem[off + p]]
-                  : static_cast<const double*>(a.r)[a.mem[off + p]];
+    for (int p = tid; p < n; p += T) {
+      const double v = F32 ? (double)static_cast<const float*>(a.r)[a.mem[off + p]]
+                           : static_cast<const double*>(a.r)[a.mem[off + p]];
+      if (HALF)
+        rlf[p] = (float)v;
+      else
+        rl[p] = v;
+    }
     __syncthreads();
     const int rows = RESTRICTED ? a.ncore[sub] : n;
-    const int row = task.y + tid;
-    if (row >= rows) continue;
-    const float* w = a.W + a.woff[sub] + row;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = 0;
-    for (; b + 4 <= n; b += 4) {
-      a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
-      a1 = fma((double)w[(int64_t)(b + 1) * n], rl[b + 1], a1);
-      a2 = fma((double)w[(int64_t)(b + 2) * n], rl[b + 2], a2);
-      a3 = fma((double)w[(int64_t)(b + 3) * n], rl[b + 3], a3);
+    auto store = [&](int row, double y) {
+      if (RESTRICTED && F32)
+        static_cast<float*>(a.out)[a.mem[off + row]] = (float)y;
+      else if (RESTRICTED)
+        static_cast<double*>(a.out)[a.mem[off + row]] = y;
+      else
+        static_cast<double*>(a.out)[off + row] = y;
+    };
+    if constexpr (HALF) {
+      // two rows per lane, read as one 4-byte pair per column (rows of even
+      // length: 4-byte aligned; the pad entry of an odd block feeds a row
+      // that is not stored); float32 products and sums (their rounding, at
+      // most n u32 <= 2^-14, is below the float16 entries' own), each a
+      // mixed-precision FMA on the float16 entry
+      const int row = task.y + 2 * tid;
+      if (row >= rows) continue;
+      const int ld = (n + 1) & ~1;
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(a.W16 + a.woff[sub] + row);
+      // 16 columns' loads in flight per wave before the first is used
+      constexpr int kU = 16;
+      float e[4] = {0.f, 0.f, 0.f, 0.f}, o[4] = {0.f, 0.f, 0.f, 0.f};
+      int b = 0;
+      for (; b + kU <= n; b += kU) {
+        uint32_t v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = w[(int64_t)(b + u) * (ld / 2)];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const float r = rlf[b + u];
+          e[u & 3] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)v[u]), r, e[u & 3]);
+          o[u & 3] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(v[u] >> 16)), r, o[u & 3]);
+        }
+      }
+      for (; b < n; ++b) {
+        const uint32_t v = w[(int64_t)b * (ld / 2)];
+        const float r = rlf[b];
+        e[0] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)v), r, e[0]);
+        o[0] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)), r, o[0]);
+      }
+      store(row, (double)((e[0] + e[1]) + (e[2] + e[3])));
+      if (row + 1 < rows) store(row + 1, (double)((o[0] + o[1]) + (o[2] + o[3])));
+    } else {
+      const int row = task.y + tid;
+      if (row >= rows) continue;
+      const float* w = a.W + a.woff[sub] + row;
+      // 16 columns' loads in flight per wave before the first is used
+      constexpr int kU = 16;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      int b = 0;
+      for (; b + kU <= n; b += kU) {
+        float v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = w[(int64_t)(b + u) * n];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc[u & 3] = fma((double)v[u], rl[b + u], acc[u & 3]);
+      }
+      for (; b < n; ++b) acc[0] = fma((double)w[(int64_t)b * n], rl[b], acc[0]);
+      store(row, (acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
-    for (; b < n; ++b) a0 = fma((double)w[(int64_t)b * n], rl[b], a0);
-    const double y = (a0 + a1) + (a2 + a3);
-    if (RESTRICTED && F32)
-      static_cast<float*>(a.out)[a.mem[off + row]] = (float)y;
-    else if (RESTRICTED)
-      static_cast<double*>(a.out)[a.mem[off + row]] = y;
-    else
-      static_cast<double*>(a.out)[off + row] = y;
   }
 }
 
@@ -738,7 +798,8 @@ int schwarz_core_cap(int max_block, int pct) {
 
 void free_schwarz(SchwarzData* d) {
   if (!d) return;
-  for (void* p : {(void*)d->mem_off, (void*)d->ncore, (void*)d->mem, (void*)d->woff, (void*)d->W, (void*)d->Y,
+  for (void* p : {(void*)d->mem_off, (void*)d->ncore, (void*)d->mem, (void*)d->woff, (void*)d->W, (void*)d->W16,
+                  (void*)d->Y,
                   (void*)d->occ_off, (void*)d->occ_slot, (void*)d->z, (void*)d->t, (void*)d->z32})
     dfree(p);
   dfree(d->tasks);
@@ -749,7 +810,9 @@ namespace {
 
 // The tasks of the apply for strips of T rows: (subdomain, first row), by
 // decreasing work (rows x block size), ties by subdomain and row.
-std::vector<int2> apply_tasks(const SchwarzData& d, int T) {
+std::vector<int2> apply_tasks(const SchwarzData& d, int threads) {
+  // rows per task: one per thread, two with float16 inverses
+  const int T = d.half ? 2 * threads : threads;
   std::vector<std::pair<int64_t, int2>> t;
   for (int64_t i = 0; i < d.nsub; ++i) {
     const int n = (int)(d.h_mem_off[i + 1] - d.h_mem_off[i]);
@@ -762,35 +825,45 @@ std::vector<int2> apply_tasks(const SchwarzData& d, int T) {
   return out;
 }
 
-template <bool F32>
-void launch_local_t(const SchwarzData& d, int T, const dim3& g, const ApplyArgs& aa, hipStream_t s) {
-  if (d.restricted) {
-    if (T == 512)
-      hipLaunchKernelGGL((k_schwarz_local<true, 512, F32>), g, dim3(512), 0, s, aa);
-    else
-      hipLaunchKernelGGL((k_schwarz_local<true, 256, F32>), g, dim3(256), 0, s, aa);
-  } else {
-    if (T == 512)
-      hipLaunchKernelGGL((k_schwarz_local<false, 512, F32>), g, dim3(512), 0, s, aa);
-    else
-      hipLaunchKernelGGL((k_schwarz_local<false, 256, F32>), g, dim3(256), 0, s, aa);
-  }
+template <bool RESTRICTED, bool F32, bool HALF>
+void launch_local_t(int T, const dim3& g, const ApplyArgs& aa, hipStream_t s) {
+  if (T == 512)
+    hipLaunchKernelGGL((k_schwarz_local<RESTRICTED, 512, F32, HALF>), g, dim3(512), 0, s, aa);
+  else if (T == 256)
+    hipLaunchKernelGGL((k_schwarz_local<RESTRICTED, 256, F32, HALF>), g, dim3(256), 0, s, aa);
+  else
+    hipLaunchKernelGGL((k_schwarz_local<RESTRICTED, 128, F32, HALF>), g, dim3(128), 0, s, aa);
   RBF_HIP(hipGetLastError());
+}
+template <bool RESTRICTED, bool F32>
+void launch_local_h(const SchwarzData& d, int T, const dim3& g, const ApplyArgs& aa, hipStream_t s) {
+  if (d.half)
+    launch_local_t<RESTRICTED, F32, true>(T, g, aa, s);
+  else
+    launch_local_t<RESTRICTED, F32, false>(T, g, aa, s);
 }
 
 // f32: r is float32, and the restricted form writes out in float32.
 void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, int64_t ntask, const void* r,
                   void* out, hipStream_t s, const int* skip, bool f32 = false) {
-  const ApplyArgs aa{tasks, ntask, d.mem_off, d.ncore, d.mem, d.woff, d.W, r, out, skip};
+  const ApplyArgs aa{tasks, ntask, d.mem_off, d.ncore, d.mem, d.woff, d.W, d.W16, r, out, skip};
   const dim3 g((unsigned)std::max(blocks, 1));
-  if (f32)
-    launch_local_t<true>(d, T, g, aa, s);
-  else
-    launch_local_t<false>(d, T, g, aa, s);
+  if (d.restricted) {
+    if (f32)
+      launch_local_h<true, true>(d, T, g, aa, s);
+    else
+      launch_local_h<true, false>(d, T, g, aa, s);
+  } else {
+    if (f32)
+      launch_local_h<false, true>(d, T, g, aa, s);
+    else
+      launch_local_h<false, false>(d, T, g, aa, s);
+  }
 }
 
-// The apply's launch shape: strips of 256 or 512 rows, taken by 2, 4 or 8
-// workgroups per compute unit or by one workgroup per task.  The two task
+// The apply's launch shape: workgroups of 128, 256 or 512 threads (strips of
+// as many rows, twice as many with float16 inverses), taken by 2, 4 or 8
+// workgroups per compute unit or by one workgroup per task.  The three task
 // lists are built and uploaded once; after one untimed apply every candidate
 // runs once between its own pair of events, all back to back (the work and
 // the result do not depend on the values), and the host waits once; the
@@ -800,16 +873,18 @@ void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
     int T, mult, blocks;
     hipEvent_t e0, e1;
   };
-  const int Ts[2] = {256, 512};
-  int2* dt[2];
-  int64_t nt[2];
-  for (int k = 0; k < 2; ++k) {
+  constexpr int kShapes = 3;
+  const int Ts[kShapes] = {128, 256, 512};
+  int2* dt[kShapes];
+  int64_t nt[kShapes];
+  for (int k = 0; k < kShapes; ++k) {
     std::vector<int2> ht = apply_tasks(d, Ts[k]);
     dt[k] = upload(ht, s);
     nt[k] = (int64_t)ht.size();
   }
+  auto shape = [&](int T) { return T == Ts[0] ? 0 : T == Ts[1] ? 1 : 2; };
   std::vector<Cand> cands;
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < kShapes; ++k)
     for (int mult : {2, 4, 8, 0}) {
       Cand c{Ts[k], mult, 0, nullptr, nullptr};
       c.blocks = mult > 0 ? (int)std::min<int64_t>((int64_t)mult * cus, nt[k]) : (int)nt[k];
@@ -818,7 +893,7 @@ void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
   double* out = d.restricted ? d.z : d.Y;
   launch_local(d, cands[0].T, cands[0].blocks, dt[0], nt[0], d.t, out, s, nullptr);   // warm-up
   for (Cand& c : cands) {
-    const int k = c.T == Ts[0] ? 0 : 1;
+    const int k = shape(c.T);
     RBF_HIP(hipEventCreate(&c.e0));
     RBF_HIP(hipEventCreate(&c.e1));
     RBF_HIP(hipEventRecord(c.e0, s));
@@ -838,11 +913,12 @@ void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
     RBF_HIP(hipEventDestroy(cands[i].e0));
     RBF_HIP(hipEventDestroy(cands[i].e1));
   }
-  const int k = cands[pick].T == Ts[0] ? 0 : 1;
+  const int k = shape(cands[pick].T);
   dfree(d.tasks);
   d.tasks = dt[k];
   d.ntask = nt[k];
-  dfree(dt[1 - k]);
+  for (int j = 0; j < kShapes; ++j)
+    if (j != k) dfree(dt[j]);
   d.apply_threads = cands[pick].T;
   d.apply_blocks = cands[pick].blocks;
 }
@@ -891,7 +967,7 @@ __global__ void k_members_sorted(const uint32_t* __restrict__ mem_paper, int64_t
 }  // namespace
 
 SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted, int min_block, double shift,
-                           int tune, hipStream_t s) {
+                           int tune, bool half, hipStream_t s) {
   const int64_t n = c.n, m = c.m;
   const int cap = schwarz_core_cap(max_block, pct);
   // 1. root cube of the surface points and their Hilbert order on it
@@ -1083,6 +1159,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
   SchwarzData* d = new SchwarzData();
   d->nsub = nsub;
   d->restricted = restricted;
+  d->half = half;
   d->shift = shift;
   d->max_block = max_block;
   d->pct = pct;
@@ -1100,7 +1177,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     d->h_mem_off[i + 1] = d->h_mem_off[i] + nb;
     d->h_ncore[i] = nc;
     woff[i] = wtotal;
-    wtotal += nb * nb;
+    wtotal += nb * (half ? (nb + 1) / 2 * 2 : nb);
     order[i] = (int32_t)i;
   }
   d->nmem = d->h_mem_off[nsub];
@@ -1121,7 +1198,10 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     dfree(d_paper);
   }
   d->woff = upload(woff, s);
-  d->W = dalloc<float>(std::max<int64_t>(wtotal, 1));
+  if (half)
+    d->W16 = dalloc<_Float16>(std::max<int64_t>(wtotal, 2));
+  else
+    d->W = dalloc<float>(std::max<int64_t>(wtotal, 1));
   d->w_total = wtotal;
   if (!restricted) {
     // counts (m + 1 entries, the last 0), their exclusive scan, the fill
@@ -1167,7 +1247,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     const int64_t big_stride = maxn * maxn + 2 * kPanel * maxn;
     double* big = talloc<double>(big_stride * grid);
     FacArgs fa{c.xs, d->mem_off, d->mem, d_order, nsub, d->woff, 2.0 * c.sigma * c.sigma, shift, 8,
-               d->W, d_shift, d_retries, d_flags + 1, d_flags, big, maxn, big_stride};
+               d->W, d->W16, d_shift, d_retries, d_flags + 1, d_flags, big, maxn, big_stride};
     hipEvent_t e0, e1;
     RBF_HIP(hipEventCreate(&e0));
     RBF_HIP(hipEventCreate(&e1));

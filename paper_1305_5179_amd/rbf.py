@@ -41,7 +41,7 @@ class SolveOpts(C.Structure):
 
 class SchwarzOpts(C.Structure):
     _fields_ = [("max_block", C.c_int), ("overlap_pct", C.c_int), ("restricted", C.c_int),
-                ("min_block", C.c_int), ("shift", C.c_double), ("tune", C.c_int), ("reserved", C.c_int)]
+                ("min_block", C.c_int), ("shift", C.c_double), ("tune", C.c_int), ("half", C.c_int)]
 
 
 class SchwarzInfo(C.Structure):

@@ -53,7 +53,7 @@ def test_default_schwarz_options():
     o = rbf.SchwarzOpts()
     lib = rbf.load_library()
     assert lib.rbf_default_schwarz_opts(C.byref(o)) == rbf.RBF_OK
-    assert (o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, o.reserved) == (192, 10, 0, 0, 0.3, 1, 0)
+    assert (o.max_block, o.overlap_pct, o.restricted, o.min_block, o.shift, o.tune, o.half) == (192, 10, 0, 0, 0.3, 1, 0)
     assert lib.rbf_default_schwarz_opts(None) == rbf.RBF_EINVAL
 
 

@@ -6,7 +6,11 @@ C ABI, against the CPU oracle (oracle/schwarz.py) on the same seeded inputs.
   * z = M^{-1} r: the device inverts each block in float64 and keeps the
     inverse in float32, so |z_gpu - z_oracle|_j <= 4 u32 sum_i sum_b
     |(A_i + shift I)^{-1}_{jb}| |r_b| (the oracle's own inverses give the
-    bound) plus a float64 term;
+    bound) plus a float64 term; with `half` in float16, every entry rounded
+    once (relative 2^-11, absolute 2^-25 below the normal range), and the
+    products and sums in float32 (at most n u32 <= 2^-14 relative for blocks
+    up to 1024), so |z_gpu - z_oracle|_j <= 2 u16 sum_i sum_b (|inv_{jb}| +
+    2^-13) |r_b|;
   * the preconditioned solve: the float64 residual the library reports is
     the oracle's, and on a small well-conditioned system the weights match
     LU to 1e-5.
@@ -80,7 +84,12 @@ OPTS = {
     # the merge of small leaves; mixed sizes in one launch
     "large_merged": dict(max_block=1024, min_block=64),
     "mixed_restricted": dict(max_block=600, min_block=200, restricted=1),
+    # the inverses in float16 (rows of even length; odd blocks occur)
+    "default_half": dict(half=1),
+    "restricted_half": dict(restricted=1, overlap_pct=30, half=1),
+    "large_half": dict(max_block=1024, min_block=64, half=1),
 }
+U16 = 2.0 ** -11
 
 
 def _subs_key(subs):
@@ -111,6 +120,7 @@ def built(torch, R):
 def _oracle_opts(optname):
     d = dict(max_block=192, overlap_pct=10, restricted=0, shift=0.3, min_block=0)
     d.update(OPTS[optname])
+    d.pop("half", None)
     return d
 
 
@@ -144,12 +154,12 @@ def test_subdomains_are_the_oracles(built, name, optname):
         assert np.array_equal(g[k0][1], want), (k0, g[k0][1][:8], want[:8])
 
 
-def _apply_bound(X, subs, sigma, shift, r, restricted):
-    """sum_i sum_b |inv_i[j, b]| |r_b| over the subdomains i holding j."""
+def _apply_bound(X, subs, sigma, shift, r, restricted, floor=0.0):
+    """sum_i sum_b (|inv_i[j, b]| + floor) |r_b| over the subdomains i holding j."""
     B = np.zeros(len(X))
     for core, ov in subs:
         mem = np.concatenate([core, ov])
-        inv = np.abs(np.linalg.inv(S.local_matrix(X, mem, sigma, shift)))
+        inv = np.abs(np.linalg.inv(S.local_matrix(X, mem, sigma, shift))) + floor
         rows = core.size if restricted else mem.size
         B[mem[:rows]] += inv[:rows] @ np.abs(r[mem])
     return B
@@ -166,11 +176,13 @@ def test_apply_matches_the_oracle(torch, built, name, optname):
     z = host(ctx.schwarz_apply(dev(torch, r)))
     torch.cuda.synchronize()
     want = S.schwarz_apply(X, subs, sigma, oo["shift"], r, restricted=bool(oo["restricted"]))
-    B = _apply_bound(X, subs, sigma, oo["shift"], r, bool(oo["restricted"]))
+    half = OPTS[optname].get("half", 0) == 1
+    B = _apply_bound(X, subs, sigma, oo["shift"], r, bool(oo["restricted"]), floor=2.0 ** -13 if half else 0.0)
     err = np.abs(z - want)
-    tol = 4 * U32 * B + 1e-12 * np.abs(want).max()
+    tol = (2 * U16 if half else 4 * U32) * B + 1e-12 * np.abs(want).max()
     assert np.all(np.isfinite(z))
     worst = int(np.argmax(err / tol))
+    _say(f"[schwarz] apply {name} {optname}: max err / bound {(err / tol).max():.3f}")
     assert np.all(err <= tol), (worst, err[worst], tol[worst], (err / (U32 * B)).max())
 
 
@@ -223,9 +235,12 @@ def test_apply_small_shift_and_torus_sample(torch, R, max_block):
         ctx.close()
 
 
-def test_preconditioned_solve_small_well_conditioned(torch, R):
+@pytest.mark.parametrize("half", [0, 1])
+def test_preconditioned_solve_small_well_conditioned(torch, R, half):
     """A small sphere with sigma below the spacing: the preconditioned IR
-    solve reaches 1e-12 and its weights match LU to 1e-5."""
+    solve reaches 1e-12 and its weights match LU to 1e-5 (with float32 or
+    float16 local inverses: the preconditioner changes, the residual the
+    solver stops on is the float64 one)."""
     c = w.sphere(300, 3)
     eps, sigma = 0.08, 0.06
     X, b = o.extended_centres(c.points, c.normals, eps)
@@ -234,7 +249,7 @@ def test_preconditioned_solve_small_well_conditioned(torch, R):
     c_lu = np.linalg.solve(A, b)
     ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), eps, sigma, math.inf)
     try:
-        ctx.schwarz_setup(max_block=60, overlap_pct=20)
+        ctx.schwarz_setup(max_block=60, overlap_pct=20, half=half)
         for mode in (R.RBF_SOLVE_IR_FP32, R.RBF_SOLVE_PLAIN_FP64):
             _say(f"[schwarz] solve sphere300 mode {mode}")
             cw, res = ctx.solve(tol=1e-12, mode=mode, precond=R.RBF_PRECOND_SCHWARZ, max_iters=3000)
@@ -272,7 +287,7 @@ def test_setup_rejects_bad_options(torch, R):
     ctx = R.Rbf(dev(torch, c.points), dev(torch, c.normals), 0.01, 0.05, math.inf)
     try:
         for bad in (dict(max_block=2), dict(max_block=1025), dict(overlap_pct=-1), dict(overlap_pct=101),
-                    dict(restricted=2), dict(reserved=1), dict(shift=-1.0), dict(shift=float("nan")),
+                    dict(restricted=2), dict(half=2), dict(shift=-1.0), dict(shift=float("nan")),
                     dict(max_block=3, overlap_pct=10), dict(min_block=-1), dict(max_block=100, min_block=101),
                     dict(tune=2)):
             with pytest.raises(R.RbfError) as e:
