@@ -272,9 +272,14 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     bounding_box(c->xpaper, c->m, box, box + 6, s);
     int hf[2] = {0, 0};
     double hb[6];
-    RBF_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipStreamSynchronize(s));
+    {
+      PinnedSlots rb(7);   // the two flags in slot 0, the box in slots 1..6
+      RBF_HIP(hipMemcpyAsync(rb.p, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipMemcpyAsync(rb.p + 1, box, sizeof(hb), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipStreamSynchronize(s));
+      std::memcpy(hf, rb.p, sizeof(hf));
+      std::memcpy(hb, rb.p + 1, sizeof(hb));
+    }
     temp_free(flags);
     temp_free(box);
     if (hf[0]) return fail(c, RBF_EINVAL, "points or normals contain NaN or Inf");
@@ -293,7 +298,8 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     c->xk = dalloc<double4>(c->m + 1);
     gather_sorted(c->xpaper, c->perm, c->m, c->sqrt_k, c->xs, c->xk, s);
     // 5. coarse cells
-    int64_t* ncell_parts = pinned_slots();
+    PinnedSlots late(3);   // read after the final wait: the cell count's two parts, the inner entries
+    int64_t* ncell_parts = late.p;
     ncell_parts[0] = ncell_parts[1] = 0;
     if (std::isfinite(cutoff)) {
       build_cells(c->keys, c->xs, c->m, c->lat, &c->cell_start, &c->cell_count, &c->cell_map, &c->cell_xyz,
@@ -304,7 +310,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     TargetSet& ts = c->centres;
     ts.dense = !std::isfinite(cutoff);
     centre_targets(*c, ts, s);
-    build_lists(*c, ts, s);
+    build_lists(*c, ts, s, late.p + 2);
     // 7. work vectors
     c->vin = dalloc<double>(c->mpad);
     c->vout = dalloc<double>(c->mpad);
@@ -312,6 +318,7 @@ int rbf_setup(const double* points, const double* normals, int64_t n, double off
     RBF_HIP(hipMemsetAsync(c->vout, 0, sizeof(double) * c->mpad, s));
     RBF_HIP(hipStreamSynchronize(s));
     c->n_cells = ncell_parts[0] + ncell_parts[1];
+    ts.inner_entries = late.p[2];
     return RBF_OK;
   });
   if (st != RBF_OK) {

@@ -300,8 +300,25 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
 // has been synchronised.
 void build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
                  int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, int64_t* ncell_parts, hipStream_t s);
-int64_t* pinned_slots();
-void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s);
+// Pinned host slots of the calling thread for small read-backs.  A copy into
+// pinned memory is queued without a wait of its own (a copy into pageable
+// memory waits for the stream), so several values cost one wait; they are
+// there once the stream has been synchronised.  Slots come from a
+// per-thread stack of kPinnedSlots and go back when the holder ends
+// (holders nest, last in first out).
+constexpr int kPinnedSlots = 64;
+struct PinnedSlots {
+  explicit PinnedSlots(int count);
+  ~PinnedSlots();
+  PinnedSlots(const PinnedSlots&) = delete;
+  PinnedSlots& operator=(const PinnedSlots&) = delete;
+  int64_t* p;
+  int n;
+};
+// The source lists of a target set.  inner_slot (pinned, or null): where
+// the count of inner-chunk entries is queued for the caller to read after
+// its own synchronisation; null: read here, with a wait.
+void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s, int64_t* inner_slot = nullptr);
 constexpr int64_t kCellSatMax = int64_t(1) << 26;   // entries of the summed cell counts (512 MB)
 int64_t* build_cell_sat(const Ctx& c, hipStream_t s);
 void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_t M, TargetSet& ts, hipStream_t s);

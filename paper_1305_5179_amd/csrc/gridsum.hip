@@ -414,11 +414,11 @@ int64_t compact_tiles(int64_t* ws, const SlotSpace& S, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_compact, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, tmask, pos, S,
                      compact_tiles_out(ws, S), compact_masks_out(ws, S));
   RBF_HIP(hipGetLastError());
-  int64_t last_pos = 0, last_flag = 0;
-  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_flag, flag + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PinnedSlots last(2);
+  RBF_HIP(hipMemcpyAsync(last.p, pos + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(last.p + 1, flag + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
-  return last_pos + last_flag;
+  return last.p[0] + last.p[1];
 }
 
 }  // namespace

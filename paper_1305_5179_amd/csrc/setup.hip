@@ -1095,14 +1095,27 @@ void gather_sorted(const double* pts3, const uint32_t* perm, int64_t m, double s
   RBF_HIP(hipGetLastError());
 }
 
-// Pinned host slots of the calling thread for values read back without a
-// wait of their own: the copy is queued, and the value is there once the
-// stream has been synchronised.
-int64_t* pinned_slots() {
-  static thread_local int64_t* p = nullptr;
-  if (!p) RBF_HIP(hipHostMalloc((void**)&p, 8 * sizeof(int64_t), hipHostMallocDefault));
-  return p;
+namespace {
+struct PinnedStack {
+  int64_t* base = nullptr;   // kPinnedSlots slots, kept until the thread ends
+  int top = 0;
+};
+PinnedStack& pinned_stack() {
+  static thread_local PinnedStack st;
+  if (!st.base) RBF_HIP(hipHostMalloc((void**)&st.base, kPinnedSlots * sizeof(int64_t), hipHostMallocDefault));
+  return st;
 }
+}  // namespace
+
+PinnedSlots::PinnedSlots(int count) : p(nullptr), n(0) {
+  PinnedStack& st = pinned_stack();
+  if (count < 0 || st.top + count > kPinnedSlots)
+    throw Error{RBF_EDEVICE, "pinned read-back slots exhausted (internal error)"};
+  p = st.base + st.top;
+  n = count;
+  st.top += count;
+}
+PinnedSlots::~PinnedSlots() { pinned_stack().top -= n; }
 
 void build_cells(const uint32_t* keys, const double4* xs, int64_t m, const Lattice& lat, int32_t** cell_start,
                  int32_t** cell_count, int32_t** cell_map, int32_t** cell_xyz, int64_t* ncell_parts, hipStream_t s) {
@@ -1141,12 +1154,12 @@ void group_targets(const Ctx& c, const double4* sp, const uint32_t* orig, int64_
   hipLaunchKernelGGL(k_group_greedy, dim3(gblocks), dim3(kThreads), 0, s, sp, M, E * E, gcount, local_slot);
   RBF_HIP(hipGetLastError());
   scan_exclusive_i64(gcount, goff, nseg, s);
-  int64_t last_off = 0, last_cnt = 0;
-  RBF_HIP(hipMemcpyAsync(&last_off, goff + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_cnt, gcount + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PinnedSlots last(2);
+  RBF_HIP(hipMemcpyAsync(last.p, goff + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(last.p + 1, gcount + (nseg - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
   ts.n_targets = M;
-  ts.n_groups = last_off + last_cnt;
+  ts.n_groups = last.p[0] + last.p[1];
   const int64_t total = ts.n_groups * kGroup;
   ts.pts = set_alloc<double4>(ts, total);
   ts.index = set_alloc<int64_t>(ts, total);
@@ -1211,7 +1224,7 @@ void fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 // Builds ts.groups / ts.list for the targets in ts.pts (n_groups*16 points).
-void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
+void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s, int64_t* inner_slot) {
   const int64_t G = ts.n_groups;
   ts.groups = set_alloc<GroupInfo>(ts, G);
   ts.owned.push_back(ts.groups);
@@ -1247,11 +1260,14 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
                          (uint32_t*)nullptr, (uint32_t*)nullptr, (uint16_t*)nullptr, (int*)nullptr);
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(bnd, soff, G, s);
-    int64_t last_soff = 0, last_bnd = 0;
-    RBF_HIP(hipMemcpyAsync(&last_soff, soff + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(&last_bnd, bnd + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipStreamSynchronize(s));
-    const int64_t staged = last_soff + last_bnd;
+    int64_t staged = 0;
+    {
+      PinnedSlots last(2);
+      RBF_HIP(hipMemcpyAsync(last.p, soff + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipMemcpyAsync(last.p + 1, bnd + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipStreamSynchronize(s));
+      staged = last.p[0] + last.p[1];
+    }
     uint32_t* slist = talloc<uint32_t>(staged);
     uint16_t* smask = talloc<uint16_t>(staged);
     int* overflow = talloc<int>(1);
@@ -1271,13 +1287,20 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     RBF_HIP(hipGetLastError());
     scan_exclusive_i64(len, off, G, s);
     sum_i64(use, G, tmp, s);
-    int64_t last_off = 0, last_len = 0;
-    int overflowed = 0;
-    RBF_HIP(hipMemcpyAsync(&last_off, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(&last_len, len + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(&ts.useful, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipMemcpyAsync(&overflowed, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
-    RBF_HIP(hipStreamSynchronize(s));
+    int64_t last_off = 0, last_len = 0, overflowed = 0;
+    {
+      PinnedSlots v(4);
+      v.p[3] = 0;
+      RBF_HIP(hipMemcpyAsync(v.p, off + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipMemcpyAsync(v.p + 1, len + (G - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipMemcpyAsync(v.p + 2, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipMemcpyAsync(v.p + 3, overflow, sizeof(int), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipStreamSynchronize(s));
+      last_off = v.p[0];
+      last_len = v.p[1];
+      ts.useful = v.p[2];
+      overflowed = (int)(uint32_t)v.p[3];
+    }
     temp_free(overflow);
     if (overflowed) throw Error{RBF_EDEVICE, "source list larger than its candidate bound (internal error)"};
     ts.list_entries = last_off + last_len;
@@ -1294,10 +1317,17 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s) {
     hipLaunchKernelGGL(k_inner_lengths, dim3(grid_for(G)), dim3(kThreads), 0, s, ts.groups, G, len);
     RBF_HIP(hipGetLastError());
     sum_i64(len, G, tmp, s);
-    RBF_HIP(hipMemcpyAsync(&ts.inner_entries, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     temp_free(use); temp_free(vm); temp_free(len); temp_free(off);
+    if (inner_slot) {
+      RBF_HIP(hipMemcpyAsync(inner_slot, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    } else {
+      PinnedSlots v(1);
+      RBF_HIP(hipMemcpyAsync(v.p, tmp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      RBF_HIP(hipStreamSynchronize(s));
+      ts.inner_entries = v.p[0];
+    }
   }
-  RBF_HIP(hipStreamSynchronize(s));
+  if (ts.dense && inner_slot) *inner_slot = ts.inner_entries;
   temp_free(tmp);
 }
 
@@ -1358,11 +1388,11 @@ static int64_t mark_support_bricks(const Ctx& c, const GridDesc& gd, int64_t nbr
                                    int64_t* scan_ws, hipStream_t s) {
   mark_support(c, gd, mark, nbricks, s);
   scan_exclusive_i64_ws(mark, pos, nbricks, scan_ws, s);
-  int64_t last_pos = 0, last_mark = 0;
-  RBF_HIP(hipMemcpyAsync(&last_pos, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  RBF_HIP(hipMemcpyAsync(&last_mark, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PinnedSlots last(2);
+  RBF_HIP(hipMemcpyAsync(last.p, pos + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  RBF_HIP(hipMemcpyAsync(last.p + 1, mark + (nbricks - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipStreamSynchronize(s));
-  return last_pos + last_mark;
+  return last.p[0] + last.p[1];
 }
 
 int64_t support_bricks(const Ctx& c, const rbf_grid& g, int64_t** ids_out, hipStream_t s) {
