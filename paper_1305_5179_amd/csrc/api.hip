@@ -698,7 +698,7 @@ int rbf_eval_grid_noalloc(rbf_ctx* c, const double* cw, const rbf_grid* grid, fl
     gather_to_sorted(cw, c->perm, c->m, c->vin, s);
     fill_f32(out, 0.0f, total, s);
     const int64_t *tiles = nullptr, *masks = nullptr;
-    const int64_t nt = support_tiles(*c, *grid, ws, &tiles, &masks, s);
+    const int64_t nt = support_tiles(*c, *grid, ws, &tiles, &masks, s, /*pinned=*/false);
     brick_sum_tiles(*c, *grid, tiles, masks, nt, c->vin, out, nullptr, nullptr, s);
     RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;

@@ -344,7 +344,8 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
 // is not cleared).
 //   support_tiles: the tiles of the support and their masks, carved from a
 //   workspace of support_tiles_ws_elems(g) int64 entries; returns the count
-//   (waits for it).  Needs a cutoff.
+//   (waits for it; pinned = false: read without the pinned slots, which a
+//   thread's first use allocates).  Needs a cutoff.
 //   brick_sum_tiles: the sums over such a tile list; t0, t1: start/stop
 //   events the launch carries (optional).  useful/examined: optional HOST
 //   totals of the pairs inside the cutoff and of the pairs computed (then the
@@ -353,7 +354,7 @@ void pairsum_f64(const Ctx& c, const TargetSet& ts, const double* w, bool out_f3
 bool brick_sum_applies(const Ctx& c, const rbf_grid& g);
 int64_t support_tiles_ws_elems(const rbf_grid& g);
 int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_t** tiles, const int64_t** masks,
-                      hipStream_t s);
+                      hipStream_t s, bool pinned = true);
 void brick_sum_tiles(const Ctx& c, const rbf_grid& g, const int64_t* tiles, const int64_t* masks, int64_t nt,
                      const double* w_sorted, float* out, int64_t* useful, int64_t* examined, hipStream_t s,
                      hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);

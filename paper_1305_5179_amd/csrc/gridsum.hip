@@ -405,8 +405,10 @@ int64_t* compact_tiles_out(int64_t* ws, const SlotSpace& S) { return ws + 3 * S.
 int64_t* compact_masks_out(int64_t* ws, const SlotSpace& S) { return ws + 3 * S.n + S.nt0 * S.nt1 * S.nt2; }
 
 // Scan of the slot flags and compaction of the marked tiles in slot order;
-// returns the count (waits for it).
-int64_t compact_tiles(int64_t* ws, const SlotSpace& S, hipStream_t s) {
+// returns the count (waits for it).  pinned: the count's two parts are read
+// through pinned slots (one wait); else into pageable memory (a wait per
+// copy, and no allocation on any call, also the first of a thread).
+int64_t compact_tiles(int64_t* ws, const SlotSpace& S, hipStream_t s, bool pinned = true) {
   int64_t* tmask = ws;
   int64_t* flag = ws + S.n;
   int64_t* pos = ws + 2 * S.n;
@@ -414,6 +416,13 @@ int64_t compact_tiles(int64_t* ws, const SlotSpace& S, hipStream_t s) {
   hipLaunchKernelGGL(k_tile_compact, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, tmask, pos, S,
                      compact_tiles_out(ws, S), compact_masks_out(ws, S));
   RBF_HIP(hipGetLastError());
+  if (!pinned) {
+    int64_t h[2] = {0, 0};
+    RBF_HIP(hipMemcpyAsync(h, pos + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipMemcpyAsync(h + 1, flag + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    return h[0] + h[1];
+  }
   PinnedSlots last(2);
   RBF_HIP(hipMemcpyAsync(last.p, pos + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
   RBF_HIP(hipMemcpyAsync(last.p + 1, flag + (S.n - 1), sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -441,7 +450,7 @@ int64_t support_tiles_ws_elems(const rbf_grid& g) {
 }
 
 int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_t** tiles, const int64_t** masks,
-                      hipStream_t s) {
+                      hipStream_t s, bool pinned) {
   const GridDesc gd = grid_desc(g);
   const SlotSpace S = grid_slots(gd);
   const int64_t nbricks = gd.nb[0] * gd.nb[1] * gd.nb[2];
@@ -450,7 +459,7 @@ int64_t support_tiles(const Ctx& c, const rbf_grid& g, int64_t* ws, const int64_
   mark_support(c, gd, mark, nbricks, s);
   hipLaunchKernelGGL(k_tiles_from_marks, dim3(blocks_of(S.n)), dim3(kThreadsT), 0, s, mark, gd, S, tw, tw + S.n);
   RBF_HIP(hipGetLastError());
-  const int64_t nt = compact_tiles(tw, S, s);
+  const int64_t nt = compact_tiles(tw, S, s, pinned);
   *tiles = compact_tiles_out(tw, S);
   *masks = compact_masks_out(tw, S);
   return nt;
