@@ -36,6 +36,7 @@
 // rows of the subdomains that hold it, in subdomain order.
 #include <algorithm>
 #include <functional>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -268,6 +269,20 @@ __global__ __launch_bounds__(kOvThreads) void k_schwarz_overlap(OvArgs a) {
 // ---------------------------------------------------------------------------
 // Local inverses: one persistent launch, a subdomain per workgroup at a time.
 // ---------------------------------------------------------------------------
+// Storage of a block's inverse W (n x n, symmetric) in column quads: columns
+// 4q .. 4q+3 of every row r lie together at (q * ld + r) * 4 + (c & 3),
+// with ld rows (n, or with float16 entries n rounded up to even) and
+// ceil(n / 4) quads (the pad columns hold 0).  A lane that forms row r of
+// W x (rows r, r + 1 with float16 entries) reads its four (eight) entries of
+// a quad as one 16-byte load.
+__host__ __device__ inline int quad_rows(int n, bool half) { return half ? (n + 1) & ~1 : n; }
+__host__ __device__ inline int64_t quad_elems(int n, bool half) {
+  return (int64_t)((n + 3) >> 2) * 4 * quad_rows(n, half);
+}
+__host__ __device__ inline int64_t quad_at(int col, int row, int ld) {
+  return ((int64_t)(col >> 2) * ld + row) * 4 + (col & 3);
+}
+
 struct FacArgs {
   const double4* xs;        // sorted centres
   const int64_t* mem_off;   // nsub + 1
@@ -278,8 +293,8 @@ struct FacArgs {
   double two_s2;            // 2 sigma^2
   double shift;
   int max_retry;
-  float* W;                 // float32 inverses, or null
-  _Float16* W16;            // float16 inverses (rows of even length), or null
+  float* W;                 // float32 inverses (column quads), or null
+  _Float16* W16;            // float16 inverses (column quads), or null
   double* shift_used;
   int32_t* retries;
   int* failed;
@@ -594,27 +609,32 @@ __global__ __launch_bounds__(kFacThreads) void k_schwarz_factor(FacArgs a) {
       shift = shift > 0.0 ? 10.0 * shift : 1e-10;
     }
     __syncthreads();
-    // W = -(swept matrix), full n x n; the lower triangle holds the result:
-    // read along its rows, each entry stored at (i, j) and (j, i)
+    // W = -(swept matrix), full n x n in column quads; the lower triangle
+    // holds the result: read along its rows, each entry stored at (i, j) and
+    // (j, i); then the pad columns of the last quad, 0 in every row
+    const int npad = 4 * ((n + 3) >> 2) - n;
     if (a.W16) {
       _Float16* W = a.W16 + a.woff[sub];
-      const int ld = (n + 1) & ~1;
+      const int ld = quad_rows(n, true);
       for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
         const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
         if (j > i) continue;
         const _Float16 v = ok ? (_Float16)(float)(-big[e]) : (_Float16)0.0f;
-        W[(int64_t)i * ld + j] = v;
-        W[(int64_t)j * ld + i] = v;
+        W[quad_at(j, i, ld)] = v;
+        W[quad_at(i, j, ld)] = v;
       }
+      for (int e = tid; e < npad * ld; e += kFacThreads) W[quad_at(n + e / ld, e % ld, ld)] = (_Float16)0.0f;
     } else {
       float* W = a.W + a.woff[sub];
+      const int ld = quad_rows(n, false);
       for (int64_t e = tid; e < (int64_t)n * n; e += kFacThreads) {
         const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
         if (j > i) continue;
         const float v = ok ? (float)(-big[e]) : 0.0f;
-        W[e] = v;
-        W[(int64_t)j * n + i] = v;
+        W[quad_at(j, i, ld)] = v;
+        W[quad_at(i, j, ld)] = v;
       }
+      for (int e = tid; e < npad * ld; e += kFacThreads) W[quad_at(n + e / ld, e % ld, ld)] = 0.0f;
     }
     if (tid == 0) {
       a.shift_used[sub] = shift;
@@ -634,8 +654,8 @@ struct ApplyArgs {
   const int32_t* ncore;
   const uint32_t* mem;
   const int64_t* woff;
-  const float* W;           // float32 inverses (n x n), or
-  const _Float16* W16;      // float16 inverses (n rows of even length)
+  const float* W;           // float32 inverses (column quads), or
+  const _Float16* W16;      // float16 inverses (column quads)
   const void* r;            // float64, or float32 with F32
   void* out;                // restricted: z (sorted order; float32 with F32); additive: the local solutions
                             // by member slot (float64)
@@ -643,90 +663,104 @@ struct ApplyArgs {
 };
 
 // One persistent launch: workgroup b takes tasks b, b + gridDim.x, ...; a
-// task gathers its block's vector into LDS and forms T rows of W r, a lane
-// per row (W is symmetric, so lane p reads column p of each row b:
-// consecutive lanes, consecutive addresses).  The restricted form scatters
-// the core rows (the cores partition the centres); the additive form stores
-// every row by member slot.
+// task gathers its block's vector into LDS (0 in the last quad's pad) and
+// forms T rows of W r, a lane per row, or two with float16 entries (W is
+// symmetric and stored in column quads: lane p reads its row's entries of a
+// quad, consecutive lanes at consecutive addresses, 16 bytes each).  The
+// restricted form scatters the core rows (the cores partition the
+// centres); the additive form stores every row by member slot.
 template <bool RESTRICTED, int T, bool F32, bool HALF>
 __global__ __launch_bounds__(T) void k_schwarz_local(ApplyArgs a) {
   if (a.skip && *a.skip) return;
-  __shared__ double rl[kSchwarzMaxBlock];
+  __shared__ __align__(16) double rl[kSchwarzMaxBlock];
   float* rlf = reinterpret_cast<float*>(rl);   // the float32 copy of the HALF form
   const int tid = threadIdx.x;
+  // quads' loads in flight per wave before the first is used
+  constexpr int kQ = 8;
+  // a lane's entries of one quad: rows (row, row + 1) in float16, or row in float32
+  using Quad = typename std::conditional<HALF, uint4, float4>::type;
   for (int64_t t = blockIdx.x; t < a.ntask; t += gridDim.x) {
     const int2 task = a.tasks[t];
     const int64_t sub = task.x;
     const int64_t off = a.mem_off[sub];
     const int n = (int)(a.mem_off[sub + 1] - off);
+    const int nq = (n + 3) >> 2;
+    const int rows = RESTRICTED ? a.ncore[sub] : n;
+    // this lane's rows (row is even in the HALF form, so the eight entries
+    // of a quad are one aligned 16-byte load; the pad row of an odd block
+    // feeds a row that is not stored) and the stride of its quads
+    const int row = task.y + (HALF ? 2 : 1) * tid;
+    const bool active = row < rows;
+    const int64_t qs = HALF ? quad_rows(n, true) >> 1 : quad_rows(n, false);
+    const Quad* w = HALF ? reinterpret_cast<const Quad*>(a.W16 + a.woff[sub]) + (row >> 1)
+                         : reinterpret_cast<const Quad*>(a.W + a.woff[sub]) + row;
     __syncthreads();   // the previous task is done with rl
-    for (int p = tid; p < n; p += T) {
-      const double v = F32 ? (double)static_cast<const float*>(a.r)[a.mem[off + p]]
-                           : static_cast<const double*>(a.r)[a.mem[off + p]];
+    for (int p = tid; p < 4 * nq; p += T) {
+      double x = 0.0;
+      if (p < n)
+        x = F32 ? (double)static_cast<const float*>(a.r)[a.mem[off + p]]
+                : static_cast<const double*>(a.r)[a.mem[off + p]];
       if (HALF)
-        rlf[p] = (float)v;
+        rlf[p] = (float)x;
       else
-        rl[p] = v;
+        rl[p] = x;
     }
     __syncthreads();
-    const int rows = RESTRICTED ? a.ncore[sub] : n;
-    auto store = [&](int row, double y) {
+    if (!active) continue;
+    auto store = [&](int rr, double y) {
       if (RESTRICTED && F32)
-        static_cast<float*>(a.out)[a.mem[off + row]] = (float)y;
+        static_cast<float*>(a.out)[a.mem[off + rr]] = (float)y;
       else if (RESTRICTED)
-        static_cast<double*>(a.out)[a.mem[off + row]] = y;
+        static_cast<double*>(a.out)[a.mem[off + rr]] = y;
       else
-        static_cast<double*>(a.out)[off + row] = y;
+        static_cast<double*>(a.out)[off + rr] = y;
     };
     if constexpr (HALF) {
-      // two rows per lane, read as one 4-byte pair per column (rows of even
-      // length: 4-byte aligned; the pad entry of an odd block feeds a row
-      // that is not stored); float32 products and sums (their rounding, at
-      // most n u32 <= 2^-14, is below the float16 entries' own), each a
-      // mixed-precision FMA on the float16 entry
-      const int row = task.y + 2 * tid;
-      if (row >= rows) continue;
-      const int ld = (n + 1) & ~1;
-      const uint32_t* w = reinterpret_cast<const uint32_t*>(a.W16 + a.woff[sub] + row);
-      // 16 columns' loads in flight per wave before the first is used
-      constexpr int kU = 16;
-      float e[4] = {0.f, 0.f, 0.f, 0.f}, o[4] = {0.f, 0.f, 0.f, 0.f};
-      int b = 0;
-      for (; b + kU <= n; b += kU) {
-        uint32_t v[kU];
+      // float32 products and sums (their rounding, at most n u32 <= 2^-14, is
+      // below the float16 entries' own), each a mixed-precision FMA on the
+      // float16 entry
+      const float4* r4 = reinterpret_cast<const float4*>(rlf);
+      auto h = [](uint32_t x, int k) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(x >> (16 * k))); };
+      auto quad = [&](const uint4& e8, const float4& r, float& ea, float& oa) {
+        ea = __builtin_fmaf(h(e8.x, 0), r.x, ea);
+        oa = __builtin_fmaf(h(e8.z, 0), r.x, oa);
+        ea = __builtin_fmaf(h(e8.x, 1), r.y, ea);
+        oa = __builtin_fmaf(h(e8.z, 1), r.y, oa);
+        ea = __builtin_fmaf(h(e8.y, 0), r.z, ea);
+        oa = __builtin_fmaf(h(e8.w, 0), r.z, oa);
+        ea = __builtin_fmaf(h(e8.y, 1), r.w, ea);
+        oa = __builtin_fmaf(h(e8.w, 1), r.w, oa);
+      };
+      float e[2] = {0.f, 0.f}, o[2] = {0.f, 0.f};
+      int q = 0;
+      for (; q + kQ <= nq; q += kQ) {
+        Quad v[kQ];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = w[(int64_t)(b + u) * (ld / 2)];
+        for (int u = 0; u < kQ; ++u) v[u] = w[(int64_t)(q + u) * qs];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const float r = rlf[b + u];
-          e[u & 3] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)v[u]), r, e[u & 3]);
-          o[u & 3] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(v[u] >> 16)), r, o[u & 3]);
-        }
+        for (int u = 0; u < kQ; ++u) quad(v[u], r4[q + u], e[u & 1], o[u & 1]);
       }
-      for (; b < n; ++b) {
-        const uint32_t v = w[(int64_t)b * (ld / 2)];
-        const float r = rlf[b];
-        e[0] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)v), r, e[0]);
-        o[0] = __builtin_fmaf((float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)), r, o[0]);
-      }
-      store(row, (double)((e[0] + e[1]) + (e[2] + e[3])));
-      if (row + 1 < rows) store(row + 1, (double)((o[0] + o[1]) + (o[2] + o[3])));
+      for (; q < nq; ++q) quad(w[(int64_t)q * qs], r4[q], e[0], o[0]);
+      store(row, (double)(e[0] + e[1]));
+      if (row + 1 < rows) store(row + 1, (double)(o[0] + o[1]));
     } else {
-      const int row = task.y + tid;
-      if (row >= rows) continue;
-      const float* w = a.W + a.woff[sub] + row;
-      // 16 columns' loads in flight per wave before the first is used
-      constexpr int kU = 16;
+      // float64 products and sums of the float32 entries
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      int b = 0;
-      for (; b + kU <= n; b += kU) {
-        float v[kU];
+      auto quad = [&](const float4& e4, int qq, double& ac) {
+        ac = fma((double)e4.x, rl[4 * qq], ac);
+        ac = fma((double)e4.y, rl[4 * qq + 1], ac);
+        ac = fma((double)e4.z, rl[4 * qq + 2], ac);
+        ac = fma((double)e4.w, rl[4 * qq + 3], ac);
+      };
+      int q = 0;
+      for (; q + kQ <= nq; q += kQ) {
+        Quad v[kQ];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) v[u] = w[(int64_t)(b + u) * n];
+        for (int u = 0; u < kQ; ++u) v[u] = w[(int64_t)(q + u) * qs];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) acc[u & 3] = fma((double)v[u], rl[b + u], acc[u & 3]);
+        for (int u = 0; u < kQ; ++u) quad(v[u], q + u, acc[u & 3]);
       }
-      for (; b < n; ++b) acc[0] = fma((double)w[(int64_t)b * n], rl[b], acc[0]);
+      for (; q < nq; ++q) quad(w[(int64_t)q * qs], q, acc[0]);
       store(row, (acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
   }
@@ -1177,7 +1211,7 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     d->h_mem_off[i + 1] = d->h_mem_off[i] + nb;
     d->h_ncore[i] = nc;
     woff[i] = wtotal;
-    wtotal += nb * (half ? (nb + 1) / 2 * 2 : nb);
+    wtotal += quad_elems((int)nb, half);
     order[i] = (int32_t)i;
   }
   d->nmem = d->h_mem_off[nsub];
