@@ -84,9 +84,10 @@ __host__ __device__ inline bool expanded_form(bool dense, double rk, double sqrt
 
 // The overlapping Schwarz preconditioner (schwarz.hip).  Subdomain i has
 // members mem[mem_off[i] .. mem_off[i+1]) (sorted positions), its ncore[i]
-// core centres first; its local inverse is W[woff[i] ..], float32, n x n, or
-// with `half` W16[woff[i] ..], float16, n rows of ld = n rounded up to even
-// entries (the pad entry of odd n unused).
+// core centres first; its local inverse is W[woff[i] ..], float32, or with
+// `half` W16[woff[i] ..], float16, n x n in column quads (schwarz.hip:
+// columns 4q .. 4q+3 of a row together; float16 rows padded to an even
+// count).
 constexpr int kSchwarzMaxBlock = 1024;   // largest subdomain (core + overlap centres)
 constexpr int kSchwarzDefaultBlock = 192;
 struct SchwarzData {
