@@ -91,8 +91,9 @@ typedef struct {
                           cap allows, 0..max_block */
     double shift;      /* added to the unit diagonal of every local block, >= 0 (default 0.3) */
     int tune;          /* 1: time the apply kernel's launch shapes at setup and keep the
-                          fastest (default); 0: the fixed shape (256 threads, 4 workgroups
-                          per compute unit) */
+                          fastest (default); 0: no timing: workgroups of the smallest of
+                          128, 256, 512 threads whose task covers the largest block's rows
+                          (two rows per thread with half), one workgroup per task */
     int half;          /* 1: the local inverses stored in float16 (half the apply's bytes; each
                           entry then carries a relative rounding of at most 2^-11, and the
                           apply's products and sums are float32; this changes the

@@ -895,31 +895,46 @@ void launch_local(const SchwarzData& d, int T, int blocks, const int2* tasks, in
   }
 }
 
-// The apply's launch shape: workgroups of 128, 256 or 512 threads (strips of
-// as many rows, twice as many with float16 inverses), taken by 2, 4 or 8
-// workgroups per compute unit or by one workgroup per task.  The three task
-// lists are built and uploaded once; after one untimed apply every candidate
-// runs once between its own pair of events, all back to back (the work and
-// the result do not depend on the values), and the host waits once; the
-// fastest is kept.
+// The workgroup size whose task (a strip of as many rows, twice as many with
+// float16 inverses) covers the largest block's rows in one task: 128, 256
+// or 512 threads.
+int covering_threads(const SchwarzData& d) {
+  int64_t rows = 0;
+  for (int64_t i = 0; i < d.nsub; ++i)
+    rows = std::max<int64_t>(rows, d.restricted ? d.h_ncore[i] : d.h_mem_off[i + 1] - d.h_mem_off[i]);
+  const int64_t lanes = d.half ? (rows + 1) / 2 : rows;
+  return lanes <= 128 ? 128 : lanes <= 256 ? 256 : 512;
+}
+
+// The apply's launch shape.  Candidates: the covering workgroup size and
+// the next smaller one (two tasks for the largest blocks), each taken by 8
+// workgroups per compute unit or by one workgroup per task (on the torus
+// workloads these always won; 2 and 4 per compute unit and a larger size
+// never did).  The task lists are built and uploaded once; after one untimed
+// apply every candidate runs once between its own pair of events, all back
+// to back (the work and the result do not depend on the values), and the
+// host waits once; the fastest is kept.
 void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
   struct Cand {
     int T, mult, blocks;
     hipEvent_t e0, e1;
   };
-  constexpr int kShapes = 3;
-  const int Ts[kShapes] = {128, 256, 512};
-  int2* dt[kShapes];
-  int64_t nt[kShapes];
-  for (int k = 0; k < kShapes; ++k) {
+  const int top = covering_threads(d);
+  std::vector<int> Ts;
+  if (top > 128) Ts.push_back(top / 2);
+  Ts.push_back(top);
+  const int nshape = (int)Ts.size();
+  std::vector<int2*> dt(nshape);
+  std::vector<int64_t> nt(nshape);
+  for (int k = 0; k < nshape; ++k) {
     std::vector<int2> ht = apply_tasks(d, Ts[k]);
     dt[k] = upload(ht, s);
     nt[k] = (int64_t)ht.size();
   }
-  auto shape = [&](int T) { return T == Ts[0] ? 0 : T == Ts[1] ? 1 : 2; };
+  auto shape = [&](int T) { return T == Ts[0] ? 0 : 1; };
   std::vector<Cand> cands;
-  for (int k = 0; k < kShapes; ++k)
-    for (int mult : {2, 4, 8, 0}) {
+  for (int k = 0; k < nshape; ++k)
+    for (int mult : {8, 0}) {
       Cand c{Ts[k], mult, 0, nullptr, nullptr};
       c.blocks = mult > 0 ? (int)std::min<int64_t>((int64_t)mult * cus, nt[k]) : (int)nt[k];
       cands.push_back(c);
@@ -951,7 +966,7 @@ void tune_apply(SchwarzData& d, int cus, hipStream_t s) {
   dfree(d.tasks);
   d.tasks = dt[k];
   d.ntask = nt[k];
-  for (int j = 0; j < kShapes; ++j)
+  for (int j = 0; j < nshape; ++j)
     if (j != k) dfree(dt[j]);
   d.apply_threads = cands[pick].T;
   d.apply_blocks = cands[pick].blocks;
@@ -1314,11 +1329,13 @@ SchwarzData* schwarz_setup(const Ctx& c, int max_block, int pct, int restricted,
     if (tune) {
       tune_apply(*d, cus, s);
     } else {
-      std::vector<int2> ht = apply_tasks(*d, 256);
+      // the covering workgroup size, one workgroup per task
+      const int T = covering_threads(*d);
+      std::vector<int2> ht = apply_tasks(*d, T);
       d->tasks = upload(ht, s);
       d->ntask = (int64_t)ht.size();
-      d->apply_threads = 256;
-      d->apply_blocks = (int)std::min<int64_t>(4 * (int64_t)cus, d->ntask);
+      d->apply_threads = T;
+      d->apply_blocks = (int)std::max<int64_t>(d->ntask, 1);
       RBF_HIP(hipStreamSynchronize(s));
     }
   }
