@@ -26,6 +26,7 @@ constexpr int kGroup = 16;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;
 constexpr int kBlock = 256;          // threads per block of the pair kernels (4 independent waves)
+constexpr int kGroupsPerLaunchBlock = kBlock / kWave;   // groups (one per wave) per workgroup of the pair kernels
 // Padding entries after the last group's list: the pair kernels read the
 // list indices up to three chunks ahead without bounds tests.
 constexpr int kListTail = 3 * kChunk;
@@ -152,6 +153,8 @@ struct TargetSet {
   bool temp = false;        // arrays are stream-ordered temporaries (per-call sets)
   int kind = 0;             // 0: the centres (operator), 1: evaluation targets
   bool lattice = false;     // groups are bricks of grid nodes (4 x 2 x 2, node order of k_brick_targets)
+  int32_t* order = nullptr; // launch order of the groups for the pair kernels (operator sets), or null
+                            // (identity): group order[slot] runs in launch slot `slot`
   std::vector<void*> owned; // device allocations to free with the set
 };
 

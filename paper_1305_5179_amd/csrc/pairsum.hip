@@ -40,6 +40,7 @@ struct PairArgs {
   const GroupInfo* groups;
   const uint32_t* list;
   const uint64_t* mask;  // per-step lane masks of the non-inner chunks
+  const int32_t* order;  // launch order of the groups, or null (identity)
   int64_t G;
   const double4* xk;     // scaled sources (float32 path)
   const double4* xs;     // unscaled sources
@@ -412,15 +413,26 @@ __device__ __forceinline__ GroupInfo load_group(const GroupInfo* gp) {
 // but measured 3 % slower: the kernel is bound by VALU issue, not by the
 // tail.
 constexpr int kPairWaves = 4;
+static_assert(kPairWaves == kGroupsPerLaunchBlock, "the group launch order assumes four groups per workgroup");
+
+// The group a wave runs: its launch slot (each XCD a contiguous range of
+// slots), through the set's launch order when it has one.  Uniform, so the
+// order is read by a scalar load.
+__device__ __forceinline__ int64_t slot_group(const PairArgs& a, int64_t slot) {
+  if (!a.order) return slot;
+  typedef const __attribute__((address_space(4))) int32_t* ConstI32;
+  return ((ConstI32)a.order)[slot];
+}
 
 template <bool W32, bool BUF>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pairsum_f32(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * kPairWaves + wave;
-  if (g >= a.G) return;
+  const int64_t slot = xcd_remap(blockIdx.x, gridDim.x) * kPairWaves + wave;
+  if (slot >= a.G) return;
   if (a.skip && *a.skip) return;
+  const int64_t g = slot_group(a, slot);
   const GroupInfo gi = load_group(a.groups + g);
   if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
     expanded_group<W32, BUF>(a, gi, g, lane);
@@ -564,9 +576,10 @@ __global__ __launch_bounds__(kBlock, 6) void k_pairsum_f64(PairArgs a) {
   // the wave index is uniform across the wave: keep it (and all group data) scalar
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t g = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (g >= a.G) return;
+  const int64_t slot = xcd_remap(blockIdx.x, gridDim.x) * kGroupsPerLaunchBlock + wave;
+  if (slot >= a.G) return;
   if (a.skip && *a.skip) return;
+  const int64_t g = slot_group(a, slot);
   const GroupInfo gi = load_group(a.groups + g);
   if (expanded_form(a.dense != 0, gi.radius * a.sqrt_k, a.sqrt_T))
     expanded_group_f64(a, gi, g, wave, lane, sh);
@@ -605,6 +618,7 @@ PairArgs make_args(const Ctx& c, const TargetSet& ts, const double* w, bool out_
   a.groups = ts.groups;
   a.list = ts.list;
   a.mask = reinterpret_cast<const uint64_t*>(ts.mask);
+  a.order = ts.order;
   a.G = ts.n_groups;
   a.xk = c.xk;
   a.xs = c.xs;

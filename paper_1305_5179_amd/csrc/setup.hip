@@ -729,6 +729,46 @@ __global__ __launch_bounds__(kThreads) void k_list_compact(GroupInfo* __restrict
   }
 }
 
+// Launch order of an operator set's groups for the pair kernels.  A launch
+// of nb workgroups of four groups runs the workgroups of XCD x on a
+// contiguous range of slots (xcd_remap), in slot order; within each XCD's
+// range the groups with more chunks take the first slots (16 classes of
+// chunk count, descending; any order inside a class), so that a launch ends
+// on short groups.  The order only moves whole groups between slots: every
+// group's sums stay the same.  One workgroup per XCD.
+constexpr int kOrderClasses = 16;
+__global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __restrict__ groups, int64_t G,
+                                                          int64_t nb, int32_t* __restrict__ order) {
+  __shared__ int32_t cnt[kOrderClasses], base[kOrderClasses], smax[kThreads / kWave];
+  const int x = blockIdx.x, t = threadIdx.x;
+  const int64_t q = nb / 8, r = nb % 8;
+  const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  const int64_t count = q + (x < r ? 1 : 0);
+  const int64_t g0 = min(G, first * kGroupsPerLaunchBlock), g1 = min(G, (first + count) * kGroupsPerLaunchBlock);
+  // the largest chunk count of the range sets the class width
+  int32_t m = 0;
+  for (int64_t g = g0 + t; g < g1; g += kThreads) m = max(m, groups[g].n_chunks);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if ((t & 63) == 0) smax[t >> 6] = m;
+  if (t < kOrderClasses) cnt[t] = 0;
+  __syncthreads();
+  m = 0;
+  for (int w = 0; w < kThreads / kWave; ++w) m = max(m, smax[w]);
+  const int32_t width = m / kOrderClasses + 1;
+  auto cls = [&](int64_t g) { return kOrderClasses - 1 - min(kOrderClasses - 1, groups[g].n_chunks / width); };
+  for (int64_t g = g0 + t; g < g1; g += kThreads) atomicAdd(&cnt[cls(g)], 1);
+  __syncthreads();
+  if (t == 0) {
+    int32_t acc = 0;
+    for (int k = 0; k < kOrderClasses; ++k) {
+      base[k] = acc;
+      acc += cnt[k];
+    }
+  }
+  __syncthreads();
+  for (int64_t g = g0 + t; g < g1; g += kThreads) order[g0 + atomicAdd(&base[cls(g)], 1)] = (int32_t)g;
+}
+
 __global__ void k_list_lengths(const GroupInfo* __restrict__ groups, int64_t G, int64_t* __restrict__ len) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g < G) len[g] = (int64_t)groups[g].n_chunks * kChunk;
@@ -1328,6 +1368,14 @@ void build_lists(const Ctx& c, TargetSet& ts, hipStream_t s, int64_t* inner_slot
     }
   }
   if (ts.dense && inner_slot) *inner_slot = ts.inner_entries;
+  // the operator's groups run many times: longest first within each XCD's slots
+  if (!ts.dense && ts.kind == 0 && G > 0 && G < ((int64_t)1 << 31)) {
+    ts.order = set_alloc<int32_t>(ts, G);
+    ts.owned.push_back(ts.order);
+    hipLaunchKernelGGL(k_group_order, dim3(8), dim3(kThreads), 0, s, ts.groups, G,
+                       ceil_div(G, (int64_t)kGroupsPerLaunchBlock), ts.order);
+    RBF_HIP(hipGetLastError());
+  }
   temp_free(tmp);
 }
 
@@ -1346,6 +1394,7 @@ void free_targets(TargetSet& ts) {
   ts.groups = nullptr;
   ts.list = nullptr;
   ts.mask = nullptr;
+  ts.order = nullptr;
 }
 
 int64_t* build_cell_sat(const Ctx& c, hipStream_t s) {
