@@ -733,13 +733,16 @@ __global__ __launch_bounds__(kThreads) void k_list_compact(GroupInfo* __restrict
 // of nb workgroups of four groups runs the workgroups of XCD x on a
 // contiguous range of slots (xcd_remap), in slot order; within each XCD's
 // range the groups with more chunks take the first slots (16 classes of
-// chunk count, descending; any order inside a class), so that a launch ends
-// on short groups.  The order only moves whole groups between slots: every
-// group's sums stay the same.  One workgroup per XCD.
+// chunk count, descending), so that a launch ends on short groups, and
+// inside a class the groups keep their order (neighbouring groups, which
+// share most candidate sources, stay close in time).  The order only moves
+// whole groups between slots: every group's sums stay the same.  One
+// workgroup per XCD.
 constexpr int kOrderClasses = 16;
 __global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __restrict__ groups, int64_t G,
                                                           int64_t nb, int32_t* __restrict__ order) {
   __shared__ int32_t cnt[kOrderClasses], base[kOrderClasses], smax[kThreads / kWave];
+  __shared__ int32_t wcnt[kThreads / kWave][kOrderClasses];
   const int x = blockIdx.x, t = threadIdx.x;
   const int64_t q = nb / 8, r = nb % 8;
   const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
@@ -766,7 +769,30 @@ __global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __res
     }
   }
   __syncthreads();
-  for (int64_t g = g0 + t; g < g1; g += kThreads) order[g0 + atomicAdd(&base[cls(g)], 1)] = (int32_t)g;
+  // a stable split, a tile of kThreads groups at a time: a group's slot is
+  // its class's base, plus the groups of its class in the earlier waves of
+  // the tile, plus those in its own wave below it
+  const int wave = t >> 6, lane = t & 63;
+  for (int64_t t0 = g0; t0 < g1; t0 += kThreads) {
+    const int64_t g = t0 + t;
+    const int c = g < g1 ? cls(g) : -1;
+    int rank = 0;
+    for (int k = 0; k < kOrderClasses; ++k) {
+      const uint64_t b = ballot(c == k);
+      if (c == k) rank = (int)lanes_below(b);
+      if (lane == 0) wcnt[wave][k] = __popcll(b);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int32_t at = base[c] + rank;
+      for (int w = 0; w < wave; ++w) at += wcnt[w][c];
+      order[g0 + at] = (int32_t)g;
+    }
+    __syncthreads();
+    if (t < kOrderClasses)
+      for (int w = 0; w < kThreads / kWave; ++w) base[t] += wcnt[w][t];
+    __syncthreads();
+  }
 }
 
 __global__ void k_list_lengths(const GroupInfo* __restrict__ groups, int64_t G, int64_t* __restrict__ len) {
