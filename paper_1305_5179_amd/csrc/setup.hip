@@ -732,17 +732,19 @@ __global__ __launch_bounds__(kThreads) void k_list_compact(GroupInfo* __restrict
 // Launch order of an operator set's groups for the pair kernels.  A launch
 // of nb workgroups of four groups runs the workgroups of XCD x on a
 // contiguous range of slots (xcd_remap), in slot order; within each XCD's
-// range the groups with more chunks take the first slots (16 classes of
-// chunk count, descending), so that a launch ends on short groups, and
-// inside a class the groups keep their order (neighbouring groups, which
-// share most candidate sources, stay close in time).  The order only moves
-// whole groups between slots: every group's sums stay the same.  One
-// workgroup per XCD.
+// range the longest eighth of the groups (whole classes of 16 classes of
+// chunk count) takes the first slots, so that a launch does not end on a
+// long group, and every group keeps its spatial order otherwise
+// (neighbouring groups, which share most candidate sources, stay close in
+// time).  The order only moves whole groups between slots: every group's
+// sums stay the same.  One workgroup per XCD.
 constexpr int kOrderClasses = 16;
+constexpr int kLongShare = 8;
 __global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __restrict__ groups, int64_t G,
                                                           int64_t nb, int32_t* __restrict__ order) {
   __shared__ int32_t cnt[kOrderClasses], base[kOrderClasses], smax[kThreads / kWave];
   __shared__ int32_t wcnt[kThreads / kWave][kOrderClasses];
+  __shared__ int32_t s_cut;
   const int x = blockIdx.x, t = threadIdx.x;
   const int64_t q = nb / 8, r = nb % 8;
   const int64_t first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
@@ -762,22 +764,32 @@ __global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __res
   for (int64_t g = g0 + t; g < g1; g += kThreads) atomicAdd(&cnt[cls(g)], 1);
   __syncthreads();
   if (t == 0) {
-    int32_t acc = 0;
+    // the longest classes holding at least 1/kLongShare of the range go
+    // first; every other group keeps its place in the spatial order
+    const int32_t want = (int32_t)((g1 - g0 + kLongShare - 1) / kLongShare);
+    int32_t acc = 0, cut = kOrderClasses - 1;
     for (int k = 0; k < kOrderClasses; ++k) {
-      base[k] = acc;
       acc += cnt[k];
+      if (acc >= want) {
+        cut = k;
+        break;
+      }
     }
+    s_cut = cut;
+    base[0] = 0;
+    base[1] = acc;
   }
   __syncthreads();
   // a stable split, a tile of kThreads groups at a time: a group's slot is
   // its class's base, plus the groups of its class in the earlier waves of
   // the tile, plus those in its own wave below it
   const int wave = t >> 6, lane = t & 63;
+  const int cut = s_cut;
   for (int64_t t0 = g0; t0 < g1; t0 += kThreads) {
     const int64_t g = t0 + t;
-    const int c = g < g1 ? cls(g) : -1;
+    const int c = g < g1 ? (cls(g) <= cut ? 0 : 1) : -1;
     int rank = 0;
-    for (int k = 0; k < kOrderClasses; ++k) {
+    for (int k = 0; k < 2; ++k) {
       const uint64_t b = ballot(c == k);
       if (c == k) rank = (int)lanes_below(b);
       if (lane == 0) wcnt[wave][k] = __popcll(b);
@@ -789,7 +801,7 @@ __global__ __launch_bounds__(kThreads) void k_group_order(const GroupInfo* __res
       order[g0 + at] = (int32_t)g;
     }
     __syncthreads();
-    if (t < kOrderClasses)
+    if (t < 2)
       for (int w = 0; w < kThreads / kWave; ++w) base[t] += wcnt[w][t];
     __syncthreads();
   }
